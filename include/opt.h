@@ -1,0 +1,202 @@
+/*
+ * opt.h - C ABI of a matrix-free Gauss-Newton / Levenberg-Marquardt least-squares
+ * solver for MI355X (gfx950), after Opt (DeVito et al., arXiv 1604.06525).
+ *
+ * The solver minimises E(x) = sum_r f_r(x)^2 (Sec. 4) for a fixed set of energies
+ * written by hand (the energy listings of Appendix C), on a 2D pixel grid or on
+ * a graph.  Every outer iteration linearises F at x and solves the normal
+ * equations J^T J d = -J^T F (Sec. 4; the factor 2 on both sides cancels) with a
+ * Jacobi-preconditioned conjugate gradient started from d = 0 (Sec. 4.1), whose
+ * products J^T F, J^T J p and diag(J^T J) are evaluated on the fly from the
+ * unknowns and the energy's data (matrix-free, Secs. 4.1-4.2).  Levenberg-
+ * Marquardt adds lambda * diag(J^T J) to the system (Sec. 4).
+ *
+ * Conventions shared by every call
+ * --------------------------------
+ * - Every function returns 0 on success or a negative OPT_E* code; the message
+ *   of the last failure on the calling thread is returned by opt_last_error().
+ *   A failed call leaves the problem as it was, except OPT_EHIP from an enqueued
+ *   kernel, after which the problem's device state is undefined.
+ * - Device pointers are plain HIP device addresses on the device that is current
+ *   when the problem is created.  Host pointers are ordinary host memory.
+ * - A field of c channels over n sites is stored as c planes of n values
+ *   ("SoA"): element (ch, site) at offset ch*n + site.  On a grid of width W and
+ *   height H, site (i, j) is j*W + i, with i along the width (the first grid
+ *   dimension in the paper's listings).
+ * - Bulk values (unknowns, data arrays, internal vectors) are float64 under
+ *   OPT_FP64 and float32 under OPT_MIXED.  Dot products, costs, the PCG scalars
+ *   and the LM step test are accumulated in float64 under both (Sec. 7, "Numerical
+ *   Precision", offers float and double; the mixed form keeps the reductions in
+ *   double).  Masks are uint8.
+ * - All work is enqueued on the HIP stream given at creation, in order.  Calls
+ *   that return host values synchronise that stream once before returning.
+ * - The library allocates no device memory: all of its device state lives in a
+ *   caller-owned workspace of opt_workspace_size() bytes.  Data arrays are
+ *   referenced, not copied: they must stay valid and unchanged while work that
+ *   reads them is in flight, and the caller may edit them between calls (the
+ *   multi-pass use of Sec. 7).
+ * - A problem handle is not thread-safe; calls on one handle must not overlap.
+ */
+#ifndef OPT_H
+#define OPT_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* error codes */
+#define OPT_OK 0
+#define OPT_EINVAL (-1)       /* invalid argument, size or descriptor field */
+#define OPT_ENOMEM (-2)       /* workspace smaller than opt_workspace_size() */
+#define OPT_EHIP (-3)         /* a HIP runtime call failed; message names it */
+#define OPT_EAGAIN (-4)       /* resource busy (reserved for the server API) */
+#define OPT_ENUMERIC (-5)     /* a cost came out NaN or infinite */
+#define OPT_EUNSUPPORTED (-6) /* combination of domain/energy/precision not built */
+
+typedef enum { OPT_GRID2D = 0, OPT_GRAPH = 1 } opt_domain;
+
+/*
+ * Energies.  For each: unknown channels; arrays[] in order; params[] in order.
+ *
+ * OPT_E_ARAP_WARP (grid; Fig. 24, Appendix A.1.1).  Unknowns 3: offset x, offset y,
+ *   angle.  arrays: [0] U rest positions (2 planes), [1] C targets (2 planes; a
+ *   target is used when both components are >= 0), [2] mask (uint8; pixels with
+ *   mask != 0 are excluded from the solve but keep their terms).  params:
+ *   w_fit, w_reg (square roots of the energy weights).
+ * OPT_E_POISSON (grid; Fig. 27, A.1.4).  Unknowns 4 (RGBA).  arrays: [0] T
+ *   (4 planes), [1] mask (uint8; mask != 0 excluded).  params: none.
+ * OPT_E_SFS (grid; Fig. 26, A.1.3).  Unknowns 1 (depth).  arrays: [0] D_i input
+ *   depth (D_i <= 0 is excluded), [1] Im intensity, [2] edgeMaskR (uint8),
+ *   [3] edgeMaskC (uint8).  params: w_p, w_s, w_g (energy weights; their square
+ *   roots are applied), f_x, f_y, u_x, u_y, L1..L9.
+ * OPT_E_FLOW (grid; Fig. 30, A.2.3).  Unknowns 2 (u, v).  arrays: [0] I,
+ *   [1] I_hat, [2] dI_hat/dx, [3] dI_hat/dy.  params: w_fit, w_reg.
+ * OPT_E_ARAP_MESH (graph; Fig. 25, A.1.2).  Unknowns 6: offset xyz, Euler angles
+ *   xyz with R = Rz Ry Rx.  arrays: [0] U rest positions (3 planes), [1] C targets
+ *   (3 planes; a component is used when >= -999999.9).  Each listed undirected
+ *   edge {v0, v1} contributes the ARAP residual in both orientations.  params:
+ *   w_fit, w_reg.
+ */
+typedef enum {
+  OPT_E_LAPLACIAN = 0,
+  OPT_E_ARAP_WARP = 1,
+  OPT_E_POISSON = 2,
+  OPT_E_SFS = 3,
+  OPT_E_FLOW = 4,
+  OPT_E_ARAP_MESH = 5
+} opt_energy;
+
+typedef enum { OPT_FP64 = 0, OPT_MIXED = 1 } opt_precision;
+typedef enum { OPT_GN = 0, OPT_LM = 1 } opt_method;
+
+typedef struct {
+  int32_t domain;     /* opt_domain */
+  int32_t energy;     /* opt_energy */
+  int32_t precision;  /* opt_precision */
+  int32_t width, height;           /* grid size (OPT_GRID2D), each >= 1 */
+  int32_t n_vertices, n_edges;     /* graph size (OPT_GRAPH), V >= 1, E >= 0 */
+  const int32_t* edges;            /* device, [E][2] vertex ids (v0, v1); read by
+                                      opt_problem_create only */
+  const void* arrays[8];           /* device, energy-specific (see opt_energy) */
+  double params[16];               /* energy-specific (see opt_energy) */
+  int32_t n_params;                /* number of params[] entries supplied */
+} opt_problem_desc;
+
+typedef struct opt_problem opt_problem;
+
+/* Text of the last error on the calling thread ("" if none).  Never NULL. */
+const char* opt_last_error(void);
+
+/* Bytes of device workspace the problem needs.  Pure host computation. */
+int opt_workspace_size(const opt_problem_desc* desc, size_t* bytes);
+
+/*
+ * Create a problem (Fig. 4's define + plan steps; with hand-written energies both
+ * collapse into one call).  `workspace` is caller-owned device memory of at least
+ * opt_workspace_size() bytes, 256-byte aligned, that must outlive the handle.
+ * `hip_stream` is a hipStream_t (NULL = the null stream).  For a graph the edge
+ * list is sorted into a per-vertex incidence list inside the workspace (this
+ * synchronises the stream once).  On failure *out is set to NULL.
+ */
+int opt_problem_create(const opt_problem_desc* desc, void* workspace, size_t workspace_bytes,
+                       void* hip_stream, opt_problem** out);
+
+/* Release the handle (not the workspace or arrays).  NULL is accepted. */
+int opt_problem_destroy(opt_problem* prob);
+
+typedef struct {
+  int32_t method;       /* opt_method */
+  int32_t outer_iters;  /* nonlinear iterations K >= 0 (LM: rejected steps count) */
+  int32_t pcg_iters;    /* linear iterations L >= 0 per outer iteration */
+  int32_t use_precond;  /* 1: Jacobi M = diag(J^T J) (Sec. 4.1); 0: plain CG */
+  double lm_radius0;    /* initial trust-region radius; lambda = 1/radius (Sec. 4) */
+  double lm_radius_min; /* LM stops once the radius falls below this */
+  double lm_radius_max; /* cap on the radius */
+  double lm_diag_min, lm_diag_max; /* clamp of the damping diagonal D */
+  double lm_min_rel_decrease;      /* step accepted iff model decrease m > 0 and
+                                      (E(x) - E(x+d)) / m exceeds this */
+} opt_solve_params;
+
+typedef struct {
+  double cost_initial;   /* E(x) before the first iteration */
+  double cost_final;     /* E(x) after the last */
+  int32_t outer_done;    /* iterations executed (LM may stop early) */
+  int32_t steps_accepted;/* GN: outer_done; LM: accepted steps */
+  double* cost_trace;    /* optional host array of outer_iters+1 entries: E at the
+                            start of each iteration, then the final E; NULL = skip */
+} opt_solve_report;
+
+/* Fill `p` with the defaults: GN, 10 x 50, preconditioned, LM radius 1e4 in
+   [1e-32, 1e16], diagonal clamp [1e-6, 1e32], min relative decrease 1e-3. */
+void opt_default_params(opt_solve_params* p);
+
+/*
+ * Run the solver on `unknowns` (device, channels x sites, in/out), following
+ * Sec. 4: GN updates x += d after each PCG solve; LM takes or rejects the step
+ * by the gain ratio and updates the radius.  Excluded unknowns never change.
+ * If `report` is NULL the call only enqueues work and returns; otherwise it
+ * synchronises once and fills the report.  Returns OPT_ENUMERIC (with the report
+ * filled) if a cost is NaN or infinite.
+ */
+int opt_solve(opt_problem* prob, void* unknowns, const opt_solve_params* params,
+              opt_solve_report* report);
+
+/* E(x) = sum_r f_r(x)^2 in float64 at `unknowns` (device); synchronises. */
+int opt_cost(opt_problem* prob, const void* unknowns, double* cost);
+
+/*
+ * Step-level entry points.  They expose the stages of one outer iteration so
+ * each can be checked and timed on its own; opt_solve chains the same kernels.
+ *
+ * opt_linearize: evaluate the residuals at `unknowns` and store the per-site
+ *   state the matrix-free products need (Sec. 7's precomputed arrays: e.g. the
+ *   rotation's cosine and sine, the shading term and its gradient, sampled image
+ *   derivatives).  Writes E(x) to *cost if cost != NULL (then synchronises).
+ *   The later step calls read `unknowns` again: it must stay valid and unchanged
+ *   until the next opt_linearize or opt_solve on this problem.
+ * opt_eval_jtf: at the last linearisation point, write b = -J^T F and
+ *   diag(J^T J) (device, channels x sites, bulk type; either may be NULL).
+ *   Excluded unknowns get 0 in both.
+ * opt_apply_jtj: at the last linearisation point, q = (J^T J + lambda D) p with
+ *   D = clamp(diag(J^T J), lm_diag_min, lm_diag_max) from `params` (which may be
+ *   NULL when lambda == 0).  p, q: device, channels x sites; excluded entries of
+ *   p are ignored and of q set to 0.  p and q must not overlap.
+ * opt_pcg: at the last linearisation point, run params->pcg_iters PCG iterations
+ *   on (J^T J + lambda D) d = -J^T F from d = 0 and write d (device).
+ */
+int opt_linearize(opt_problem* prob, const void* unknowns, double* cost);
+int opt_eval_jtf(opt_problem* prob, void* b_out, void* diag_out);
+int opt_apply_jtj(opt_problem* prob, const void* p, void* q, double lambda,
+                  const opt_solve_params* params);
+int opt_pcg(opt_problem* prob, const opt_solve_params* params, double lambda, void* delta_out);
+
+/* Number of unknown channels per site for an energy (0 if unknown). */
+int opt_energy_channels(int32_t energy);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* OPT_H */

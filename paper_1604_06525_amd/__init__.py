@@ -1,0 +1,230 @@
+"""Python binding of the MI355X matrix-free GN/LM least-squares library (libopt.so).
+
+Argument marshalling only: every step of a solve runs in the HIP kernels of
+``libopt.so``; this module turns torch tensors into device pointers and calls
+the C ABI of ``include/opt.h`` with the same names.  The first call raises if the
+library has not been built (``__graft_entry__.build()`` or
+``python -m paper_1604_06525_amd.build``); there is no fallback.
+"""
+import ctypes
+import os
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libopt.so")
+
+OPT_OK, OPT_EINVAL, OPT_ENOMEM, OPT_EHIP, OPT_EAGAIN, OPT_ENUMERIC, OPT_EUNSUPPORTED = 0, -1, -2, -3, -4, -5, -6
+GRID2D, GRAPH = 0, 1
+ENERGIES = {"laplacian": 0, "arap_warp": 1, "poisson": 2, "sfs": 3, "flow": 4, "arap_mesh": 5}
+PRECISIONS = {"fp64": 0, "mixed": 1}
+GN, LM = 0, 1
+
+
+class opt_problem_desc(ctypes.Structure):
+    _fields_ = [("domain", ctypes.c_int32), ("energy", ctypes.c_int32), ("precision", ctypes.c_int32),
+                ("width", ctypes.c_int32), ("height", ctypes.c_int32),
+                ("n_vertices", ctypes.c_int32), ("n_edges", ctypes.c_int32),
+                ("edges", ctypes.c_void_p), ("arrays", ctypes.c_void_p * 8),
+                ("params", ctypes.c_double * 16), ("n_params", ctypes.c_int32)]
+
+
+class opt_solve_params(ctypes.Structure):
+    _fields_ = [("method", ctypes.c_int32), ("outer_iters", ctypes.c_int32),
+                ("pcg_iters", ctypes.c_int32), ("use_precond", ctypes.c_int32),
+                ("lm_radius0", ctypes.c_double), ("lm_radius_min", ctypes.c_double),
+                ("lm_radius_max", ctypes.c_double), ("lm_diag_min", ctypes.c_double),
+                ("lm_diag_max", ctypes.c_double), ("lm_min_rel_decrease", ctypes.c_double)]
+
+
+class opt_solve_report(ctypes.Structure):
+    _fields_ = [("cost_initial", ctypes.c_double), ("cost_final", ctypes.c_double),
+                ("outer_done", ctypes.c_int32), ("steps_accepted", ctypes.c_int32),
+                ("cost_trace", ctypes.POINTER(ctypes.c_double))]
+
+
+_P = ctypes.c_void_p
+_proto = {
+    "opt_last_error": (ctypes.c_char_p, []),
+    "opt_workspace_size": (ctypes.c_int, [ctypes.POINTER(opt_problem_desc), ctypes.POINTER(ctypes.c_size_t)]),
+    "opt_problem_create": (ctypes.c_int, [ctypes.POINTER(opt_problem_desc), _P, ctypes.c_size_t, _P,
+                                          ctypes.POINTER(_P)]),
+    "opt_problem_destroy": (ctypes.c_int, [_P]),
+    "opt_default_params": (None, [ctypes.POINTER(opt_solve_params)]),
+    "opt_solve": (ctypes.c_int, [_P, _P, ctypes.POINTER(opt_solve_params), ctypes.POINTER(opt_solve_report)]),
+    "opt_cost": (ctypes.c_int, [_P, _P, ctypes.POINTER(ctypes.c_double)]),
+    "opt_linearize": (ctypes.c_int, [_P, _P, ctypes.POINTER(ctypes.c_double)]),
+    "opt_eval_jtf": (ctypes.c_int, [_P, _P, _P]),
+    "opt_apply_jtj": (ctypes.c_int, [_P, _P, _P, ctypes.c_double, ctypes.POINTER(opt_solve_params)]),
+    "opt_pcg": (ctypes.c_int, [_P, ctypes.POINTER(opt_solve_params), ctypes.c_double, _P]),
+    "opt_energy_channels": (ctypes.c_int, [ctypes.c_int32]),
+}
+_lib = None
+
+
+def lib():
+    """The loaded libopt.so; raises if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is missing: build the HIP library first "
+                              "(python -m paper_1604_06525_amd.build)")
+        h = ctypes.CDLL(LIB_PATH)
+        for name, (res, args) in _proto.items():
+            f = getattr(h, name)
+            f.restype = res
+            f.argtypes = args
+        _lib = h
+    return _lib
+
+
+class OptError(RuntimeError):
+    def __init__(self, code, where):
+        self.code = code
+        msg = lib().opt_last_error().decode(errors="replace")
+        super().__init__(f"{where} returned {code}: {msg}")
+
+
+def _check(code, where):
+    if code != OPT_OK:
+        raise OptError(code, where)
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None else ctypes.c_void_p(0)
+
+
+def default_params(**kw):
+    p = opt_solve_params()
+    lib().opt_default_params(ctypes.byref(p))
+    for k, v in kw.items():
+        if k == "method" and isinstance(v, str):
+            v = {"gn": GN, "lm": LM}[v.lower()]
+        if not hasattr(p, k):
+            raise TypeError(f"unknown solve parameter {k}")
+        setattr(p, k, v)
+    return p
+
+
+def energy_channels(energy):
+    return lib().opt_energy_channels(ENERGIES[energy] if isinstance(energy, str) else energy)
+
+
+class Problem:
+    """One problem instance: a grid or graph, an energy and its data arrays.
+
+    ``arrays`` are device tensors in the energy's order (include/opt.h); float64
+    under precision "fp64", float32 under "mixed", uint8 for masks.  They are
+    referenced, not copied, and kept alive by this object.  The workspace is a
+    torch uint8 tensor on the same device.
+    """
+
+    def __init__(self, energy, arrays, params=(), precision="mixed", width=0, height=0,
+                 n_vertices=0, edges=None, stream=None):
+        self.energy = energy
+        self.precision = precision
+        self.dtype = torch.float64 if precision == "fp64" else torch.float32
+        self.channels = energy_channels(energy)
+        d = opt_problem_desc()
+        d.domain = GRAPH if n_vertices else GRID2D
+        d.energy = ENERGIES[energy]
+        d.precision = PRECISIONS[precision]
+        d.width, d.height = width, height
+        d.n_vertices = n_vertices
+        self.edges = None
+        if edges is not None:
+            self.edges = edges
+            d.n_edges = int(edges.shape[0])
+            d.edges = edges.data_ptr()
+        self.arrays = list(arrays)
+        for k, a in enumerate(self.arrays):
+            if not a.is_contiguous():
+                raise ValueError(f"array {k} must be contiguous")
+            d.arrays[k] = a.data_ptr()
+        params = list(params)
+        for k, v in enumerate(params):
+            d.params[k] = float(v)
+        d.n_params = len(params)
+        self.desc = d
+        self.n_sites = n_vertices if n_vertices else width * height
+        nbytes = ctypes.c_size_t(0)
+        _check(lib().opt_workspace_size(ctypes.byref(d), ctypes.byref(nbytes)), "opt_workspace_size")
+        dev = self.arrays[0].device
+        self.device = dev
+        self.workspace = torch.empty(nbytes.value, dtype=torch.uint8, device=dev)
+        self.stream = stream if stream is not None else torch.cuda.current_stream(dev)
+        h = ctypes.c_void_p(0)
+        _check(lib().opt_problem_create(ctypes.byref(d), _ptr(self.workspace), nbytes.value,
+                                       ctypes.c_void_p(self.stream.cuda_stream), ctypes.byref(h)),
+               "opt_problem_create")
+        self.handle = h
+
+    def __del__(self):
+        h = getattr(self, "handle", None)
+        if h is not None and h.value:
+            lib().opt_problem_destroy(h)
+            self.handle = None
+
+    def _vec(self, t, name):
+        shape = (self.channels, self.n_sites)
+        if t.dtype != self.dtype or not t.is_contiguous() or t.numel() != shape[0] * shape[1]:
+            raise ValueError(f"{name} must be a contiguous {self.dtype} tensor of {shape[0]}x{shape[1]}")
+        return t
+
+    def new_vector(self):
+        return torch.zeros((self.channels, self.n_sites), dtype=self.dtype, device=self.device)
+
+    def solve(self, x, params=None, report=True, **kw):
+        """opt_solve on x (in place).  Returns a dict with the report, or None."""
+        self._vec(x, "x")
+        self._lin_x = None
+        p = params if params is not None else default_params(**kw)
+        if not report:
+            _check(lib().opt_solve(self.handle, _ptr(x), ctypes.byref(p), None), "opt_solve")
+            return None
+        trace = (ctypes.c_double * (p.outer_iters + 1))()
+        rep = opt_solve_report()
+        rep.cost_trace = ctypes.cast(trace, ctypes.POINTER(ctypes.c_double))
+        code = lib().opt_solve(self.handle, _ptr(x), ctypes.byref(p), ctypes.byref(rep))
+        out = dict(cost_initial=rep.cost_initial, cost_final=rep.cost_final,
+                   outer_done=rep.outer_done, steps_accepted=rep.steps_accepted,
+                   cost_trace=list(trace), code=code)
+        _check(code, "opt_solve")
+        return out
+
+    def cost(self, x):
+        self._vec(x, "x")
+        c = ctypes.c_double(0)
+        _check(lib().opt_cost(self.handle, _ptr(x), ctypes.byref(c)), "opt_cost")
+        return c.value
+
+    def linearize(self, x, want_cost=True):
+        """opt_linearize.  eval_jtf/apply_jtj/pcg read x again later, so the
+        tensor is kept alive here until the next linearize or solve."""
+        self._vec(x, "x")
+        self._lin_x = x
+        if not want_cost:
+            _check(lib().opt_linearize(self.handle, _ptr(x), None), "opt_linearize")
+            return None
+        c = ctypes.c_double(0)
+        _check(lib().opt_linearize(self.handle, _ptr(x), ctypes.byref(c)), "opt_linearize")
+        return c.value
+
+    def eval_jtf(self):
+        b, d = self.new_vector(), self.new_vector()
+        _check(lib().opt_eval_jtf(self.handle, _ptr(b), _ptr(d)), "opt_eval_jtf")
+        return b, d
+
+    def apply_jtj(self, p, lam=0.0, params=None):
+        self._vec(p, "p")
+        q = self.new_vector()
+        prm = params if params is not None else default_params()
+        _check(lib().opt_apply_jtj(self.handle, _ptr(p), _ptr(q), float(lam), ctypes.byref(prm)),
+               "opt_apply_jtj")
+        return q
+
+    def pcg(self, iters, lam=0.0, use_precond=True, params=None):
+        prm = params if params is not None else default_params(pcg_iters=iters, use_precond=int(use_precond))
+        d = self.new_vector()
+        _check(lib().opt_pcg(self.handle, ctypes.byref(prm), float(lam), _ptr(d)), "opt_pcg")
+        return d

@@ -1,0 +1,199 @@
+// As-rigid-as-possible image warping on a pixel grid (Fig. 24, Appendix A.1.1).
+//
+// Unknowns per pixel p: offset O_p (2 planes) and angle t_p (1 plane).  Data:
+// rest positions U (2 planes), targets C (2 planes), mask (uint8).
+// Residuals anchored at p:
+//   for each stencil offset s, q = p + s, when q is on the grid and both p and q
+//   have mask 0:  r = w_reg [ (O_p - O_q) - R(t_p) (U_p - U_q) ]       (2 rows)
+//   when both components of C_p are >= 0:  r = w_fit (O_p - C_p)       (2 rows)
+// with R(t) = [[cos t, -sin t], [sin t, cos t]].  Pixels with mask != 0 are
+// excluded (Exclude in Fig. 24): constants that keep their terms.
+//
+// Matrix-free products (the template-shift view of Sec. 5.3.1): the residuals
+// that read the unknowns of p are p's own four regularisers, the four
+// regularisers anchored at its neighbours that point back at p, and p's fit.
+// With d = U_p - U_q, a_p = R'(t_p) d and a_q = R'(t_q)(U_q - U_p):
+//   own    J p = w_reg [ (P_p - P_q) - a_p P^t_p ]
+//   back   J p = w_reg [ (P_q - P_p) - a_q P^t_q ]
+//   (J^T J P)_O(p) += w_reg (own) - w_reg (back),  (J^T J P)_t(p) += -w_reg a_p . (own)
+// R'(t) d is R(t) d turned by +90 degrees, so |a_p| = |d|.
+#pragma once
+#include "common.h"
+
+namespace optmi {
+
+template <typename T>
+struct ArapWarp {
+  using Real = T;
+  static constexpr int C = 3;  // unknown channels
+  static constexpr int kStatePlanes = 2;  // cos t, sin t
+
+  int W, H, n;
+  const T* __restrict__ U;   // [2][n]
+  const T* __restrict__ Ct;  // [2][n]
+  const uint8_t* __restrict__ mask;
+  T* __restrict__ cs;         // [2][n] cos and sin of t at the linearisation point
+  uint8_t* __restrict__ flags;// bit0: not excluded, bit1: fit target valid
+  T wf, wr;                   // w_fit, w_reg
+
+  __device__ __forceinline__ bool active(int s) const { return flags[s] & 1; }
+
+  // Neighbour k of site (i, j) in the order (1,0), (-1,0), (0,1), (0,-1);
+  // returns its id or -1 when it is off the grid.
+  __device__ __forceinline__ int nbr(int i, int j, int s, int k) const {
+    switch (k) {
+      case 0: return i + 1 < W ? s + 1 : -1;
+      case 1: return i > 0 ? s - 1 : -1;
+      case 2: return j + 1 < H ? s + W : -1;
+      default: return j > 0 ? s - W : -1;
+    }
+  }
+
+  // FP64 sum of squares of the residuals anchored at s, for unknowns read
+  // through X(ch, site) (already rounded to the bulk type, returned as double).
+  template <class XA>
+  __device__ __forceinline__ double cost(XA X, int s) const {
+    const int i = s % W, j = s / W;
+    const bool ap = mask[s] == 0;
+    const double th = X(2, s);
+    double sn, c;
+    sincos_t(th, &sn, &c);
+    const double Ox = X(0, s), Oy = X(1, s);
+    const double Ux = U[s], Uy = U[n + s];
+    double e = 0.0;
+    if (ap) {
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        const int q = nbr(i, j, s, k);
+        if (q < 0 || mask[q] != 0) continue;
+        const double dx = Ux - (double)U[q], dy = Uy - (double)U[n + q];
+        const double rx = (double)wr * ((Ox - X(0, q)) - (c * dx - sn * dy));
+        const double ry = (double)wr * ((Oy - X(1, q)) - (sn * dx + c * dy));
+        e += rx * rx + ry * ry;
+      }
+    }
+    const double cx = Ct[s], cy = Ct[n + s];
+    if (cx >= 0.0 && cy >= 0.0) {
+      const double fx = (double)wf * (Ox - cx), fy = (double)wf * (Oy - cy);
+      e += fx * fx + fy * fy;
+    }
+    return e;
+  }
+
+  // Per-site state for the products: cos/sin of the angle and the flags.
+  __device__ __forceinline__ void linearize(const T* __restrict__ x, int s) const {
+    T sn, c;
+    sincos_t(x[2 * n + s], &sn, &c);
+    cs[s] = c;
+    cs[n + s] = sn;
+    const bool fit = Ct[s] >= T(0) && Ct[n + s] >= T(0);
+    flags[s] = (uint8_t)((mask[s] == 0 ? 1 : 0) | (fit ? 2 : 0));
+  }
+
+  // b = -J^T F and diag(J^T J) at the linearisation point, for an active site.
+  __device__ __forceinline__ void jtf_diag(const T* __restrict__ x, int s, T* b, T* d) const {
+    const int i = s % W, j = s / W;
+    const T c = cs[s], sn = cs[n + s];
+    const T Ox = x[s], Oy = x[n + s], Ux = U[s], Uy = U[n + s];
+    T bx = 0, by = 0, bt = 0, dO = 0, dt = 0;
+    const T wr2 = wr * wr;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      const int q = nbr(i, j, s, k);
+      if (q < 0 || !(flags[q] & 1)) continue;
+      const T dx = Ux - U[q], dy = Uy - U[n + q];
+      const T cq = cs[q], sq = cs[n + q];
+      const T ex = Ox - x[q], ey = Oy - x[n + q];
+      // own residual / w_reg, and the back residual / w_reg
+      const T f1x = ex - (c * dx - sn * dy), f1y = ey - (sn * dx + c * dy);
+      const T f2x = -ex + (cq * dx - sq * dy), f2y = -ey + (sq * dx + cq * dy);
+      const T apx = -sn * dx - c * dy, apy = c * dx - sn * dy;
+      bx += wr2 * (f2x - f1x);
+      by += wr2 * (f2y - f1y);
+      bt += wr2 * (apx * f1x + apy * f1y);
+      dO += T(2) * wr2;
+      dt += wr2 * (apx * apx + apy * apy);
+    }
+    if (flags[s] & 2) {
+      const T wf2 = wf * wf;
+      bx -= wf2 * (Ox - Ct[s]);
+      by -= wf2 * (Oy - Ct[n + s]);
+      dO += wf2;
+    }
+    b[0] = bx; b[1] = by; b[2] = bt;
+    d[0] = dO; d[1] = dO; d[2] = dt;
+  }
+
+  // g = J^T J P at an active site; P(ch, site) gives the direction.
+  template <class PA>
+  __device__ __forceinline__ void jtjp(int s, PA P, T* g) const {
+    const int i = s % W, j = s / W;
+    const T c = cs[s], sn = cs[n + s];
+    const T Ux = U[s], Uy = U[n + s];
+    const T px = P(0, s), py = P(1, s), pt = P(2, s);
+    T gx = 0, gy = 0, gt = 0;
+    const T wr2 = wr * wr;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      const int q = nbr(i, j, s, k);
+      if (q < 0 || !(flags[q] & 1)) continue;
+      const T dx = Ux - U[q], dy = Uy - U[n + q];
+      const T cq = cs[q], sq = cs[n + q];
+      const T qx = P(0, q), qy = P(1, q), qt = P(2, q);
+      const T apx = -sn * dx - c * dy, apy = c * dx - sn * dy;
+      const T aqx = sq * dx + cq * dy, aqy = -cq * dx + sq * dy;
+      const T ex = px - qx, ey = py - qy;
+      const T j1x = ex - apx * pt, j1y = ey - apy * pt;
+      const T j2x = -ex - aqx * qt, j2y = -ey - aqy * qt;
+      gx += wr2 * (j1x - j2x);
+      gy += wr2 * (j1y - j2y);
+      gt -= wr2 * (apx * j1x + apy * j1y);
+    }
+    if (flags[s] & 2) {
+      const T wf2 = wf * wf;
+      gx += wf2 * px;
+      gy += wf2 * py;
+    }
+    g[0] = gx; g[1] = gy; g[2] = gt;
+  }
+
+  // LM model term of the residuals anchored at s, in FP64:
+  //   sum_r (J d)_r (2 F_r + (J d)_r), J and F at X, step Dl.
+  template <class XA, class DA>
+  __device__ __forceinline__ double model(XA X, DA Dl, int s) const {
+    const int i = s % W, j = s / W;
+    const bool ap = mask[s] == 0;
+    double acc = 0.0;
+    const double Ox = X(0, s), Oy = X(1, s);
+    const double dOx = Dl(0, s), dOy = Dl(1, s);
+    if (ap) {
+      double sn, c;
+      sincos_t(X(2, s), &sn, &c);
+      const double dt = Dl(2, s);
+      const double Ux = U[s], Uy = U[n + s];
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        const int q = nbr(i, j, s, k);
+        if (q < 0 || mask[q] != 0) continue;
+        const double dx = Ux - (double)U[q], dy = Uy - (double)U[n + q];
+        const double w = wr;
+        const double fx = w * ((Ox - X(0, q)) - (c * dx - sn * dy));
+        const double fy = w * ((Oy - X(1, q)) - (sn * dx + c * dy));
+        const double apx = -sn * dx - c * dy, apy = c * dx - sn * dy;
+        const double jx = w * ((dOx - Dl(0, q)) - apx * dt);
+        const double jy = w * ((dOy - Dl(1, q)) - apy * dt);
+        acc += jx * (2.0 * fx + jx) + jy * (2.0 * fy + jy);
+      }
+    }
+    const double cx = Ct[s], cy = Ct[n + s];
+    if (cx >= 0.0 && cy >= 0.0) {
+      const double w = wf;
+      const double fx = w * (Ox - cx), fy = w * (Oy - cy);
+      const double jx = w * dOx, jy = w * dOy;
+      acc += jx * (2.0 * fx + jx) + jy * (2.0 * fy + jy);
+    }
+    return acc;
+  }
+};
+
+}  // namespace optmi

@@ -1,0 +1,505 @@
+// Host side of the C ABI declared in include/opt.h: descriptor validation,
+// workspace layout, and the order in which the kernels of a solve are enqueued
+// (Sec. 4: per outer iteration linearise, PCG-init, L PCG iterations, update;
+// LM adds the model decrease, the trial cost and the step decision).
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <memory>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "opt.h"
+#include "common.h"
+#include "kernels.h"
+#include "energies.h"
+
+using namespace optmi;
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  return code;
+}
+
+#define HIP_TRY(call)                                                                     \
+  do {                                                                                    \
+    hipError_t e_ = (call);                                                               \
+    if (e_ != hipSuccess)                                                                 \
+      return fail(OPT_EHIP, "%s failed: %s (%s:%d)", #call, hipGetErrorString(e_), __FILE__, \
+                  __LINE__);                                                              \
+  } while (0)
+
+#define HIP_LAUNCHED(name)                                                               \
+  do {                                                                                    \
+    hipError_t e_ = hipGetLastError();                                                    \
+    if (e_ != hipSuccess)                                                                 \
+      return fail(OPT_EHIP, "launch of %s failed: %s", name, hipGetErrorString(e_));     \
+  } while (0)
+
+constexpr size_t kAlign = 256;
+constexpr int kTraceCap = 4097;  // outer iterations + 1 that a report can hold
+constexpr int kMaxOuter = kTraceCap - 1;
+
+size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
+
+struct Shape {
+  int C = 0;           // unknown channels
+  int state_planes = 0;
+  int n = 0;           // sites
+  size_t tsize = 0;    // bytes of the bulk type
+};
+
+// Byte offsets of every region of the workspace.
+struct Layout {
+  size_t r, diag, delta, p0, p1, q, state, flags, parts, scal, trace, total;
+};
+
+Layout make_layout(const Shape& sh) {
+  Layout L{};
+  size_t off = 0;
+  const size_t vec = align_up((size_t)sh.C * sh.n * sh.tsize);
+  L.r = off; off += vec;
+  L.diag = off; off += vec;
+  L.delta = off; off += vec;
+  L.p0 = off; off += vec;
+  L.p1 = off; off += vec;
+  L.q = off; off += vec;
+  L.state = off; off += align_up((size_t)sh.state_planes * sh.n * sh.tsize);
+  L.flags = off; off += align_up((size_t)sh.n);
+  L.parts = off; off += align_up(7 * (size_t)kMaxBlocks * sizeof(double));
+  L.scal = off; off += align_up(sizeof(DevScalars));
+  L.trace = off; off += align_up((size_t)kTraceCap * sizeof(double));
+  L.total = off;
+  return L;
+}
+
+int energy_channels(int e) {
+  switch (e) {
+    case OPT_E_ARAP_WARP: return 3;
+    default: return 0;
+  }
+}
+
+int energy_state_planes(int e) {
+  switch (e) {
+    case OPT_E_ARAP_WARP: return 2;
+    default: return 0;
+  }
+}
+
+int n_params_needed(int e) {
+  switch (e) {
+    case OPT_E_ARAP_WARP: return 2;
+    default: return 0;
+  }
+}
+
+int n_arrays_needed(int e) {
+  switch (e) {
+    case OPT_E_ARAP_WARP: return 3;
+    default: return 0;
+  }
+}
+
+int check_desc(const opt_problem_desc* d, Shape* sh) {
+  if (!d) return fail(OPT_EINVAL, "descriptor is NULL");
+  if (d->precision != OPT_FP64 && d->precision != OPT_MIXED)
+    return fail(OPT_EINVAL, "precision %d is not OPT_FP64 or OPT_MIXED", d->precision);
+  const int C = energy_channels(d->energy);
+  if (C == 0) return fail(OPT_EUNSUPPORTED, "energy %d is not built", d->energy);
+  const bool grid_energy = d->energy != OPT_E_ARAP_MESH;
+  if (d->domain == OPT_GRID2D) {
+    if (!grid_energy) return fail(OPT_EUNSUPPORTED, "energy %d needs the graph domain", d->energy);
+    if (d->width < 1 || d->height < 1)
+      return fail(OPT_EINVAL, "grid size %d x %d must be positive", d->width, d->height);
+    if ((long long)d->width * d->height > (1LL << 30))
+      return fail(OPT_EINVAL, "grid of %lld sites is too large", (long long)d->width * d->height);
+    sh->n = d->width * d->height;
+  } else if (d->domain == OPT_GRAPH) {
+    return fail(OPT_EUNSUPPORTED, "graph domain is not built for energy %d", d->energy);
+  } else {
+    return fail(OPT_EINVAL, "domain %d is not OPT_GRID2D or OPT_GRAPH", d->domain);
+  }
+  if (d->n_params < n_params_needed(d->energy) || d->n_params > 16)
+    return fail(OPT_EINVAL, "energy %d needs %d params, got %d", d->energy,
+                n_params_needed(d->energy), d->n_params);
+  for (int k = 0; k < n_arrays_needed(d->energy); ++k)
+    if (!d->arrays[k]) return fail(OPT_EINVAL, "arrays[%d] is NULL", k);
+  sh->C = C;
+  sh->state_planes = energy_state_planes(d->energy);
+  sh->tsize = d->precision == OPT_FP64 ? sizeof(double) : sizeof(float);
+  return OPT_OK;
+}
+
+struct PrecondArgs {
+  double lam, dmin, dmax;
+  int use;
+};
+
+// Launch sequence for one energy and bulk type.
+class Impl {
+ public:
+  virtual ~Impl() = default;
+  virtual int linearize(const void* x, int lm_gate) = 0;
+  virtual int init(const void* x, double* trace, int idx, PrecondArgs pa, int lm_gate) = 0;
+  virtual int pcg_a(int k, PrecondArgs pa, int lm_gate) = 0;
+  virtual int pcg_b(int k, PrecondArgs pa, int lm_gate) = 0;
+  virtual int apply_jtj(const void* p, void* q, PrecondArgs pa) = 0;
+  virtual int apply_step(void* x, int lm_gate) = 0;
+  virtual int cost(const void* x, const void* delta, int lm_gate) = 0;
+  virtual int model(const void* x) = 0;
+};
+
+}  // namespace
+
+struct opt_problem {
+  opt_problem_desc desc;
+  Shape sh;
+  Layout L;
+  hipStream_t stream = nullptr;
+  char* ws = nullptr;
+  int nblk = 1;
+  const void* last_x = nullptr;
+  std::unique_ptr<Impl> impl;
+
+  void* at(size_t off) const { return ws + off; }
+  double* part(int k) const { return (double*)(ws + L.parts) + (size_t)k * kMaxBlocks; }
+  DevScalars* S() const { return (DevScalars*)(ws + L.scal); }
+  double* trace() const { return (double*)(ws + L.trace); }
+};
+
+namespace {
+
+enum { P_LIN = 0, P_RZ0 = 1, P_RZ1 = 2, P_PQ = 3, P_COST = 4, P_M = 5 };
+
+template <class E>
+class ImplT final : public Impl {
+ public:
+  using T = typename E::Real;
+  ImplT(opt_problem* p, const E& e) : p_(p), e_(e) {}
+
+  Precond<T> pc(PrecondArgs a) const {
+    Precond<T> c;
+    c.lam = (T)a.lam;
+    c.dmin = (T)a.dmin;
+    c.dmax = (T)a.dmax;
+    c.use = a.use;
+    return c;
+  }
+  T* vec(size_t off) const { return (T*)p_->at(off); }
+  T* pbuf(int k) const { return vec((k & 1) ? p_->L.p1 : p_->L.p0); }
+
+  int linearize(const void* x, int lm_gate) override {
+    k_linearize<E><<<p_->nblk, kBlock, 0, p_->stream>>>(e_, (const T*)x, p_->part(P_LIN), p_->S(),
+                                                         lm_gate);
+    HIP_LAUNCHED("k_linearize");
+    return OPT_OK;
+  }
+  int init(const void* x, double* trace, int idx, PrecondArgs pa, int lm_gate) override {
+    k_init<E><<<p_->nblk, kBlock, 0, p_->stream>>>(
+        e_, (const T*)x, vec(p_->L.r), vec(p_->L.diag), vec(p_->L.delta), p_->part(P_LIN),
+        p_->nblk, p_->part(P_RZ0), p_->S(), trace, idx, pc(pa), lm_gate);
+    HIP_LAUNCHED("k_init");
+    return OPT_OK;
+  }
+  int pcg_a(int k, PrecondArgs pa, int lm_gate) override {
+    k_pcg_a<E, 0><<<p_->nblk, kBlock, 0, p_->stream>>>(
+        e_, k, vec(p_->L.r), vec(p_->L.diag), pbuf(k + 1), pbuf(k), vec(p_->L.q),
+        p_->part((k & 1) ? P_RZ1 : P_RZ0), p_->nblk, p_->part(P_PQ), p_->S(), pc(pa), lm_gate);
+    HIP_LAUNCHED("k_pcg_a");
+    return OPT_OK;
+  }
+  int pcg_b(int k, PrecondArgs pa, int lm_gate) override {
+    k_pcg_b<T, E::C><<<p_->nblk, kBlock, 0, p_->stream>>>(
+        e_.n, k, nullptr, vec(p_->L.delta), vec(p_->L.r), pbuf(k), vec(p_->L.q), vec(p_->L.diag),
+        p_->part(P_PQ), p_->nblk, p_->part((k & 1) ? P_RZ0 : P_RZ1), p_->S(), pc(pa), lm_gate);
+    HIP_LAUNCHED("k_pcg_b");
+    return OPT_OK;
+  }
+  int apply_jtj(const void* pin, void* qout, PrecondArgs pa) override {
+    k_pcg_a<E, 1><<<p_->nblk, kBlock, 0, p_->stream>>>(
+        e_, 0, nullptr, vec(p_->L.diag), (const T*)pin, nullptr, (T*)qout, nullptr, 0, nullptr,
+        p_->S(), pc(pa), 0);
+    HIP_LAUNCHED("k_pcg_a<apply>");
+    return OPT_OK;
+  }
+  int apply_step(void* x, int lm_gate) override {
+    k_apply_step<E><<<p_->nblk, kBlock, 0, p_->stream>>>(e_, (T*)x, vec(p_->L.delta), p_->S(),
+                                                          lm_gate);
+    HIP_LAUNCHED("k_apply_step");
+    return OPT_OK;
+  }
+  int cost(const void* x, const void* delta, int lm_gate) override {
+    k_cost<E><<<p_->nblk, kBlock, 0, p_->stream>>>(e_, (const T*)x, (const T*)delta,
+                                                    p_->part(P_COST), p_->S(), lm_gate);
+    HIP_LAUNCHED("k_cost");
+    return OPT_OK;
+  }
+  int model(const void* x) override {
+    k_model<E><<<p_->nblk, kBlock, 0, p_->stream>>>(e_, (const T*)x, vec(p_->L.delta),
+                                                     p_->part(P_M), p_->S());
+    HIP_LAUNCHED("k_model");
+    return OPT_OK;
+  }
+
+ private:
+  opt_problem* p_;
+  E e_;
+};
+
+template <typename T>
+std::unique_ptr<Impl> make_impl_t(opt_problem* p) {
+  const opt_problem_desc& d = p->desc;
+  switch (d.energy) {
+    case OPT_E_ARAP_WARP: {
+      ArapWarp<T> e;
+      e.W = d.width;
+      e.H = d.height;
+      e.n = p->sh.n;
+      e.U = (const T*)d.arrays[0];
+      e.Ct = (const T*)d.arrays[1];
+      e.mask = (const uint8_t*)d.arrays[2];
+      e.cs = (T*)p->at(p->L.state);
+      e.flags = (uint8_t*)p->at(p->L.flags);
+      e.wf = (T)d.params[0];
+      e.wr = (T)d.params[1];
+      return std::unique_ptr<Impl>(new ImplT<ArapWarp<T>>(p, e));
+    }
+    default:
+      return nullptr;
+  }
+}
+
+std::unique_ptr<Impl> make_impl(opt_problem* p) {
+  if (p->desc.precision == OPT_FP64) return make_impl_t<double>(p);
+  return make_impl_t<float>(p);
+}
+
+int check_params(const opt_solve_params* sp) {
+  if (!sp) return fail(OPT_EINVAL, "solve params are NULL");
+  if (sp->method != OPT_GN && sp->method != OPT_LM)
+    return fail(OPT_EINVAL, "method %d is not OPT_GN or OPT_LM", sp->method);
+  if (sp->outer_iters < 0 || sp->outer_iters > kMaxOuter)
+    return fail(OPT_EINVAL, "outer_iters %d outside [0, %d]", sp->outer_iters, kMaxOuter);
+  if (sp->pcg_iters < 0 || sp->pcg_iters > 1000000)
+    return fail(OPT_EINVAL, "pcg_iters %d outside [0, 1000000]", sp->pcg_iters);
+  if (sp->method == OPT_LM) {
+    if (!(sp->lm_radius0 > 0) || !(sp->lm_radius_max > 0) || !(sp->lm_radius_min >= 0))
+      return fail(OPT_EINVAL, "LM radii must be positive");
+  }
+  if (!(sp->lm_diag_min >= 0) || !(sp->lm_diag_max >= sp->lm_diag_min))
+    return fail(OPT_EINVAL, "LM diagonal clamp [%g, %g] is invalid", sp->lm_diag_min,
+                sp->lm_diag_max);
+  return OPT_OK;
+}
+
+int sync_scalars(opt_problem* p, DevScalars* hs) {
+  HIP_TRY(hipMemcpyAsync(hs, p->S(), sizeof(DevScalars), hipMemcpyDeviceToHost, p->stream));
+  HIP_TRY(hipStreamSynchronize(p->stream));
+  return OPT_OK;
+}
+
+#define TRY(x)              \
+  do {                      \
+    int rc_ = (x);          \
+    if (rc_ != OPT_OK) return rc_; \
+  } while (0)
+
+}  // namespace
+
+extern "C" {
+
+const char* opt_last_error(void) { return g_err.c_str(); }
+
+int opt_energy_channels(int32_t energy) { return energy_channels(energy); }
+
+void opt_default_params(opt_solve_params* p) {
+  if (!p) return;
+  p->method = OPT_GN;
+  p->outer_iters = 10;
+  p->pcg_iters = 50;
+  p->use_precond = 1;
+  p->lm_radius0 = 1e4;
+  p->lm_radius_min = 1e-32;
+  p->lm_radius_max = 1e16;
+  p->lm_diag_min = 1e-6;
+  p->lm_diag_max = 1e32;
+  p->lm_min_rel_decrease = 1e-3;
+}
+
+int opt_workspace_size(const opt_problem_desc* desc, size_t* bytes) {
+  if (!bytes) return fail(OPT_EINVAL, "bytes is NULL");
+  Shape sh;
+  TRY(check_desc(desc, &sh));
+  *bytes = make_layout(sh).total;
+  return OPT_OK;
+}
+
+int opt_problem_create(const opt_problem_desc* desc, void* workspace, size_t workspace_bytes,
+                       void* hip_stream, opt_problem** out) {
+  if (!out) return fail(OPT_EINVAL, "out is NULL");
+  *out = nullptr;
+  Shape sh;
+  TRY(check_desc(desc, &sh));
+  const Layout L = make_layout(sh);
+  if (!workspace) return fail(OPT_EINVAL, "workspace is NULL");
+  if (((uintptr_t)workspace) % kAlign)
+    return fail(OPT_EINVAL, "workspace must be %zu-byte aligned", kAlign);
+  if (workspace_bytes < L.total)
+    return fail(OPT_ENOMEM, "workspace of %zu bytes is smaller than the %zu needed", workspace_bytes,
+                L.total);
+  std::unique_ptr<opt_problem> p(new (std::nothrow) opt_problem());
+  if (!p) return fail(OPT_ENOMEM, "host allocation failed");
+  p->desc = *desc;
+  p->sh = sh;
+  p->L = L;
+  p->stream = (hipStream_t)hip_stream;
+  p->ws = (char*)workspace;
+  p->nblk = (int)std::min<long long>(kMaxBlocks, (sh.n + kBlock - 1) / kBlock);
+  if (p->nblk < 1) p->nblk = 1;
+  p->impl = make_impl(p.get());
+  if (!p->impl) return fail(OPT_EUNSUPPORTED, "energy %d is not built", desc->energy);
+  k_setup<<<1, 64, 0, p->stream>>>(p->S(), 0.0, 1.0, 0);
+  HIP_LAUNCHED("k_setup");
+  *out = p.release();
+  return OPT_OK;
+}
+
+int opt_problem_destroy(opt_problem* prob) {
+  delete prob;
+  return OPT_OK;
+}
+
+int opt_linearize(opt_problem* p, const void* x, double* cost) {
+  if (!p || !x) return fail(OPT_EINVAL, "problem or unknowns is NULL");
+  TRY(p->impl->linearize(x, 0));
+  p->last_x = x;
+  if (cost) {
+    k_finish_cost<<<1, kBlock, 0, p->stream>>>(p->S(), p->part(P_LIN), p->nblk, nullptr, 0);
+    HIP_LAUNCHED("k_finish_cost");
+    DevScalars hs;
+    TRY(sync_scalars(p, &hs));
+    *cost = hs.E_final;
+    if (!std::isfinite(hs.E_final)) return fail(OPT_ENUMERIC, "cost is not finite");
+  }
+  return OPT_OK;
+}
+
+int opt_eval_jtf(opt_problem* p, void* b_out, void* diag_out) {
+  if (!p) return fail(OPT_EINVAL, "problem is NULL");
+  if (!p->last_x) return fail(OPT_EINVAL, "opt_linearize has not been called");
+  PrecondArgs pa{0.0, 0.0, 0.0, 1};
+  TRY(p->impl->init(p->last_x, nullptr, 0, pa, 0));
+  const size_t bytes = (size_t)p->sh.C * p->sh.n * p->sh.tsize;
+  if (b_out) HIP_TRY(hipMemcpyAsync(b_out, p->at(p->L.r), bytes, hipMemcpyDeviceToDevice, p->stream));
+  if (diag_out)
+    HIP_TRY(hipMemcpyAsync(diag_out, p->at(p->L.diag), bytes, hipMemcpyDeviceToDevice, p->stream));
+  return OPT_OK;
+}
+
+int opt_apply_jtj(opt_problem* p, const void* pin, void* qout, double lambda,
+                  const opt_solve_params* sp) {
+  if (!p || !pin || !qout) return fail(OPT_EINVAL, "problem, p or q is NULL");
+  if (!p->last_x) return fail(OPT_EINVAL, "opt_linearize has not been called");
+  if (pin == qout) return fail(OPT_EINVAL, "p and q must not overlap");
+  PrecondArgs pa{0.0, 0.0, 0.0, 1};
+  if (lambda != 0.0) {
+    if (!sp) return fail(OPT_EINVAL, "params are needed when lambda != 0");
+    TRY(p->impl->init(p->last_x, nullptr, 0, pa, 0));
+    pa = PrecondArgs{lambda, sp->lm_diag_min, sp->lm_diag_max, 1};
+  }
+  return p->impl->apply_jtj(pin, qout, pa);
+}
+
+int opt_pcg(opt_problem* p, const opt_solve_params* sp, double lambda, void* delta_out) {
+  if (!p) return fail(OPT_EINVAL, "problem is NULL");
+  TRY(check_params(sp));
+  if (!p->last_x) return fail(OPT_EINVAL, "opt_linearize has not been called");
+  PrecondArgs pa{lambda, sp->lm_diag_min, sp->lm_diag_max, sp->use_precond};
+  k_setup<<<1, 64, 0, p->stream>>>(p->S(), lambda, 1.0, 0);
+  HIP_LAUNCHED("k_setup");
+  TRY(p->impl->init(p->last_x, nullptr, 0, pa, 0));
+  for (int k = 0; k < sp->pcg_iters; ++k) {
+    TRY(p->impl->pcg_a(k, pa, 0));
+    TRY(p->impl->pcg_b(k, pa, 0));
+  }
+  if (delta_out) {
+    const size_t bytes = (size_t)p->sh.C * p->sh.n * p->sh.tsize;
+    HIP_TRY(hipMemcpyAsync(delta_out, p->at(p->L.delta), bytes, hipMemcpyDeviceToDevice, p->stream));
+  }
+  return OPT_OK;
+}
+
+int opt_cost(opt_problem* p, const void* x, double* cost) {
+  if (!p || !x || !cost) return fail(OPT_EINVAL, "problem, unknowns or cost is NULL");
+  TRY(p->impl->cost(x, nullptr, 0));
+  k_finish_cost<<<1, kBlock, 0, p->stream>>>(p->S(), p->part(P_COST), p->nblk, nullptr, 0);
+  HIP_LAUNCHED("k_finish_cost");
+  DevScalars hs;
+  TRY(sync_scalars(p, &hs));
+  *cost = hs.E_final;
+  if (!std::isfinite(hs.E_final)) return fail(OPT_ENUMERIC, "cost is not finite");
+  return OPT_OK;
+}
+
+int opt_solve(opt_problem* p, void* x, const opt_solve_params* sp, opt_solve_report* rep) {
+  if (!p || !x) return fail(OPT_EINVAL, "problem or unknowns is NULL");
+  TRY(check_params(sp));
+  const int K = sp->outer_iters, Lp = sp->pcg_iters;
+  const int lm = sp->method == OPT_LM;
+  double* trace = p->trace();
+  k_setup<<<1, 64, 0, p->stream>>>(p->S(), 0.0, sp->lm_radius0, lm);
+  HIP_LAUNCHED("k_setup");
+  PrecondArgs pa{0.0, sp->lm_diag_min, sp->lm_diag_max, sp->use_precond};
+  LMConsts lc{sp->lm_radius_min, sp->lm_radius_max, sp->lm_min_rel_decrease};
+  for (int k = 0; k < K; ++k) {
+    TRY(p->impl->linearize(x, lm));
+    TRY(p->impl->init(x, trace, k, pa, lm));
+    for (int l = 0; l < Lp; ++l) {
+      TRY(p->impl->pcg_a(l, pa, lm));
+      TRY(p->impl->pcg_b(l, pa, lm));
+    }
+    if (lm) {
+      TRY(p->impl->model(x));
+      TRY(p->impl->cost(x, p->at(p->L.delta), 1));
+      k_lm_decide<<<1, kBlock, 0, p->stream>>>(p->S(), p->part(P_M), p->part(P_COST), p->nblk, lc);
+      HIP_LAUNCHED("k_lm_decide");
+    }
+    TRY(p->impl->apply_step(x, lm));
+  }
+  TRY(p->impl->cost(x, nullptr, 0));
+  k_finish_cost<<<1, kBlock, 0, p->stream>>>(p->S(), p->part(P_COST), p->nblk, nullptr, 0);
+  HIP_LAUNCHED("k_finish_cost");
+  p->last_x = nullptr;
+  if (!rep) return OPT_OK;
+  DevScalars hs;
+  TRY(sync_scalars(p, &hs));
+  const int done = lm ? hs.outer_done : K;
+  std::vector<double> tr((size_t)K + 1, hs.E_final);
+  if (done > 0)
+    HIP_TRY(hipMemcpy(tr.data(), trace, sizeof(double) * (size_t)done, hipMemcpyDeviceToHost));
+  tr[(size_t)done] = hs.E_final;
+  for (int k = done + 1; k <= K; ++k) tr[(size_t)k] = hs.E_final;
+  rep->cost_initial = K > 0 ? tr[0] : hs.E_final;
+  rep->cost_final = hs.E_final;
+  rep->outer_done = done;
+  rep->steps_accepted = lm ? hs.n_accepted : K;
+  if (rep->cost_trace) memcpy(rep->cost_trace, tr.data(), sizeof(double) * ((size_t)K + 1));
+  if (hs.nonfinite) return fail(OPT_ENUMERIC, "a cost was NaN or infinite");
+  return OPT_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,42 @@
+"""Helpers for the GPU parity tests: build a library problem from a seeded
+workload, move vectors between numpy and the device."""
+import numpy as np
+import pytest
+import torch
+
+from workloads.layout import problem_args
+
+
+def require_gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+
+
+def make_problem(d, precision="fp64"):
+    import paper_1604_06525_amd as pkg
+    dt = np.float64 if precision == "fp64" else np.float32
+    energy, arrs, params, dims = problem_args(d, dt)
+    dev = torch.device("cuda:0")
+    t_arrs = [torch.from_numpy(a).to(dev) for a in arrs]
+    if "edges" in dims:
+        dims = dict(dims, edges=torch.from_numpy(dims["edges"]).to(dev))
+    prob = pkg.Problem(energy, t_arrs, params, precision=precision, **dims)
+    return prob
+
+
+def to_dev(prob, v):
+    c = prob.channels
+    a = np.ascontiguousarray(np.asarray(v, dtype=np.float64).reshape(c, -1))
+    return torch.from_numpy(a).to(device=prob.device, dtype=prob.dtype).contiguous()
+
+
+def to_np(t):
+    return t.detach().cpu().double().numpy().ravel()
+
+
+def relmax(a, b):
+    """max |a-b| / max |b| (0 when both vanish)."""
+    a, b = np.asarray(a, float).ravel(), np.asarray(b, float).ravel()
+    s = np.abs(b).max()
+    d = np.abs(a - b).max()
+    return 0.0 if d == 0 else d / (s if s > 0 else 1.0)

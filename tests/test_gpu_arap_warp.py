@@ -1,0 +1,170 @@
+"""GPU parity of the ARAP image-warping path against the FP64 oracle.
+
+Every comparison calls through the C ABI (libopt.so) and checks element by
+element against the oracle on the same seeded inputs.  FP64 operator products
+must agree to 1e-12 of their largest entry (rounding order only); FP64 solves to
+1e-9 relative cost; the mixed-precision path (FP32 bulk, FP64 reductions) to
+1e-4 relative final cost.
+"""
+import numpy as np
+import pytest
+
+import oracle as o
+import workloads as w
+from tests.gpu_util import make_problem, relmax, require_gpu, to_dev, to_np
+
+pytestmark = pytest.mark.gpu
+
+SHAPES = [(8, 8, "none"), (37, 29, "random"), (70, 65, "hole")]
+
+
+def _case(W, H, mask, seed=3):
+    d = w.arap_warp(W, H, seed=seed, n_constraints=max(2, W * H // 64), margin=2, mask=mask)
+    rng = np.random.default_rng(seed)
+    x = d["x0"] + np.concatenate([rng.normal(0, 0.5, (2, H, W)), rng.normal(0, 0.2, (1, H, W))])
+    act = (d["mask"] == 0)
+    x = np.where(act[None], x, d["x0"])
+    return d, x
+
+
+@pytest.fixture(autouse=True)
+def _gpu():
+    require_gpu()
+
+
+@pytest.mark.parametrize("W,H,mask", SHAPES)
+def test_cost_linearize_jtf_diag(W, H, mask):
+    d, x = _case(W, H, mask)
+    e = o.make_energy(d)
+    lin = o.Linearization(e, x)
+    prob = make_problem(d, "fp64")
+    xt = to_dev(prob, x)
+    assert abs(prob.cost(xt) - lin.E) <= 1e-12 * lin.E
+    assert abs(prob.linearize(xt) - lin.E) <= 1e-12 * lin.E
+    b, dg = prob.eval_jtf()
+    assert relmax(to_np(b), lin.jtf()) < 1e-12
+    assert relmax(to_np(dg), lin.diag) < 1e-12
+
+
+@pytest.mark.parametrize("W,H,mask", SHAPES)
+def test_jtjp_random(W, H, mask):
+    d, x = _case(W, H, mask)
+    e = o.make_energy(d)
+    lin = o.Linearization(e, x)
+    prob = make_problem(d, "fp64")
+    prob.linearize(to_dev(prob, x))
+    rng = np.random.default_rng(7)
+    p = rng.normal(size=lin.diag.size) * lin.active
+    q = to_np(prob.apply_jtj(to_dev(prob, p)))
+    assert relmax(q, lin.apply(p)) < 1e-12
+    D = lin.damping()
+    q2 = to_np(prob.apply_jtj(to_dev(prob, p), lam=0.37))
+    assert relmax(q2, lin.apply(p, 0.37, D)) < 1e-12
+
+
+def test_dense_jtj_8x8():
+    """The matrix-free product applied to every unit vector reproduces the dense
+    J^T J of the oracle's explicit Jacobian."""
+    d, x = _case(8, 8, "random", seed=5)
+    e = o.make_energy(d)
+    lin = o.Linearization(e, x)
+    A = (lin.J.T @ lin.J).toarray()
+    prob = make_problem(d, "fp64")
+    prob.linearize(to_dev(prob, x))
+    N = A.shape[0]
+    cols = []
+    for k in range(N):
+        ek = np.zeros(N)
+        ek[k] = 1.0
+        cols.append(to_np(prob.apply_jtj(to_dev(prob, ek))))
+    G = np.stack(cols, 1)
+    act = lin.active
+    assert np.abs(G - A)[np.ix_(act, act)].max() <= 1e-13 * np.abs(A).max()
+
+
+@pytest.mark.parametrize("W,H,mask", SHAPES)
+@pytest.mark.parametrize("precond", [True, False])
+def test_pcg(W, H, mask, precond):
+    d, x = _case(W, H, mask)
+    e = o.make_energy(d)
+    lin = o.Linearization(e, x)
+    prob = make_problem(d, "fp64")
+    xt = to_dev(prob, x)
+    prob.linearize(xt)
+    A = (lin.JT @ lin.J).tocsr()
+    for L in (1, 7, 25):
+        ref, _ = o.pcg(lin.apply, lin.jtf(), lin.minv(precond), L)
+        # Once CG loses orthogonality its iterates depend on rounding order; the
+        # oracle's own spread between J^T(Jp) and (J^T J)p bounds what can agree.
+        ref2, _ = o.pcg(lambda v: A @ v, lin.jtf(), lin.minv(precond), L)
+        tol = max(1e-9, 100 * relmax(ref2, ref))
+        got = to_np(prob.pcg(L, use_precond=precond))
+        assert relmax(got, ref) < tol, (L, tol)
+
+
+def test_gn_config1_fp64():
+    """ARAP warp 64x64, FP64, GN 5 x 20, Jacobi: the parity configuration."""
+    d = w.arap_warp(64, 64, seed=1)
+    e = o.make_energy(d)
+    xo, costs = o.gauss_newton(e, d["x0"], 5, 20)
+    prob = make_problem(d, "fp64")
+    xt = to_dev(prob, d["x0"])
+    rep = prob.solve(xt, method="gn", outer_iters=5, pcg_iters=20)
+    assert np.allclose(rep["cost_trace"], costs, rtol=1e-9, atol=0)
+    assert relmax(to_np(xt) - d["x0"].ravel(), xo - d["x0"].ravel()) < 1e-8
+
+
+def test_gn_mixed_precision():
+    d = w.arap_warp(64, 64, seed=1)
+    e = o.make_energy(d)
+    xo, costs = o.gauss_newton(e, d["x0"], 5, 20)
+    prob = make_problem(d, "mixed")
+    xt = to_dev(prob, d["x0"])
+    rep = prob.solve(xt, method="gn", outer_iters=5, pcg_iters=20)
+    assert abs(rep["cost_final"] - costs[-1]) <= 1e-4 * costs[-1]
+    assert relmax(to_np(xt) - d["x0"].ravel(), xo - d["x0"].ravel()) < 1e-3
+
+
+def test_lm_fp64():
+    d = w.arap_warp(40, 33, seed=4, n_constraints=12, sigma=4.0, margin=3, mask="random")
+    e = o.make_energy(d)
+    xo, costs, acc = o.levenberg_marquardt(e, d["x0"], 6, 15)
+    prob = make_problem(d, "fp64")
+    xt = to_dev(prob, d["x0"])
+    rep = prob.solve(xt, method="lm", outer_iters=6, pcg_iters=15)
+    assert rep["steps_accepted"] == sum(acc)
+    assert np.allclose(rep["cost_trace"][:len(costs)], costs, rtol=1e-9, atol=0)
+    assert relmax(to_np(xt) - d["x0"].ravel(), xo - d["x0"].ravel()) < 1e-8
+
+
+def test_deterministic():
+    d = w.arap_warp(70, 65, seed=2, mask="hole")
+    outs = []
+    for _ in range(2):
+        prob = make_problem(d, "mixed")
+        xt = to_dev(prob, d["x0"])
+        rep = prob.solve(xt, method="gn", outer_iters=3, pcg_iters=10)
+        outs.append((rep["cost_trace"], to_np(xt)))
+    assert outs[0][0] == outs[1][0]
+    assert np.array_equal(outs[0][1], outs[1][1])
+
+
+def test_excluded_unknowns_unchanged():
+    d = w.arap_warp(37, 29, seed=3, mask="random")
+    prob = make_problem(d, "mixed")
+    xt = to_dev(prob, d["x0"])
+    prob.solve(xt, method="gn", outer_iters=2, pcg_iters=10)
+    x = to_np(xt).reshape(3, -1)
+    ex = (d["mask"] != 0).ravel()
+    assert np.array_equal(x[:, ex], d["x0"].reshape(3, -1)[:, ex].astype(np.float32))
+
+
+def test_zero_iterations_and_tiny_grid():
+    d = w.arap_warp(1, 1, seed=1, n_constraints=1, margin=0)
+    prob = make_problem(d, "fp64")
+    xt = to_dev(prob, d["x0"])
+    rep = prob.solve(xt, method="gn", outer_iters=0, pcg_iters=0)
+    assert rep["cost_final"] == o.cost(o.make_energy(d), d["x0"])
+    rep = prob.solve(xt, method="gn", outer_iters=2, pcg_iters=3)
+    xo, costs = o.gauss_newton(o.make_energy(d), d["x0"], 2, 3)
+    assert np.allclose(rep["cost_trace"], costs, rtol=1e-12, atol=1e-300)
