@@ -193,6 +193,16 @@ int opt_apply_jtj(opt_problem* prob, const void* p, void* q, double lambda,
                   const opt_solve_params* params);
 int opt_pcg(opt_problem* prob, const opt_solve_params* params, double lambda, void* delta_out);
 
+/*
+ * Timing of the PCG phase.  After opt_profile_enable(prob, 1) every opt_solve
+ * records a HIP event pair on the problem's stream around the L PCG iterations of
+ * each outer iteration.  opt_profile_read synchronises the stream, adds the
+ * elapsed times of all pairs recorded since the last read into *pcg_ms, the
+ * number of PCG iterations they cover into *pcg_iters, and clears them.
+ */
+int opt_profile_enable(opt_problem* prob, int enable);
+int opt_profile_read(opt_problem* prob, double* pcg_ms, int64_t* pcg_iters);
+
 /* Number of unknown channels per site for an energy (0 if unknown). */
 int opt_energy_channels(int32_t energy);
 

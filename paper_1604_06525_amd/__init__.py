@@ -58,6 +58,8 @@ _proto = {
     "opt_apply_jtj": (ctypes.c_int, [_P, _P, _P, ctypes.c_double, ctypes.POINTER(opt_solve_params)]),
     "opt_pcg": (ctypes.c_int, [_P, ctypes.POINTER(opt_solve_params), ctypes.c_double, _P]),
     "opt_energy_channels": (ctypes.c_int, [ctypes.c_int32]),
+    "opt_profile_enable": (ctypes.c_int, [_P, ctypes.c_int]),
+    "opt_profile_read": (ctypes.c_int, [_P, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64)]),
 }
 _lib = None
 
@@ -222,6 +224,16 @@ class Problem:
         _check(lib().opt_apply_jtj(self.handle, _ptr(p), _ptr(q), float(lam), ctypes.byref(prm)),
                "opt_apply_jtj")
         return q
+
+    def profile_enable(self, on=True):
+        _check(lib().opt_profile_enable(self.handle, int(on)), "opt_profile_enable")
+
+    def profile_read(self):
+        """(milliseconds, PCG iterations) of the PCG phases timed since the last read."""
+        ms = ctypes.c_double(0)
+        it = ctypes.c_int64(0)
+        _check(lib().opt_profile_read(self.handle, ctypes.byref(ms), ctypes.byref(it)), "opt_profile_read")
+        return ms.value, it.value
 
     def pcg(self, iters, lam=0.0, use_precond=True, params=None):
         prm = params if params is not None else default_params(pcg_iters=iters, use_precond=int(use_precond))

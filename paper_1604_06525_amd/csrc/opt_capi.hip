@@ -174,6 +174,15 @@ struct opt_problem {
   int nblk = 1;
   const void* last_x = nullptr;
   std::unique_ptr<Impl> impl;
+  // PCG-phase timing (opt_profile_enable)
+  bool profile = false;
+  std::vector<hipEvent_t> ev_pool;   // created on demand, reused
+  size_t ev_used = 0;                // events recorded since the last read
+  int64_t prof_iters = 0;
+
+  ~opt_problem() {
+    for (hipEvent_t e : ev_pool) (void)hipEventDestroy(e);
+  }
 
   void* at(size_t off) const { return ws + off; }
   double* part(int k) const { return (double*)(ws + L.parts) + (size_t)k * kMaxBlocks; }
@@ -312,6 +321,18 @@ int sync_scalars(opt_problem* p, DevScalars* hs) {
   return OPT_OK;
 }
 
+// Record the next profiling event on the problem's stream.
+int record_event(opt_problem* p) {
+  if (p->ev_used == p->ev_pool.size()) {
+    hipEvent_t e;
+    HIP_TRY(hipEventCreate(&e));
+    p->ev_pool.push_back(e);
+  }
+  HIP_TRY(hipEventRecord(p->ev_pool[p->ev_used], p->stream));
+  p->ev_used++;
+  return OPT_OK;
+}
+
 #define TRY(x)              \
   do {                      \
     int rc_ = (x);          \
@@ -443,6 +464,28 @@ int opt_pcg(opt_problem* p, const opt_solve_params* sp, double lambda, void* del
   return OPT_OK;
 }
 
+int opt_profile_enable(opt_problem* p, int enable) {
+  if (!p) return fail(OPT_EINVAL, "problem is NULL");
+  p->profile = enable != 0;
+  return OPT_OK;
+}
+
+int opt_profile_read(opt_problem* p, double* pcg_ms, int64_t* pcg_iters) {
+  if (!p || !pcg_ms || !pcg_iters) return fail(OPT_EINVAL, "NULL argument");
+  HIP_TRY(hipStreamSynchronize(p->stream));
+  double total = 0.0;
+  for (size_t k = 0; k + 1 < p->ev_used; k += 2) {
+    float ms = 0.f;
+    HIP_TRY(hipEventElapsedTime(&ms, p->ev_pool[k], p->ev_pool[k + 1]));
+    total += ms;
+  }
+  *pcg_ms = total;
+  *pcg_iters = p->prof_iters;
+  p->ev_used = 0;
+  p->prof_iters = 0;
+  return OPT_OK;
+}
+
 int opt_cost(opt_problem* p, const void* x, double* cost) {
   if (!p || !x || !cost) return fail(OPT_EINVAL, "problem, unknowns or cost is NULL");
   TRY(p->impl->cost(x, nullptr, 0));
@@ -468,9 +511,14 @@ int opt_solve(opt_problem* p, void* x, const opt_solve_params* sp, opt_solve_rep
   for (int k = 0; k < K; ++k) {
     TRY(p->impl->linearize(x, lm));
     TRY(p->impl->init(x, trace, k, pa, lm));
+    if (p->profile) TRY(record_event(p));
     for (int l = 0; l < Lp; ++l) {
       TRY(p->impl->pcg_a(l, pa, lm));
       TRY(p->impl->pcg_b(l, pa, lm));
+    }
+    if (p->profile) {
+      TRY(record_event(p));
+      p->prof_iters += Lp;
     }
     if (lm) {
       TRY(p->impl->model(x));
