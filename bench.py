@@ -125,7 +125,7 @@ def main():
                    "precision": "mixed: FP32 bulk, FP64 dot products and costs", "seed": WARP["seed"]},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": None,
-                     "unit_of_work": "one PCG iteration (k_pcg_a + k_pcg_b)",
+                     "unit_of_work": "one PCG iteration = one k_fused launch",
                      "bytes_per_iter": bpi, "iter_us": iter_us},
         "pcg_phase_iters_per_s": pcg_iters / (pcg_ms / 1e3),
         "cost_initial": rep["cost_initial"],

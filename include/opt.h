@@ -92,6 +92,17 @@ typedef enum {
 typedef enum { OPT_FP64 = 0, OPT_MIXED = 1 } opt_precision;
 typedef enum { OPT_GN = 0, OPT_LM = 1 } opt_method;
 
+/*
+ * Form of the preconditioned CG inner solve (Sec. 4.1).  Both give the same
+ * iterates in exact arithmetic and differ only by rounding.
+ * OPT_PCG_FUSED: one kernel per iteration, the single-reduction recurrence of
+ *   Chronopoulos and Gear (alpha and beta from r.z and (A z).z of the previous
+ *   iteration), with A p evaluated exactly; r, p and d each cross HBM once.
+ * OPT_PCG_SPLIT: the textbook recurrence (alpha = r.z / p.Ap, then beta), two
+ *   kernels per iteration.
+ */
+typedef enum { OPT_PCG_FUSED = 0, OPT_PCG_SPLIT = 1 } opt_pcg_variant;
+
 typedef struct {
   int32_t domain;     /* opt_domain */
   int32_t energy;     /* opt_energy */
@@ -138,6 +149,7 @@ typedef struct {
   double lm_diag_min, lm_diag_max; /* clamp of the damping diagonal D */
   double lm_min_rel_decrease;      /* step accepted iff model decrease m > 0 and
                                       (E(x) - E(x+d)) / m exceeds this */
+  int32_t pcg_variant;  /* opt_pcg_variant */
 } opt_solve_params;
 
 typedef struct {
@@ -150,7 +162,8 @@ typedef struct {
 } opt_solve_report;
 
 /* Fill `p` with the defaults: GN, 10 x 50, preconditioned, LM radius 1e4 in
-   [1e-32, 1e16], diagonal clamp [1e-6, 1e32], min relative decrease 1e-3. */
+   [1e-32, 1e16], diagonal clamp [1e-6, 1e32], min relative decrease 1e-3,
+   OPT_PCG_FUSED. */
 void opt_default_params(opt_solve_params* p);
 
 /*
@@ -185,7 +198,8 @@ int opt_cost(opt_problem* prob, const void* unknowns, double* cost);
  *   NULL when lambda == 0).  p, q: device, channels x sites; excluded entries of
  *   p are ignored and of q set to 0.  p and q must not overlap.
  * opt_pcg: at the last linearisation point, run params->pcg_iters PCG iterations
- *   on (J^T J + lambda D) d = -J^T F from d = 0 and write d (device).
+ *   (in the form params->pcg_variant) on (J^T J + lambda D) d = -J^T F from d = 0
+ *   and write d (device).
  */
 int opt_linearize(opt_problem* prob, const void* unknowns, double* cost);
 int opt_eval_jtf(opt_problem* prob, void* b_out, void* diag_out);

@@ -19,6 +19,7 @@ GRID2D, GRAPH = 0, 1
 ENERGIES = {"laplacian": 0, "arap_warp": 1, "poisson": 2, "sfs": 3, "flow": 4, "arap_mesh": 5}
 PRECISIONS = {"fp64": 0, "mixed": 1}
 GN, LM = 0, 1
+PCG_FUSED, PCG_SPLIT = 0, 1
 
 
 class opt_problem_desc(ctypes.Structure):
@@ -34,7 +35,8 @@ class opt_solve_params(ctypes.Structure):
                 ("pcg_iters", ctypes.c_int32), ("use_precond", ctypes.c_int32),
                 ("lm_radius0", ctypes.c_double), ("lm_radius_min", ctypes.c_double),
                 ("lm_radius_max", ctypes.c_double), ("lm_diag_min", ctypes.c_double),
-                ("lm_diag_max", ctypes.c_double), ("lm_min_rel_decrease", ctypes.c_double)]
+                ("lm_diag_max", ctypes.c_double), ("lm_min_rel_decrease", ctypes.c_double),
+                ("pcg_variant", ctypes.c_int32)]
 
 
 class opt_solve_report(ctypes.Structure):
@@ -102,6 +104,8 @@ def default_params(**kw):
     for k, v in kw.items():
         if k == "method" and isinstance(v, str):
             v = {"gn": GN, "lm": LM}[v.lower()]
+        if k == "pcg_variant" and isinstance(v, str):
+            v = {"fused": PCG_FUSED, "split": PCG_SPLIT}[v.lower()]
         if not hasattr(p, k):
             raise TypeError(f"unknown solve parameter {k}")
         setattr(p, k, v)
@@ -235,8 +239,9 @@ class Problem:
         _check(lib().opt_profile_read(self.handle, ctypes.byref(ms), ctypes.byref(it)), "opt_profile_read")
         return ms.value, it.value
 
-    def pcg(self, iters, lam=0.0, use_precond=True, params=None):
-        prm = params if params is not None else default_params(pcg_iters=iters, use_precond=int(use_precond))
+    def pcg(self, iters, lam=0.0, use_precond=True, params=None, variant="fused"):
+        prm = params if params is not None else default_params(
+            pcg_iters=iters, use_precond=int(use_precond), pcg_variant=variant)
         d = self.new_vector()
         _check(lib().opt_pcg(self.handle, ctypes.byref(prm), float(lam), _ptr(d)), "opt_pcg")
         return d

@@ -16,7 +16,9 @@ constexpr int kMaxBlocks = 1024; // cap on the grid of every site kernel; also t
 // never waits inside the loop.  Written by block 0 of one kernel and read by the
 // kernels that follow it in stream order.
 struct DevScalars {
-  double rz[2];      // r.z of PCG iteration k, stored at slot k & 1
+  double rz[2];      // split form: r.z of PCG iteration k, stored at slot k & 1
+  double gam[2];     // fused form: gamma_i and alpha_i at slot i & 1
+  double alpha[2];
   double E0;         // cost at the current linearisation point
   double E1;         // LM: cost at the trial point x + d
   double m;          // LM: model decrease

@@ -16,7 +16,12 @@
 //   own    J p = w_reg [ (P_p - P_q) - a_p P^t_p ]
 //   back   J p = w_reg [ (P_q - P_p) - a_q P^t_q ]
 //   (J^T J P)_O(p) += w_reg (own) - w_reg (back),  (J^T J P)_t(p) += -w_reg a_p . (own)
-// R'(t) d is R(t) d turned by +90 degrees, so |a_p| = |d|.
+// R'(t) d is R(t) d turned by +90 degrees, so |a_p| = |d|.  J^T J couples a
+// pixel to its four neighbours only (operator radius 1).
+//
+// Stencil functions read through views: P(c, di, dj) and S(k, di, dj) give
+// unknown-vector channel c and state plane k at offset (di, dj) from the centre,
+// F(di, dj) the flags there (0 off the grid).  State planes: cos t, sin t, U_x, U_y.
 #pragma once
 #include "common.h"
 
@@ -25,21 +30,27 @@ namespace optmi {
 template <typename T>
 struct ArapWarp {
   using Real = T;
-  static constexpr int C = 3;  // unknown channels
-  static constexpr int kStatePlanes = 2;  // cos t, sin t
+  static constexpr int C = 3;             // unknown channels
+  static constexpr int kStatePlanes = 4;  // cos t, sin t, U_x, U_y
+  static constexpr int kOwnState = 2;     // planes the library stores (cos, sin)
+  static constexpr int kRadius = 1;       // stencil radius of J^T J
+  enum : uint32_t { ACTIVE = 1, INGRID = 2, FIT = 4 };
 
   int W, H, n;
-  const T* __restrict__ U;   // [2][n]
-  const T* __restrict__ Ct;  // [2][n]
+  const T* __restrict__ U;    // [2][n]
+  const T* __restrict__ Ct;   // [2][n]
   const uint8_t* __restrict__ mask;
   T* __restrict__ cs;         // [2][n] cos and sin of t at the linearisation point
-  uint8_t* __restrict__ flags;// bit0: not excluded, bit1: fit target valid
-  T wf, wr;                   // w_fit, w_reg
+  uint8_t* __restrict__ flags;
+  T wf, wr;                   // w_fit, w_reg in the bulk type
+  double wf_d, wr_d;          // and in double for the cost
 
-  __device__ __forceinline__ bool active(int s) const { return flags[s] & 1; }
+  __device__ __forceinline__ const T* state_plane(int k) const {
+    return k < 2 ? cs + (size_t)k * n : U + (size_t)(k - 2) * n;
+  }
 
   // Neighbour k of site (i, j) in the order (1,0), (-1,0), (0,1), (0,-1);
-  // returns its id or -1 when it is off the grid.
+  // its id, or -1 off the grid.
   __device__ __forceinline__ int nbr(int i, int j, int s, int k) const {
     switch (k) {
       case 0: return i + 1 < W ? s + 1 : -1;
@@ -49,15 +60,14 @@ struct ArapWarp {
     }
   }
 
-  // FP64 sum of squares of the residuals anchored at s, for unknowns read
-  // through X(ch, site) (already rounded to the bulk type, returned as double).
+  // FP64 sum of squares of the residuals anchored at s, unknowns read through
+  // X(ch, site) (values of the bulk type, returned as double).
   template <class XA>
   __device__ __forceinline__ double cost(XA X, int s) const {
     const int i = s % W, j = s / W;
     const bool ap = mask[s] == 0;
-    const double th = X(2, s);
     double sn, c;
-    sincos_t(th, &sn, &c);
+    sincos_t(X(2, s), &sn, &c);
     const double Ox = X(0, s), Oy = X(1, s);
     const double Ux = U[s], Uy = U[n + s];
     double e = 0.0;
@@ -67,14 +77,14 @@ struct ArapWarp {
         const int q = nbr(i, j, s, k);
         if (q < 0 || mask[q] != 0) continue;
         const double dx = Ux - (double)U[q], dy = Uy - (double)U[n + q];
-        const double rx = (double)wr * ((Ox - X(0, q)) - (c * dx - sn * dy));
-        const double ry = (double)wr * ((Oy - X(1, q)) - (sn * dx + c * dy));
+        const double rx = wr_d * ((Ox - X(0, q)) - (c * dx - sn * dy));
+        const double ry = wr_d * ((Oy - X(1, q)) - (sn * dx + c * dy));
         e += rx * rx + ry * ry;
       }
     }
     const double cx = Ct[s], cy = Ct[n + s];
     if (cx >= 0.0 && cy >= 0.0) {
-      const double fx = (double)wf * (Ox - cx), fy = (double)wf * (Oy - cy);
+      const double fx = wf_d * (Ox - cx), fy = wf_d * (Oy - cy);
       e += fx * fx + fy * fy;
     }
     return e;
@@ -83,27 +93,28 @@ struct ArapWarp {
   // Per-site state for the products: cos/sin of the angle and the flags.
   __device__ __forceinline__ void linearize(const T* __restrict__ x, int s) const {
     T sn, c;
-    sincos_t(x[2 * n + s], &sn, &c);
+    sincos_t(x[2 * (size_t)n + s], &sn, &c);
     cs[s] = c;
     cs[n + s] = sn;
     const bool fit = Ct[s] >= T(0) && Ct[n + s] >= T(0);
-    flags[s] = (uint8_t)((mask[s] == 0 ? 1 : 0) | (fit ? 2 : 0));
+    flags[s] = (uint8_t)(INGRID | (mask[s] == 0 ? ACTIVE : 0) | (fit ? FIT : 0));
   }
 
-  // b = -J^T F and diag(J^T J) at the linearisation point, for an active site.
-  __device__ __forceinline__ void jtf_diag(const T* __restrict__ x, int s, T* b, T* d) const {
-    const int i = s % W, j = s / W;
-    const T c = cs[s], sn = cs[n + s];
-    const T Ox = x[s], Oy = x[n + s], Ux = U[s], Uy = U[n + s];
+  // b = -J^T F and diag(J^T J) at an active site s (global index) at the
+  // linearisation point; X views the unknowns.
+  template <class XV, class SV, class FV>
+  __device__ __forceinline__ void jtf_diag(XV X, SV S, FV F, int s, T* b, T* d) const {
+    const T c = S(0, 0, 0), sn = S(1, 0, 0), Ux = S(2, 0, 0), Uy = S(3, 0, 0);
+    const T Ox = X(0, 0, 0), Oy = X(1, 0, 0);
     T bx = 0, by = 0, bt = 0, dO = 0, dt = 0;
     const T wr2 = wr * wr;
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
-      const int q = nbr(i, j, s, k);
-      if (q < 0 || !(flags[q] & 1)) continue;
-      const T dx = Ux - U[q], dy = Uy - U[n + q];
-      const T cq = cs[q], sq = cs[n + q];
-      const T ex = Ox - x[q], ey = Oy - x[n + q];
+      const int di = k == 0 ? 1 : (k == 1 ? -1 : 0), dj = k == 2 ? 1 : (k == 3 ? -1 : 0);
+      if (!(F(di, dj) & ACTIVE)) continue;
+      const T dx = Ux - S(2, di, dj), dy = Uy - S(3, di, dj);
+      const T cq = S(0, di, dj), sq = S(1, di, dj);
+      const T ex = Ox - X(0, di, dj), ey = Oy - X(1, di, dj);
       // own residual / w_reg, and the back residual / w_reg
       const T f1x = ex - (c * dx - sn * dy), f1y = ey - (sn * dx + c * dy);
       const T f2x = -ex + (cq * dx - sq * dy), f2y = -ey + (sq * dx + cq * dy);
@@ -114,7 +125,7 @@ struct ArapWarp {
       dO += T(2) * wr2;
       dt += wr2 * (apx * apx + apy * apy);
     }
-    if (flags[s] & 2) {
+    if (F(0, 0) & FIT) {
       const T wf2 = wf * wf;
       bx -= wf2 * (Ox - Ct[s]);
       by -= wf2 * (Oy - Ct[n + s]);
@@ -124,22 +135,20 @@ struct ArapWarp {
     d[0] = dO; d[1] = dO; d[2] = dt;
   }
 
-  // g = J^T J P at an active site; P(ch, site) gives the direction.
-  template <class PA>
-  __device__ __forceinline__ void jtjp(int s, PA P, T* g) const {
-    const int i = s % W, j = s / W;
-    const T c = cs[s], sn = cs[n + s];
-    const T Ux = U[s], Uy = U[n + s];
-    const T px = P(0, s), py = P(1, s), pt = P(2, s);
+  // g = J^T J P at an active centre site.
+  template <class PV, class SV, class FV>
+  __device__ __forceinline__ void apply(PV P, SV S, FV F, T* g) const {
+    const T c = S(0, 0, 0), sn = S(1, 0, 0), Ux = S(2, 0, 0), Uy = S(3, 0, 0);
+    const T px = P(0, 0, 0), py = P(1, 0, 0), pt = P(2, 0, 0);
     T gx = 0, gy = 0, gt = 0;
     const T wr2 = wr * wr;
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
-      const int q = nbr(i, j, s, k);
-      if (q < 0 || !(flags[q] & 1)) continue;
-      const T dx = Ux - U[q], dy = Uy - U[n + q];
-      const T cq = cs[q], sq = cs[n + q];
-      const T qx = P(0, q), qy = P(1, q), qt = P(2, q);
+      const int di = k == 0 ? 1 : (k == 1 ? -1 : 0), dj = k == 2 ? 1 : (k == 3 ? -1 : 0);
+      if (!(F(di, dj) & ACTIVE)) continue;
+      const T dx = Ux - S(2, di, dj), dy = Uy - S(3, di, dj);
+      const T cq = S(0, di, dj), sq = S(1, di, dj);
+      const T qx = P(0, di, dj), qy = P(1, di, dj), qt = P(2, di, dj);
       const T apx = -sn * dx - c * dy, apy = c * dx - sn * dy;
       const T aqx = sq * dx + cq * dy, aqy = -cq * dx + sq * dy;
       const T ex = px - qx, ey = py - qy;
@@ -149,7 +158,7 @@ struct ArapWarp {
       gy += wr2 * (j1y - j2y);
       gt -= wr2 * (apx * j1x + apy * j1y);
     }
-    if (flags[s] & 2) {
+    if (F(0, 0) & FIT) {
       const T wf2 = wf * wf;
       gx += wf2 * px;
       gy += wf2 * py;
@@ -176,20 +185,18 @@ struct ArapWarp {
         const int q = nbr(i, j, s, k);
         if (q < 0 || mask[q] != 0) continue;
         const double dx = Ux - (double)U[q], dy = Uy - (double)U[n + q];
-        const double w = wr;
-        const double fx = w * ((Ox - X(0, q)) - (c * dx - sn * dy));
-        const double fy = w * ((Oy - X(1, q)) - (sn * dx + c * dy));
+        const double fx = wr_d * ((Ox - X(0, q)) - (c * dx - sn * dy));
+        const double fy = wr_d * ((Oy - X(1, q)) - (sn * dx + c * dy));
         const double apx = -sn * dx - c * dy, apy = c * dx - sn * dy;
-        const double jx = w * ((dOx - Dl(0, q)) - apx * dt);
-        const double jy = w * ((dOy - Dl(1, q)) - apy * dt);
+        const double jx = wr_d * ((dOx - Dl(0, q)) - apx * dt);
+        const double jy = wr_d * ((dOy - Dl(1, q)) - apy * dt);
         acc += jx * (2.0 * fx + jx) + jy * (2.0 * fy + jy);
       }
     }
     const double cx = Ct[s], cy = Ct[n + s];
     if (cx >= 0.0 && cy >= 0.0) {
-      const double w = wf;
-      const double fx = w * (Ox - cx), fy = w * (Oy - cy);
-      const double jx = w * dOx, jy = w * dOy;
+      const double fx = wf_d * (Ox - cx), fy = wf_d * (Oy - cy);
+      const double jx = wf_d * dOx, jy = wf_d * dOy;
       acc += jx * (2.0 * fx + jx) + jy * (2.0 * fy + jy);
     }
     return acc;

@@ -1,20 +1,33 @@
-// Kernels of one solve, generic over the energy.
+// Kernels of one solve on a 2D grid, generic over the energy.
 //
-// One PCG iteration (Sec. 4.1) is two kernels.  Kernel boundaries are the only
-// grid-wide synchronisation: a scalar that needs a sum over the whole problem
-// (p.q, r.z) is produced as per-block FP64 partials by one kernel and summed,
-// in a fixed order, by every block of the next kernel, so no fence or atomic is
-// needed and the result is the same on every run.
+// Kernel boundaries are the only grid-wide synchronisation.  A scalar that
+// needs a sum over the whole problem is produced as per-block FP64 partials by
+// one kernel and summed, in a fixed order, by every block of the next kernel, so
+// no fence or atomic is needed and every run gives the same bits.
 //
-//   pcg_a(k):  beta = rz_k / rz_{k-1} (k > 0);  p_k = z_k + beta p_{k-1}, with
-//              z = M^-1 r, evaluated on the fly for each site and for the
-//              neighbours its product reads;  q = (J^T J + lambda D) p_k;
-//              write p_k and q;  partials of p_k . q.
-//   pcg_b(k):  alpha = rz_k / (p.q);  d += alpha p;  r -= alpha q;
-//              z = M^-1 r;  partials of r . z = rz_{k+1}.
+// Two forms of the preconditioned CG inner solve (Sec. 4.1) are built.
 //
-// If p.q is not positive the PCG stops (DevScalars::stopped) and every later
-// iteration kernel returns at once, which leaves d as it was.
+// Split (two kernels per iteration, the textbook recurrence):
+//   pcg_a(k):  beta = rz_k / rz_{k-1} (k > 0);  p_k = z_k + beta p_{k-1}, z = M^-1 r,
+//              evaluated for each site and the neighbours its product reads;
+//              q = A p_k;  write p_k, q;  partials of p_k . q.
+//   pcg_b(k):  alpha = rz_k / (p.q);  d += alpha p;  r -= alpha q;  partials of r.z.
+//
+// Fused (one kernel per iteration): the single-reduction recurrence of
+// Chronopoulos and Gear, which gives the same iterates in exact arithmetic.  With
+// u = M^-1 r, w = A u, gamma = r.u and delta = w.u summed by the previous kernel:
+//   beta_i = gamma_i/gamma_{i-1},  alpha_i = gamma_i / (delta_i - beta_i gamma_i/alpha_{i-1})
+//   p_i = u_i + beta_i p_{i-1};  s_i = A p_i;  d += alpha_i p_i;  r_{i+1} = r_i - alpha_i s_i
+//   partials of gamma_{i+1} = r_{i+1}.u_{i+1} and delta_{i+1} = (A u_{i+1}).u_{i+1}.
+// A block stages r_i, p_{i-1}, M^-1 and the energy's state for its tile plus a
+// halo of twice the operator radius in LDS, computes p_i on all of it, s_i and
+// r_{i+1} on the tile plus one operator radius, and A u_{i+1} on the tile, so
+// only r, p and d cross HBM once per iteration.  s_i = A p_i is formed exactly
+// (not by its own recurrence).  A first "priming" launch with alpha = beta = 0
+// produces gamma_0 and delta_0.
+//
+// If the curvature p.Ap is not positive the solve stops (DevScalars::stopped):
+// every later iteration kernel returns at once and d keeps its value.
 #pragma once
 #include "common.h"
 
@@ -25,12 +38,21 @@ namespace optmi {
 #define OPT_SITE_LOOP(s, n) \
   for (int s = blockIdx.x * kBlock + threadIdx.x; s < (n); s += gridDim.x * kBlock)
 
+// Views over global memory centred at site s = j*W + i of a W x H grid.
+#define OPT_GRID_VIEWS(e, s)                                                          \
+  const int vi_ = (s) % (e).W, vj_ = (s) / (e).W;                                     \
+  auto Fg = [&](int di, int dj) -> uint32_t {                                         \
+    const int ii = vi_ + di, jj = vj_ + dj;                                           \
+    return (ii >= 0 && ii < (e).W && jj >= 0 && jj < (e).H) ? (e).flags[(s) + dj * (e).W + di] \
+                                                            : 0u;                     \
+  };                                                                                  \
+  auto Sg = [&](int k, int di, int dj) { return (e).state_plane(k)[(s) + dj * (e).W + di]; };
+
 // ---------------------------------------------------------------- linearize
 template <class E>
 __global__ void __launch_bounds__(kBlock)
 k_linearize(E e, const typename E::Real* __restrict__ x, double* __restrict__ part,
             const DevScalars* __restrict__ S, int lm_gate) {
-  using T = typename E::Real;
   if (lm_gate && (S->done || !S->need_lin)) return;
   double acc = 0.0;
   const int n = e.n;
@@ -40,16 +62,24 @@ k_linearize(E e, const typename E::Real* __restrict__ x, double* __restrict__ pa
     acc += e.cost(X, s);
   }
   block_store(acc, part);
-  (void)sizeof(T);
 }
 
 // ---------------------------------------------------------------- init
-// r = b = -J^T F, diag = diag(J^T J), d = 0, rz_0 partials; also finishes the
-// cost of the linearisation (trace entry k) and resets the PCG state.
+// r = b = -J^T F, diag = diag(J^T J), M^-1 and (LM) the damping lambda*D, d = 0,
+// and partials of r.z for the split form; also finishes the cost of the
+// linearisation (trace entry) and resets the PCG state.
+template <typename T>
+struct InitOut {
+  T* r;
+  T* diag;
+  T* minv;
+  T* damp;   // nullptr unless LM
+  T* delta;
+};
+
 template <class E>
 __global__ void __launch_bounds__(kBlock)
-k_init(E e, const typename E::Real* __restrict__ x, typename E::Real* __restrict__ r,
-       typename E::Real* __restrict__ diag, typename E::Real* __restrict__ delta,
+k_init(E e, const typename E::Real* __restrict__ x, InitOut<typename E::Real> o,
        const double* __restrict__ lin_part, int n_lin, double* __restrict__ rz_part,
        DevScalars* S, double* __restrict__ trace, int trace_idx, Precond<typename E::Real> pc,
        int lm_gate) {
@@ -75,34 +105,46 @@ k_init(E e, const typename E::Real* __restrict__ x, typename E::Real* __restrict
   double rz = 0.0;
   OPT_SITE_LOOP(s, n) {
     T b[C], d[C];
-    if (e.active(s)) {
-      e.jtf_diag(x, s, b, d);
+    OPT_GRID_VIEWS(e, s)
+    if (Fg(0, 0) & E::ACTIVE) {
+      auto Xg = [&](int c, int di, int dj) { return x[(size_t)c * n + s + dj * e.W + di]; };
+      e.jtf_diag(Xg, Sg, Fg, s, b, d);
     } else {
 #pragma unroll
       for (int c = 0; c < C; ++c) { b[c] = T(0); d[c] = T(0); }
     }
 #pragma unroll
     for (int c = 0; c < C; ++c) {
-      const size_t o = (size_t)c * n + s;
-      r[o] = b[c];
-      diag[o] = d[c];
-      delta[o] = T(0);
-      const T z = pc.minv(d[c]) * b[c];
-      rz += (double)b[c] * (double)z;
+      const size_t k = (size_t)c * n + s;
+      const T m = pc.minv(d[c]);
+      o.r[k] = b[c];
+      o.diag[k] = d[c];
+      o.minv[k] = m;
+      if (o.damp) o.damp[k] = pc.lam != T(0) ? pc.damp(d[c]) : T(0);
+      o.delta[k] = T(0);
+      rz += (double)b[c] * (double)(m * b[c]);
     }
   }
   block_store(rz, rz_part);
 }
 
-// ---------------------------------------------------------------- pcg_a
+// ---------------------------------------------------------------- split: pcg_a
 // MODE 0: PCG iteration (p from r, the previous p and beta).
-// MODE 1: plain product q = (J^T J + lambda D) p_in (p_in passed as `pold`).
+// MODE 1: plain product q = (J^T J + damp) p_in (p_in passed as `pold`).
+template <typename T>
+struct SplitBufs {
+  const T* r;
+  const T* minv;
+  const T* damp;  // nullptr: no damping
+  const T* pold;
+  T* pnew;
+  T* q;
+};
+
 template <class E, int MODE>
 __global__ void __launch_bounds__(kBlock)
-k_pcg_a(E e, int k, const typename E::Real* __restrict__ r, const typename E::Real* __restrict__ diag,
-        const typename E::Real* __restrict__ pold, typename E::Real* __restrict__ pnew,
-        typename E::Real* __restrict__ q, const double* __restrict__ rz_part, int n_rz,
-        double* __restrict__ pq_part, DevScalars* S, Precond<typename E::Real> pc, int lm_gate) {
+k_pcg_a(E e, int k, SplitBufs<typename E::Real> b, const double* __restrict__ rz_part, int n_rz,
+        double* __restrict__ pq_part, DevScalars* S, int lm_gate) {
   using T = typename E::Real;
   constexpr int C = E::C;
   const int n = e.n;
@@ -113,65 +155,226 @@ k_pcg_a(E e, int k, const typename E::Real* __restrict__ r, const typename E::Re
     if (k > 0) beta = (T)(rz / S->rz[(k - 1) & 1]);
     if (is_block_leader()) S->rz[k & 1] = rz;
   }
-  if (lm_gate) pc.lam = (T)S->lambda;
-  auto P = [&](int c, int s) -> T {
-    const size_t o = (size_t)c * n + s;
-    if (MODE == 1) return pold[o];
-    const T z = pc.minv(diag[o]) * r[o];
-    return k == 0 ? z : fma(beta, pold[o], z);
-  };
   double pq = 0.0;
   OPT_SITE_LOOP(s, n) {
+    OPT_GRID_VIEWS(e, s)
+    auto Pg = [&](int c, int di, int dj) -> T {
+      const size_t o = (size_t)c * n + s + dj * e.W + di;
+      if (MODE == 1) return b.pold[o];
+      const T z = b.minv[o] * b.r[o];
+      return k == 0 ? z : fma(beta, b.pold[o], z);
+    };
     T g[C];
-    const bool act = e.active(s);
-    if (act) e.jtjp(s, P, g);
+    const bool act = Fg(0, 0) & E::ACTIVE;
+    if (act) e.apply(Pg, Sg, Fg, g);
 #pragma unroll
     for (int c = 0; c < C; ++c) {
       const size_t o = (size_t)c * n + s;
       T pv = T(0), qv = T(0);
       if (act) {
-        pv = P(c, s);
+        pv = Pg(c, 0, 0);
         qv = g[c];
-        if (pc.lam != T(0)) qv += pc.damp(diag[o]) * pv;
+        if (b.damp) qv += b.damp[o] * pv;
       }
-      if (MODE == 0) pnew[o] = pv;
-      q[o] = qv;
+      if (MODE == 0) b.pnew[o] = pv;
+      b.q[o] = qv;
       pq += (double)pv * (double)qv;
     }
   }
   if (MODE == 0) block_store(pq, pq_part);
 }
 
-// ---------------------------------------------------------------- pcg_b
+// ---------------------------------------------------------------- split: pcg_b
 template <typename T, int C>
 __global__ void __launch_bounds__(kBlock)
-k_pcg_b(int n, int k, const uint8_t* __restrict__ flags_unused, T* __restrict__ delta,
-        T* __restrict__ r, const T* __restrict__ p, const T* __restrict__ q,
-        const T* __restrict__ diag, const double* __restrict__ pq_part, int n_pq,
-        double* __restrict__ rz_part, DevScalars* S, Precond<T> pc, int lm_gate) {
+k_pcg_b(int n, int k, T* __restrict__ delta, T* __restrict__ r, const T* __restrict__ p,
+        const T* __restrict__ q, const T* __restrict__ minv, const double* __restrict__ pq_part,
+        int n_pq, double* __restrict__ rz_part, DevScalars* S, int lm_gate) {
   if (S->stopped || (lm_gate && S->done)) return;
   const double pq = reduce_partials(pq_part, n_pq);
   if (!(pq > 0.0)) {
     if (is_block_leader()) S->stopped = 1;
     return;
   }
-  if (lm_gate) pc.lam = (T)S->lambda;
   const T alpha = (T)(S->rz[k & 1] / pq);
   double rz = 0.0;
   OPT_SITE_LOOP(s, n) {
 #pragma unroll
     for (int c = 0; c < C; ++c) {
       const size_t o = (size_t)c * n + s;
-      const T pv = p[o];
-      delta[o] = fma(alpha, pv, delta[o]);
+      delta[o] = fma(alpha, p[o], delta[o]);
       const T rv = fma(-alpha, q[o], r[o]);
       r[o] = rv;
-      const T z = pc.minv(diag[o]) * rv;
-      rz += (double)rv * (double)z;
+      rz += (double)rv * (double)(minv[o] * rv);
     }
   }
   block_store(rz, rz_part);
-  (void)flags_unused;
+}
+
+// ---------------------------------------------------------------- fused iteration
+template <typename T>
+struct FusedBufs {
+  const T* r_in;
+  T* r_out;
+  const T* p_in;
+  T* p_out;
+  T* x;            // the PCG solution d, updated in place
+  const T* minv;
+  const T* damp;   // nullptr: no damping
+  const double* part_in;   // [gamma partials | delta partials], kMaxBlocks apart
+  double* part_out;
+  int n_part_in;
+};
+
+// Tile geometry: TW x TH sites per tile, halo 2*radius, one tile at a time per
+// block; blocks stride over the tiles in an XCD-aware order.
+template <class E, int TW, int TH>
+struct FusedGeom {
+  static constexpr int HALO = 2 * E::kRadius;
+  static constexpr int RW = TW + 2 * HALO, RH = TH + 2 * HALO, N = RW * RH;
+  static constexpr int R1 = HALO - E::kRadius;              // ring-1 offset in the region
+  static constexpr int R1W = TW + 2 * E::kRadius, R1H = TH + 2 * E::kRadius;
+};
+
+// The k-th tile of this block.  Blocks are spread over the 8 XCDs round-robin;
+// each XCD takes one contiguous run of tiles so neighbouring tiles share its L2.
+__device__ __forceinline__ int tile_of(int k, int n_tiles) {
+  const int G = gridDim.x;
+  if (G % 8 != 0) return blockIdx.x + k * G;
+  const int per = G / 8, xcd = blockIdx.x % 8, slot = blockIdx.x / 8;
+  const int chunk = (n_tiles + 7) / 8;
+  const int t = xcd * chunk + slot + k * per;
+  return t < min((xcd + 1) * chunk, n_tiles) ? t : n_tiles;
+}
+
+template <class E, int TW, int TH>
+__global__ void __launch_bounds__(kBlock, 2)
+k_fused(E e, FusedBufs<typename E::Real> b, DevScalars* S, int iter, int lm_gate, int tiles_x,
+        int n_tiles) {
+  using T = typename E::Real;
+  using G = FusedGeom<E, TW, TH>;
+  constexpr int C = E::C, NS = E::kStatePlanes, N = G::N, RW = G::RW;
+  __shared__ T sP[C * N], sR[C * N], sM[C * N], sS[NS * N];
+  __shared__ uint8_t sF[N];
+
+  if (S->stopped || (lm_gate && S->done)) return;
+  double alpha = 0.0, beta = 0.0;
+  if (iter >= 0) {
+    const double gam = reduce_partials(b.part_in, b.n_part_in);
+    const double del = reduce_partials(b.part_in + kMaxBlocks, b.n_part_in);
+    double den = del;
+    if (iter > 0) {
+      beta = gam / S->gam[(iter - 1) & 1];
+      den = del - beta * gam / S->alpha[(iter - 1) & 1];
+    }
+    if (!(den > 0.0)) {
+      if (is_block_leader()) S->stopped = 1;
+      return;
+    }
+    alpha = gam / den;
+    if (is_block_leader()) {
+      S->gam[iter & 1] = gam;
+      S->alpha[iter & 1] = alpha;
+    }
+  }
+  const T aT = (T)alpha, bT = (T)beta;
+  const int W = e.W, H = e.H, n = e.n;
+  double g_acc = 0.0, d_acc = 0.0;
+
+  for (int k = 0;; ++k) {
+    const int tile = tile_of(k, n_tiles);
+    if (tile >= n_tiles) break;
+    const int tx0 = (tile % tiles_x) * TW - G::HALO, ty0 = (tile / tiles_x) * TH - G::HALO;
+    // phase 1: stage the region; p_i = M^-1 r_i + beta p_{i-1}
+    for (int t = threadIdx.x; t < N; t += kBlock) {
+      const int i = tx0 + t % RW, j = ty0 + t / RW;
+      if (i >= 0 && i < W && j >= 0 && j < H) {
+        const int s = j * W + i;
+#pragma unroll
+        for (int c = 0; c < C; ++c) {
+          const size_t o = (size_t)c * n + s;
+          const T r = b.r_in[o], m = b.minv[o];
+          const T u = m * r;
+          sP[c * N + t] = iter > 0 ? fma(bT, b.p_in[o], u) : u;
+          sR[c * N + t] = r;
+          sM[c * N + t] = m;
+        }
+#pragma unroll
+        for (int q = 0; q < NS; ++q) sS[q * N + t] = e.state_plane(q)[s];
+        sF[t] = e.flags[s];
+      } else {
+#pragma unroll
+        for (int c = 0; c < C; ++c) {
+          sP[c * N + t] = T(0);
+          sR[c * N + t] = T(0);
+          sM[c * N + t] = T(0);
+        }
+#pragma unroll
+        for (int q = 0; q < NS; ++q) sS[q * N + t] = T(0);
+        sF[t] = 0;
+      }
+    }
+    __syncthreads();
+    // phase 2: s_i = A p_i and r_{i+1} = r_i - alpha s_i on the tile plus one radius
+    for (int t = threadIdx.x; t < G::R1W * G::R1H; t += kBlock) {
+      const int rx = G::R1 + t % G::R1W, ry = G::R1 + t / G::R1W;
+      const int idx = ry * RW + rx;
+      if (!(sF[idx] & E::ACTIVE)) continue;
+      auto Pv = [&](int c, int di, int dj) { return sP[c * N + idx + dj * RW + di]; };
+      auto Sv = [&](int q, int di, int dj) { return sS[q * N + idx + dj * RW + di]; };
+      auto Fv = [&](int di, int dj) -> uint32_t { return sF[idx + dj * RW + di]; };
+      T g[C];
+      e.apply(Pv, Sv, Fv, g);
+      if (b.damp) {
+        const int s = (ty0 + ry) * W + (tx0 + rx);
+#pragma unroll
+        for (int c = 0; c < C; ++c) g[c] += b.damp[(size_t)c * n + s] * sP[c * N + idx];
+      }
+#pragma unroll
+      for (int c = 0; c < C; ++c) sR[c * N + idx] = fma(-aT, g[c], sR[c * N + idx]);
+    }
+    __syncthreads();
+    // phase 3: w = A u_{i+1} on the tile; partials; d += alpha p_i; store r, p
+    for (int t = threadIdx.x; t < TW * TH; t += kBlock) {
+      const int rx = G::HALO + t % TW, ry = G::HALO + t / TW;
+      const int i = tx0 + rx, j = ty0 + ry;
+      if (i >= W || j >= H) continue;
+      const int idx = ry * RW + rx, s = j * W + i;
+      const bool act = sF[idx] & E::ACTIVE;
+      if (act) {
+        auto Uv = [&](int c, int di, int dj) {
+          const int o = c * N + idx + dj * RW + di;
+          return sM[o] * sR[o];
+        };
+        auto Sv = [&](int q, int di, int dj) { return sS[q * N + idx + dj * RW + di]; };
+        auto Fv = [&](int di, int dj) -> uint32_t { return sF[idx + dj * RW + di]; };
+        T w[C];
+        e.apply(Uv, Sv, Fv, w);
+#pragma unroll
+        for (int c = 0; c < C; ++c) {
+          const T uo = Uv(c, 0, 0);
+          if (b.damp) w[c] += b.damp[(size_t)c * n + s] * uo;
+          g_acc += (double)sR[c * N + idx] * (double)uo;
+          d_acc += (double)w[c] * (double)uo;
+        }
+      }
+#pragma unroll
+      for (int c = 0; c < C; ++c) {
+        const size_t o = (size_t)c * n + s;
+        const T pv = act ? sP[c * N + idx] : T(0);
+        if (iter >= 0 && act) b.x[o] = fma(aT, pv, b.x[o]);
+        b.r_out[o] = sR[c * N + idx];
+        b.p_out[o] = pv;
+      }
+    }
+    __syncthreads();
+  }
+  const double gs = block_sum(g_acc);
+  const double ds = block_sum(d_acc);
+  if (threadIdx.x == 0) {
+    b.part_out[blockIdx.x] = gs;
+    b.part_out[kMaxBlocks + blockIdx.x] = ds;
+  }
 }
 
 // ---------------------------------------------------------------- updates
@@ -184,7 +387,7 @@ k_apply_step(E e, typename E::Real* __restrict__ x, const typename E::Real* __re
   if (lm_gate && !S->accepted) return;
   const int n = e.n;
   OPT_SITE_LOOP(s, n) {
-    if (!e.active(s)) continue;
+    if (!(e.flags[s] & E::ACTIVE)) continue;
 #pragma unroll
     for (int c = 0; c < C; ++c) {
       const size_t o = (size_t)c * n + s;
@@ -213,7 +416,7 @@ k_cost(E e, const typename E::Real* __restrict__ x, const typename E::Real* __re
   block_store(acc, part);
 }
 
-// LM model decrease partials: sum_r (J d)_r (2 F_r + (J d)_r) at x.
+// LM model partials: sum_r (J d)_r (2 F_r + (J d)_r) at x.
 template <class E>
 __global__ void __launch_bounds__(kBlock)
 k_model(E e, const typename E::Real* __restrict__ x, const typename E::Real* __restrict__ delta,
@@ -236,6 +439,8 @@ struct LMConsts {
 __global__ void k_setup(DevScalars* S, double lambda, double radius0, int lm) {
   if (threadIdx.x == 0) {
     S->rz[0] = S->rz[1] = 0.0;
+    S->gam[0] = S->gam[1] = 0.0;
+    S->alpha[0] = S->alpha[1] = 0.0;
     S->E0 = S->E1 = S->m = 0.0;
     S->radius = radius0;
     S->nu = 2.0;

@@ -64,22 +64,22 @@ struct Shape {
 
 // Byte offsets of every region of the workspace.
 struct Layout {
-  size_t r, diag, delta, p0, p1, q, state, flags, parts, scal, trace, total;
+  size_t r0, r1, p0, p1, q, diag, minv, damp, delta, state, flags, parts, scal, trace, total;
 };
+
+constexpr int kNumPartBufs = 10;  // see the P_* indices
 
 Layout make_layout(const Shape& sh) {
   Layout L{};
   size_t off = 0;
   const size_t vec = align_up((size_t)sh.C * sh.n * sh.tsize);
-  L.r = off; off += vec;
-  L.diag = off; off += vec;
-  L.delta = off; off += vec;
-  L.p0 = off; off += vec;
-  L.p1 = off; off += vec;
-  L.q = off; off += vec;
+  for (size_t* v : {&L.r0, &L.r1, &L.p0, &L.p1, &L.q, &L.diag, &L.minv, &L.damp, &L.delta}) {
+    *v = off;
+    off += vec;
+  }
   L.state = off; off += align_up((size_t)sh.state_planes * sh.n * sh.tsize);
   L.flags = off; off += align_up((size_t)sh.n);
-  L.parts = off; off += align_up(7 * (size_t)kMaxBlocks * sizeof(double));
+  L.parts = off; off += align_up(kNumPartBufs * (size_t)kMaxBlocks * sizeof(double));
   L.scal = off; off += align_up(sizeof(DevScalars));
   L.trace = off; off += align_up((size_t)kTraceCap * sizeof(double));
   L.total = off;
@@ -95,7 +95,7 @@ int energy_channels(int e) {
 
 int energy_state_planes(int e) {
   switch (e) {
-    case OPT_E_ARAP_WARP: return 2;
+    case OPT_E_ARAP_WARP: return ArapWarp<float>::kOwnState;
     default: return 0;
   }
 }
@@ -147,6 +147,7 @@ int check_desc(const opt_problem_desc* d, Shape* sh) {
 struct PrecondArgs {
   double lam, dmin, dmax;
   int use;
+  bool damped;  // LM: write and apply the damping vector
 };
 
 // Launch sequence for one energy and bulk type.
@@ -157,6 +158,7 @@ class Impl {
   virtual int init(const void* x, double* trace, int idx, PrecondArgs pa, int lm_gate) = 0;
   virtual int pcg_a(int k, PrecondArgs pa, int lm_gate) = 0;
   virtual int pcg_b(int k, PrecondArgs pa, int lm_gate) = 0;
+  virtual int fused(int iter, PrecondArgs pa, int lm_gate) = 0;
   virtual int apply_jtj(const void* p, void* q, PrecondArgs pa) = 0;
   virtual int apply_step(void* x, int lm_gate) = 0;
   virtual int cost(const void* x, const void* delta, int lm_gate) = 0;
@@ -192,7 +194,13 @@ struct opt_problem {
 
 namespace {
 
-enum { P_LIN = 0, P_RZ0 = 1, P_RZ1 = 2, P_PQ = 3, P_COST = 4, P_M = 5 };
+// partial-sum buffers (kMaxBlocks doubles each); the fused form uses two pairs
+enum { P_LIN = 0, P_RZ0 = 1, P_RZ1 = 2, P_PQ = 3, P_COST = 4, P_M = 5, P_F0 = 6, P_F1 = 8 };
+
+// Tile of the fused PCG kernel: 64 x 16 sites in FP32, 64 x 8 in FP64 (LDS).
+template <typename T> struct FusedTile { static constexpr int TW = 64, TH = 16; };
+template <> struct FusedTile<double> { static constexpr int TW = 64, TH = 8; };
+constexpr int kFusedMaxGrid = 512;
 
 template <class E>
 class ImplT final : public Impl {
@@ -210,6 +218,8 @@ class ImplT final : public Impl {
   }
   T* vec(size_t off) const { return (T*)p_->at(off); }
   T* pbuf(int k) const { return vec((k & 1) ? p_->L.p1 : p_->L.p0); }
+  T* rbuf(int k) const { return vec((k & 1) ? p_->L.r1 : p_->L.r0); }
+  T* damp(PrecondArgs pa) const { return pa.damped ? vec(p_->L.damp) : nullptr; }
 
   int linearize(const void* x, int lm_gate) override {
     k_linearize<E><<<p_->nblk, kBlock, 0, p_->stream>>>(e_, (const T*)x, p_->part(P_LIN), p_->S(),
@@ -218,30 +228,52 @@ class ImplT final : public Impl {
     return OPT_OK;
   }
   int init(const void* x, double* trace, int idx, PrecondArgs pa, int lm_gate) override {
-    k_init<E><<<p_->nblk, kBlock, 0, p_->stream>>>(
-        e_, (const T*)x, vec(p_->L.r), vec(p_->L.diag), vec(p_->L.delta), p_->part(P_LIN),
-        p_->nblk, p_->part(P_RZ0), p_->S(), trace, idx, pc(pa), lm_gate);
+    InitOut<T> o{rbuf(0), vec(p_->L.diag), vec(p_->L.minv), damp(pa), vec(p_->L.delta)};
+    k_init<E><<<p_->nblk, kBlock, 0, p_->stream>>>(e_, (const T*)x, o, p_->part(P_LIN), p_->nblk,
+                                                    p_->part(P_RZ0), p_->S(), trace, idx, pc(pa),
+                                                    lm_gate);
     HIP_LAUNCHED("k_init");
     return OPT_OK;
   }
   int pcg_a(int k, PrecondArgs pa, int lm_gate) override {
+    SplitBufs<T> b{rbuf(0), vec(p_->L.minv), damp(pa), pbuf(k + 1), pbuf(k), vec(p_->L.q)};
     k_pcg_a<E, 0><<<p_->nblk, kBlock, 0, p_->stream>>>(
-        e_, k, vec(p_->L.r), vec(p_->L.diag), pbuf(k + 1), pbuf(k), vec(p_->L.q),
-        p_->part((k & 1) ? P_RZ1 : P_RZ0), p_->nblk, p_->part(P_PQ), p_->S(), pc(pa), lm_gate);
+        e_, k, b, p_->part((k & 1) ? P_RZ1 : P_RZ0), p_->nblk, p_->part(P_PQ), p_->S(), lm_gate);
     HIP_LAUNCHED("k_pcg_a");
     return OPT_OK;
   }
   int pcg_b(int k, PrecondArgs pa, int lm_gate) override {
+    (void)pa;
     k_pcg_b<T, E::C><<<p_->nblk, kBlock, 0, p_->stream>>>(
-        e_.n, k, nullptr, vec(p_->L.delta), vec(p_->L.r), pbuf(k), vec(p_->L.q), vec(p_->L.diag),
-        p_->part(P_PQ), p_->nblk, p_->part((k & 1) ? P_RZ0 : P_RZ1), p_->S(), pc(pa), lm_gate);
+        e_.n, k, vec(p_->L.delta), rbuf(0), pbuf(k), vec(p_->L.q), vec(p_->L.minv),
+        p_->part(P_PQ), p_->nblk, p_->part((k & 1) ? P_RZ0 : P_RZ1), p_->S(), lm_gate);
     HIP_LAUNCHED("k_pcg_b");
     return OPT_OK;
   }
+  // iter = -1 is the priming launch; iteration i reads the partials of i-1.
+  int fused(int iter, PrecondArgs pa, int lm_gate) override {
+    constexpr int TW = FusedTile<T>::TW, TH = FusedTile<T>::TH;
+    const int tx = (e_.W + TW - 1) / TW, ty = (e_.H + TH - 1) / TH;
+    const int n_tiles = tx * ty;
+    const int grid = std::min(n_tiles, kFusedMaxGrid);
+    FusedBufs<T> b;
+    b.r_in = iter < 0 ? rbuf(0) : rbuf(iter + 1);
+    b.r_out = iter < 0 ? rbuf(1) : rbuf(iter);
+    b.p_in = pbuf(iter + 1);
+    b.p_out = iter < 0 ? pbuf(1) : pbuf(iter);
+    b.x = vec(p_->L.delta);
+    b.minv = vec(p_->L.minv);
+    b.damp = damp(pa);
+    b.part_in = p_->part((iter & 1) ? P_F0 : P_F1);
+    b.part_out = p_->part((iter & 1) ? P_F1 : P_F0);
+    b.n_part_in = grid;
+    k_fused<E, TW, TH><<<grid, kBlock, 0, p_->stream>>>(e_, b, p_->S(), iter, lm_gate, tx, n_tiles);
+    HIP_LAUNCHED("k_fused");
+    return OPT_OK;
+  }
   int apply_jtj(const void* pin, void* qout, PrecondArgs pa) override {
-    k_pcg_a<E, 1><<<p_->nblk, kBlock, 0, p_->stream>>>(
-        e_, 0, nullptr, vec(p_->L.diag), (const T*)pin, nullptr, (T*)qout, nullptr, 0, nullptr,
-        p_->S(), pc(pa), 0);
+    SplitBufs<T> b{nullptr, nullptr, damp(pa), (const T*)pin, nullptr, (T*)qout};
+    k_pcg_a<E, 1><<<p_->nblk, kBlock, 0, p_->stream>>>(e_, 0, b, nullptr, 0, nullptr, p_->S(), 0);
     HIP_LAUNCHED("k_pcg_a<apply>");
     return OPT_OK;
   }
@@ -285,6 +317,8 @@ std::unique_ptr<Impl> make_impl_t(opt_problem* p) {
       e.flags = (uint8_t*)p->at(p->L.flags);
       e.wf = (T)d.params[0];
       e.wr = (T)d.params[1];
+      e.wf_d = d.params[0];
+      e.wr_d = d.params[1];
       return std::unique_ptr<Impl>(new ImplT<ArapWarp<T>>(p, e));
     }
     default:
@@ -309,6 +343,8 @@ int check_params(const opt_solve_params* sp) {
     if (!(sp->lm_radius0 > 0) || !(sp->lm_radius_max > 0) || !(sp->lm_radius_min >= 0))
       return fail(OPT_EINVAL, "LM radii must be positive");
   }
+  if (sp->pcg_variant != OPT_PCG_FUSED && sp->pcg_variant != OPT_PCG_SPLIT)
+    return fail(OPT_EINVAL, "pcg_variant %d is not OPT_PCG_FUSED or OPT_PCG_SPLIT", sp->pcg_variant);
   if (!(sp->lm_diag_min >= 0) || !(sp->lm_diag_max >= sp->lm_diag_min))
     return fail(OPT_EINVAL, "LM diagonal clamp [%g, %g] is invalid", sp->lm_diag_min,
                 sp->lm_diag_max);
@@ -339,6 +375,20 @@ int record_event(opt_problem* p) {
     if (rc_ != OPT_OK) return rc_; \
   } while (0)
 
+// The L iterations of the inner solve after init, in the chosen form.
+int run_pcg(opt_problem* p, PrecondArgs pa, int lm, int L, int variant) {
+  if (variant == OPT_PCG_FUSED) {
+    if (L > 0) TRY(p->impl->fused(-1, pa, lm));
+    for (int i = 0; i < L; ++i) TRY(p->impl->fused(i, pa, lm));
+  } else {
+    for (int k = 0; k < L; ++k) {
+      TRY(p->impl->pcg_a(k, pa, lm));
+      TRY(p->impl->pcg_b(k, pa, lm));
+    }
+  }
+  return OPT_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -359,6 +409,7 @@ void opt_default_params(opt_solve_params* p) {
   p->lm_diag_min = 1e-6;
   p->lm_diag_max = 1e32;
   p->lm_min_rel_decrease = 1e-3;
+  p->pcg_variant = OPT_PCG_FUSED;
 }
 
 int opt_workspace_size(const opt_problem_desc* desc, size_t* bytes) {
@@ -422,10 +473,10 @@ int opt_linearize(opt_problem* p, const void* x, double* cost) {
 int opt_eval_jtf(opt_problem* p, void* b_out, void* diag_out) {
   if (!p) return fail(OPT_EINVAL, "problem is NULL");
   if (!p->last_x) return fail(OPT_EINVAL, "opt_linearize has not been called");
-  PrecondArgs pa{0.0, 0.0, 0.0, 1};
+  PrecondArgs pa{0.0, 0.0, 0.0, 1, false};
   TRY(p->impl->init(p->last_x, nullptr, 0, pa, 0));
   const size_t bytes = (size_t)p->sh.C * p->sh.n * p->sh.tsize;
-  if (b_out) HIP_TRY(hipMemcpyAsync(b_out, p->at(p->L.r), bytes, hipMemcpyDeviceToDevice, p->stream));
+  if (b_out) HIP_TRY(hipMemcpyAsync(b_out, p->at(p->L.r0), bytes, hipMemcpyDeviceToDevice, p->stream));
   if (diag_out)
     HIP_TRY(hipMemcpyAsync(diag_out, p->at(p->L.diag), bytes, hipMemcpyDeviceToDevice, p->stream));
   return OPT_OK;
@@ -436,11 +487,11 @@ int opt_apply_jtj(opt_problem* p, const void* pin, void* qout, double lambda,
   if (!p || !pin || !qout) return fail(OPT_EINVAL, "problem, p or q is NULL");
   if (!p->last_x) return fail(OPT_EINVAL, "opt_linearize has not been called");
   if (pin == qout) return fail(OPT_EINVAL, "p and q must not overlap");
-  PrecondArgs pa{0.0, 0.0, 0.0, 1};
+  PrecondArgs pa{0.0, 0.0, 0.0, 1, false};
   if (lambda != 0.0) {
     if (!sp) return fail(OPT_EINVAL, "params are needed when lambda != 0");
+    pa = PrecondArgs{lambda, sp->lm_diag_min, sp->lm_diag_max, 1, true};
     TRY(p->impl->init(p->last_x, nullptr, 0, pa, 0));
-    pa = PrecondArgs{lambda, sp->lm_diag_min, sp->lm_diag_max, 1};
   }
   return p->impl->apply_jtj(pin, qout, pa);
 }
@@ -449,14 +500,11 @@ int opt_pcg(opt_problem* p, const opt_solve_params* sp, double lambda, void* del
   if (!p) return fail(OPT_EINVAL, "problem is NULL");
   TRY(check_params(sp));
   if (!p->last_x) return fail(OPT_EINVAL, "opt_linearize has not been called");
-  PrecondArgs pa{lambda, sp->lm_diag_min, sp->lm_diag_max, sp->use_precond};
+  PrecondArgs pa{lambda, sp->lm_diag_min, sp->lm_diag_max, sp->use_precond, lambda != 0.0};
   k_setup<<<1, 64, 0, p->stream>>>(p->S(), lambda, 1.0, 0);
   HIP_LAUNCHED("k_setup");
   TRY(p->impl->init(p->last_x, nullptr, 0, pa, 0));
-  for (int k = 0; k < sp->pcg_iters; ++k) {
-    TRY(p->impl->pcg_a(k, pa, 0));
-    TRY(p->impl->pcg_b(k, pa, 0));
-  }
+  TRY(run_pcg(p, pa, 0, sp->pcg_iters, sp->pcg_variant));
   if (delta_out) {
     const size_t bytes = (size_t)p->sh.C * p->sh.n * p->sh.tsize;
     HIP_TRY(hipMemcpyAsync(delta_out, p->at(p->L.delta), bytes, hipMemcpyDeviceToDevice, p->stream));
@@ -506,16 +554,13 @@ int opt_solve(opt_problem* p, void* x, const opt_solve_params* sp, opt_solve_rep
   double* trace = p->trace();
   k_setup<<<1, 64, 0, p->stream>>>(p->S(), 0.0, sp->lm_radius0, lm);
   HIP_LAUNCHED("k_setup");
-  PrecondArgs pa{0.0, sp->lm_diag_min, sp->lm_diag_max, sp->use_precond};
+  PrecondArgs pa{0.0, sp->lm_diag_min, sp->lm_diag_max, sp->use_precond, lm != 0};
   LMConsts lc{sp->lm_radius_min, sp->lm_radius_max, sp->lm_min_rel_decrease};
   for (int k = 0; k < K; ++k) {
     TRY(p->impl->linearize(x, lm));
     TRY(p->impl->init(x, trace, k, pa, lm));
     if (p->profile) TRY(record_event(p));
-    for (int l = 0; l < Lp; ++l) {
-      TRY(p->impl->pcg_a(l, pa, lm));
-      TRY(p->impl->pcg_b(l, pa, lm));
-    }
+    TRY(run_pcg(p, pa, lm, Lp, sp->pcg_variant));
     if (p->profile) {
       TRY(record_event(p));
       p->prof_iters += Lp;

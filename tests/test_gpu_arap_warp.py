@@ -84,7 +84,8 @@ def test_dense_jtj_8x8():
 
 @pytest.mark.parametrize("W,H,mask", SHAPES)
 @pytest.mark.parametrize("precond", [True, False])
-def test_pcg(W, H, mask, precond):
+@pytest.mark.parametrize("variant", ["fused", "split"])
+def test_pcg(W, H, mask, precond, variant):
     d, x = _case(W, H, mask)
     e = o.make_energy(d)
     lin = o.Linearization(e, x)
@@ -98,52 +99,56 @@ def test_pcg(W, H, mask, precond):
         # oracle's own spread between J^T(Jp) and (J^T J)p bounds what can agree.
         ref2, _ = o.pcg(lambda v: A @ v, lin.jtf(), lin.minv(precond), L)
         tol = max(1e-9, 100 * relmax(ref2, ref))
-        got = to_np(prob.pcg(L, use_precond=precond))
+        got = to_np(prob.pcg(L, use_precond=precond, variant=variant))
         assert relmax(got, ref) < tol, (L, tol)
 
 
-def test_gn_config1_fp64():
+@pytest.mark.parametrize("variant", ["fused", "split"])
+def test_gn_config1_fp64(variant):
     """ARAP warp 64x64, FP64, GN 5 x 20, Jacobi: the parity configuration."""
     d = w.arap_warp(64, 64, seed=1)
     e = o.make_energy(d)
     xo, costs = o.gauss_newton(e, d["x0"], 5, 20)
     prob = make_problem(d, "fp64")
     xt = to_dev(prob, d["x0"])
-    rep = prob.solve(xt, method="gn", outer_iters=5, pcg_iters=20)
+    rep = prob.solve(xt, method="gn", outer_iters=5, pcg_iters=20, pcg_variant=variant)
     assert np.allclose(rep["cost_trace"], costs, rtol=1e-9, atol=0)
     assert relmax(to_np(xt) - d["x0"].ravel(), xo - d["x0"].ravel()) < 1e-8
 
 
-def test_gn_mixed_precision():
+@pytest.mark.parametrize("variant", ["fused", "split"])
+def test_gn_mixed_precision(variant):
     d = w.arap_warp(64, 64, seed=1)
     e = o.make_energy(d)
     xo, costs = o.gauss_newton(e, d["x0"], 5, 20)
     prob = make_problem(d, "mixed")
     xt = to_dev(prob, d["x0"])
-    rep = prob.solve(xt, method="gn", outer_iters=5, pcg_iters=20)
+    rep = prob.solve(xt, method="gn", outer_iters=5, pcg_iters=20, pcg_variant=variant)
     assert abs(rep["cost_final"] - costs[-1]) <= 1e-4 * costs[-1]
     assert relmax(to_np(xt) - d["x0"].ravel(), xo - d["x0"].ravel()) < 1e-3
 
 
-def test_lm_fp64():
+@pytest.mark.parametrize("variant", ["fused", "split"])
+def test_lm_fp64(variant):
     d = w.arap_warp(40, 33, seed=4, n_constraints=12, sigma=4.0, margin=3, mask="random")
     e = o.make_energy(d)
     xo, costs, acc = o.levenberg_marquardt(e, d["x0"], 6, 15)
     prob = make_problem(d, "fp64")
     xt = to_dev(prob, d["x0"])
-    rep = prob.solve(xt, method="lm", outer_iters=6, pcg_iters=15)
+    rep = prob.solve(xt, method="lm", outer_iters=6, pcg_iters=15, pcg_variant=variant)
     assert rep["steps_accepted"] == sum(acc)
     assert np.allclose(rep["cost_trace"][:len(costs)], costs, rtol=1e-9, atol=0)
     assert relmax(to_np(xt) - d["x0"].ravel(), xo - d["x0"].ravel()) < 1e-8
 
 
-def test_deterministic():
-    d = w.arap_warp(70, 65, seed=2, mask="hole")
+@pytest.mark.parametrize("variant", ["fused", "split"])
+def test_deterministic(variant):
+    d = w.arap_warp(150, 130, seed=2, mask="hole")
     outs = []
     for _ in range(2):
         prob = make_problem(d, "mixed")
         xt = to_dev(prob, d["x0"])
-        rep = prob.solve(xt, method="gn", outer_iters=3, pcg_iters=10)
+        rep = prob.solve(xt, method="gn", outer_iters=3, pcg_iters=10, pcg_variant=variant)
         outs.append((rep["cost_trace"], to_np(xt)))
     assert outs[0][0] == outs[1][0]
     assert np.array_equal(outs[0][1], outs[1][1])
@@ -157,6 +162,43 @@ def test_excluded_unknowns_unchanged():
     x = to_np(xt).reshape(3, -1)
     ex = (d["mask"] != 0).ravel()
     assert np.array_equal(x[:, ex], d["x0"].reshape(3, -1)[:, ex].astype(np.float32))
+
+
+def test_lm_damped_pcg_matches_oracle():
+    d, x = _case(70, 65, "hole")
+    e = o.make_energy(d)
+    lin = o.Linearization(e, x)
+    prob = make_problem(d, "fp64")
+    xt = to_dev(prob, x)
+    prob.linearize(xt)
+    lam = 0.3
+    D = lin.damping()
+    ref, _ = o.pcg(lambda v: lin.apply(v, lam, D), lin.jtf(), lin.minv(True, lam, D), 12)
+    for variant in ("fused", "split"):
+        got = to_np(prob.pcg(12, lam=lam, variant=variant))
+        assert relmax(got, ref) < 1e-9, variant
+
+
+def test_full_size_operators_mixed():
+    """1024 x 1024 (the benchmark size): J^T F, diag and J^T J p in FP32 against
+    the FP64 oracle, and one GN iteration of 10 PCG steps."""
+    d = w.arap_warp(1024, 1024, seed=2)
+    e = o.make_energy(d)
+    rng = np.random.default_rng(0)
+    x = d["x0"] + np.concatenate([rng.normal(0, 0.3, (2, 1024, 1024)), rng.normal(0, 0.05, (1, 1024, 1024))])
+    lin = o.Linearization(e, x)
+    prob = make_problem(d, "mixed")
+    xt = to_dev(prob, x)
+    assert abs(prob.linearize(xt) - lin.E) <= 1e-6 * lin.E
+    b, dg = prob.eval_jtf()
+    assert relmax(to_np(b), lin.jtf()) < 1e-5
+    assert relmax(to_np(dg), lin.diag) < 1e-6
+    p = rng.normal(size=lin.diag.size)
+    assert relmax(to_np(prob.apply_jtj(to_dev(prob, p))), lin.apply(p)) < 1e-5
+    xo, costs = o.gauss_newton(e, d["x0"], 1, 10)
+    x0t = to_dev(prob, d["x0"])
+    rep = prob.solve(x0t, method="gn", outer_iters=1, pcg_iters=10)
+    assert abs(rep["cost_final"] - costs[-1]) <= 1e-4 * costs[-1]
 
 
 def test_zero_iterations_and_tiny_grid():
