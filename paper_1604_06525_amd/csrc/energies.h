@@ -1,3 +1,7 @@
 // All hand-written energies.
 #pragma once
+#include "energy_arap_mesh.h"
 #include "energy_arap_warp.h"
+#include "energy_flow.h"
+#include "energy_poisson.h"
+#include "energy_sfs.h"

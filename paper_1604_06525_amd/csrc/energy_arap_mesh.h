@@ -1,0 +1,269 @@
+// As-rigid-as-possible mesh deformation on a graph (Fig. 25, Appendix A.1.2).
+//
+// Unknowns per vertex: offset O (3 planes) and Euler angles a (3 planes) with
+// R(a) = Rz(a_z) Ry(a_y) Rx(a_x).  Data: rest positions U (3 planes), targets C
+// (3 planes; component k is used when C_k >= -999999.9).
+// Residuals:
+//   fit   r = w_fit (O_v - C_v), per valid component
+//   edge  for every listed edge {v0, v1}, both orientations (3 rows each):
+//         r(v->u) = w_reg [ (O_v - O_u) - R(a_v)(U_v - U_u) ]
+//
+// The edge list is turned into a per-vertex incidence list (CSR, neighbours in
+// edge-list order) when the problem is created, so each vertex gathers the terms
+// of its own edges: no atomics, and every sum has a fixed order.  The paper
+// scatters per edge with atomic adds instead (Sec. 4.1, graph residuals).
+// With d = U_v - U_u and G_v(d) = [dR/da_x d, dR/da_y d, dR/da_z d] at a_v:
+//   own   J p = w_reg [ (P^O_v - P^O_u) - G_v(d) P^a_v ]
+//   back  J p = w_reg [ (P^O_u - P^O_v) + G_u(d) P^a_u ]
+//   (J^T J P)^O_v += w_reg (own) - w_reg (back),  (J^T J P)^a_v += -w_reg G_v(d)^T (own)
+// Per-vertex state: cos and sin of the three angles at the linearisation point.
+#pragma once
+#include "common.h"
+
+namespace optmi {
+
+template <typename R>
+struct EulerTrig {
+  R cx, sx, cy, sy, cz, sz;
+};
+
+// R d and G(d) (columns: d/da_x, d/da_y, d/da_z of R d) for R = Rz Ry Rx.
+template <typename R>
+__device__ __forceinline__ void euler_rot_grad(const EulerTrig<R>& t, const R* d, R* Rd, R (*G)[3]) {
+  // x-rotation and its derivative
+  const R v1[3] = {d[0], t.cx * d[1] - t.sx * d[2], t.sx * d[1] + t.cx * d[2]};
+  const R v1x[3] = {R(0), -t.sx * d[1] - t.cx * d[2], t.cx * d[1] - t.sx * d[2]};
+  auto ry = [&](const R* v, R* o) {
+    o[0] = t.cy * v[0] + t.sy * v[2];
+    o[1] = v[1];
+    o[2] = -t.sy * v[0] + t.cy * v[2];
+  };
+  auto ry_d = [&](const R* v, R* o) {
+    o[0] = -t.sy * v[0] + t.cy * v[2];
+    o[1] = R(0);
+    o[2] = -t.cy * v[0] - t.sy * v[2];
+  };
+  auto rz = [&](const R* v, R* o) {
+    o[0] = t.cz * v[0] - t.sz * v[1];
+    o[1] = t.sz * v[0] + t.cz * v[1];
+    o[2] = v[2];
+  };
+  auto rz_d = [&](const R* v, R* o) {
+    o[0] = -t.sz * v[0] - t.cz * v[1];
+    o[1] = t.cz * v[0] - t.sz * v[1];
+    o[2] = R(0);
+  };
+  R v2[3], v2x[3], v2y[3];
+  ry(v1, v2);
+  ry(v1x, v2x);
+  ry_d(v1, v2y);
+  rz(v2, Rd);
+  rz(v2x, G[0]);
+  rz(v2y, G[1]);
+  rz_d(v2, G[2]);
+}
+
+template <typename T>
+struct ArapMesh {
+  using Real = T;
+  static constexpr bool kGraph = true;
+  static constexpr int C = 6;
+  static constexpr int kStatePlanes = 6;  // cos/sin of a_x, a_y, a_z
+  static constexpr int kOwnState = 6;
+  static constexpr int kRadius = 1;
+  enum : uint32_t { ACTIVE = 1, INGRID = 2, FIT0 = 4 };  // FIT0 << k: component k
+
+  int n;                         // vertices
+  const int* __restrict__ rp;    // [n+1] CSR offsets
+  const int* __restrict__ nb;    // [2E] neighbour ids
+  const T* __restrict__ U;       // [3][n]
+  const T* __restrict__ Ct;      // [3][n]
+  T* __restrict__ trig;          // [6][n]
+  uint8_t* __restrict__ flags;
+  T wf, wr;
+  double wf_d, wr_d;
+
+  __device__ __forceinline__ const T* state_plane(int k) const { return trig + (size_t)k * n; }
+
+  __device__ __forceinline__ EulerTrig<T> trig_at(int v) const {
+    EulerTrig<T> t;
+    t.cx = trig[v];
+    t.sx = trig[n + v];
+    t.cy = trig[2 * (size_t)n + v];
+    t.sy = trig[3 * (size_t)n + v];
+    t.cz = trig[4 * (size_t)n + v];
+    t.sz = trig[5 * (size_t)n + v];
+    return t;
+  }
+  template <class XA>
+  __device__ __forceinline__ EulerTrig<double> trig_d(XA X, int v) const {
+    EulerTrig<double> t;
+    sincos_t((double)X(3, v), &t.sx, &t.cx);
+    sincos_t((double)X(4, v), &t.sy, &t.cy);
+    sincos_t((double)X(5, v), &t.sz, &t.cz);
+    return t;
+  }
+
+  template <class XA>
+  __device__ __forceinline__ double cost(XA X, int v) const {
+    double e = 0.0;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      const double cv = Ct[(size_t)c * n + v];
+      if (cv >= -999999.9) {
+        const double f = wf_d * (X(c, v) - cv);
+        e += f * f;
+      }
+    }
+    const EulerTrig<double> t = trig_d(X, v);
+    for (int k = rp[v]; k < rp[v + 1]; ++k) {
+      const int u = nb[k];
+      double d[3], Rd[3], G[3][3];
+#pragma unroll
+      for (int c = 0; c < 3; ++c) d[c] = (double)U[(size_t)c * n + v] - (double)U[(size_t)c * n + u];
+      euler_rot_grad(t, d, Rd, G);
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        const double f = wr_d * ((X(c, v) - X(c, u)) - Rd[c]);
+        e += f * f;
+      }
+    }
+    return e;
+  }
+
+  __device__ __forceinline__ void linearize(const T* __restrict__ x, int v) const {
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      T s, c;
+      sincos_t(x[(size_t)(3 + k) * n + v], &s, &c);
+      trig[(size_t)(2 * k) * n + v] = c;
+      trig[(size_t)(2 * k + 1) * n + v] = s;
+    }
+    uint32_t f = ACTIVE | INGRID;
+#pragma unroll
+    for (int c = 0; c < 3; ++c)
+      if (Ct[(size_t)c * n + v] >= T(-999999.9)) f |= FIT0 << c;
+    flags[v] = (uint8_t)f;
+  }
+
+  // b = -J^T F and diag(J^T J) at vertex v; X(c, site) reads the unknowns.
+  template <class XA>
+  __device__ __forceinline__ void jtf_diag_site(XA X, int v, T* b, T* dg) const {
+    const EulerTrig<T> tv = trig_at(v);
+    T bO[3] = {}, ba[3] = {}, dO = 0, da[3] = {};
+    const T wr2 = wr * wr;
+    for (int k = rp[v]; k < rp[v + 1]; ++k) {
+      const int u = nb[k];
+      const EulerTrig<T> tu = trig_at(u);
+      T d[3], Rv[3], Gv[3][3], Ru[3], Gu[3][3];
+#pragma unroll
+      for (int c = 0; c < 3; ++c) d[c] = U[(size_t)c * n + v] - U[(size_t)c * n + u];
+      euler_rot_grad(tv, d, Rv, Gv);
+      euler_rot_grad(tu, d, Ru, Gu);
+      T f1[3];
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        const T e = X(c, v) - X(c, u);
+        f1[c] = e - Rv[c];
+        const T f2 = -e + Ru[c];
+        bO[c] += wr2 * (f2 - f1[c]);
+      }
+#pragma unroll
+      for (int q = 0; q < 3; ++q) {
+        ba[q] += wr2 * (Gv[q][0] * f1[0] + Gv[q][1] * f1[1] + Gv[q][2] * f1[2]);
+        da[q] += wr2 * (Gv[q][0] * Gv[q][0] + Gv[q][1] * Gv[q][1] + Gv[q][2] * Gv[q][2]);
+      }
+      dO += T(2) * wr2;
+    }
+    const uint32_t fl = flags[v];
+    const T wf2 = wf * wf;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      T dc = dO;
+      if (fl & (FIT0 << c)) {
+        bO[c] -= wf2 * (X(c, v) - Ct[(size_t)c * n + v]);
+        dc += wf2;
+      }
+      b[c] = bO[c];
+      dg[c] = dc;
+      b[3 + c] = ba[c];
+      dg[3 + c] = da[c];
+    }
+  }
+
+  // g = J^T J P at vertex v; P(c, site) reads the direction.
+  template <class PA>
+  __device__ __forceinline__ void apply_site(PA P, int v, T* g) const {
+    const EulerTrig<T> tv = trig_at(v);
+    T pO[3], pa[3];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      pO[c] = P(c, v);
+      pa[c] = P(3 + c, v);
+    }
+    T gO[3] = {}, ga[3] = {};
+    const T wr2 = wr * wr;
+    for (int k = rp[v]; k < rp[v + 1]; ++k) {
+      const int u = nb[k];
+      const EulerTrig<T> tu = trig_at(u);
+      T d[3], Rv[3], Gv[3][3], Ru[3], Gu[3][3];
+#pragma unroll
+      for (int c = 0; c < 3; ++c) d[c] = U[(size_t)c * n + v] - U[(size_t)c * n + u];
+      euler_rot_grad(tv, d, Rv, Gv);
+      euler_rot_grad(tu, d, Ru, Gu);
+      T qa[3];
+#pragma unroll
+      for (int c = 0; c < 3; ++c) qa[c] = P(3 + c, u);
+      T j1[3];
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        const T e = pO[c] - P(c, u);
+        j1[c] = e - (Gv[0][c] * pa[0] + Gv[1][c] * pa[1] + Gv[2][c] * pa[2]);
+        const T j2 = -e + (Gu[0][c] * qa[0] + Gu[1][c] * qa[1] + Gu[2][c] * qa[2]);
+        gO[c] += wr2 * (j1[c] - j2);
+      }
+#pragma unroll
+      for (int q = 0; q < 3; ++q)
+        ga[q] -= wr2 * (Gv[q][0] * j1[0] + Gv[q][1] * j1[1] + Gv[q][2] * j1[2]);
+    }
+    const uint32_t fl = flags[v];
+    const T wf2 = wf * wf;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      g[c] = (fl & (FIT0 << c)) ? gO[c] + wf2 * pO[c] : gO[c];
+      g[3 + c] = ga[c];
+    }
+  }
+
+  template <class XA, class DA>
+  __device__ __forceinline__ double model(XA X, DA Dl, int v) const {
+    double acc = 0.0;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      const double cv = Ct[(size_t)c * n + v];
+      if (cv >= -999999.9) {
+        const double f = wf_d * (X(c, v) - cv);
+        const double jd = wf_d * Dl(c, v);
+        acc += jd * (2.0 * f + jd);
+      }
+    }
+    const EulerTrig<double> t = trig_d(X, v);
+    for (int k = rp[v]; k < rp[v + 1]; ++k) {
+      const int u = nb[k];
+      double d[3], Rd[3], G[3][3];
+#pragma unroll
+      for (int c = 0; c < 3; ++c) d[c] = (double)U[(size_t)c * n + v] - (double)U[(size_t)c * n + u];
+      euler_rot_grad(t, d, Rd, G);
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        const double f = wr_d * ((X(c, v) - X(c, u)) - Rd[c]);
+        const double jd = wr_d * ((Dl(c, v) - Dl(c, u)) -
+                                  (G[0][c] * Dl(3, v) + G[1][c] * Dl(4, v) + G[2][c] * Dl(5, v)));
+        acc += jd * (2.0 * f + jd);
+      }
+    }
+    return acc;
+  }
+};
+
+}  // namespace optmi

@@ -30,6 +30,7 @@ namespace optmi {
 template <typename T>
 struct ArapWarp {
   using Real = T;
+  static constexpr bool kGraph = false;
   static constexpr int C = 3;             // unknown channels
   static constexpr int kStatePlanes = 4;  // cos t, sin t, U_x, U_y
   static constexpr int kOwnState = 2;     // planes the library stores (cos, sin)
@@ -103,7 +104,7 @@ struct ArapWarp {
   // b = -J^T F and diag(J^T J) at an active site s (global index) at the
   // linearisation point; X views the unknowns.
   template <class XV, class SV, class FV>
-  __device__ __forceinline__ void jtf_diag(XV X, SV S, FV F, int s, T* b, T* d) const {
+  __device__ __forceinline__ void jtf_diag(XV X, SV S, FV F, int s, int, int, T* b, T* d) const {
     const T c = S(0, 0, 0), sn = S(1, 0, 0), Ux = S(2, 0, 0), Uy = S(3, 0, 0);
     const T Ox = X(0, 0, 0), Oy = X(1, 0, 0);
     T bx = 0, by = 0, bt = 0, dO = 0, dt = 0;
@@ -137,7 +138,7 @@ struct ArapWarp {
 
   // g = J^T J P at an active centre site.
   template <class PV, class SV, class FV>
-  __device__ __forceinline__ void apply(PV P, SV S, FV F, T* g) const {
+  __device__ __forceinline__ void apply(PV P, SV S, FV F, int, int, T* g) const {
     const T c = S(0, 0, 0), sn = S(1, 0, 0), Ux = S(2, 0, 0), Uy = S(3, 0, 0);
     const T px = P(0, 0, 0), py = P(1, 0, 0), pt = P(2, 0, 0);
     T gx = 0, gy = 0, gt = 0;

@@ -29,6 +29,8 @@
 // If the curvature p.Ap is not positive the solve stops (DevScalars::stopped):
 // every later iteration kernel returns at once and d keeps its value.
 #pragma once
+#include <type_traits>
+
 #include "common.h"
 
 namespace optmi {
@@ -38,15 +40,53 @@ namespace optmi {
 #define OPT_SITE_LOOP(s, n) \
   for (int s = blockIdx.x * kBlock + threadIdx.x; s < (n); s += gridDim.x * kBlock)
 
-// Views over global memory centred at site s = j*W + i of a W x H grid.
+// Views over global memory centred at site s = (vi_, vj_) of a W x H grid; every
+// read off the grid returns 0 (flags 0: not on the grid).
 #define OPT_GRID_VIEWS(e, s)                                                          \
   const int vi_ = (s) % (e).W, vj_ = (s) / (e).W;                                     \
-  auto Fg = [&](int di, int dj) -> uint32_t {                                         \
+  auto inb_ = [&](int di, int dj) {                                                   \
     const int ii = vi_ + di, jj = vj_ + dj;                                           \
-    return (ii >= 0 && ii < (e).W && jj >= 0 && jj < (e).H) ? (e).flags[(s) + dj * (e).W + di] \
-                                                            : 0u;                     \
+    return ii >= 0 && ii < (e).W && jj >= 0 && jj < (e).H;                            \
   };                                                                                  \
-  auto Sg = [&](int k, int di, int dj) { return (e).state_plane(k)[(s) + dj * (e).W + di]; };
+  auto Fg = [&](int di, int dj) -> uint32_t {                                         \
+    return inb_(di, dj) ? (uint32_t)(e).flags[(s) + dj * (e).W + di] : 0u;            \
+  };                                                                                  \
+  auto Sg = [&](int k, int di, int dj) -> typename E::Real {                          \
+    return inb_(di, dj) ? (e).state_plane(k)[(s) + dj * (e).W + di] : typename E::Real(0); \
+  };
+
+// b = -J^T F and diag(J^T J) at an active site s at the linearisation point x.
+template <class E>
+__device__ __forceinline__ void site_jtf_diag(const E& e, const typename E::Real* __restrict__ x,
+                                              int s, typename E::Real* b, typename E::Real* d) {
+  using T = typename E::Real;
+  const int n = e.n;
+  if constexpr (E::kGraph) {
+    auto X = [&](int c, int v) -> T { return x[(size_t)c * n + v]; };
+    e.jtf_diag_site(X, s, b, d);
+  } else {
+    OPT_GRID_VIEWS(e, s)
+    auto Xg = [&](int c, int di, int dj) -> T {
+      return inb_(di, dj) ? x[(size_t)c * n + s + dj * e.W + di] : T(0);
+    };
+    e.jtf_diag(Xg, Sg, Fg, s, vi_, vj_, b, d);
+  }
+}
+
+// g = J^T J P at an active site s; P(c, site) reads the direction.
+template <class E, class PA>
+__device__ __forceinline__ void site_apply(const E& e, int s, PA P, typename E::Real* g) {
+  using T = typename E::Real;
+  if constexpr (E::kGraph) {
+    e.apply_site(P, s, g);
+  } else {
+    OPT_GRID_VIEWS(e, s)
+    auto Pv = [&](int c, int di, int dj) -> T {
+      return inb_(di, dj) ? P(c, s + dj * e.W + di) : T(0);
+    };
+    e.apply(Pv, Sg, Fg, vi_, vj_, g);
+  }
+}
 
 // ---------------------------------------------------------------- linearize
 template <class E>
@@ -105,10 +145,8 @@ k_init(E e, const typename E::Real* __restrict__ x, InitOut<typename E::Real> o,
   double rz = 0.0;
   OPT_SITE_LOOP(s, n) {
     T b[C], d[C];
-    OPT_GRID_VIEWS(e, s)
-    if (Fg(0, 0) & E::ACTIVE) {
-      auto Xg = [&](int c, int di, int dj) { return x[(size_t)c * n + s + dj * e.W + di]; };
-      e.jtf_diag(Xg, Sg, Fg, s, b, d);
+    if (e.flags[s] & E::ACTIVE) {
+      site_jtf_diag(e, x, s, b, d);
     } else {
 #pragma unroll
       for (int c = 0; c < C; ++c) { b[c] = T(0); d[c] = T(0); }
@@ -156,23 +194,22 @@ k_pcg_a(E e, int k, SplitBufs<typename E::Real> b, const double* __restrict__ rz
     if (is_block_leader()) S->rz[k & 1] = rz;
   }
   double pq = 0.0;
+  auto Pg = [&](int c, int site) -> T {
+    const size_t o = (size_t)c * n + site;
+    if (MODE == 1) return b.pold[o];
+    const T z = b.minv[o] * b.r[o];
+    return k == 0 ? z : fma(beta, b.pold[o], z);
+  };
   OPT_SITE_LOOP(s, n) {
-    OPT_GRID_VIEWS(e, s)
-    auto Pg = [&](int c, int di, int dj) -> T {
-      const size_t o = (size_t)c * n + s + dj * e.W + di;
-      if (MODE == 1) return b.pold[o];
-      const T z = b.minv[o] * b.r[o];
-      return k == 0 ? z : fma(beta, b.pold[o], z);
-    };
     T g[C];
-    const bool act = Fg(0, 0) & E::ACTIVE;
-    if (act) e.apply(Pg, Sg, Fg, g);
+    const bool act = e.flags[s] & E::ACTIVE;
+    if (act) site_apply(e, s, Pg, g);
 #pragma unroll
     for (int c = 0; c < C; ++c) {
       const size_t o = (size_t)c * n + s;
       T pv = T(0), qv = T(0);
       if (act) {
-        pv = Pg(c, 0, 0);
+        pv = Pg(c, s);
         qv = g[c];
         if (b.damp) qv += b.damp[o] * pv;
       }
@@ -226,37 +263,101 @@ struct FusedBufs {
   int n_part_in;
 };
 
-// Tile geometry: TW x TH sites per tile, halo 2*radius, one tile at a time per
-// block; blocks stride over the tiles in an XCD-aware order.
-template <class E, int TW, int TH>
-struct FusedGeom {
-  static constexpr int HALO = 2 * E::kRadius;
-  static constexpr int RW = TW + 2 * HALO, RH = TH + 2 * HALO, N = RW * RH;
-  static constexpr int R1 = HALO - E::kRadius;              // ring-1 offset in the region
-  static constexpr int R1W = TW + 2 * E::kRadius, R1H = TH + 2 * E::kRadius;
+// Value that lane l-1 (from_left) or l+1 (from_right) of the wave holds; 0 past
+// the ends of the wave.  DPP wave shifts, so no LDS traffic.
+__device__ __forceinline__ uint32_t dpp_from_left(uint32_t v) {
+  return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x138, 0xF, 0xF, true);  // wave_shr:1
+}
+__device__ __forceinline__ uint32_t dpp_from_right(uint32_t v) {
+  return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x130, 0xF, 0xF, true);  // wave_shl:1
+}
+__device__ __forceinline__ float from_left(float v) {
+  return __uint_as_float(dpp_from_left(__float_as_uint(v)));
+}
+__device__ __forceinline__ float from_right(float v) {
+  return __uint_as_float(dpp_from_right(__float_as_uint(v)));
+}
+__device__ __forceinline__ double from_left(double v) {
+  const uint64_t u = (uint64_t)__double_as_longlong(v);
+  const uint64_t lo = dpp_from_left((uint32_t)u), hi = dpp_from_left((uint32_t)(u >> 32));
+  return __longlong_as_double((long long)(lo | (hi << 32)));
+}
+__device__ __forceinline__ double from_right(double v) {
+  const uint64_t u = (uint64_t)__double_as_longlong(v);
+  const uint64_t lo = dpp_from_right((uint32_t)u), hi = dpp_from_right((uint32_t)(u >> 32));
+  return __longlong_as_double((long long)(lo | (hi << 32)));
+}
+__device__ __forceinline__ uint32_t from_left(uint32_t v) { return dpp_from_left(v); }
+__device__ __forceinline__ uint32_t from_right(uint32_t v) { return dpp_from_right(v); }
+
+// Geometry of the fused kernel on a grid: one wave per strip of 64 columns
+// (60 produced, 2 halo columns on each side) and kStripRows-or-fewer rows.
+constexpr int kStripCols = 60;
+
+// One grid row as one lane sees it (its column), for the streaming kernel.
+template <class E>
+struct StreamRow {
+  using T = typename E::Real;
+  static constexpr int C = E::C, NS = E::kStatePlanes > 0 ? E::kStatePlanes : 1;
+  T r[C];    // r_i, later r_{i+1}
+  T m[C];    // M^-1, later u_{i+1} = M^-1 r_{i+1}
+  T p[C];    // p_i
+  T x[C];    // d (only on produced rows)
+  T dmp[C];  // LM damping (only when damped)
+  T st[NS];
+  uint32_t f;
 };
 
-// The k-th tile of this block.  Blocks are spread over the 8 XCDs round-robin;
-// each XCD takes one contiguous run of tiles so neighbouring tiles share its L2.
-__device__ __forceinline__ int tile_of(int k, int n_tiles) {
-  const int G = gridDim.x;
-  if (G % 8 != 0) return blockIdx.x + k * G;
-  const int per = G / 8, xcd = blockIdx.x % 8, slot = blockIdx.x / 8;
-  const int chunk = (n_tiles + 7) / 8;
-  const int t = xcd * chunk + slot + k * per;
-  return t < min((xcd + 1) * chunk, n_tiles) ? t : n_tiles;
+// Apply the energy's operator at the centre row R with rows U (above) and D
+// (below); V selects the vector (p or u).  Horizontal neighbours come from the
+// adjacent lanes.
+template <class E, class VSel>
+__device__ __forceinline__ void stream_apply(const E& e, const StreamRow<E>& U,
+                                             const StreamRow<E>& R, const StreamRow<E>& D,
+                                             VSel V, int col, int row, typename E::Real* g) {
+  using T = typename E::Real;
+  constexpr int C = E::C, NS = StreamRow<E>::NS;
+  T vl[C], vr[C], sl[NS], sr[NS];
+#pragma unroll
+  for (int c = 0; c < C; ++c) {
+    vl[c] = from_left(V(R, c));
+    vr[c] = from_right(V(R, c));
+  }
+#pragma unroll
+  for (int q = 0; q < NS; ++q) {
+    sl[q] = from_left(R.st[q]);
+    sr[q] = from_right(R.st[q]);
+  }
+  const uint32_t fl = from_left(R.f), fr = from_right(R.f);
+  auto Pv = [&](int c, int di, int dj) -> T {
+    return dj < 0 ? V(U, c) : dj > 0 ? V(D, c) : di < 0 ? vl[c] : di > 0 ? vr[c] : V(R, c);
+  };
+  auto Sv = [&](int q, int di, int dj) -> T {
+    return dj < 0 ? U.st[q] : dj > 0 ? D.st[q] : di < 0 ? sl[q] : di > 0 ? sr[q] : R.st[q];
+  };
+  auto Fv = [&](int di, int dj) -> uint32_t {
+    return dj < 0 ? U.f : dj > 0 ? D.f : di < 0 ? fl : di > 0 ? fr : R.f;
+  };
+  e.apply(Pv, Sv, Fv, col, row, g);
 }
 
-template <class E, int TW, int TH>
-__global__ void __launch_bounds__(kBlock, 2)
-k_fused(E e, FusedBufs<typename E::Real> b, DevScalars* S, int iter, int lm_gate, int tiles_x,
-        int n_tiles) {
-  using T = typename E::Real;
-  using G = FusedGeom<E, TW, TH>;
-  constexpr int C = E::C, NS = E::kStatePlanes, N = G::N, RW = G::RW;
-  __shared__ T sP[C * N], sR[C * N], sM[C * N], sS[NS * N];
-  __shared__ uint8_t sF[N];
+// The k-th unit of work of this block, XCD-aware: blocks go to the 8 XCDs
+// round-robin, and each XCD takes one contiguous run of units so neighbouring
+// strips share its L2.
+__device__ __forceinline__ int unit_of_block(int n_units) {
+  const int G = gridDim.x;
+  if (G % 8 != 0) return blockIdx.x;
+  const int per = G / 8;
+  return (blockIdx.x % 8) * per + blockIdx.x / 8;
+}
 
+template <class E>
+__global__ void __launch_bounds__(kBlock)
+k_fused(E e, FusedBufs<typename E::Real> b, DevScalars* S, int iter, int lm_gate, int n_sx,
+        int n_sy, int Hs) {
+  using T = typename E::Real;
+  using Row = StreamRow<E>;
+  constexpr int C = E::C, NS = E::kStatePlanes;
   if (S->stopped || (lm_gate && S->done)) return;
   double alpha = 0.0, beta = 0.0;
   if (iter >= 0) {
@@ -278,102 +379,117 @@ k_fused(E e, FusedBufs<typename E::Real> b, DevScalars* S, int iter, int lm_gate
     }
   }
   const T aT = (T)alpha, bT = (T)beta;
+  const bool read_pold = iter > 0, write_out = iter >= 0, damped = b.damp != nullptr;
   const int W = e.W, H = e.H, n = e.n;
+  const int lane = threadIdx.x & 63;
+  const int strip = unit_of_block(gridDim.x) * kWaves + (threadIdx.x >> 6);
   double g_acc = 0.0, d_acc = 0.0;
 
-  for (int k = 0;; ++k) {
-    const int tile = tile_of(k, n_tiles);
-    if (tile >= n_tiles) break;
-    const int tx0 = (tile % tiles_x) * TW - G::HALO, ty0 = (tile / tiles_x) * TH - G::HALO;
-    // phase 1: stage the region; p_i = M^-1 r_i + beta p_{i-1}
-    for (int t = threadIdx.x; t < N; t += kBlock) {
-      const int i = tx0 + t % RW, j = ty0 + t / RW;
-      if (i >= 0 && i < W && j >= 0 && j < H) {
-        const int s = j * W + i;
-#pragma unroll
-        for (int c = 0; c < C; ++c) {
-          const size_t o = (size_t)c * n + s;
-          const T r = b.r_in[o], m = b.minv[o];
-          const T u = m * r;
-          sP[c * N + t] = iter > 0 ? fma(bT, b.p_in[o], u) : u;
-          sR[c * N + t] = r;
-          sM[c * N + t] = m;
-        }
-#pragma unroll
-        for (int q = 0; q < NS; ++q) sS[q * N + t] = e.state_plane(q)[s];
-        sF[t] = e.flags[s];
-      } else {
-#pragma unroll
-        for (int c = 0; c < C; ++c) {
-          sP[c * N + t] = T(0);
-          sR[c * N + t] = T(0);
-          sM[c * N + t] = T(0);
-        }
-#pragma unroll
-        for (int q = 0; q < NS; ++q) sS[q * N + t] = T(0);
-        sF[t] = 0;
-      }
-    }
-    __syncthreads();
-    // phase 2: s_i = A p_i and r_{i+1} = r_i - alpha s_i on the tile plus one radius
-    for (int t = threadIdx.x; t < G::R1W * G::R1H; t += kBlock) {
-      const int rx = G::R1 + t % G::R1W, ry = G::R1 + t / G::R1W;
-      const int idx = ry * RW + rx;
-      if (!(sF[idx] & E::ACTIVE)) continue;
-      auto Pv = [&](int c, int di, int dj) { return sP[c * N + idx + dj * RW + di]; };
-      auto Sv = [&](int q, int di, int dj) { return sS[q * N + idx + dj * RW + di]; };
-      auto Fv = [&](int di, int dj) -> uint32_t { return sF[idx + dj * RW + di]; };
-      T g[C];
-      e.apply(Pv, Sv, Fv, g);
-      if (b.damp) {
-        const int s = (ty0 + ry) * W + (tx0 + rx);
-#pragma unroll
-        for (int c = 0; c < C; ++c) g[c] += b.damp[(size_t)c * n + s] * sP[c * N + idx];
-      }
-#pragma unroll
-      for (int c = 0; c < C; ++c) sR[c * N + idx] = fma(-aT, g[c], sR[c * N + idx]);
-    }
-    __syncthreads();
-    // phase 3: w = A u_{i+1} on the tile; partials; d += alpha p_i; store r, p
-    for (int t = threadIdx.x; t < TW * TH; t += kBlock) {
-      const int rx = G::HALO + t % TW, ry = G::HALO + t / TW;
-      const int i = tx0 + rx, j = ty0 + ry;
-      if (i >= W || j >= H) continue;
-      const int idx = ry * RW + rx, s = j * W + i;
-      const bool act = sF[idx] & E::ACTIVE;
-      if (act) {
-        auto Uv = [&](int c, int di, int dj) {
-          const int o = c * N + idx + dj * RW + di;
-          return sM[o] * sR[o];
-        };
-        auto Sv = [&](int q, int di, int dj) { return sS[q * N + idx + dj * RW + di]; };
-        auto Fv = [&](int di, int dj) -> uint32_t { return sF[idx + dj * RW + di]; };
-        T w[C];
-        e.apply(Uv, Sv, Fv, w);
-#pragma unroll
-        for (int c = 0; c < C; ++c) {
-          const T uo = Uv(c, 0, 0);
-          if (b.damp) w[c] += b.damp[(size_t)c * n + s] * uo;
-          g_acc += (double)sR[c * N + idx] * (double)uo;
-          d_acc += (double)w[c] * (double)uo;
-        }
-      }
+  if (strip < n_sx * n_sy) {
+    const int sx = strip / n_sy, sy = strip % n_sy;
+    const int col = sx * kStripCols - 2 + lane;
+    const int y0 = sy * Hs, y1 = min(y0 + Hs, H);
+    const bool colin = col >= 0 && col < W;
+    const bool out_lane = colin && lane >= 2 && lane < 2 + kStripCols;
+    const int K = (y1 - y0) + 4;  // rows y0-2 .. y1+1
+    Row ring[4];
+    // Raw loads of the rows 1..4 steps ahead: row y0-2+k is issued at step k-4
+    // and finished at step k, so its memory latency overlaps four steps of work.
+    Row pre[4];
+
+    auto issue = [&](Row& R, int y) {
+      const bool in = colin && y >= 0 && y < H && y <= y1 + 1;
+      const int s = in ? y * W + col : 0;
+      const bool prod = in && y >= y0 && y < y1;
 #pragma unroll
       for (int c = 0; c < C; ++c) {
         const size_t o = (size_t)c * n + s;
-        const T pv = act ? sP[c * N + idx] : T(0);
-        if (iter >= 0 && act) b.x[o] = fma(aT, pv, b.x[o]);
-        b.r_out[o] = sR[c * N + idx];
-        b.p_out[o] = pv;
+        R.r[c] = in ? b.r_in[o] : T(0);
+        R.m[c] = in ? b.minv[o] : T(0);
+        R.p[c] = (in && read_pold) ? b.p_in[o] : T(0);
+        R.x[c] = (prod && write_out) ? b.x[o] : T(0);
+        R.dmp[c] = (in && damped) ? b.damp[o] : T(0);
       }
+#pragma unroll
+      for (int q = 0; q < NS; ++q) R.st[q] = in ? e.state_plane(q)[s] : T(0);
+      R.f = in ? (uint32_t)e.flags[s] : 0u;
+    };
+    // p_i = M^-1 r_i + beta p_{i-1} (the staged p holds p_{i-1})
+    auto finish = [&](Row& R, const Row& P) {
+      R = P;
+#pragma unroll
+      for (int c = 0; c < C; ++c) {
+        const T u = R.m[c] * R.r[c];
+        R.p[c] = read_pold ? fma(bT, P.p[c], u) : u;
+      }
+    };
+    auto selp = [](const Row& R, int c) { return R.p[c]; };
+    auto selu = [](const Row& R, int c) { return R.m[c]; };
+
+    auto step = [&](auto PH, int k) {
+      constexpr int ph = decltype(PH)::value;
+      Row& R0 = ring[ph];            // row y = y0 - 2 + k
+      Row& R1 = ring[(ph + 3) & 3];  // y - 1
+      Row& R2 = ring[(ph + 2) & 3];  // y - 2
+      Row& R3 = ring[(ph + 1) & 3];  // y - 3
+      const int y = y0 - 2 + k;
+      finish(R0, pre[ph]);
+      issue(pre[ph], y + 4);
+      if (k >= 2) {
+        // s = A p and r_{i+1}, u_{i+1} on row y - 1
+        T g[C];
+        stream_apply(e, R2, R1, R0, selp, col, y - 1, g);
+        const bool act = R1.f & E::ACTIVE;
+#pragma unroll
+        for (int c = 0; c < C; ++c) {
+          const T sv = damped ? fma(R1.dmp[c], R1.p[c], g[c]) : g[c];
+          R1.r[c] = act ? fma(-aT, sv, R1.r[c]) : T(0);
+          R1.m[c] = act ? R1.m[c] * R1.r[c] : T(0);
+        }
+      }
+      if (k >= 4) {
+        // w = A u_{i+1} on row y - 2; partials and outputs
+        const int yo = y - 2;
+        T wv[C];
+        stream_apply(e, R3, R2, R1, selu, col, yo, wv);
+        const bool act = R2.f & E::ACTIVE;
+        if (out_lane && act) {
+#pragma unroll
+          for (int c = 0; c < C; ++c) {
+            const T ww = damped ? fma(R2.dmp[c], R2.m[c], wv[c]) : wv[c];
+            g_acc += (double)R2.r[c] * (double)R2.m[c];
+            d_acc += (double)ww * (double)R2.m[c];
+          }
+        }
+        if (write_out && out_lane) {
+          const int s = yo * W + col;
+#pragma unroll
+          for (int c = 0; c < C; ++c) {
+            const size_t o = (size_t)c * n + s;
+            const T pv = act ? R2.p[c] : T(0);
+            if (act) b.x[o] = fma(aT, pv, R2.x[c]);
+            b.r_out[o] = R2.r[c];
+            b.p_out[o] = pv;
+          }
+        }
+      }
+    };
+    issue(pre[0], y0 - 2);
+    issue(pre[1], y0 - 1);
+    issue(pre[2], y0);
+    issue(pre[3], y0 + 1);
+    for (int k = 0; k < K; k += 4) {
+      step(std::integral_constant<int, 0>{}, k);
+      if (k + 1 < K) step(std::integral_constant<int, 1>{}, k + 1);
+      if (k + 2 < K) step(std::integral_constant<int, 2>{}, k + 2);
+      if (k + 3 < K) step(std::integral_constant<int, 3>{}, k + 3);
     }
-    __syncthreads();
   }
-  const double gs = block_sum(g_acc);
-  const double ds = block_sum(d_acc);
+  const double gs_ = block_sum(g_acc);
+  const double ds_ = block_sum(d_acc);
   if (threadIdx.x == 0) {
-    b.part_out[blockIdx.x] = gs;
-    b.part_out[kMaxBlocks + blockIdx.x] = ds;
+    b.part_out[blockIdx.x] = gs_;
+    b.part_out[kMaxBlocks + blockIdx.x] = ds_;
   }
 }
 

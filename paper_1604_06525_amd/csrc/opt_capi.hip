@@ -60,11 +60,13 @@ struct Shape {
   int state_planes = 0;
   int n = 0;           // sites
   size_t tsize = 0;    // bytes of the bulk type
+  int n_edges = 0;     // graph: listed undirected edges
+  bool graph = false;
 };
 
 // Byte offsets of every region of the workspace.
 struct Layout {
-  size_t r0, r1, p0, p1, q, diag, minv, damp, delta, state, flags, parts, scal, trace, total;
+  size_t r0, r1, p0, p1, q, diag, minv, damp, delta, state, flags, csr, parts, scal, trace, total;
 };
 
 constexpr int kNumPartBufs = 10;  // see the P_* indices
@@ -79,6 +81,8 @@ Layout make_layout(const Shape& sh) {
   }
   L.state = off; off += align_up((size_t)sh.state_planes * sh.n * sh.tsize);
   L.flags = off; off += align_up((size_t)sh.n);
+  L.csr = off;  // graph: row offsets [n+1], then neighbour ids [2E]
+  if (sh.graph) off += align_up(sizeof(int) * ((size_t)sh.n + 1 + 2 * (size_t)sh.n_edges));
   L.parts = off; off += align_up(kNumPartBufs * (size_t)kMaxBlocks * sizeof(double));
   L.scal = off; off += align_up(sizeof(DevScalars));
   L.trace = off; off += align_up((size_t)kTraceCap * sizeof(double));
@@ -88,7 +92,11 @@ Layout make_layout(const Shape& sh) {
 
 int energy_channels(int e) {
   switch (e) {
-    case OPT_E_ARAP_WARP: return 3;
+    case OPT_E_ARAP_WARP: return ArapWarp<float>::C;
+    case OPT_E_POISSON: return Poisson<float>::C;
+    case OPT_E_FLOW: return OpticalFlow<float>::C;
+    case OPT_E_SFS: return ShapeFromShading<float>::C;
+    case OPT_E_ARAP_MESH: return ArapMesh<float>::C;
     default: return 0;
   }
 }
@@ -96,6 +104,10 @@ int energy_channels(int e) {
 int energy_state_planes(int e) {
   switch (e) {
     case OPT_E_ARAP_WARP: return ArapWarp<float>::kOwnState;
+    case OPT_E_POISSON: return Poisson<float>::kOwnState;
+    case OPT_E_FLOW: return OpticalFlow<float>::kOwnState;
+    case OPT_E_SFS: return ShapeFromShading<float>::kOwnState;
+    case OPT_E_ARAP_MESH: return ArapMesh<float>::kOwnState;
     default: return 0;
   }
 }
@@ -103,6 +115,10 @@ int energy_state_planes(int e) {
 int n_params_needed(int e) {
   switch (e) {
     case OPT_E_ARAP_WARP: return 2;
+    case OPT_E_POISSON: return 0;
+    case OPT_E_FLOW: return 2;
+    case OPT_E_SFS: return 16;
+    case OPT_E_ARAP_MESH: return 2;
     default: return 0;
   }
 }
@@ -110,6 +126,10 @@ int n_params_needed(int e) {
 int n_arrays_needed(int e) {
   switch (e) {
     case OPT_E_ARAP_WARP: return 3;
+    case OPT_E_POISSON: return 2;
+    case OPT_E_FLOW: return 4;
+    case OPT_E_SFS: return 4;
+    case OPT_E_ARAP_MESH: return 2;
     default: return 0;
   }
 }
@@ -125,11 +145,20 @@ int check_desc(const opt_problem_desc* d, Shape* sh) {
     if (!grid_energy) return fail(OPT_EUNSUPPORTED, "energy %d needs the graph domain", d->energy);
     if (d->width < 1 || d->height < 1)
       return fail(OPT_EINVAL, "grid size %d x %d must be positive", d->width, d->height);
+    if (d->width > kStripCols * kWaves * kMaxBlocks)
+      return fail(OPT_EINVAL, "grid width %d exceeds %d", d->width, kStripCols * kWaves * kMaxBlocks);
     if ((long long)d->width * d->height > (1LL << 30))
       return fail(OPT_EINVAL, "grid of %lld sites is too large", (long long)d->width * d->height);
     sh->n = d->width * d->height;
   } else if (d->domain == OPT_GRAPH) {
-    return fail(OPT_EUNSUPPORTED, "graph domain is not built for energy %d", d->energy);
+    if (grid_energy) return fail(OPT_EUNSUPPORTED, "energy %d needs the grid domain", d->energy);
+    if (d->n_vertices < 1 || d->n_edges < 0)
+      return fail(OPT_EINVAL, "graph of %d vertices and %d edges", d->n_vertices, d->n_edges);
+    if (d->n_edges > (1 << 29)) return fail(OPT_EINVAL, "%d edges is too many", d->n_edges);
+    if (d->n_edges > 0 && !d->edges) return fail(OPT_EINVAL, "edges is NULL");
+    sh->n = d->n_vertices;
+    sh->n_edges = d->n_edges;
+    sh->graph = true;
   } else {
     return fail(OPT_EINVAL, "domain %d is not OPT_GRID2D or OPT_GRAPH", d->domain);
   }
@@ -159,6 +188,7 @@ class Impl {
   virtual int pcg_a(int k, PrecondArgs pa, int lm_gate) = 0;
   virtual int pcg_b(int k, PrecondArgs pa, int lm_gate) = 0;
   virtual int fused(int iter, PrecondArgs pa, int lm_gate) = 0;
+  virtual bool has_fused() const = 0;
   virtual int apply_jtj(const void* p, void* q, PrecondArgs pa) = 0;
   virtual int apply_step(void* x, int lm_gate) = 0;
   virtual int cost(const void* x, const void* delta, int lm_gate) = 0;
@@ -197,10 +227,27 @@ namespace {
 // partial-sum buffers (kMaxBlocks doubles each); the fused form uses two pairs
 enum { P_LIN = 0, P_RZ0 = 1, P_RZ1 = 2, P_PQ = 3, P_COST = 4, P_M = 5, P_F0 = 6, P_F1 = 8 };
 
-// Tile of the fused PCG kernel: 64 x 16 sites in FP32, 64 x 8 in FP64 (LDS).
-template <typename T> struct FusedTile { static constexpr int TW = 64, TH = 16; };
-template <> struct FusedTile<double> { static constexpr int TW = 64, TH = 8; };
-constexpr int kFusedMaxGrid = 512;
+// Strips of the fused kernel: about this many waves per launch (4.5 per CU).
+constexpr int kFusedTargetStrips = 1152;
+
+struct StripGeom {
+  int n_sx, n_sy, Hs, grid;
+};
+
+StripGeom strip_geom(int W, int H) {
+  StripGeom g;
+  g.n_sx = (W + kStripCols - 1) / kStripCols;
+  g.Hs = std::max(4, (g.n_sx * H + kFusedTargetStrips - 1) / kFusedTargetStrips);
+  g.n_sy = (H + g.Hs - 1) / g.Hs;
+  const int max_strips = kWaves * kMaxBlocks;
+  if (g.n_sx * g.n_sy > max_strips) {
+    const int n_sy = std::max(1, max_strips / g.n_sx);
+    g.Hs = (H + n_sy - 1) / n_sy;
+    g.n_sy = (H + g.Hs - 1) / g.Hs;
+  }
+  g.grid = (g.n_sx * g.n_sy + kWaves - 1) / kWaves;
+  return g;
+}
 
 template <class E>
 class ImplT final : public Impl {
@@ -250,24 +297,31 @@ class ImplT final : public Impl {
     HIP_LAUNCHED("k_pcg_b");
     return OPT_OK;
   }
-  // iter = -1 is the priming launch; iteration i reads the partials of i-1.
+  // iter = -1 is the priming launch (it writes only partials); iteration i reads
+  // r from rbuf(i), p_{i-1} from pbuf(i+1), and the partials of i-1.
+  bool has_fused() const override { return E::kRadius == 1 && !E::kGraph; }
   int fused(int iter, PrecondArgs pa, int lm_gate) override {
-    constexpr int TW = FusedTile<T>::TW, TH = FusedTile<T>::TH;
-    const int tx = (e_.W + TW - 1) / TW, ty = (e_.H + TH - 1) / TH;
-    const int n_tiles = tx * ty;
-    const int grid = std::min(n_tiles, kFusedMaxGrid);
+    if constexpr (E::kRadius != 1 || E::kGraph) {
+      return fail(OPT_EUNSUPPORTED, "the fused PCG kernel needs an operator of radius 1");
+    } else {
+      return fused_launch(iter, pa, lm_gate);
+    }
+  }
+  int fused_launch(int iter, PrecondArgs pa, int lm_gate) {
+    const StripGeom g = strip_geom(e_.W, e_.H);
     FusedBufs<T> b;
-    b.r_in = iter < 0 ? rbuf(0) : rbuf(iter + 1);
-    b.r_out = iter < 0 ? rbuf(1) : rbuf(iter);
+    b.r_in = iter < 0 ? rbuf(0) : rbuf(iter);
+    b.r_out = iter < 0 ? nullptr : rbuf(iter + 1);
     b.p_in = pbuf(iter + 1);
-    b.p_out = iter < 0 ? pbuf(1) : pbuf(iter);
+    b.p_out = iter < 0 ? nullptr : pbuf(iter);
     b.x = vec(p_->L.delta);
     b.minv = vec(p_->L.minv);
     b.damp = damp(pa);
     b.part_in = p_->part((iter & 1) ? P_F0 : P_F1);
     b.part_out = p_->part((iter & 1) ? P_F1 : P_F0);
-    b.n_part_in = grid;
-    k_fused<E, TW, TH><<<grid, kBlock, 0, p_->stream>>>(e_, b, p_->S(), iter, lm_gate, tx, n_tiles);
+    b.n_part_in = g.grid;
+    k_fused<E><<<g.grid, kBlock, 0, p_->stream>>>(e_, b, p_->S(), iter, lm_gate, g.n_sx, g.n_sy,
+                                                   g.Hs);
     HIP_LAUNCHED("k_fused");
     return OPT_OK;
   }
@@ -321,6 +375,72 @@ std::unique_ptr<Impl> make_impl_t(opt_problem* p) {
       e.wr_d = d.params[1];
       return std::unique_ptr<Impl>(new ImplT<ArapWarp<T>>(p, e));
     }
+    case OPT_E_POISSON: {
+      Poisson<T> e;
+      e.W = d.width;
+      e.H = d.height;
+      e.n = p->sh.n;
+      e.Tg = (const T*)d.arrays[0];
+      e.mask = (const uint8_t*)d.arrays[1];
+      e.flags = (uint8_t*)p->at(p->L.flags);
+      return std::unique_ptr<Impl>(new ImplT<Poisson<T>>(p, e));
+    }
+    case OPT_E_FLOW: {
+      OpticalFlow<T> e;
+      e.W = d.width;
+      e.H = d.height;
+      e.n = p->sh.n;
+      e.I = (const T*)d.arrays[0];
+      e.Ih = (const T*)d.arrays[1];
+      e.Idx = (const T*)d.arrays[2];
+      e.Idy = (const T*)d.arrays[3];
+      e.jf = (T*)p->at(p->L.state);
+      e.flags = (uint8_t*)p->at(p->L.flags);
+      e.wf = (T)d.params[0];
+      e.wr = (T)d.params[1];
+      e.wf_d = d.params[0];
+      e.wr_d = d.params[1];
+      return std::unique_ptr<Impl>(new ImplT<OpticalFlow<T>>(p, e));
+    }
+    case OPT_E_SFS: {
+      ShapeFromShading<T> e;
+      e.W = d.width;
+      e.H = d.height;
+      e.n = p->sh.n;
+      e.D = (const T*)d.arrays[0];
+      e.Im = (const T*)d.arrays[1];
+      e.eR = (const uint8_t*)d.arrays[2];
+      e.eC = (const uint8_t*)d.arrays[3];
+      e.st = (T*)p->at(p->L.state);
+      e.flags = (uint8_t*)p->at(p->L.flags);
+      e.sw_p = std::sqrt(d.params[0]);
+      e.sw_s = std::sqrt(d.params[1]);
+      e.sw_g = std::sqrt(d.params[2]);
+      e.fx = d.params[3];
+      e.fy = d.params[4];
+      e.ux = d.params[5];
+      e.uy = d.params[6];
+      for (int k = 0; k < 9; ++k) e.L[k] = d.params[7 + k];
+      e.sw_pT = (T)e.sw_p;
+      e.sw_sT = (T)e.sw_s;
+      e.sw_gT = (T)e.sw_g;
+      return std::unique_ptr<Impl>(new ImplT<ShapeFromShading<T>>(p, e));
+    }
+    case OPT_E_ARAP_MESH: {
+      ArapMesh<T> e;
+      e.n = p->sh.n;
+      e.rp = (const int*)p->at(p->L.csr);
+      e.nb = e.rp + (p->sh.n + 1);
+      e.U = (const T*)d.arrays[0];
+      e.Ct = (const T*)d.arrays[1];
+      e.trig = (T*)p->at(p->L.state);
+      e.flags = (uint8_t*)p->at(p->L.flags);
+      e.wf = (T)d.params[0];
+      e.wr = (T)d.params[1];
+      e.wf_d = d.params[0];
+      e.wr_d = d.params[1];
+      return std::unique_ptr<Impl>(new ImplT<ArapMesh<T>>(p, e));
+    }
     default:
       return nullptr;
   }
@@ -329,6 +449,41 @@ std::unique_ptr<Impl> make_impl_t(opt_problem* p) {
 std::unique_ptr<Impl> make_impl(opt_problem* p) {
   if (p->desc.precision == OPT_FP64) return make_impl_t<double>(p);
   return make_impl_t<float>(p);
+}
+
+// Graph domain: turn the edge list into a per-vertex incidence list (CSR) in the
+// workspace.  A stable counting sort on the host: vertex v lists, in edge-list
+// order, the other end of every edge that touches it, so the order of every
+// per-vertex sum is fixed.  Synchronises the stream.
+int build_incidence(opt_problem* p) {
+  const int V = p->sh.n, E = p->sh.n_edges;
+  std::vector<int> edges((size_t)2 * E), rp((size_t)V + 1, 0), nb((size_t)2 * E);
+  if (E > 0) {
+    HIP_TRY(hipMemcpyAsync(edges.data(), p->desc.edges, sizeof(int) * 2 * (size_t)E,
+                           hipMemcpyDeviceToHost, p->stream));
+    HIP_TRY(hipStreamSynchronize(p->stream));
+  }
+  for (int e = 0; e < E; ++e) {
+    const int a = edges[2 * (size_t)e], b = edges[2 * (size_t)e + 1];
+    if (a < 0 || a >= V || b < 0 || b >= V)
+      return fail(OPT_EINVAL, "edge %d = (%d, %d) names a vertex outside [0, %d)", e, a, b, V);
+    rp[(size_t)a + 1]++;
+    rp[(size_t)b + 1]++;
+  }
+  for (int v = 0; v < V; ++v) rp[(size_t)v + 1] += rp[v];
+  std::vector<int> pos(rp.begin(), rp.end() - 1);
+  for (int e = 0; e < E; ++e) {
+    const int a = edges[2 * (size_t)e], b = edges[2 * (size_t)e + 1];
+    nb[(size_t)pos[a]++] = b;
+    nb[(size_t)pos[b]++] = a;
+  }
+  int* dst = (int*)p->at(p->L.csr);
+  HIP_TRY(hipMemcpyAsync(dst, rp.data(), sizeof(int) * rp.size(), hipMemcpyHostToDevice, p->stream));
+  if (E > 0)
+    HIP_TRY(hipMemcpyAsync(dst + V + 1, nb.data(), sizeof(int) * nb.size(), hipMemcpyHostToDevice,
+                           p->stream));
+  HIP_TRY(hipStreamSynchronize(p->stream));
+  return OPT_OK;
 }
 
 int check_params(const opt_solve_params* sp) {
@@ -375,9 +530,11 @@ int record_event(opt_problem* p) {
     if (rc_ != OPT_OK) return rc_; \
   } while (0)
 
-// The L iterations of the inner solve after init, in the chosen form.
+// The L iterations of the inner solve after init, in the chosen form.  Energies
+// whose operator reaches further than one site (shape from shading) always use
+// the split form.
 int run_pcg(opt_problem* p, PrecondArgs pa, int lm, int L, int variant) {
-  if (variant == OPT_PCG_FUSED) {
+  if (variant == OPT_PCG_FUSED && p->impl->has_fused()) {
     if (L > 0) TRY(p->impl->fused(-1, pa, lm));
     for (int i = 0; i < L; ++i) TRY(p->impl->fused(i, pa, lm));
   } else {
@@ -444,6 +601,7 @@ int opt_problem_create(const opt_problem_desc* desc, void* workspace, size_t wor
   if (p->nblk < 1) p->nblk = 1;
   p->impl = make_impl(p.get());
   if (!p->impl) return fail(OPT_EUNSUPPORTED, "energy %d is not built", desc->energy);
+  if (sh.graph) TRY(build_incidence(p.get()));
   k_setup<<<1, 64, 0, p->stream>>>(p->S(), 0.0, 1.0, 0);
   HIP_LAUNCHED("k_setup");
   *out = p.release();

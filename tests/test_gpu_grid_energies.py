@@ -1,0 +1,145 @@
+"""GPU parity of the grid energies (Poisson image editing, optical flow, ARAP
+warp) against the FP64 oracle, through the C ABI.
+
+Tolerances: FP64 operator products (J^T F, diag, J^T J p) agree to 1e-12 of
+their largest entry; FP64 PCG iterates to 1e-9 (or 100x the oracle's own spread
+between two valid evaluation orders, once CG has lost orthogonality); FP64 GN and
+LM cost traces to 1e-9 relative; mixed precision to 1e-4 relative final cost.
+Sizes span several 64 x 16 tiles and end in ragged partial tiles.
+"""
+import numpy as np
+import pytest
+
+import oracle as o
+import workloads as w
+from tests.gpu_util import make_problem, relmax, require_gpu, to_dev, to_np
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(autouse=True)
+def _gpu():
+    require_gpu()
+
+
+def _poisson(W, H, seed=5):
+    d = w.poisson_edit(W, H, seed=seed)
+    rng = np.random.default_rng(seed)
+    act = d["mask"] == 0
+    x = np.where(act[None], d["x0"] + 0.1 * rng.normal(size=d["x0"].shape), d["x0"])
+    return d, x
+
+
+def _flow(W, H, seed=4):
+    d = w.optical_flow(W, H, seed=seed)
+    rng = np.random.default_rng(seed)
+    x = d["flow_true"] * 0.7 + 0.3 * rng.normal(size=d["x0"].shape)
+    return d, x
+
+
+def _warp(W, H, seed=3):
+    d = w.arap_warp(W, H, seed=seed, n_constraints=max(2, W * H // 64), margin=2, mask="random")
+    rng = np.random.default_rng(seed)
+    x = d["x0"] + np.concatenate([rng.normal(0, 0.5, (2, H, W)), rng.normal(0, 0.2, (1, H, W))])
+    return d, np.where((d["mask"] == 0)[None], x, d["x0"])
+
+
+def _sfs(W, H, seed=2):
+    d = w.shape_from_shading(W, H, seed=seed, invalid="hole" if W > 20 else "none",
+                             edge_zero_frac=0.1)
+    rng = np.random.default_rng(seed)
+    x = d["x0"] + 1e-4 * rng.normal(size=d["x0"].shape)
+    return d, np.where((d["D"] > 0)[None], x, d["x0"])
+
+
+MAKERS = {"poisson": _poisson, "flow": _flow, "warp": _warp, "sfs": _sfs}
+SIZES = [(9, 7), (97, 41), (130, 70)]
+CASES = [(k, W, H) for k in MAKERS for (W, H) in SIZES]
+
+
+@pytest.mark.parametrize("kind,W,H", CASES)
+def test_operators_fp64(kind, W, H):
+    d, x = MAKERS[kind](W, H)
+    e = o.make_energy(d)
+    lin = o.Linearization(e, x)
+    prob = make_problem(d, "fp64")
+    xt = to_dev(prob, x)
+    assert abs(prob.cost(xt) - lin.E) <= 1e-12 * lin.E
+    assert abs(prob.linearize(xt) - lin.E) <= 1e-12 * lin.E
+    b, dg = prob.eval_jtf()
+    assert relmax(to_np(b), lin.jtf()) < 1e-12
+    assert relmax(to_np(dg), lin.diag) < 1e-12
+    rng = np.random.default_rng(1)
+    p = rng.normal(size=lin.diag.size) * lin.active
+    assert relmax(to_np(prob.apply_jtj(to_dev(prob, p))), lin.apply(p)) < 1e-12
+    D = lin.damping()
+    assert relmax(to_np(prob.apply_jtj(to_dev(prob, p), lam=0.21)), lin.apply(p, 0.21, D)) < 1e-12
+
+
+@pytest.mark.parametrize("kind,W,H", CASES)
+@pytest.mark.parametrize("variant", ["fused", "split"])
+def test_pcg_fp64(kind, W, H, variant):
+    d, x = MAKERS[kind](W, H)
+    e = o.make_energy(d)
+    lin = o.Linearization(e, x)
+    prob = make_problem(d, "fp64")
+    xt = to_dev(prob, x)
+    prob.linearize(xt)
+    A = (lin.JT @ lin.J).tocsr()
+    for precond in (True, False):
+        for L in (1, 9, 30):
+            ref, _ = o.pcg(lin.apply, lin.jtf(), lin.minv(precond), L)
+            ref2, _ = o.pcg(lambda v: A @ v, lin.jtf(), lin.minv(precond), L)
+            tol = max(1e-9, 100 * relmax(ref2, ref))
+            got = to_np(prob.pcg(L, use_precond=precond, variant=variant))
+            assert relmax(got, ref) < tol, (precond, L, tol)
+
+
+@pytest.mark.parametrize("kind", list(MAKERS))
+@pytest.mark.parametrize("variant", ["fused", "split"])
+def test_gn_fp64(kind, variant):
+    d, _ = MAKERS[kind](97, 41)
+    e = o.make_energy(d)
+    xo, costs = o.gauss_newton(e, d["x0"], 3, 15)
+    prob = make_problem(d, "fp64")
+    xt = to_dev(prob, d["x0"])
+    rep = prob.solve(xt, method="gn", outer_iters=3, pcg_iters=15, pcg_variant=variant)
+    assert np.allclose(rep["cost_trace"], costs, rtol=1e-9, atol=0)
+    assert relmax(to_np(xt) - d["x0"].ravel(), xo - d["x0"].ravel()) < 1e-8
+
+
+@pytest.mark.parametrize("kind", list(MAKERS))
+def test_gn_mixed(kind):
+    d, _ = MAKERS[kind](130, 70)
+    e = o.make_energy(d)
+    xo, costs = o.gauss_newton(e, d["x0"], 4, 20)
+    prob = make_problem(d, "mixed")
+    xt = to_dev(prob, d["x0"])
+    rep = prob.solve(xt, method="gn", outer_iters=4, pcg_iters=20)
+    assert abs(rep["cost_final"] - costs[-1]) <= 1e-4 * costs[-1]
+
+
+@pytest.mark.parametrize("kind", list(MAKERS))
+def test_lm_fp64(kind):
+    d, _ = MAKERS[kind](97, 41)
+    e = o.make_energy(d)
+    xo, costs, acc = o.levenberg_marquardt(e, d["x0"], 4, 12)
+    prob = make_problem(d, "fp64")
+    xt = to_dev(prob, d["x0"])
+    rep = prob.solve(xt, method="lm", outer_iters=4, pcg_iters=12)
+    assert rep["steps_accepted"] == sum(acc)
+    assert np.allclose(rep["cost_trace"][:len(costs)], costs, rtol=1e-9, atol=0)
+
+
+def test_poisson_one_step_exact():
+    """GN reaches the minimiser of the linear Poisson energy in one outer
+    iteration given an (effectively) exact inner solve (Sec. 8.1): a second
+    iteration no longer lowers the cost."""
+    d = w.poisson_edit(40, 24, seed=7)
+    prob = make_problem(d, "fp64")
+    xt = to_dev(prob, d["x0"])
+    rep = prob.solve(xt, method="gn", outer_iters=2, pcg_iters=400)
+    e = o.make_energy(d)
+    xo, costs = o.gauss_newton(e, d["x0"], 1, 400)
+    assert abs(rep["cost_trace"][1] - costs[1]) <= 1e-10 * costs[1]
+    assert abs(rep["cost_trace"][2] - rep["cost_trace"][1]) <= 1e-10 * rep["cost_trace"][1]

@@ -1,0 +1,130 @@
+"""GPU parity of the ARAP mesh (graph domain) path against the FP64 oracle.
+
+The library builds a per-vertex incidence list from the edge list; every product
+is a per-vertex gather.  Tolerances as for the grid energies: FP64 operators
+1e-12 of their largest entry, FP64 PCG 1e-9, FP64 GN/LM cost traces 1e-9
+relative, mixed precision 1e-4 relative final cost.
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle as o
+import workloads as w
+from tests.gpu_util import make_problem, relmax, require_gpu, to_dev, to_np
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(autouse=True)
+def _gpu():
+    require_gpu()
+
+
+def _mesh(level, seed=3, handle_frac=0.02, sigma=0.1, scale=0.2):
+    d = w.arap_mesh(level, seed=seed, handle_frac=handle_frac, sigma=sigma)
+    rng = np.random.default_rng(seed)
+    x = d["x0"] + scale * rng.normal(size=d["x0"].shape)
+    return d, x
+
+
+@pytest.mark.parametrize("level", [1, 3])
+def test_operators_fp64(level):
+    d, x = _mesh(level)
+    e = o.make_energy(d)
+    lin = o.Linearization(e, x)
+    prob = make_problem(d, "fp64")
+    xt = to_dev(prob, x)
+    assert abs(prob.cost(xt) - lin.E) <= 1e-12 * lin.E
+    assert abs(prob.linearize(xt) - lin.E) <= 1e-12 * lin.E
+    b, dg = prob.eval_jtf()
+    assert relmax(to_np(b), lin.jtf()) < 1e-12
+    assert relmax(to_np(dg), lin.diag) < 1e-12
+    p = np.random.default_rng(2).normal(size=lin.diag.size)
+    assert relmax(to_np(prob.apply_jtj(to_dev(prob, p))), lin.apply(p)) < 1e-12
+    D = lin.damping()
+    assert relmax(to_np(prob.apply_jtj(to_dev(prob, p), lam=0.4)), lin.apply(p, 0.4, D)) < 1e-12
+
+
+def test_dense_jtj_icosphere_level1():
+    d, x = _mesh(1, seed=5)
+    e = o.make_energy(d)
+    lin = o.Linearization(e, x)
+    A = (lin.J.T @ lin.J).toarray()
+    prob = make_problem(d, "fp64")
+    xt = to_dev(prob, x)
+    prob.linearize(xt)
+    N = A.shape[0]
+    G = np.stack([to_np(prob.apply_jtj(to_dev(prob, np.eye(N)[k]))) for k in range(N)], 1)
+    assert np.abs(G - A).max() <= 1e-13 * np.abs(A).max()
+
+
+@pytest.mark.parametrize("variant", ["fused", "split"])
+def test_pcg_fp64(variant):
+    d, x = _mesh(3)
+    e = o.make_energy(d)
+    lin = o.Linearization(e, x)
+    prob = make_problem(d, "fp64")
+    xt = to_dev(prob, x)
+    prob.linearize(xt)
+    A = (lin.JT @ lin.J).tocsr()
+    for L in (1, 10, 30):
+        ref, _ = o.pcg(lin.apply, lin.jtf(), lin.minv(True), L)
+        ref2, _ = o.pcg(lambda v: A @ v, lin.jtf(), lin.minv(True), L)
+        tol = max(1e-9, 100 * relmax(ref2, ref))
+        got = to_np(prob.pcg(L, variant=variant))
+        assert relmax(got, ref) < tol, (L, tol)
+
+
+def test_lm_fp64():
+    d = w.arap_mesh(3, seed=3, handle_frac=0.02, sigma=0.2)
+    e = o.make_energy(d)
+    xo, costs, acc = o.levenberg_marquardt(e, d["x0"], 5, 20)
+    prob = make_problem(d, "fp64")
+    xt = to_dev(prob, d["x0"])
+    rep = prob.solve(xt, method="lm", outer_iters=5, pcg_iters=20)
+    assert rep["steps_accepted"] == sum(acc)
+    assert np.allclose(rep["cost_trace"][:len(costs)], costs, rtol=1e-9, atol=0)
+    assert relmax(to_np(xt) - d["x0"].ravel(), xo - d["x0"].ravel()) < 1e-8
+
+
+def test_gn_fp64():
+    d = w.arap_mesh(2, seed=4, handle_frac=0.05)
+    e = o.make_energy(d)
+    xo, costs = o.gauss_newton(e, d["x0"], 3, 15)
+    prob = make_problem(d, "fp64")
+    xt = to_dev(prob, d["x0"])
+    rep = prob.solve(xt, method="gn", outer_iters=3, pcg_iters=15)
+    assert np.allclose(rep["cost_trace"], costs, rtol=1e-9, atol=0)
+
+
+def test_lm_mixed_level5():
+    """Config-3 style: 1% handles, LM with 40 PCG iterations, mixed precision."""
+    d = w.arap_mesh(5, seed=3)
+    e = o.make_energy(d)
+    xo, costs, acc = o.levenberg_marquardt(e, d["x0"], 4, 40)
+    prob = make_problem(d, "mixed")
+    xt = to_dev(prob, d["x0"])
+    rep = prob.solve(xt, method="lm", outer_iters=4, pcg_iters=40)
+    assert abs(rep["cost_final"] - costs[-1]) <= 1e-4 * costs[-1]
+
+
+def test_deterministic_mixed():
+    d = w.arap_mesh(4, seed=6)
+    outs = []
+    for _ in range(2):
+        prob = make_problem(d, "mixed")
+        xt = to_dev(prob, d["x0"])
+        rep = prob.solve(xt, method="lm", outer_iters=3, pcg_iters=15)
+        outs.append((rep["cost_trace"], to_np(xt)))
+    assert outs[0][0] == outs[1][0] and np.array_equal(outs[0][1], outs[1][1])
+
+
+def test_bad_edge_rejected():
+    import paper_1604_06525_amd as pkg
+    d = w.arap_mesh(1, seed=3)
+    d["edges"] = d["edges"].copy()
+    d["edges"][5, 1] = d["V"] + 3
+    with pytest.raises(pkg.OptError) as err:
+        make_problem(d, "mixed")
+    assert err.value.code == pkg.OPT_EINVAL
