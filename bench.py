@@ -1,6 +1,7 @@
 """Benchmark of the matrix-free GN PCG path on one MI355X.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
+    python bench.py --serve [--serve-requests N]
 
 A step is one whole solve: ARAP image warping on a 1024 x 1024 pixel grid
 (3 unknowns per pixel, 8,192 positional constraints), Gauss-Newton 10 outer x 50
@@ -15,6 +16,15 @@ algorithmic bytes of an iteration (p, d and r each read and written once per
 unknown, plus the per-pixel angle, rest position and flags).  ``cpu_baseline`` is the
 FP64 oracle (explicit sparse Jacobian, scipy) on one outer iteration of the same
 workload on the host.
+
+``--serve`` measures the batching server instead: a seeded Poisson-arrival
+stream of mixed requests (ARAP warps and Poisson edits on grids of side
+128..1024, ARAP icosphere meshes of 10k..164k vertices; mixed precision) is
+served at several loads, relative to the measured capacity of plain FIFO
+single-problem solves, once by the server (continuous batching, 8 GiB arena) and
+once plainly; it prints one JSON line with p50/p99 latency (arrival to result on
+the host) and sustained solves/s for both, and whether every request gave
+bit-identical unknowns both ways.
 """
 import argparse
 import json
@@ -37,6 +47,9 @@ def parse():
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--serve", action="store_true")
+    ap.add_argument("--serve-requests", type=int, default=200)
+    ap.add_argument("--serve-loads", type=str, default="0.25,0.5,0.75,0.9,1.0,1.2")
     return ap.parse_args()
 
 
@@ -60,12 +73,166 @@ def cpu_baseline(d, pcg_iters):
                       f"{dt:.1f} s"}
 
 
+SERVE_ARENA = 8 << 30
+SERVE_SLOTS = 64
+
+
+def _serve_pool(torch, pkg, dev):
+    import workloads
+    from workloads.layout import problem_args
+    from workloads.serving import SCHEDULE, pool_spec
+    entries = []
+    for spec in pool_spec():
+        kind, size, seed = spec["kind"], spec["size"], spec["seed"]
+        if kind == "arap_warp":
+            d = workloads.arap_warp(size, size, seed=seed)
+        elif kind == "poisson":
+            d = workloads.poisson_edit(size, size, seed=seed)
+        else:
+            d = workloads.arap_mesh(size, seed=seed)
+        energy, arrs, params, dims = problem_args(d, np.float32)
+        arrays = [torch.from_numpy(a).to(dev) for a in arrs]
+        if "edges" in dims:
+            dims = dict(dims, edges=torch.from_numpy(dims["edges"]).to(dev))
+        x0 = torch.from_numpy(np.ascontiguousarray(np.asarray(d["x0"], np.float32).reshape(-1))).to(dev)
+        method, K, L = SCHEDULE[kind]
+        sp = pkg.default_params(method=method, outer_iters=K, pcg_iters=L)
+        plain = pkg.Problem(energy, arrays, params, precision="mixed", **dims)
+        entries.append(dict(spec=spec, energy=energy, arrays=arrays, params=params, dims=dims, x0=x0,
+                            sp=sp, plain=plain))
+    return entries
+
+
+def _pct(v, q):
+    return float(np.percentile(np.asarray(v) * 1e3, q))
+
+
+def _run_plain(entries, arrivals, which, keep):
+    lat, xs = [], {}
+    t0 = time.perf_counter()
+    for k in range(len(arrivals)):
+        wait = arrivals[k] - (time.perf_counter() - t0)
+        if wait > 0:
+            time.sleep(wait)
+        e = entries[which[k]]
+        x = e["x0"].clone().reshape(e["plain"].channels, -1)
+        e["plain"].solve(x, params=e["sp"], report=True)
+        lat.append(time.perf_counter() - t0 - arrivals[k])
+        if keep:
+            xs[k] = x.reshape(-1)
+    span = time.perf_counter() - t0
+    return lat, span, xs
+
+
+def _run_batched(pkg, entries, arrivals, which, keep):
+    sv = pkg.Server(SERVE_ARENA, max_slots=SERVE_SLOTS)
+    n = len(arrivals)
+    lat = [None] * n
+    xs, live, queue = {}, {}, []
+    nxt, done, steps, held_sum = 0, 0, 0, 0
+    t0 = time.perf_counter()
+    while done < n:
+        now = time.perf_counter() - t0
+        while nxt < n and arrivals[nxt] <= now:
+            queue.append(nxt)
+            nxt += 1
+        while queue:
+            k = queue[0]
+            e = entries[which[k]]
+            x = e["x0"].clone()
+            t = sv.submit(e["energy"], e["arrays"], x, e["params"], precision="mixed", **e["dims"],
+                          solve_params=e["sp"])
+            if t is None:
+                break
+            queue.pop(0)
+            live[t] = (k, x)
+        if not live:
+            wait = arrivals[nxt] - (time.perf_counter() - t0)
+            if wait > 0:
+                time.sleep(wait)
+            continue
+        held_sum += len(live)
+        steps += 1
+        sv.step()
+        now = time.perf_counter() - t0
+        for t in list(live):
+            if sv.poll(t) is not None:
+                k, x = live.pop(t)
+                lat[k] = now - arrivals[k]
+                done += 1
+                if keep:
+                    xs[k] = x
+    span = time.perf_counter() - t0
+    return lat, span, xs, held_sum / max(1, steps)
+
+
+def serve_main(args):
+    import torch
+    import paper_1604_06525_amd as pkg
+    from workloads.serving import request_stream
+    dev = torch.device("cuda:0")
+    entries = _serve_pool(torch, pkg, dev)
+    print(f"serve: pool of {len(entries)} problems ready", file=sys.stderr, flush=True)
+    # warm up every problem once, then measure the plain capacity on a sample
+    for e in entries:
+        e["plain"].solve(e["x0"].clone().reshape(e["plain"].channels, -1), params=e["sp"], report=True)
+    _, which = request_stream(entries_spec := [e["spec"] for e in entries], 40, 1.0, seed=99)
+    t0 = time.perf_counter()
+    for k in which:
+        e = entries[k]
+        e["plain"].solve(e["x0"].clone().reshape(e["plain"].channels, -1), params=e["sp"], report=True)
+    capacity = len(which) / (time.perf_counter() - t0)
+    print(f"serve: plain capacity {capacity:.1f} solves/s", file=sys.stderr, flush=True)
+    loads = [float(v) for v in args.serve_loads.split(",")]
+    rows, equal, compared = [], 0, 0
+    for li, load in enumerate(loads):
+        arrivals, which = request_stream(entries_spec, args.serve_requests, load * capacity, seed=5 + li)
+        keep = li == 0
+        lat_b, span_b, xs_b, mean_held = _run_batched(pkg, entries, arrivals, which, keep)
+        lat_p, span_p, xs_p = _run_plain(entries, arrivals, which, keep)
+        if keep:
+            for k in xs_p:
+                compared += 1
+                equal += int(torch.equal(xs_p[k], xs_b[k]))
+        n = len(arrivals)
+        rows.append({"load": load, "rate_per_s": load * capacity,
+                     "batched": {"p50_ms": _pct(lat_b, 50), "p99_ms": _pct(lat_b, 99),
+                                 "solves_per_s": n / span_b, "mean_requests_per_step": mean_held},
+                     "plain": {"p50_ms": _pct(lat_p, 50), "p99_ms": _pct(lat_p, 99),
+                               "solves_per_s": n / span_p}})
+        print(f"serve: load {load}: batched p50/p99 {rows[-1]['batched']['p50_ms']:.1f}/"
+              f"{rows[-1]['batched']['p99_ms']:.1f} ms, plain {rows[-1]['plain']['p50_ms']:.1f}/"
+              f"{rows[-1]['plain']['p99_ms']:.1f} ms", file=sys.stderr, flush=True)
+    at1 = min(rows, key=lambda r: abs(r["load"] - 1.0))
+    out = {
+        "metric": "serving p99 latency at the plain capacity (batched)",
+        "value": at1["batched"]["p99_ms"],
+        "unit": "ms",
+        "n_gpus": 1,
+        "higher_is_better": False,
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "serving mix: 40% ARAP warp / 40% Poisson edit (grid side 128..1024, "
+                               "GN 10x50), 20% ARAP icosphere mesh (level 5..7, LM 10x40); mixed precision",
+                   "requests_per_load": args.serve_requests, "arena_bytes": SERVE_ARENA,
+                   "max_slots": SERVE_SLOTS, "pool": [e["spec"] for e in entries]},
+        "plain_capacity_solves_per_s": capacity,
+        "loads": rows,
+        "bitwise_equal_to_plain": f"{equal}/{compared}",
+    }
+    print(json.dumps(out), flush=True)
+
+
 def main():
     args = parse()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU; --gpus {args.gpus} is not supported "
               "(the path is single-GPU; see the design notes on sharding)", file=sys.stderr)
         sys.exit(2)
+    if args.serve:
+        serve_main(args)
+        return
     import torch
     import paper_1604_06525_amd as pkg
     import workloads

@@ -52,7 +52,7 @@ extern "C" {
 #define OPT_EINVAL (-1)       /* invalid argument, size or descriptor field */
 #define OPT_ENOMEM (-2)       /* workspace smaller than opt_workspace_size() */
 #define OPT_EHIP (-3)         /* a HIP runtime call failed; message names it */
-#define OPT_EAGAIN (-4)       /* resource busy (reserved for the server API) */
+#define OPT_EAGAIN (-4)       /* server: no free slot or arena range; retry later */
 #define OPT_ENUMERIC (-5)     /* a cost came out NaN or infinite */
 #define OPT_EUNSUPPORTED (-6) /* combination of domain/energy/precision not built */
 
@@ -217,8 +217,84 @@ int opt_pcg(opt_problem* prob, const opt_solve_params* params, double lambda, vo
 int opt_profile_enable(opt_problem* prob, int enable);
 int opt_profile_read(opt_problem* prob, double* pcg_ms, int64_t* pcg_iters);
 
+/*
+ * Launch tuning of a problem (no effect on results: every choice computes the
+ * same iterates, only the work split changes).
+ *   strip_rows: the fused PCG kernel gives each wavefront a strip of 60 columns
+ *   and this many rows (0 = automatic: about 1,152 strips per launch).  Shorter
+ *   strips mean more wavefronts in flight but more halo rows read twice.
+ * opt_problem_get_tuning returns the values in force (strip_rows resolved).
+ */
+typedef struct {
+  int32_t strip_rows;
+} opt_tuning;
+
+int opt_problem_set_tuning(opt_problem* prob, const opt_tuning* tuning);
+int opt_problem_get_tuning(opt_problem* prob, opt_tuning* tuning);
+
 /* Number of unknown channels per site for an energy (0 if unknown). */
 int opt_energy_channels(int32_t energy);
+
+/*
+ * Serving: many solves at once (continuous batching).
+ *
+ * Small problems use a GPU poorly (Sec. 8 notes the solver is inefficient below
+ * a few thousand unknowns): each kernel launch carries little work.  A server
+ * advances every active request by one outer iteration per opt_server_step, and
+ * runs each stage of that iteration as one launch per energy kind covering all
+ * of its requests.  Each request keeps the arithmetic and reduction order of
+ * opt_solve with the same parameters, so its result is bit-identical to solving
+ * it alone, whatever else runs beside it.
+ *
+ * Memory: the caller hands the server one device arena (256-byte aligned).  The
+ * first opt_server_reserved_bytes(max_slots) bytes hold the server's argument
+ * tables; each admitted request's workspace (opt_workspace_size of its
+ * descriptor) is carved from the rest, first fit, and returned when it leaves.
+ * The arena size is therefore the memory budget.  The server also allocates a
+ * little pinned host memory for staging.
+ *
+ * opt_server_submit: admit a request: a problem descriptor (arrays referenced as
+ *   by opt_problem_create; they and `unknowns` must stay valid until the request
+ *   is collected or cancelled) and solve parameters.  Returns OPT_EAGAIN (nothing
+ *   admitted) if no slot is free or no free arena range is large enough; the
+ *   request may be submitted again after a step has retired others.  A graph's
+ *   edges are read at submission (this synchronises the stream).  *ticket names
+ *   the request.
+ * opt_server_step: one quantum: requests admitted since the last step start;
+ *   every running request does one outer iteration (linearise, PCG init, its
+ *   pcg_iters PCG iterations, LM decision, update); requests that reach their
+ *   outer_iters (or whose LM radius fell below the minimum) get their final cost
+ *   and leave.  Synchronises the stream once.  A request's unknowns are written
+ *   in place.
+ * opt_server_poll: *done = 1 once the request has left; then the report (as
+ *   opt_solve's; cost_trace, if not NULL, must hold outer_iters + 1 entries) is
+ *   filled and the ticket is forgotten.  Returns OPT_ENUMERIC (report filled) if
+ *   a cost was NaN or infinite.  *done = 0 while it runs.  OPT_EINVAL for a
+ *   ticket that is unknown or already collected.
+ * opt_server_cancel: drop a running request (its unknowns are left part-way) or
+ *   an uncollected result.
+ * opt_server_info: requests held (running or admitted) and free arena bytes.
+ * opt_server_add_tuning: launch tuning (opt_tuning) applied at admission to
+ *   requests of that energy and precision whose site count lies in
+ *   [min_sites, max_sites]; a later entry overrides an earlier one.
+ *
+ * A server is not thread-safe: calls on one server must not overlap.  The
+ * server's stream must not be used for other work while a step runs.
+ */
+typedef struct opt_server opt_server;
+
+int opt_server_reserved_bytes(int32_t max_slots, size_t* bytes);
+int opt_server_create(void* arena, size_t arena_bytes, int32_t max_slots, void* hip_stream,
+                      opt_server** out);
+int opt_server_destroy(opt_server* server);
+int opt_server_submit(opt_server* server, const opt_problem_desc* desc, void* unknowns,
+                      const opt_solve_params* params, int64_t* ticket);
+int opt_server_step(opt_server* server);
+int opt_server_poll(opt_server* server, int64_t ticket, int32_t* done, opt_solve_report* report);
+int opt_server_cancel(opt_server* server, int64_t ticket);
+int opt_server_info(opt_server* server, int32_t* active, size_t* arena_free);
+int opt_server_add_tuning(opt_server* server, int32_t energy, int32_t precision, int64_t min_sites,
+                          int64_t max_sites, const opt_tuning* tuning);
 
 #ifdef __cplusplus
 }

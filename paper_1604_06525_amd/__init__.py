@@ -39,6 +39,10 @@ class opt_solve_params(ctypes.Structure):
                 ("pcg_variant", ctypes.c_int32)]
 
 
+class opt_tuning(ctypes.Structure):
+    _fields_ = [("strip_rows", ctypes.c_int32)]
+
+
 class opt_solve_report(ctypes.Structure):
     _fields_ = [("cost_initial", ctypes.c_double), ("cost_final", ctypes.c_double),
                 ("outer_done", ctypes.c_int32), ("steps_accepted", ctypes.c_int32),
@@ -62,6 +66,20 @@ _proto = {
     "opt_energy_channels": (ctypes.c_int, [ctypes.c_int32]),
     "opt_profile_enable": (ctypes.c_int, [_P, ctypes.c_int]),
     "opt_profile_read": (ctypes.c_int, [_P, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64)]),
+    "opt_problem_set_tuning": (ctypes.c_int, [_P, ctypes.POINTER(opt_tuning)]),
+    "opt_problem_get_tuning": (ctypes.c_int, [_P, ctypes.POINTER(opt_tuning)]),
+    "opt_server_reserved_bytes": (ctypes.c_int, [ctypes.c_int32, ctypes.POINTER(ctypes.c_size_t)]),
+    "opt_server_create": (ctypes.c_int, [_P, ctypes.c_size_t, ctypes.c_int32, _P, ctypes.POINTER(_P)]),
+    "opt_server_destroy": (ctypes.c_int, [_P]),
+    "opt_server_submit": (ctypes.c_int, [_P, ctypes.POINTER(opt_problem_desc), _P,
+                                         ctypes.POINTER(opt_solve_params), ctypes.POINTER(ctypes.c_int64)]),
+    "opt_server_step": (ctypes.c_int, [_P]),
+    "opt_server_poll": (ctypes.c_int, [_P, ctypes.c_int64, ctypes.POINTER(ctypes.c_int32),
+                                       ctypes.POINTER(opt_solve_report)]),
+    "opt_server_cancel": (ctypes.c_int, [_P, ctypes.c_int64]),
+    "opt_server_info": (ctypes.c_int, [_P, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_size_t)]),
+    "opt_server_add_tuning": (ctypes.c_int, [_P, ctypes.c_int32, ctypes.c_int32, ctypes.c_int64, ctypes.c_int64,
+                                             ctypes.POINTER(opt_tuning)]),
 }
 _lib = None
 
@@ -116,6 +134,33 @@ def energy_channels(energy):
     return lib().opt_energy_channels(ENERGIES[energy] if isinstance(energy, str) else energy)
 
 
+def make_desc(energy, arrays, params=(), precision="mixed", width=0, height=0, n_vertices=0,
+              edges=None):
+    """An opt_problem_desc for the given tensors; returns (desc, arrays, edges)
+    (the tensors the descriptor points to, to be kept alive by the caller)."""
+    d = opt_problem_desc()
+    d.domain = GRAPH if n_vertices else GRID2D
+    d.energy = ENERGIES[energy]
+    d.precision = PRECISIONS[precision]
+    d.width, d.height = width, height
+    d.n_vertices = n_vertices
+    if edges is not None:
+        if not edges.is_contiguous() or edges.dtype != torch.int32:
+            raise ValueError("edges must be a contiguous int32 tensor of E x 2")
+        d.n_edges = int(edges.shape[0])
+        d.edges = edges.data_ptr()
+    arrays = list(arrays)
+    for k, a in enumerate(arrays):
+        if not a.is_contiguous():
+            raise ValueError(f"array {k} must be contiguous")
+        d.arrays[k] = a.data_ptr()
+    params = list(params)
+    for k, v in enumerate(params):
+        d.params[k] = float(v)
+    d.n_params = len(params)
+    return d, arrays, edges
+
+
 class Problem:
     """One problem instance: a grid or graph, an energy and its data arrays.
 
@@ -126,41 +171,27 @@ class Problem:
     """
 
     def __init__(self, energy, arrays, params=(), precision="mixed", width=0, height=0,
-                 n_vertices=0, edges=None, stream=None):
+                 n_vertices=0, edges=None, stream=None, workspace=None):
         self.energy = energy
         self.precision = precision
         self.dtype = torch.float64 if precision == "fp64" else torch.float32
         self.channels = energy_channels(energy)
-        d = opt_problem_desc()
-        d.domain = GRAPH if n_vertices else GRID2D
-        d.energy = ENERGIES[energy]
-        d.precision = PRECISIONS[precision]
-        d.width, d.height = width, height
-        d.n_vertices = n_vertices
-        self.edges = None
-        if edges is not None:
-            self.edges = edges
-            d.n_edges = int(edges.shape[0])
-            d.edges = edges.data_ptr()
-        self.arrays = list(arrays)
-        for k, a in enumerate(self.arrays):
-            if not a.is_contiguous():
-                raise ValueError(f"array {k} must be contiguous")
-            d.arrays[k] = a.data_ptr()
-        params = list(params)
-        for k, v in enumerate(params):
-            d.params[k] = float(v)
-        d.n_params = len(params)
-        self.desc = d
+        self.desc, self.arrays, self.edges = make_desc(energy, arrays, params, precision, width, height,
+                                                       n_vertices, edges)
+        d = self.desc
         self.n_sites = n_vertices if n_vertices else width * height
         nbytes = ctypes.c_size_t(0)
         _check(lib().opt_workspace_size(ctypes.byref(d), ctypes.byref(nbytes)), "opt_workspace_size")
         dev = self.arrays[0].device
         self.device = dev
-        self.workspace = torch.empty(nbytes.value, dtype=torch.uint8, device=dev)
+        if workspace is None:
+            workspace = torch.empty(nbytes.value, dtype=torch.uint8, device=dev)
+        elif workspace.numel() < nbytes.value or workspace.dtype != torch.uint8:
+            raise ValueError(f"workspace must be a uint8 tensor of at least {nbytes.value} bytes")
+        self.workspace = workspace
         self.stream = stream if stream is not None else torch.cuda.current_stream(dev)
         h = ctypes.c_void_p(0)
-        _check(lib().opt_problem_create(ctypes.byref(d), _ptr(self.workspace), nbytes.value,
+        _check(lib().opt_problem_create(ctypes.byref(d), _ptr(self.workspace), self.workspace.numel(),
                                        ctypes.c_void_p(self.stream.cuda_stream), ctypes.byref(h)),
                "opt_problem_create")
         self.handle = h
@@ -229,6 +260,16 @@ class Problem:
                "opt_apply_jtj")
         return q
 
+    def set_tuning(self, strip_rows=0):
+        t = opt_tuning()
+        t.strip_rows = int(strip_rows)
+        _check(lib().opt_problem_set_tuning(self.handle, ctypes.byref(t)), "opt_problem_set_tuning")
+
+    def get_tuning(self):
+        t = opt_tuning()
+        _check(lib().opt_problem_get_tuning(self.handle, ctypes.byref(t)), "opt_problem_get_tuning")
+        return {"strip_rows": t.strip_rows}
+
     def profile_enable(self, on=True):
         _check(lib().opt_profile_enable(self.handle, int(on)), "opt_profile_enable")
 
@@ -245,3 +286,94 @@ class Problem:
         d = self.new_vector()
         _check(lib().opt_pcg(self.handle, ctypes.byref(prm), float(lam), _ptr(d)), "opt_pcg")
         return d
+
+
+def workspace_size(energy, arrays, params=(), precision="mixed", width=0, height=0, n_vertices=0,
+                   edges=None):
+    d, _, _ = make_desc(energy, arrays, params, precision, width, height, n_vertices, edges)
+    nbytes = ctypes.c_size_t(0)
+    _check(lib().opt_workspace_size(ctypes.byref(d), ctypes.byref(nbytes)), "opt_workspace_size")
+    return nbytes.value
+
+
+class Server:
+    """Continuous-batching server (opt_server_* in include/opt.h).
+
+    ``arena_bytes`` of device memory are allocated here as one torch tensor and
+    handed to the library: it is the memory budget of the requests held at once.
+    """
+
+    def __init__(self, arena_bytes, max_slots=64, device="cuda", stream=None):
+        self.stream = stream if stream is not None else torch.cuda.current_stream(device)
+        self.arena = torch.empty(int(arena_bytes), dtype=torch.uint8, device=device)
+        h = ctypes.c_void_p(0)
+        _check(lib().opt_server_create(_ptr(self.arena), self.arena.numel(), int(max_slots),
+                                      ctypes.c_void_p(self.stream.cuda_stream), ctypes.byref(h)),
+               "opt_server_create")
+        self.handle = h
+        self._held = {}  # ticket -> (desc, tensors, outer_iters), kept alive until collected
+
+    @staticmethod
+    def reserved_bytes(max_slots):
+        b = ctypes.c_size_t(0)
+        _check(lib().opt_server_reserved_bytes(int(max_slots), ctypes.byref(b)), "opt_server_reserved_bytes")
+        return b.value
+
+    def __del__(self):
+        h = getattr(self, "handle", None)
+        if h is not None and h.value:
+            lib().opt_server_destroy(h)
+            self.handle = None
+
+    def submit(self, energy, arrays, x, params=(), precision="mixed", width=0, height=0,
+               n_vertices=0, edges=None, solve_params=None, **kw):
+        """Admit a request solving x in place; returns its ticket, or None when
+        the server is full (OPT_EAGAIN)."""
+        d, arrays, edges = make_desc(energy, arrays, params, precision, width, height, n_vertices, edges)
+        sp = solve_params if solve_params is not None else default_params(**kw)
+        t = ctypes.c_int64(-1)
+        code = lib().opt_server_submit(self.handle, ctypes.byref(d), _ptr(x), ctypes.byref(sp),
+                                       ctypes.byref(t))
+        if code == OPT_EAGAIN:
+            return None
+        _check(code, "opt_server_submit")
+        self._held[t.value] = (d, arrays, edges, x, sp.outer_iters)
+        return t.value
+
+    def step(self):
+        _check(lib().opt_server_step(self.handle), "opt_server_step")
+
+    def poll(self, ticket):
+        """None while the request runs; its report (a dict) once it has left."""
+        done = ctypes.c_int32(0)
+        K = self._held[ticket][4] if ticket in self._held else 0
+        trace = (ctypes.c_double * (K + 1))()
+        rep = opt_solve_report()
+        rep.cost_trace = ctypes.cast(trace, ctypes.POINTER(ctypes.c_double))
+        code = lib().opt_server_poll(self.handle, int(ticket), ctypes.byref(done), ctypes.byref(rep))
+        if code not in (OPT_OK, OPT_ENUMERIC):
+            _check(code, "opt_server_poll")
+        if not done.value:
+            return None
+        self._held.pop(ticket, None)
+        return dict(cost_initial=rep.cost_initial, cost_final=rep.cost_final,
+                    outer_done=rep.outer_done, steps_accepted=rep.steps_accepted,
+                    cost_trace=list(trace), code=code)
+
+    def cancel(self, ticket):
+        _check(lib().opt_server_cancel(self.handle, int(ticket)), "opt_server_cancel")
+        self._held.pop(ticket, None)
+
+    def add_tuning(self, energy, precision, min_sites, max_sites, strip_rows):
+        t = opt_tuning()
+        t.strip_rows = int(strip_rows)
+        _check(lib().opt_server_add_tuning(self.handle, ENERGIES[energy], PRECISIONS[precision],
+                                           int(min_sites), int(max_sites), ctypes.byref(t)),
+               "opt_server_add_tuning")
+
+    def info(self):
+        """(requests held, free arena bytes)."""
+        a = ctypes.c_int32(0)
+        f = ctypes.c_size_t(0)
+        _check(lib().opt_server_info(self.handle, ctypes.byref(a), ctypes.byref(f)), "opt_server_info")
+        return a.value, f.value

@@ -52,10 +52,18 @@ __device__ __forceinline__ double block_sum(double v) {
   return t;
 }
 
-// Store the block's sum of v at out[blockIdx.x].
-__device__ __forceinline__ void block_store(double v, double* out) {
+// The grid a kernel body sees: its block id and block count.  A plain launch
+// passes the hardware grid; a batched launch passes the block's position inside
+// its problem's range of blocks, so each problem is processed exactly as if it
+// had been launched alone.
+struct VG {
+  int bid, nb;
+};
+
+// Store the block's sum of v at out[g.bid].
+__device__ __forceinline__ void block_store(double v, double* out, VG g) {
   const double t = block_sum(v);
-  if (threadIdx.x == 0) out[blockIdx.x] = t;
+  if (threadIdx.x == 0) out[g.bid] = t;
 }
 
 // Sum of the n partials written by the previous kernel, in a fixed order that
@@ -71,7 +79,7 @@ __device__ __forceinline__ double reduce_partials(const double* __restrict__ par
   return total;
 }
 
-__device__ __forceinline__ bool is_block_leader() { return blockIdx.x == 0 && threadIdx.x == 0; }
+__device__ __forceinline__ bool is_block_leader(VG g) { return g.bid == 0 && threadIdx.x == 0; }
 
 // Jacobi preconditioner entry for an unknown with diagonal d (Sec. 4.1): the
 // inverse of the damped diagonal d + lambda*clamp(d), or 0 when that is not
@@ -91,6 +99,46 @@ struct Precond {
 };
 
 __device__ __forceinline__ bool finite_d(double v) { return v - v == 0.0; }
+
+// A raw buffer view of a device array: a scalar descriptor plus a 32-bit byte
+// offset per lane.  Reads at or past `bytes` return 0 and writes there are dropped
+// (hardware range check), which lets masked lanes use an out-of-range offset
+// instead of a branch.  The third descriptor word is the gfx9-family raw-buffer
+// format word.
+constexpr unsigned kBufOutOfRange = 0xF0000000u;  // buffers must stay below 256 MB
+
+template <typename T>
+struct Buf {
+  __amdgpu_buffer_rsrc_t rs;
+  __device__ __forceinline__ static Buf make(const void* p, size_t bytes) {
+    Buf b;
+    b.rs = __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(p), (short)0, (int)bytes, 0x00020000);
+    return b;
+  }
+  __device__ __forceinline__ T load(unsigned off) const;
+  __device__ __forceinline__ void store(unsigned off, T v) const;
+};
+template <>
+__device__ __forceinline__ float Buf<float>::load(unsigned off) const {
+  return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(rs, off, 0, 0));
+}
+template <>
+__device__ __forceinline__ double Buf<double>::load(unsigned off) const {
+  return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(rs, off, 0, 0));
+}
+template <>
+__device__ __forceinline__ uint8_t Buf<uint8_t>::load(unsigned off) const {
+  return __builtin_amdgcn_raw_buffer_load_b8(rs, off, 0, 0);
+}
+template <>
+__device__ __forceinline__ void Buf<float>::store(unsigned off, float v) const {
+  __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), rs, off, 0, 0);
+}
+template <>
+__device__ __forceinline__ void Buf<double>::store(unsigned off, double v) const {
+  typedef unsigned u2 __attribute__((ext_vector_type(2)));
+  __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u2, v), rs, off, 0, 0);
+}
 
 __device__ __forceinline__ void sincos_t(float v, float* s, float* c) { sincosf(v, s, c); }
 __device__ __forceinline__ void sincos_t(double v, double* s, double* c) { sincos(v, s, c); }

@@ -146,7 +146,9 @@ struct ArapWarp {
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
       const int di = k == 0 ? 1 : (k == 1 ? -1 : 0), dj = k == 2 ? 1 : (k == 3 ? -1 : 0);
-      if (!(F(di, dj) & ACTIVE)) continue;
+      // a neighbour that is excluded or off the grid contributes nothing; its
+      // values are finite (zero off the grid), so weight instead of branching
+      const T w = (F(di, dj) & ACTIVE) ? wr2 : T(0);
       const T dx = Ux - S(2, di, dj), dy = Uy - S(3, di, dj);
       const T cq = S(0, di, dj), sq = S(1, di, dj);
       const T qx = P(0, di, dj), qy = P(1, di, dj), qt = P(2, di, dj);
@@ -155,9 +157,9 @@ struct ArapWarp {
       const T ex = px - qx, ey = py - qy;
       const T j1x = ex - apx * pt, j1y = ey - apy * pt;
       const T j2x = -ex - aqx * qt, j2y = -ey - aqy * qt;
-      gx += wr2 * (j1x - j2x);
-      gy += wr2 * (j1y - j2y);
-      gt -= wr2 * (apx * j1x + apy * j1y);
+      gx += w * (j1x - j2x);
+      gy += w * (j1y - j2y);
+      gt -= w * (apx * j1x + apy * j1y);
     }
     if (F(0, 0) & FIT) {
       const T wf2 = wf * wf;

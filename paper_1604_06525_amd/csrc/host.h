@@ -1,0 +1,242 @@
+// Host-side internals shared by the single-problem API (opt_capi.hip) and the
+// batching server (opt_server.hip): error reporting, the workspace layout, the
+// problem handle and the per-energy launch interface.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <functional>
+#include <memory>
+#include <vector>
+
+#include "opt.h"
+#include "common.h"
+#include "kernels.h"
+
+namespace optmi {
+namespace host {
+
+// Record a formatted message as the calling thread's last error; returns code.
+int fail(int code, const char* fmt, ...);
+const char* last_error();
+
+#define HIP_TRY(call)                                                                     \
+  do {                                                                                    \
+    hipError_t e_ = (call);                                                               \
+    if (e_ != hipSuccess)                                                                 \
+      return ::optmi::host::fail(OPT_EHIP, "%s failed: %s (%s:%d)", #call,                \
+                                 hipGetErrorString(e_), __FILE__, __LINE__);              \
+  } while (0)
+
+#define HIP_LAUNCHED(name)                                                                \
+  do {                                                                                    \
+    hipError_t e_ = hipGetLastError();                                                    \
+    if (e_ != hipSuccess)                                                                 \
+      return ::optmi::host::fail(OPT_EHIP, "launch of %s failed: %s", name,               \
+                                 hipGetErrorString(e_));                                  \
+  } while (0)
+
+#define TRY(x)                     \
+  do {                             \
+    int rc_ = (x);                 \
+    if (rc_ != OPT_OK) return rc_; \
+  } while (0)
+
+constexpr size_t kAlign = 256;
+constexpr size_t kMaxArgBytes = 1024;  // bound on any argument row of a batched launch
+constexpr int kTraceCap = 4097;  // outer iterations + 1 that a report can hold
+constexpr int kMaxOuter = kTraceCap - 1;
+
+inline size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
+
+struct Shape {
+  int C = 0;           // unknown channels
+  int state_planes = 0;
+  int n = 0;           // sites
+  size_t tsize = 0;    // bytes of the bulk type
+  int n_edges = 0;     // graph: listed undirected edges
+  bool graph = false;
+};
+
+// Byte offsets of every region of a problem's workspace.
+struct Layout {
+  size_t r0, r1, p0, p1, q, diag, minv, damp, delta, state, flags, csr, parts, scal, trace, total;
+};
+
+// Partial-sum buffers of kMaxBlocks doubles each; the fused form uses two pairs.
+enum { P_LIN = 0, P_RZ0 = 1, P_RZ1 = 2, P_PQ = 3, P_COST = 4, P_M = 5, P_F0 = 6, P_F1 = 8 };
+constexpr int kNumPartBufs = 10;
+
+Layout make_layout(const Shape& sh);
+int check_desc(const opt_problem_desc* d, Shape* sh);
+int check_params(const opt_solve_params* sp);
+
+struct PrecondArgs {
+  double lam, dmin, dmax;
+  int use;
+  bool damped;  // LM: write and apply the damping vector
+};
+
+// ---------------------------------------------------------------- batching
+// Argument tables of batched launches are written into pinned host staging
+// memory while a step is planned, copied to device memory in one transfer, and
+// then the recorded launches are enqueued.
+struct Batcher {
+  char* host = nullptr;   // pinned staging
+  char* dev = nullptr;    // device table area of the same size
+  size_t cap = 0, used = 0;
+  hipStream_t stream = nullptr;
+  std::vector<std::function<int()>> launches;
+
+  void reset() {
+    used = 0;
+    launches.clear();
+  }
+  // Reserve `bytes` (256-aligned); returns the offset or -1 if full.
+  long long reserve(size_t bytes) {
+    const size_t off = align_up(used);
+    if (off + bytes > cap) return -1;
+    used = off + bytes;
+    return (long long)off;
+  }
+};
+
+// One problem's part in a batched launch.
+struct SlotRef {
+  opt_problem* p;
+  void* x;
+  PrecondArgs pa;
+  int lm;
+  int L;          // PCG iterations
+  int trace_idx;  // outer iteration
+};
+
+enum class Stage { LIN, INIT, PCG, MODEL, TRIAL_COST, STEP, COST };
+
+// Launch sequence for one energy and bulk type.
+class Impl {
+ public:
+  virtual ~Impl() = default;
+  virtual int linearize(const void* x, int lm_gate) = 0;
+  virtual int init(const void* x, double* trace, int idx, PrecondArgs pa, int lm_gate) = 0;
+  virtual int pcg_a(int k, int L, PrecondArgs pa, int lm_gate) = 0;
+  virtual int pcg_b(int k, int L, PrecondArgs pa, int lm_gate) = 0;
+  virtual int fused(int iter, int L, PrecondArgs pa, int lm_gate) = 0;
+  virtual bool has_fused() const = 0;
+  virtual int apply_jtj(const void* p, void* q, PrecondArgs pa) = 0;
+  virtual int apply_step(void* x, int lm_gate) = 0;
+  virtual int cost(const void* x, const void* delta, int lm_gate) = 0;
+  virtual int model(const void* x) = 0;
+  // Record one batched launch of `stage` over n problems of this energy and
+  // type (the PCG stage records all of its launches); `fused` picks the form.
+  virtual int batch(Stage stage, const SlotRef* slots, int n, bool fused, Batcher& B) = 0;
+};
+
+}  // namespace host
+}  // namespace optmi
+
+struct opt_problem {
+  opt_problem_desc desc;
+  optmi::host::Shape sh;
+  optmi::host::Layout L;
+  hipStream_t stream = nullptr;
+  char* ws = nullptr;
+  int nblk = 1;
+  const void* last_x = nullptr;
+  opt_tuning tune{};
+  std::unique_ptr<optmi::host::Impl> impl;
+  // PCG-phase timing (opt_profile_enable)
+  bool profile = false;
+  std::vector<hipEvent_t> ev_pool;   // created on demand, reused
+  size_t ev_used = 0;                // events recorded since the last read
+  int64_t prof_iters = 0;
+
+  ~opt_problem() {
+    for (hipEvent_t e : ev_pool) (void)hipEventDestroy(e);
+  }
+
+  void* at(size_t off) const { return ws + off; }
+  double* part(int k) const { return (double*)(ws + L.parts) + (size_t)k * optmi::kMaxBlocks; }
+  optmi::DevScalars* S() const { return (optmi::DevScalars*)(ws + L.scal); }
+  double* trace() const { return (double*)(ws + L.trace); }
+};
+
+namespace optmi {
+namespace host {
+
+// Build the handle's state inside `workspace` (validated descriptor); for a
+// graph this sorts the edges into the incidence list and synchronises.
+int problem_init(opt_problem* p, const opt_problem_desc* desc, const Shape& sh, void* workspace,
+                 hipStream_t stream);
+
+// A one-block scalar kernel on the problem's stream.
+template <class A>
+int scalar_kernel(hipStream_t st, const A& a, const char* name) {
+  k_solo<A><<<1, kBlock, 0, st>>>(a, 0);
+  HIP_LAUNCHED(name);
+  return OPT_OK;
+}
+
+// A batched argument table in the staging area: one row per problem and the
+// first block of each problem's range.
+template <class A>
+struct BatchTable {
+  const A* rows = nullptr;      // device, one per problem
+  const int* start = nullptr;   // device, n + 1 entries: first block of each problem
+  const int* slot_of = nullptr; // device, problem of each block
+  int n = 0, total = 0;         // problems, blocks
+};
+
+template <class A>
+int batch_table(Batcher& B, const A* rows, const int* grids, int n, BatchTable<A>* t) {
+  static_assert(sizeof(A) <= kMaxArgBytes, "argument row larger than the table area allows");
+  long long total = 0;
+  for (int k = 0; k < n; ++k) total += grids[k];
+  if (total > (long long)n * kMaxBlocks) return fail(OPT_EINVAL, "batched grid of %lld blocks", total);
+  const size_t tbytes = sizeof(A) * (size_t)n, sbytes = sizeof(int) * ((size_t)n + 1);
+  const long long ot = B.reserve(tbytes), os = B.reserve(sbytes), om = B.reserve(sizeof(int) * total);
+  if (ot < 0 || os < 0 || om < 0) return fail(OPT_ENOMEM, "server table area is full");
+  A* ht = (A*)(B.host + ot);
+  int* hs = (int*)(B.host + os);
+  int* hm = (int*)(B.host + om);
+  int b = 0;
+  for (int k = 0; k < n; ++k) {
+    ht[k] = rows[k];
+    hs[k] = b;
+    for (int q = 0; q < grids[k]; ++q) hm[b + q] = k;
+    b += grids[k];
+  }
+  hs[n] = b;
+  t->rows = (const A*)(B.dev + ot);
+  t->start = (const int*)(B.dev + os);
+  t->slot_of = (const int*)(B.dev + om);
+  t->n = n;
+  t->total = b;
+  return OPT_OK;
+}
+
+template <class A>
+int batch_launch(const BatchTable<A>& t, int iter, hipStream_t st, const char* name) {
+  k_batch<A><<<t.total, kBlock, 0, st>>>(t.rows, t.start, t.slot_of, iter);
+  HIP_LAUNCHED(name);
+  return OPT_OK;
+}
+
+// Record a batched launch of `A` rows (one per problem) with the given block
+// counts, for iterations [iter_lo, iter_hi).
+template <class A>
+int batch_record(Batcher& B, const A* rows, const int* grids, int n, int iter_lo, int iter_hi,
+                 const char* name) {
+  if (n <= 0 || iter_lo >= iter_hi) return OPT_OK;
+  BatchTable<A> t;
+  TRY(batch_table(B, rows, grids, n, &t));
+  hipStream_t st = B.stream;
+  B.launches.push_back([=]() -> int {
+    for (int it = iter_lo; it < iter_hi; ++it) TRY(batch_launch(t, it, st, name));
+    return OPT_OK;
+  });
+  return OPT_OK;
+}
+
+}  // namespace host
+}  // namespace optmi

@@ -1,4 +1,9 @@
-// Kernels of one solve on a 2D grid, generic over the energy.
+// Kernels of one solve, generic over the energy.
+//
+// Each stage is an argument struct plus a device function run(args, grid, iter).
+// k_solo launches one problem; k_batch launches many problems of one kind at
+// once, each over its own contiguous range of blocks, and gives every block the
+// grid it would have had alone, so results do not depend on the batch.
 //
 // Kernel boundaries are the only grid-wide synchronisation.  A scalar that
 // needs a sum over the whole problem is produced as per-block FP64 partials by
@@ -19,12 +24,8 @@
 //   beta_i = gamma_i/gamma_{i-1},  alpha_i = gamma_i / (delta_i - beta_i gamma_i/alpha_{i-1})
 //   p_i = u_i + beta_i p_{i-1};  s_i = A p_i;  d += alpha_i p_i;  r_{i+1} = r_i - alpha_i s_i
 //   partials of gamma_{i+1} = r_{i+1}.u_{i+1} and delta_{i+1} = (A u_{i+1}).u_{i+1}.
-// A block stages r_i, p_{i-1}, M^-1 and the energy's state for its tile plus a
-// halo of twice the operator radius in LDS, computes p_i on all of it, s_i and
-// r_{i+1} on the tile plus one operator radius, and A u_{i+1} on the tile, so
-// only r, p and d cross HBM once per iteration.  s_i = A p_i is formed exactly
-// (not by its own recurrence).  A first "priming" launch with alpha = beta = 0
-// produces gamma_0 and delta_0.
+// s_i = A p_i is formed exactly (not by its own recurrence).  A first "priming"
+// launch (iter = -1) with alpha = beta = 0 produces gamma_0 and delta_0.
 //
 // If the curvature p.Ap is not positive the solve stops (DevScalars::stopped):
 // every later iteration kernel returns at once and d keeps its value.
@@ -37,8 +38,8 @@ namespace optmi {
 
 // Grid-stride loop over sites with a fixed per-thread order (the grid size
 // depends only on n), so the partial sums are reproducible.
-#define OPT_SITE_LOOP(s, n) \
-  for (int s = blockIdx.x * kBlock + threadIdx.x; s < (n); s += gridDim.x * kBlock)
+#define OPT_SITE_LOOP(s, n, g) \
+  for (int s = (g).bid * kBlock + threadIdx.x; s < (n); s += (g).nb * kBlock)
 
 // Views over global memory centred at site s = (vi_, vj_) of a W x H grid; every
 // read off the grid returns 0 (flags 0: not on the grid).
@@ -90,18 +91,25 @@ __device__ __forceinline__ void site_apply(const E& e, int s, PA P, typename E::
 
 // ---------------------------------------------------------------- linearize
 template <class E>
-__global__ void __launch_bounds__(kBlock)
-k_linearize(E e, const typename E::Real* __restrict__ x, double* __restrict__ part,
-            const DevScalars* __restrict__ S, int lm_gate) {
-  if (lm_gate && (S->done || !S->need_lin)) return;
+struct LinArgs {
+  E e;
+  const typename E::Real* x;
+  double* part;
+  const DevScalars* S;
+  int lm_gate;
+};
+
+template <class E>
+__device__ __forceinline__ void run(const LinArgs<E>& a, VG g, int) {
+  if (a.lm_gate && (a.S->done || !a.S->need_lin)) return;
   double acc = 0.0;
-  const int n = e.n;
-  auto X = [&](int ch, int s) -> double { return (double)x[(size_t)ch * n + s]; };
-  OPT_SITE_LOOP(s, n) {
-    e.linearize(x, s);
-    acc += e.cost(X, s);
+  const int n = a.e.n;
+  auto X = [&](int ch, int s) -> double { return (double)a.x[(size_t)ch * n + s]; };
+  OPT_SITE_LOOP(s, n, g) {
+    a.e.linearize(a.x, s);
+    acc += a.e.cost(X, s);
   }
-  block_store(acc, part);
+  block_store(acc, a.part, g);
 }
 
 // ---------------------------------------------------------------- init
@@ -118,35 +126,48 @@ struct InitOut {
 };
 
 template <class E>
-__global__ void __launch_bounds__(kBlock)
-k_init(E e, const typename E::Real* __restrict__ x, InitOut<typename E::Real> o,
-       const double* __restrict__ lin_part, int n_lin, double* __restrict__ rz_part,
-       DevScalars* S, double* __restrict__ trace, int trace_idx, Precond<typename E::Real> pc,
-       int lm_gate) {
+struct InitArgs {
+  E e;
+  const typename E::Real* x;
+  InitOut<typename E::Real> o;
+  const double* lin_part;
+  int n_lin;
+  double* rz_part;
+  DevScalars* S;
+  double* trace;
+  int trace_idx;
+  Precond<typename E::Real> pc;
+  int lm_gate;
+};
+
+template <class E>
+__device__ __forceinline__ void run(const InitArgs<E>& a, VG g, int) {
   using T = typename E::Real;
   constexpr int C = E::C;
-  if (lm_gate && S->done) return;
+  DevScalars* S = a.S;
+  if (a.lm_gate && S->done) return;
   // LM re-solves at the same x after a rejected step: the cost is then kept.
-  const bool fresh = !lm_gate || S->need_lin;
+  const bool fresh = !a.lm_gate || S->need_lin;
   double E0 = 0.0;
-  if (fresh) E0 = reduce_partials(lin_part, n_lin);
-  if (is_block_leader()) {
+  if (fresh) E0 = reduce_partials(a.lin_part, a.n_lin);
+  if (is_block_leader(g)) {
     if (fresh) {
       S->E0 = E0;
       if (!finite_d(E0)) S->nonfinite = 1;
     } else {
       E0 = S->E0;
     }
-    if (trace) trace[trace_idx] = E0;
+    if (a.trace) a.trace[a.trace_idx] = E0;
     S->stopped = 0;
   }
-  if (lm_gate) pc.lam = (T)S->lambda;
-  const int n = e.n;
+  Precond<T> pc = a.pc;
+  if (a.lm_gate) pc.lam = (T)S->lambda;
+  const int n = a.e.n;
   double rz = 0.0;
-  OPT_SITE_LOOP(s, n) {
+  OPT_SITE_LOOP(s, n, g) {
     T b[C], d[C];
-    if (e.flags[s] & E::ACTIVE) {
-      site_jtf_diag(e, x, s, b, d);
+    if (a.e.flags[s] & E::ACTIVE) {
+      site_jtf_diag(a.e, a.x, s, b, d);
     } else {
 #pragma unroll
       for (int c = 0; c < C; ++c) { b[c] = T(0); d[c] = T(0); }
@@ -155,114 +176,128 @@ k_init(E e, const typename E::Real* __restrict__ x, InitOut<typename E::Real> o,
     for (int c = 0; c < C; ++c) {
       const size_t k = (size_t)c * n + s;
       const T m = pc.minv(d[c]);
-      o.r[k] = b[c];
-      o.diag[k] = d[c];
-      o.minv[k] = m;
-      if (o.damp) o.damp[k] = pc.lam != T(0) ? pc.damp(d[c]) : T(0);
-      o.delta[k] = T(0);
+      a.o.r[k] = b[c];
+      a.o.diag[k] = d[c];
+      a.o.minv[k] = m;
+      if (a.o.damp) a.o.damp[k] = pc.lam != T(0) ? pc.damp(d[c]) : T(0);
+      a.o.delta[k] = T(0);
       rz += (double)b[c] * (double)(m * b[c]);
     }
   }
-  block_store(rz, rz_part);
+  block_store(rz, a.rz_part, g);
 }
 
 // ---------------------------------------------------------------- split: pcg_a
-// MODE 0: PCG iteration (p from r, the previous p and beta).
-// MODE 1: plain product q = (J^T J + damp) p_in (p_in passed as `pold`).
+// Iteration k of the split form (MODE 0), or the plain product
+// q = (J^T J + damp) p_in (MODE 1, with p_in in p[0]).
 template <typename T>
 struct SplitBufs {
   const T* r;
   const T* minv;
-  const T* damp;  // nullptr: no damping
-  const T* pold;
-  T* pnew;
+  const T* damp;   // nullptr: no damping
+  T* p[2];         // iteration k writes p[k & 1] and reads p_{k-1} from p[(k + 1) & 1]
   T* q;
+  double* rz_part[2];  // r.z partials of iteration k are read from rz_part[k & 1]
+  double* pq_part;
 };
 
 template <class E, int MODE>
-__global__ void __launch_bounds__(kBlock)
-k_pcg_a(E e, int k, SplitBufs<typename E::Real> b, const double* __restrict__ rz_part, int n_rz,
-        double* __restrict__ pq_part, DevScalars* S, int lm_gate) {
+struct SplitAArgs {
+  E e;
+  SplitBufs<typename E::Real> b;
+  int n_part;
+  DevScalars* S;
+  int lm_gate;
+  int L;  // iterations of this problem; later ones return at once
+};
+
+template <class E, int MODE>
+__device__ __forceinline__ void run(const SplitAArgs<E, MODE>& a, VG g, int k) {
   using T = typename E::Real;
   constexpr int C = E::C;
-  const int n = e.n;
+  const int n = a.e.n;
+  const SplitBufs<T>& b = a.b;
+  DevScalars* S = a.S;
   T beta = T(0);
   if (MODE == 0) {
-    if (S->stopped || (lm_gate && S->done)) return;
-    const double rz = reduce_partials(rz_part, n_rz);
+    if (k >= a.L || S->stopped || (a.lm_gate && S->done)) return;
+    const double rz = reduce_partials(b.rz_part[k & 1], a.n_part);
     if (k > 0) beta = (T)(rz / S->rz[(k - 1) & 1]);
-    if (is_block_leader()) S->rz[k & 1] = rz;
+    if (is_block_leader(g)) S->rz[k & 1] = rz;
   }
-  double pq = 0.0;
+  const T* pold = MODE == 1 ? b.p[0] : b.p[(k + 1) & 1];
+  T* pnew = b.p[k & 1];
   auto Pg = [&](int c, int site) -> T {
     const size_t o = (size_t)c * n + site;
-    if (MODE == 1) return b.pold[o];
+    if (MODE == 1) return pold[o];
     const T z = b.minv[o] * b.r[o];
-    return k == 0 ? z : fma(beta, b.pold[o], z);
+    return k == 0 ? z : fma(beta, pold[o], z);
   };
-  OPT_SITE_LOOP(s, n) {
-    T g[C];
-    const bool act = e.flags[s] & E::ACTIVE;
-    if (act) site_apply(e, s, Pg, g);
+  double pq = 0.0;
+  OPT_SITE_LOOP(s, n, g) {
+    T gv[C];
+    const bool act = a.e.flags[s] & E::ACTIVE;
+    if (act) site_apply(a.e, s, Pg, gv);
 #pragma unroll
     for (int c = 0; c < C; ++c) {
       const size_t o = (size_t)c * n + s;
       T pv = T(0), qv = T(0);
       if (act) {
         pv = Pg(c, s);
-        qv = g[c];
+        qv = gv[c];
         if (b.damp) qv += b.damp[o] * pv;
       }
-      if (MODE == 0) b.pnew[o] = pv;
+      if (MODE == 0) pnew[o] = pv;
       b.q[o] = qv;
       pq += (double)pv * (double)qv;
     }
   }
-  if (MODE == 0) block_store(pq, pq_part);
+  if (MODE == 0) block_store(pq, b.pq_part, g);
 }
 
 // ---------------------------------------------------------------- split: pcg_b
 template <typename T, int C>
-__global__ void __launch_bounds__(kBlock)
-k_pcg_b(int n, int k, T* __restrict__ delta, T* __restrict__ r, const T* __restrict__ p,
-        const T* __restrict__ q, const T* __restrict__ minv, const double* __restrict__ pq_part,
-        int n_pq, double* __restrict__ rz_part, DevScalars* S, int lm_gate) {
-  if (S->stopped || (lm_gate && S->done)) return;
-  const double pq = reduce_partials(pq_part, n_pq);
+struct SplitBArgs {
+  int n;
+  T* delta;
+  T* r;
+  T* p[2];
+  const T* q;
+  const T* minv;
+  const double* pq_part;
+  double* rz_part[2];  // iteration k writes rz_part[(k + 1) & 1]
+  int n_part;
+  DevScalars* S;
+  int lm_gate;
+  int L;
+};
+
+template <typename T, int C>
+__device__ __forceinline__ void run(const SplitBArgs<T, C>& a, VG g, int k) {
+  DevScalars* S = a.S;
+  if (k >= a.L || S->stopped || (a.lm_gate && S->done)) return;
+  const double pq = reduce_partials(a.pq_part, a.n_part);
   if (!(pq > 0.0)) {
-    if (is_block_leader()) S->stopped = 1;
+    if (is_block_leader(g)) S->stopped = 1;
     return;
   }
   const T alpha = (T)(S->rz[k & 1] / pq);
+  const T* p = a.p[k & 1];
   double rz = 0.0;
-  OPT_SITE_LOOP(s, n) {
+  OPT_SITE_LOOP(s, a.n, g) {
 #pragma unroll
     for (int c = 0; c < C; ++c) {
-      const size_t o = (size_t)c * n + s;
-      delta[o] = fma(alpha, p[o], delta[o]);
-      const T rv = fma(-alpha, q[o], r[o]);
-      r[o] = rv;
-      rz += (double)rv * (double)(minv[o] * rv);
+      const size_t o = (size_t)c * a.n + s;
+      a.delta[o] = fma(alpha, p[o], a.delta[o]);
+      const T rv = fma(-alpha, a.q[o], a.r[o]);
+      a.r[o] = rv;
+      rz += (double)rv * (double)(a.minv[o] * rv);
     }
   }
-  block_store(rz, rz_part);
+  block_store(rz, a.rz_part[(k + 1) & 1], g);
 }
 
 // ---------------------------------------------------------------- fused iteration
-template <typename T>
-struct FusedBufs {
-  const T* r_in;
-  T* r_out;
-  const T* p_in;
-  T* p_out;
-  T* x;            // the PCG solution d, updated in place
-  const T* minv;
-  const T* damp;   // nullptr: no damping
-  const double* part_in;   // [gamma partials | delta partials], kMaxBlocks apart
-  double* part_out;
-  int n_part_in;
-};
-
 // Value that lane l-1 (from_left) or l+1 (from_right) of the wave holds; 0 past
 // the ends of the wave.  DPP wave shifts, so no LDS traffic.
 __device__ __forceinline__ uint32_t dpp_from_left(uint32_t v) {
@@ -290,8 +325,7 @@ __device__ __forceinline__ double from_right(double v) {
 __device__ __forceinline__ uint32_t from_left(uint32_t v) { return dpp_from_left(v); }
 __device__ __forceinline__ uint32_t from_right(uint32_t v) { return dpp_from_right(v); }
 
-// Geometry of the fused kernel on a grid: one wave per strip of 64 columns
-// (60 produced, 2 halo columns on each side) and kStripRows-or-fewer rows.
+// One wave per strip of 64 columns: 60 produced, 2 halo columns on each side.
 constexpr int kStripCols = 60;
 
 // One grid row as one lane sees it (its column), for the streaming kernel.
@@ -341,87 +375,116 @@ __device__ __forceinline__ void stream_apply(const E& e, const StreamRow<E>& U,
   e.apply(Pv, Sv, Fv, col, row, g);
 }
 
-// The k-th unit of work of this block, XCD-aware: blocks go to the 8 XCDs
-// round-robin, and each XCD takes one contiguous run of units so neighbouring
-// strips share its L2.
-__device__ __forceinline__ int unit_of_block(int n_units) {
-  const int G = gridDim.x;
-  if (G % 8 != 0) return blockIdx.x;
-  const int per = G / 8;
-  return (blockIdx.x % 8) * per + blockIdx.x / 8;
+// The unit of work of a block, XCD-aware: blocks go to the 8 XCDs round-robin,
+// and each XCD takes one contiguous run of units so neighbouring strips share its
+// L2.  (In a batch the hardware placement differs; only speed depends on it.)
+__device__ __forceinline__ int unit_of_block(VG g) {
+  if (g.nb % 8 != 0) return g.bid;
+  const int per = g.nb / 8;
+  return (g.bid % 8) * per + g.bid / 8;
 }
 
+template <typename T>
+struct FusedBufs {
+  T* r[2];         // iteration i reads r_i from r[i & 1], writes r_{i+1} to r[(i + 1) & 1]
+  T* p[2];         // iteration i writes p_i to p[i & 1], reads p_{i-1} from p[(i + 1) & 1]
+  T* x;            // the PCG solution d, updated in place
+  const T* minv;
+  const T* damp;   // nullptr: no damping
+  double* part[2]; // [gamma | delta] partials, kMaxBlocks apart; iteration i writes
+                   // part[i & 1] (the priming launch writes part[1]) and reads the other
+};
+
 template <class E>
-__global__ void __launch_bounds__(kBlock)
-k_fused(E e, FusedBufs<typename E::Real> b, DevScalars* S, int iter, int lm_gate, int n_sx,
-        int n_sy, int Hs) {
+struct FusedArgs {
+  E e;
+  FusedBufs<typename E::Real> b;
+  int n_part;  // blocks of this problem
+  DevScalars* S;
+  int lm_gate;
+  int n_sx, n_sy, Hs;  // strips across, strips down, rows per strip
+  int L;
+};
+
+template <class E>
+__device__ __forceinline__ void run(const FusedArgs<E>& a, VG g, int iter) {
   using T = typename E::Real;
   using Row = StreamRow<E>;
   constexpr int C = E::C, NS = E::kStatePlanes;
-  if (S->stopped || (lm_gate && S->done)) return;
+  const E& e = a.e;
+  DevScalars* S = a.S;
+  if (iter >= a.L || S->stopped || (a.lm_gate && S->done)) return;
+  const double* part_in = a.b.part[(iter + 1) & 1];
+  double* part_out = a.b.part[iter & 1];
   double alpha = 0.0, beta = 0.0;
   if (iter >= 0) {
-    const double gam = reduce_partials(b.part_in, b.n_part_in);
-    const double del = reduce_partials(b.part_in + kMaxBlocks, b.n_part_in);
+    const double gam = reduce_partials(part_in, a.n_part);
+    const double del = reduce_partials(part_in + kMaxBlocks, a.n_part);
     double den = del;
     if (iter > 0) {
       beta = gam / S->gam[(iter - 1) & 1];
       den = del - beta * gam / S->alpha[(iter - 1) & 1];
     }
     if (!(den > 0.0)) {
-      if (is_block_leader()) S->stopped = 1;
+      if (is_block_leader(g)) S->stopped = 1;
       return;
     }
     alpha = gam / den;
-    if (is_block_leader()) {
+    if (is_block_leader(g)) {
       S->gam[iter & 1] = gam;
       S->alpha[iter & 1] = alpha;
     }
   }
   const T aT = (T)alpha, bT = (T)beta;
-  const bool read_pold = iter > 0, write_out = iter >= 0, damped = b.damp != nullptr;
-  const int W = e.W, H = e.H, n = e.n;
+  const bool read_pold = iter > 0, write_out = iter >= 0, damped = a.b.damp != nullptr;
+  const int W = e.W, H = e.H, n = e.n, n_sy = a.n_sy, Hs = a.Hs;
   const int lane = threadIdx.x & 63;
-  const int strip = unit_of_block(gridDim.x) * kWaves + (threadIdx.x >> 6);
+  const int strip = unit_of_block(g) * kWaves + (threadIdx.x >> 6);
   double g_acc = 0.0, d_acc = 0.0;
 
-  if (strip < n_sx * n_sy) {
+  if (strip < a.n_sx * n_sy) {
     const int sx = strip / n_sy, sy = strip % n_sy;
     const int col = sx * kStripCols - 2 + lane;
     const int y0 = sy * Hs, y1 = min(y0 + Hs, H);
     const bool colin = col >= 0 && col < W;
     const bool out_lane = colin && lane >= 2 && lane < 2 + kStripCols;
     const int K = (y1 - y0) + 4;  // rows y0-2 .. y1+1
-    Row ring[4];
-    // Raw loads of the rows 1..4 steps ahead: row y0-2+k is issued at step k-4
-    // and finished at step k, so its memory latency overlaps four steps of work.
-    Row pre[4];
-
+    // One raw buffer per vector (all channels), per state plane and for the
+    // flags; a lane or row off the strip reads at an out-of-range offset and gets 0.
+    const size_t vbytes = (size_t)C * n * sizeof(T);
+    const T* r_in = a.b.r[iter < 0 ? 0 : (iter & 1)];
+    T* r_out = a.b.r[(iter + 1) & 1];
+    const Buf<T> Brin = Buf<T>::make(r_in, vbytes), Bm = Buf<T>::make(a.b.minv, vbytes);
+    const Buf<T> Bpin = Buf<T>::make(a.b.p[(iter + 1) & 1], vbytes);
+    const Buf<T> Bx = Buf<T>::make(a.b.x, vbytes);
+    const Buf<T> Bd = Buf<T>::make(a.b.damp, damped ? vbytes : 0);
+    const Buf<T> Brout = Buf<T>::make(r_out, write_out ? vbytes : 0);
+    const Buf<T> Bpout = Buf<T>::make(a.b.p[iter & 1], write_out ? vbytes : 0);
+    Buf<T> Bst[NS > 0 ? NS : 1];
+#pragma unroll
+    for (int q = 0; q < NS; ++q) Bst[q] = Buf<T>::make(e.state_plane(q), (size_t)n * sizeof(T));
+    const Buf<uint8_t> Bf = Buf<uint8_t>::make(e.flags, (size_t)n);
+    const unsigned plane = (unsigned)((size_t)n * sizeof(T));
+    // Row y0-2+k lives in ring slot k & 7.  Its loads are issued four steps before
+    // it is needed, into its own slot, so their latency overlaps four steps of work.
+    Row ring[8];
     auto issue = [&](Row& R, int y) {
       const bool in = colin && y >= 0 && y < H && y <= y1 + 1;
-      const int s = in ? y * W + col : 0;
-      const bool prod = in && y >= y0 && y < y1;
+      const unsigned s = (unsigned)(y * W + col);
+      const unsigned o = in ? s * (unsigned)sizeof(T) : kBufOutOfRange;
+      const unsigned ox = (in && y >= y0 && y < y1 && write_out) ? o : kBufOutOfRange;
+      const unsigned op = read_pold ? o : kBufOutOfRange;
 #pragma unroll
       for (int c = 0; c < C; ++c) {
-        const size_t o = (size_t)c * n + s;
-        R.r[c] = in ? b.r_in[o] : T(0);
-        R.m[c] = in ? b.minv[o] : T(0);
-        R.p[c] = (in && read_pold) ? b.p_in[o] : T(0);
-        R.x[c] = (prod && write_out) ? b.x[o] : T(0);
-        R.dmp[c] = (in && damped) ? b.damp[o] : T(0);
+        R.r[c] = Brin.load(o + c * plane);
+        R.m[c] = Bm.load(o + c * plane);
+        R.p[c] = Bpin.load(op + c * plane);
+        R.x[c] = Bx.load(ox + c * plane);
+        R.dmp[c] = Bd.load(o + c * plane);
       }
 #pragma unroll
-      for (int q = 0; q < NS; ++q) R.st[q] = in ? e.state_plane(q)[s] : T(0);
-      R.f = in ? (uint32_t)e.flags[s] : 0u;
-    };
-    // p_i = M^-1 r_i + beta p_{i-1} (the staged p holds p_{i-1})
-    auto finish = [&](Row& R, const Row& P) {
-      R = P;
-#pragma unroll
-      for (int c = 0; c < C; ++c) {
-        const T u = R.m[c] * R.r[c];
-        R.p[c] = read_pold ? fma(bT, P.p[c], u) : u;
-      }
+      for (int q = 0; q < NS; ++q) R.st[q] = Bst[q].load(o);
+      R.f = Bf.load(in ? s : kBufOutOfRange);
     };
     auto selp = [](const Row& R, int c) { return R.p[c]; };
     auto selu = [](const Row& R, int c) { return R.m[c]; };
@@ -429,20 +492,25 @@ k_fused(E e, FusedBufs<typename E::Real> b, DevScalars* S, int iter, int lm_gate
     auto step = [&](auto PH, int k) {
       constexpr int ph = decltype(PH)::value;
       Row& R0 = ring[ph];            // row y = y0 - 2 + k
-      Row& R1 = ring[(ph + 3) & 3];  // y - 1
-      Row& R2 = ring[(ph + 2) & 3];  // y - 2
-      Row& R3 = ring[(ph + 1) & 3];  // y - 3
+      Row& R1 = ring[(ph + 7) & 7];  // y - 1
+      Row& R2 = ring[(ph + 6) & 7];  // y - 2
+      Row& R3 = ring[(ph + 5) & 7];  // y - 3
       const int y = y0 - 2 + k;
-      finish(R0, pre[ph]);
-      issue(pre[ph], y + 4);
+      issue(ring[(ph + 4) & 7], y + 4);
+      // p_i = M^-1 r_i + beta p_{i-1} on row y (R0.p holds p_{i-1})
+#pragma unroll
+      for (int c = 0; c < C; ++c) {
+        const T u = R0.m[c] * R0.r[c];
+        R0.p[c] = read_pold ? fma(bT, R0.p[c], u) : u;
+      }
       if (k >= 2) {
         // s = A p and r_{i+1}, u_{i+1} on row y - 1
-        T g[C];
-        stream_apply(e, R2, R1, R0, selp, col, y - 1, g);
+        T gv[C];
+        stream_apply(e, R2, R1, R0, selp, col, y - 1, gv);
         const bool act = R1.f & E::ACTIVE;
 #pragma unroll
         for (int c = 0; c < C; ++c) {
-          const T sv = damped ? fma(R1.dmp[c], R1.p[c], g[c]) : g[c];
+          const T sv = damped ? fma(R1.dmp[c], R1.p[c], gv[c]) : gv[c];
           R1.r[c] = act ? fma(-aT, sv, R1.r[c]) : T(0);
           R1.m[c] = act ? R1.m[c] * R1.r[c] : T(0);
         }
@@ -461,133 +529,177 @@ k_fused(E e, FusedBufs<typename E::Real> b, DevScalars* S, int iter, int lm_gate
             d_acc += (double)ww * (double)R2.m[c];
           }
         }
-        if (write_out && out_lane) {
-          const int s = yo * W + col;
+        // masked lanes store out of range (dropped)
+        const unsigned o = out_lane ? (unsigned)(yo * W + col) * (unsigned)sizeof(T) : kBufOutOfRange;
+        const unsigned ox = (act && write_out) ? o : kBufOutOfRange;
 #pragma unroll
-          for (int c = 0; c < C; ++c) {
-            const size_t o = (size_t)c * n + s;
-            const T pv = act ? R2.p[c] : T(0);
-            if (act) b.x[o] = fma(aT, pv, R2.x[c]);
-            b.r_out[o] = R2.r[c];
-            b.p_out[o] = pv;
-          }
+        for (int c = 0; c < C; ++c) {
+          const T pv = act ? R2.p[c] : T(0);
+          Bx.store(ox + c * plane, fma(aT, pv, R2.x[c]));
+          Brout.store(o + c * plane, R2.r[c]);
+          Bpout.store(o + c * plane, pv);
         }
       }
     };
-    issue(pre[0], y0 - 2);
-    issue(pre[1], y0 - 1);
-    issue(pre[2], y0);
-    issue(pre[3], y0 + 1);
-    for (int k = 0; k < K; k += 4) {
+#pragma unroll
+    for (int k = 0; k < 4; ++k) issue(ring[k], y0 - 2 + k);
+    for (int k = 0; k < K; k += 8) {
       step(std::integral_constant<int, 0>{}, k);
       if (k + 1 < K) step(std::integral_constant<int, 1>{}, k + 1);
       if (k + 2 < K) step(std::integral_constant<int, 2>{}, k + 2);
       if (k + 3 < K) step(std::integral_constant<int, 3>{}, k + 3);
+      if (k + 4 < K) step(std::integral_constant<int, 4>{}, k + 4);
+      if (k + 5 < K) step(std::integral_constant<int, 5>{}, k + 5);
+      if (k + 6 < K) step(std::integral_constant<int, 6>{}, k + 6);
+      if (k + 7 < K) step(std::integral_constant<int, 7>{}, k + 7);
     }
   }
-  const double gs_ = block_sum(g_acc);
-  const double ds_ = block_sum(d_acc);
+  const double gs = block_sum(g_acc);
+  const double ds = block_sum(d_acc);
   if (threadIdx.x == 0) {
-    b.part_out[blockIdx.x] = gs_;
-    b.part_out[kMaxBlocks + blockIdx.x] = ds_;
+    part_out[g.bid] = gs;
+    part_out[kMaxBlocks + g.bid] = ds;
   }
 }
 
 // ---------------------------------------------------------------- updates
 // GN: x += d on active sites.  LM: the same, only if the step was accepted.
 template <class E>
-__global__ void __launch_bounds__(kBlock)
-k_apply_step(E e, typename E::Real* __restrict__ x, const typename E::Real* __restrict__ delta,
-             const DevScalars* __restrict__ S, int lm_gate) {
+struct StepArgs {
+  E e;
+  typename E::Real* x;
+  const typename E::Real* delta;
+  const DevScalars* S;
+  int lm_gate;
+};
+
+template <class E>
+__device__ __forceinline__ void run(const StepArgs<E>& a, VG g, int) {
   constexpr int C = E::C;
-  if (lm_gate && !S->accepted) return;
-  const int n = e.n;
-  OPT_SITE_LOOP(s, n) {
-    if (!(e.flags[s] & E::ACTIVE)) continue;
+  if (a.lm_gate && !a.S->accepted) return;
+  const int n = a.e.n;
+  OPT_SITE_LOOP(s, n, g) {
+    if (!(a.e.flags[s] & E::ACTIVE)) continue;
 #pragma unroll
     for (int c = 0; c < C; ++c) {
       const size_t o = (size_t)c * n + s;
-      x[o] = x[o] + delta[o];
+      a.x[o] = a.x[o] + a.delta[o];
     }
   }
 }
 
 // ---------------------------------------------------------------- cost
 // FP64 cost partials at x (delta == nullptr) or at the trial point x + delta,
-// rounded to the bulk type exactly as k_apply_step would store it.
+// rounded to the bulk type exactly as the step update would store it.
 template <class E>
-__global__ void __launch_bounds__(kBlock)
-k_cost(E e, const typename E::Real* __restrict__ x, const typename E::Real* __restrict__ delta,
-       double* __restrict__ part, const DevScalars* __restrict__ S, int lm_gate) {
+struct CostArgs {
+  E e;
+  const typename E::Real* x;
+  const typename E::Real* delta;
+  double* part;
+  const DevScalars* S;
+  int lm_gate;
+};
+
+template <class E>
+__device__ __forceinline__ void run(const CostArgs<E>& a, VG g, int) {
   using T = typename E::Real;
-  if (lm_gate && S->done) return;
-  const int n = e.n;
+  if (a.lm_gate && a.S->done) return;
+  const int n = a.e.n;
   auto X = [&](int c, int s) -> double {
     const size_t o = (size_t)c * n + s;
-    if (delta == nullptr) return (double)x[o];
-    return (double)(T)(x[o] + delta[o]);
+    if (a.delta == nullptr) return (double)a.x[o];
+    return (double)(T)(a.x[o] + a.delta[o]);
   };
   double acc = 0.0;
-  OPT_SITE_LOOP(s, n) acc += e.cost(X, s);
-  block_store(acc, part);
+  OPT_SITE_LOOP(s, n, g) acc += a.e.cost(X, s);
+  block_store(acc, a.part, g);
 }
 
 // LM model partials: sum_r (J d)_r (2 F_r + (J d)_r) at x.
 template <class E>
-__global__ void __launch_bounds__(kBlock)
-k_model(E e, const typename E::Real* __restrict__ x, const typename E::Real* __restrict__ delta,
-        double* __restrict__ part, const DevScalars* __restrict__ S) {
-  if (S->done) return;
-  const int n = e.n;
-  auto X = [&](int c, int s) -> double { return (double)x[(size_t)c * n + s]; };
-  auto D = [&](int c, int s) -> double { return (double)delta[(size_t)c * n + s]; };
+struct ModelArgs {
+  E e;
+  const typename E::Real* x;
+  const typename E::Real* delta;
+  double* part;
+  const DevScalars* S;
+};
+
+template <class E>
+__device__ __forceinline__ void run(const ModelArgs<E>& a, VG g, int) {
+  if (a.S->done) return;
+  const int n = a.e.n;
+  auto X = [&](int c, int s) -> double { return (double)a.x[(size_t)c * n + s]; };
+  auto D = [&](int c, int s) -> double { return (double)a.delta[(size_t)c * n + s]; };
   double acc = 0.0;
-  OPT_SITE_LOOP(s, n) acc += e.model(X, D, s);
-  block_store(acc, part);
+  OPT_SITE_LOOP(s, n, g) acc += a.e.model(X, D, s);
+  block_store(acc, a.part, g);
 }
 
-// ---------------------------------------------------------------- scalar kernels
+// ---------------------------------------------------------------- scalar kernels (one block)
 struct LMConsts {
   double radius_min, radius_max, min_rel_decrease;
 };
 
-// Single block.  Sets up the scalars of a solve.
-__global__ void k_setup(DevScalars* S, double lambda, double radius0, int lm) {
+// Sets up the scalars of a solve.
+struct SetupArgs {
+  DevScalars* S;
+  double lambda, radius0;
+  int lm;
+  double radius_min;  // LM: a solve whose initial radius is below this does nothing
+};
+
+__device__ __forceinline__ void run(const SetupArgs& a, VG, int) {
   if (threadIdx.x == 0) {
+    DevScalars* S = a.S;
     S->rz[0] = S->rz[1] = 0.0;
     S->gam[0] = S->gam[1] = 0.0;
     S->alpha[0] = S->alpha[1] = 0.0;
     S->E0 = S->E1 = S->m = 0.0;
-    S->radius = radius0;
+    S->radius = a.radius0;
     S->nu = 2.0;
-    S->lambda = lm ? 1.0 / radius0 : lambda;
+    S->lambda = a.lm ? 1.0 / a.radius0 : a.lambda;
     S->E_final = 0.0;
     S->stopped = 0;
     S->accepted = 0;
     S->need_lin = 1;
-    S->done = 0;
+    S->done = a.lm && a.radius0 < a.radius_min ? 1 : 0;
     S->n_accepted = 0;
     S->outer_done = 0;
     S->nonfinite = 0;
   }
 }
 
-// Single block.  LM step decision (gain ratio, Nielsen radius update).
-__global__ void k_lm_decide(DevScalars* S, const double* __restrict__ m_part,
-                            const double* __restrict__ c_part, int nb, LMConsts lc) {
-  if (S->done) return;
+// LM step decision (gain ratio, Nielsen radius update).
+struct DecideArgs {
+  DevScalars* S;
+  const double* m_part;
+  const double* c_part;
+  int nb;
+  LMConsts lc;
+};
+
+__device__ __forceinline__ void run(const DecideArgs& a, VG, int) {
+  DevScalars* S = a.S;
+  if (S->done) {
+    // the solve has ended: the update of this outer iteration must not repeat
+    // the last accepted step
+    if (threadIdx.x == 0) S->accepted = 0;
+    return;
+  }
   // the partials hold sum (J d)(2F + J d); the model decrease is its negation
-  const double m = -reduce_partials(m_part, nb);
-  const double E1 = reduce_partials(c_part, nb);
+  const double m = -reduce_partials(a.m_part, a.nb);
+  const double E1 = reduce_partials(a.c_part, a.nb);
   if (threadIdx.x == 0) {
     S->m = m;
     S->E1 = E1;
     if (!finite_d(E1)) S->nonfinite = 1;
     const double rho = m != 0.0 ? (S->E0 - E1) / m : -INFINITY;
-    if (m > 0.0 && rho > lc.min_rel_decrease) {
+    if (m > 0.0 && rho > a.lc.min_rel_decrease) {
       const double t = 2.0 * rho - 1.0;
       const double f = fmax(1.0 / 3.0, 1.0 - t * t * t);
-      S->radius = fmin(S->radius / f, lc.radius_max);
+      S->radius = fmin(S->radius / f, a.lc.radius_max);
       S->nu = 2.0;
       S->accepted = 1;
       S->need_lin = 1;
@@ -600,20 +712,56 @@ __global__ void k_lm_decide(DevScalars* S, const double* __restrict__ m_part,
       S->need_lin = 0;
     }
     S->outer_done += 1;
-    if (S->radius < lc.radius_min) S->done = 1;
+    if (S->radius < a.lc.radius_min) S->done = 1;
     S->lambda = 1.0 / S->radius;
   }
 }
 
-// Single block.  Finish a cost reduction into E_final (and optionally a trace slot).
-__global__ void k_finish_cost(DevScalars* S, const double* __restrict__ part, int nb,
-                              double* __restrict__ trace, int trace_idx) {
-  const double E = reduce_partials(part, nb);
+// Finish a cost reduction into E_final (and optionally a trace slot).
+struct FinishArgs {
+  DevScalars* S;
+  const double* part;
+  int nb;
+  double* trace;
+  int trace_idx;
+};
+
+__device__ __forceinline__ void run(const FinishArgs& a, VG, int) {
+  const double E = reduce_partials(a.part, a.nb);
   if (threadIdx.x == 0) {
-    S->E_final = E;
-    if (!finite_d(E)) S->nonfinite = 1;
-    if (trace) trace[trace_idx] = E;
+    a.S->E_final = E;
+    if (!finite_d(E)) a.S->nonfinite = 1;
+    if (a.trace) a.trace[a.trace_idx] = E;
   }
+}
+
+// Copy a problem's scalars into a gathering area (one read-back for many problems).
+struct GatherArgs {
+  const DevScalars* src;
+  DevScalars* dst;
+};
+
+__device__ __forceinline__ void run(const GatherArgs& a, VG, int) {
+  if (threadIdx.x == 0) *a.dst = *a.src;
+}
+
+// ---------------------------------------------------------------- launchers
+template <class A>
+__global__ void __launch_bounds__(kBlock) k_solo(A a, int iter) {
+  run(a, VG{(int)blockIdx.x, (int)gridDim.x}, iter);
+}
+
+// Many problems of one kind in one launch: problem j owns blocks
+// [start[j], start[j+1]), slot_of[b] names the problem of block b, and its
+// arguments are table[j].
+template <class A>
+__global__ void __launch_bounds__(kBlock) k_batch(const A* __restrict__ table,
+                                                  const int* __restrict__ start,
+                                                  const int* __restrict__ slot_of, int iter) {
+  const int b = blockIdx.x;
+  const int j = slot_of[b];
+  const A a = table[j];
+  run(a, VG{b - start[j], start[j + 1] - start[j]}, iter);
 }
 
 }  // namespace optmi

@@ -14,15 +14,15 @@
 #include <vector>
 
 #include "opt.h"
-#include "common.h"
-#include "kernels.h"
+#include "host.h"
 #include "energies.h"
 
-using namespace optmi;
+namespace optmi {
+namespace host {
 
 namespace {
-
 thread_local std::string g_err;
+}
 
 int fail(int code, const char* fmt, ...) {
   char buf[512];
@@ -34,42 +34,7 @@ int fail(int code, const char* fmt, ...) {
   return code;
 }
 
-#define HIP_TRY(call)                                                                     \
-  do {                                                                                    \
-    hipError_t e_ = (call);                                                               \
-    if (e_ != hipSuccess)                                                                 \
-      return fail(OPT_EHIP, "%s failed: %s (%s:%d)", #call, hipGetErrorString(e_), __FILE__, \
-                  __LINE__);                                                              \
-  } while (0)
-
-#define HIP_LAUNCHED(name)                                                               \
-  do {                                                                                    \
-    hipError_t e_ = hipGetLastError();                                                    \
-    if (e_ != hipSuccess)                                                                 \
-      return fail(OPT_EHIP, "launch of %s failed: %s", name, hipGetErrorString(e_));     \
-  } while (0)
-
-constexpr size_t kAlign = 256;
-constexpr int kTraceCap = 4097;  // outer iterations + 1 that a report can hold
-constexpr int kMaxOuter = kTraceCap - 1;
-
-size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
-
-struct Shape {
-  int C = 0;           // unknown channels
-  int state_planes = 0;
-  int n = 0;           // sites
-  size_t tsize = 0;    // bytes of the bulk type
-  int n_edges = 0;     // graph: listed undirected edges
-  bool graph = false;
-};
-
-// Byte offsets of every region of the workspace.
-struct Layout {
-  size_t r0, r1, p0, p1, q, diag, minv, damp, delta, state, flags, csr, parts, scal, trace, total;
-};
-
-constexpr int kNumPartBufs = 10;  // see the P_* indices
+const char* last_error() { return g_err.c_str(); }
 
 Layout make_layout(const Shape& sh) {
   Layout L{};
@@ -89,6 +54,8 @@ Layout make_layout(const Shape& sh) {
   L.total = off;
   return L;
 }
+
+namespace {
 
 int energy_channels(int e) {
   switch (e) {
@@ -134,6 +101,8 @@ int n_arrays_needed(int e) {
   }
 }
 
+}  // namespace
+
 int check_desc(const opt_problem_desc* d, Shape* sh) {
   if (!d) return fail(OPT_EINVAL, "descriptor is NULL");
   if (d->precision != OPT_FP64 && d->precision != OPT_MIXED)
@@ -173,59 +142,7 @@ int check_desc(const opt_problem_desc* d, Shape* sh) {
   return OPT_OK;
 }
 
-struct PrecondArgs {
-  double lam, dmin, dmax;
-  int use;
-  bool damped;  // LM: write and apply the damping vector
-};
-
-// Launch sequence for one energy and bulk type.
-class Impl {
- public:
-  virtual ~Impl() = default;
-  virtual int linearize(const void* x, int lm_gate) = 0;
-  virtual int init(const void* x, double* trace, int idx, PrecondArgs pa, int lm_gate) = 0;
-  virtual int pcg_a(int k, PrecondArgs pa, int lm_gate) = 0;
-  virtual int pcg_b(int k, PrecondArgs pa, int lm_gate) = 0;
-  virtual int fused(int iter, PrecondArgs pa, int lm_gate) = 0;
-  virtual bool has_fused() const = 0;
-  virtual int apply_jtj(const void* p, void* q, PrecondArgs pa) = 0;
-  virtual int apply_step(void* x, int lm_gate) = 0;
-  virtual int cost(const void* x, const void* delta, int lm_gate) = 0;
-  virtual int model(const void* x) = 0;
-};
-
-}  // namespace
-
-struct opt_problem {
-  opt_problem_desc desc;
-  Shape sh;
-  Layout L;
-  hipStream_t stream = nullptr;
-  char* ws = nullptr;
-  int nblk = 1;
-  const void* last_x = nullptr;
-  std::unique_ptr<Impl> impl;
-  // PCG-phase timing (opt_profile_enable)
-  bool profile = false;
-  std::vector<hipEvent_t> ev_pool;   // created on demand, reused
-  size_t ev_used = 0;                // events recorded since the last read
-  int64_t prof_iters = 0;
-
-  ~opt_problem() {
-    for (hipEvent_t e : ev_pool) (void)hipEventDestroy(e);
-  }
-
-  void* at(size_t off) const { return ws + off; }
-  double* part(int k) const { return (double*)(ws + L.parts) + (size_t)k * kMaxBlocks; }
-  DevScalars* S() const { return (DevScalars*)(ws + L.scal); }
-  double* trace() const { return (double*)(ws + L.trace); }
-};
-
 namespace {
-
-// partial-sum buffers (kMaxBlocks doubles each); the fused form uses two pairs
-enum { P_LIN = 0, P_RZ0 = 1, P_RZ1 = 2, P_PQ = 3, P_COST = 4, P_M = 5, P_F0 = 6, P_F1 = 8 };
 
 // Strips of the fused kernel: about this many waves per launch (4.5 per CU).
 constexpr int kFusedTargetStrips = 1152;
@@ -234,10 +151,12 @@ struct StripGeom {
   int n_sx, n_sy, Hs, grid;
 };
 
-StripGeom strip_geom(int W, int H) {
+// rows > 0 fixes the strip height (a tuned value); 0 picks it for about
+// kFusedTargetStrips strips.
+StripGeom strip_geom(int W, int H, int rows) {
   StripGeom g;
   g.n_sx = (W + kStripCols - 1) / kStripCols;
-  g.Hs = std::max(4, (g.n_sx * H + kFusedTargetStrips - 1) / kFusedTargetStrips);
+  g.Hs = rows > 0 ? rows : std::max(4, (g.n_sx * H + kFusedTargetStrips - 1) / kFusedTargetStrips);
   g.n_sy = (H + g.Hs - 1) / g.Hs;
   const int max_strips = kWaves * kMaxBlocks;
   if (g.n_sx * g.n_sy > max_strips) {
@@ -259,95 +178,230 @@ class ImplT final : public Impl {
     Precond<T> c;
     c.lam = (T)a.lam;
     c.dmin = (T)a.dmin;
-    c.dmax = (T)a.dmax;
     c.use = a.use;
+    c.dmax = (T)a.dmax;
     return c;
   }
   T* vec(size_t off) const { return (T*)p_->at(off); }
   T* pbuf(int k) const { return vec((k & 1) ? p_->L.p1 : p_->L.p0); }
   T* rbuf(int k) const { return vec((k & 1) ? p_->L.r1 : p_->L.r0); }
   T* damp(PrecondArgs pa) const { return pa.damped ? vec(p_->L.damp) : nullptr; }
+  int nblk() const { return p_->nblk; }
 
-  int linearize(const void* x, int lm_gate) override {
-    k_linearize<E><<<p_->nblk, kBlock, 0, p_->stream>>>(e_, (const T*)x, p_->part(P_LIN), p_->S(),
-                                                         lm_gate);
-    HIP_LAUNCHED("k_linearize");
+  // ------------------------------------------------ argument builders
+  LinArgs<E> lin_args(const void* x, int lm) const {
+    return LinArgs<E>{e_, (const T*)x, p_->part(P_LIN), p_->S(), lm};
+  }
+  InitArgs<E> init_args(const void* x, double* trace, int idx, PrecondArgs pa, int lm) const {
+    InitArgs<E> a;
+    a.e = e_;
+    a.x = (const T*)x;
+    a.o = InitOut<T>{rbuf(0), vec(p_->L.diag), vec(p_->L.minv), damp(pa), vec(p_->L.delta)};
+    a.lin_part = p_->part(P_LIN);
+    a.n_lin = p_->nblk;
+    a.rz_part = p_->part(P_RZ0);
+    a.S = p_->S();
+    a.trace = trace;
+    a.trace_idx = idx;
+    a.pc = pc(pa);
+    a.lm_gate = lm;
+    return a;
+  }
+  SplitBufs<T> split_bufs(PrecondArgs pa) const {
+    SplitBufs<T> b;
+    b.r = rbuf(0);
+    b.minv = vec(p_->L.minv);
+    b.damp = damp(pa);
+    b.p[0] = pbuf(0);
+    b.p[1] = pbuf(1);
+    b.q = vec(p_->L.q);
+    b.rz_part[0] = p_->part(P_RZ0);
+    b.rz_part[1] = p_->part(P_RZ1);
+    b.pq_part = p_->part(P_PQ);
+    return b;
+  }
+  SplitAArgs<E, 0> pcga_args(int L, PrecondArgs pa, int lm) const {
+    return SplitAArgs<E, 0>{e_, split_bufs(pa), p_->nblk, p_->S(), lm, L};
+  }
+  SplitBArgs<T, E::C> pcgb_args(int L, int lm) const {
+    SplitBArgs<T, E::C> a;
+    a.n = e_.n;
+    a.delta = vec(p_->L.delta);
+    a.r = rbuf(0);
+    a.p[0] = pbuf(0);
+    a.p[1] = pbuf(1);
+    a.q = vec(p_->L.q);
+    a.minv = vec(p_->L.minv);
+    a.pq_part = p_->part(P_PQ);
+    a.rz_part[0] = p_->part(P_RZ0);
+    a.rz_part[1] = p_->part(P_RZ1);
+    a.n_part = p_->nblk;
+    a.S = p_->S();
+    a.lm_gate = lm;
+    a.L = L;
+    return a;
+  }
+  FusedArgs<E> fused_args(int L, PrecondArgs pa, int lm, int* grid) const {
+    const StripGeom g = strip_geom(e_.W, e_.H, p_->tune.strip_rows);
+    FusedArgs<E> a;
+    a.e = e_;
+    a.b.r[0] = rbuf(0);
+    a.b.r[1] = rbuf(1);
+    a.b.p[0] = pbuf(0);
+    a.b.p[1] = pbuf(1);
+    a.b.x = vec(p_->L.delta);
+    a.b.minv = vec(p_->L.minv);
+    a.b.damp = damp(pa);
+    a.b.part[0] = p_->part(P_F0);
+    a.b.part[1] = p_->part(P_F1);
+    a.n_part = g.grid;
+    a.S = p_->S();
+    a.lm_gate = lm;
+    a.n_sx = g.n_sx;
+    a.n_sy = g.n_sy;
+    a.Hs = g.Hs;
+    a.L = L;
+    *grid = g.grid;
+    return a;
+  }
+  StepArgs<E> step_args(void* x, int lm) const {
+    return StepArgs<E>{e_, (T*)x, vec(p_->L.delta), p_->S(), lm};
+  }
+  CostArgs<E> cost_args(const void* x, const void* delta, int lm) const {
+    return CostArgs<E>{e_, (const T*)x, (const T*)delta, p_->part(P_COST), p_->S(), lm};
+  }
+  ModelArgs<E> model_args(const void* x) const {
+    return ModelArgs<E>{e_, (const T*)x, vec(p_->L.delta), p_->part(P_M), p_->S()};
+  }
+
+  // ------------------------------------------------ single-problem launches
+  template <class A>
+  int go(const A& a, int grid, int iter, const char* name) {
+    k_solo<A><<<grid, kBlock, 0, p_->stream>>>(a, iter);
+    HIP_LAUNCHED(name);
     return OPT_OK;
   }
-  int init(const void* x, double* trace, int idx, PrecondArgs pa, int lm_gate) override {
-    InitOut<T> o{rbuf(0), vec(p_->L.diag), vec(p_->L.minv), damp(pa), vec(p_->L.delta)};
-    k_init<E><<<p_->nblk, kBlock, 0, p_->stream>>>(e_, (const T*)x, o, p_->part(P_LIN), p_->nblk,
-                                                    p_->part(P_RZ0), p_->S(), trace, idx, pc(pa),
-                                                    lm_gate);
-    HIP_LAUNCHED("k_init");
-    return OPT_OK;
+
+  int linearize(const void* x, int lm) override { return go(lin_args(x, lm), nblk(), 0, "linearize"); }
+  int init(const void* x, double* trace, int idx, PrecondArgs pa, int lm) override {
+    return go(init_args(x, trace, idx, pa, lm), nblk(), 0, "init");
   }
-  int pcg_a(int k, PrecondArgs pa, int lm_gate) override {
-    SplitBufs<T> b{rbuf(0), vec(p_->L.minv), damp(pa), pbuf(k + 1), pbuf(k), vec(p_->L.q)};
-    k_pcg_a<E, 0><<<p_->nblk, kBlock, 0, p_->stream>>>(
-        e_, k, b, p_->part((k & 1) ? P_RZ1 : P_RZ0), p_->nblk, p_->part(P_PQ), p_->S(), lm_gate);
-    HIP_LAUNCHED("k_pcg_a");
-    return OPT_OK;
+  int pcg_a(int k, int L, PrecondArgs pa, int lm) override {
+    return go(pcga_args(L, pa, lm), nblk(), k, "pcg_a");
   }
-  int pcg_b(int k, PrecondArgs pa, int lm_gate) override {
-    (void)pa;
-    k_pcg_b<T, E::C><<<p_->nblk, kBlock, 0, p_->stream>>>(
-        e_.n, k, vec(p_->L.delta), rbuf(0), pbuf(k), vec(p_->L.q), vec(p_->L.minv),
-        p_->part(P_PQ), p_->nblk, p_->part((k & 1) ? P_RZ0 : P_RZ1), p_->S(), lm_gate);
-    HIP_LAUNCHED("k_pcg_b");
-    return OPT_OK;
+  int pcg_b(int k, int L, PrecondArgs, int lm) override { return go(pcgb_args(L, lm), nblk(), k, "pcg_b"); }
+  // The fused kernel addresses each vector through a raw buffer of < 256 MB.
+  bool has_fused() const override {
+    return E::kRadius == 1 && !E::kGraph && (size_t)E::C * e_.n * sizeof(T) <= (size_t(1) << 28);
   }
-  // iter = -1 is the priming launch (it writes only partials); iteration i reads
-  // r from rbuf(i), p_{i-1} from pbuf(i+1), and the partials of i-1.
-  bool has_fused() const override { return E::kRadius == 1 && !E::kGraph; }
-  int fused(int iter, PrecondArgs pa, int lm_gate) override {
+  // iter = -1 is the priming launch (it writes only partials).
+  int fused(int iter, int L, PrecondArgs pa, int lm) override {
     if constexpr (E::kRadius != 1 || E::kGraph) {
       return fail(OPT_EUNSUPPORTED, "the fused PCG kernel needs an operator of radius 1");
     } else {
-      return fused_launch(iter, pa, lm_gate);
+      int grid = 0;
+      const FusedArgs<E> a = fused_args(L, pa, lm, &grid);
+      return go(a, grid, iter, "fused");
     }
   }
-  int fused_launch(int iter, PrecondArgs pa, int lm_gate) {
-    const StripGeom g = strip_geom(e_.W, e_.H);
-    FusedBufs<T> b;
-    b.r_in = iter < 0 ? rbuf(0) : rbuf(iter);
-    b.r_out = iter < 0 ? nullptr : rbuf(iter + 1);
-    b.p_in = pbuf(iter + 1);
-    b.p_out = iter < 0 ? nullptr : pbuf(iter);
-    b.x = vec(p_->L.delta);
-    b.minv = vec(p_->L.minv);
-    b.damp = damp(pa);
-    b.part_in = p_->part((iter & 1) ? P_F0 : P_F1);
-    b.part_out = p_->part((iter & 1) ? P_F1 : P_F0);
-    b.n_part_in = g.grid;
-    k_fused<E><<<g.grid, kBlock, 0, p_->stream>>>(e_, b, p_->S(), iter, lm_gate, g.n_sx, g.n_sy,
-                                                   g.Hs);
-    HIP_LAUNCHED("k_fused");
-    return OPT_OK;
-  }
   int apply_jtj(const void* pin, void* qout, PrecondArgs pa) override {
-    SplitBufs<T> b{nullptr, nullptr, damp(pa), (const T*)pin, nullptr, (T*)qout};
-    k_pcg_a<E, 1><<<p_->nblk, kBlock, 0, p_->stream>>>(e_, 0, b, nullptr, 0, nullptr, p_->S(), 0);
-    HIP_LAUNCHED("k_pcg_a<apply>");
-    return OPT_OK;
+    SplitBufs<T> b{};
+    b.damp = damp(pa);
+    b.p[0] = (T*)pin;
+    b.q = (T*)qout;
+    return go(SplitAArgs<E, 1>{e_, b, 0, p_->S(), 0, 1}, nblk(), 0, "apply");
   }
-  int apply_step(void* x, int lm_gate) override {
-    k_apply_step<E><<<p_->nblk, kBlock, 0, p_->stream>>>(e_, (T*)x, vec(p_->L.delta), p_->S(),
-                                                          lm_gate);
-    HIP_LAUNCHED("k_apply_step");
-    return OPT_OK;
+  int apply_step(void* x, int lm) override { return go(step_args(x, lm), nblk(), 0, "step"); }
+  int cost(const void* x, const void* delta, int lm) override {
+    return go(cost_args(x, delta, lm), nblk(), 0, "cost");
   }
-  int cost(const void* x, const void* delta, int lm_gate) override {
-    k_cost<E><<<p_->nblk, kBlock, 0, p_->stream>>>(e_, (const T*)x, (const T*)delta,
-                                                    p_->part(P_COST), p_->S(), lm_gate);
-    HIP_LAUNCHED("k_cost");
-    return OPT_OK;
+  int model(const void* x) override { return go(model_args(x), nblk(), 0, "model"); }
+
+  // ------------------------------------------------ batched launches
+  // Every problem keeps the grid it has alone, so its per-block partials and
+  // results are the same bits in a batch as in a single-problem solve.
+  template <class A, class F>
+  static int rec(Batcher& B, const SlotRef* s, int n, F make, int lo, int hi, const char* name) {
+    std::vector<A> rows((size_t)n);
+    std::vector<int> grids((size_t)n);
+    for (int k = 0; k < n; ++k) {
+      const ImplT* im = static_cast<const ImplT*>(s[k].p->impl.get());
+      rows[(size_t)k] = make(*im, s[k], &grids[(size_t)k]);
+    }
+    return batch_record(B, rows.data(), grids.data(), n, lo, hi, name);
   }
-  int model(const void* x) override {
-    k_model<E><<<p_->nblk, kBlock, 0, p_->stream>>>(e_, (const T*)x, vec(p_->L.delta),
-                                                     p_->part(P_M), p_->S());
-    HIP_LAUNCHED("k_model");
-    return OPT_OK;
+
+  int batch(Stage st, const SlotRef* s, int n, bool use_fused, Batcher& B) override {
+    if (n <= 0) return OPT_OK;
+    int Lmax = 0;
+    for (int k = 0; k < n; ++k) Lmax = std::max(Lmax, s[k].L);
+    switch (st) {
+      case Stage::LIN:
+        return rec<LinArgs<E>>(B, s, n, [](const ImplT& m, const SlotRef& r, int* g) {
+          *g = m.nblk();
+          return m.lin_args(r.x, r.lm);
+        }, 0, 1, "linearize[batch]");
+      case Stage::INIT:
+        return rec<InitArgs<E>>(B, s, n, [](const ImplT& m, const SlotRef& r, int* g) {
+          *g = m.nblk();
+          return m.init_args(r.x, r.p->trace(), r.trace_idx, r.pa, r.lm);
+        }, 0, 1, "init[batch]");
+      case Stage::PCG:
+        if (use_fused) {
+          if constexpr (E::kRadius != 1 || E::kGraph) {
+            return fail(OPT_EUNSUPPORTED, "the fused PCG kernel needs an operator of radius 1");
+          } else {
+            return rec<FusedArgs<E>>(B, s, n, [](const ImplT& m, const SlotRef& r, int* g) {
+              return m.fused_args(r.L, r.pa, r.lm, g);
+            }, -1, Lmax, "fused[batch]");
+          }
+        } else {
+          // the two kernels of each iteration alternate, so record them in turn
+          std::vector<SplitAArgs<E, 0>> ra((size_t)n);
+          std::vector<SplitBArgs<T, E::C>> rb((size_t)n);
+          std::vector<int> grids((size_t)n);
+          for (int k = 0; k < n; ++k) {
+            const ImplT* im = static_cast<const ImplT*>(s[k].p->impl.get());
+            ra[(size_t)k] = im->pcga_args(s[k].L, s[k].pa, s[k].lm);
+            rb[(size_t)k] = im->pcgb_args(s[k].L, s[k].lm);
+            grids[(size_t)k] = im->nblk();
+          }
+          BatchTable<SplitAArgs<E, 0>> ta;
+          BatchTable<SplitBArgs<T, E::C>> tb;
+          TRY(batch_table(B, ra.data(), grids.data(), n, &ta));
+          TRY(batch_table(B, rb.data(), grids.data(), n, &tb));
+          hipStream_t stream = B.stream;
+          B.launches.push_back([=]() -> int {
+            for (int it = 0; it < Lmax; ++it) {
+              TRY(batch_launch(ta, it, stream, "pcg_a[batch]"));
+              TRY(batch_launch(tb, it, stream, "pcg_b[batch]"));
+            }
+            return OPT_OK;
+          });
+          return OPT_OK;
+        }
+      case Stage::MODEL:
+        return rec<ModelArgs<E>>(B, s, n, [](const ImplT& m, const SlotRef& r, int* g) {
+          *g = m.nblk();
+          return m.model_args(r.x);
+        }, 0, 1, "model[batch]");
+      case Stage::TRIAL_COST:
+        return rec<CostArgs<E>>(B, s, n, [](const ImplT& m, const SlotRef& r, int* g) {
+          *g = m.nblk();
+          return m.cost_args(r.x, r.p->at(r.p->L.delta), 1);
+        }, 0, 1, "trial_cost[batch]");
+      case Stage::STEP:
+        return rec<StepArgs<E>>(B, s, n, [](const ImplT& m, const SlotRef& r, int* g) {
+          *g = m.nblk();
+          return m.step_args(r.x, r.lm);
+        }, 0, 1, "step[batch]");
+      case Stage::COST:
+        return rec<CostArgs<E>>(B, s, n, [](const ImplT& m, const SlotRef& r, int* g) {
+          *g = m.nblk();
+          return m.cost_args(r.x, nullptr, 0);
+        }, 0, 1, "cost[batch]");
+    }
+    return fail(OPT_EINVAL, "unknown stage");
   }
 
  private:
@@ -486,6 +540,24 @@ int build_incidence(opt_problem* p) {
   return OPT_OK;
 }
 
+}  // namespace
+
+int problem_init(opt_problem* p, const opt_problem_desc* desc, const Shape& sh, void* workspace,
+                 hipStream_t stream) {
+  p->desc = *desc;
+  p->sh = sh;
+  p->L = make_layout(sh);
+  p->stream = stream;
+  p->ws = (char*)workspace;
+  p->nblk = (int)std::min<long long>(kMaxBlocks, (sh.n + kBlock - 1) / kBlock);
+  if (p->nblk < 1) p->nblk = 1;
+  p->impl = make_impl(p);
+  if (!p->impl) return fail(OPT_EUNSUPPORTED, "energy %d is not built", desc->energy);
+  if (sh.graph) TRY(build_incidence(p));
+  TRY(scalar_kernel(p->stream, SetupArgs{p->S(), 0.0, 1.0, 0, 0.0}, "setup"));
+  return OPT_OK;
+}
+
 int check_params(const opt_solve_params* sp) {
   if (!sp) return fail(OPT_EINVAL, "solve params are NULL");
   if (sp->method != OPT_GN && sp->method != OPT_LM)
@@ -506,6 +578,8 @@ int check_params(const opt_solve_params* sp) {
   return OPT_OK;
 }
 
+namespace {
+
 int sync_scalars(opt_problem* p, DevScalars* hs) {
   HIP_TRY(hipMemcpyAsync(hs, p->S(), sizeof(DevScalars), hipMemcpyDeviceToHost, p->stream));
   HIP_TRY(hipStreamSynchronize(p->stream));
@@ -524,33 +598,32 @@ int record_event(opt_problem* p) {
   return OPT_OK;
 }
 
-#define TRY(x)              \
-  do {                      \
-    int rc_ = (x);          \
-    if (rc_ != OPT_OK) return rc_; \
-  } while (0)
-
 // The L iterations of the inner solve after init, in the chosen form.  Energies
 // whose operator reaches further than one site (shape from shading) always use
 // the split form.
 int run_pcg(opt_problem* p, PrecondArgs pa, int lm, int L, int variant) {
   if (variant == OPT_PCG_FUSED && p->impl->has_fused()) {
-    if (L > 0) TRY(p->impl->fused(-1, pa, lm));
-    for (int i = 0; i < L; ++i) TRY(p->impl->fused(i, pa, lm));
+    if (L > 0) TRY(p->impl->fused(-1, L, pa, lm));
+    for (int i = 0; i < L; ++i) TRY(p->impl->fused(i, L, pa, lm));
   } else {
     for (int k = 0; k < L; ++k) {
-      TRY(p->impl->pcg_a(k, pa, lm));
-      TRY(p->impl->pcg_b(k, pa, lm));
+      TRY(p->impl->pcg_a(k, L, pa, lm));
+      TRY(p->impl->pcg_b(k, L, pa, lm));
     }
   }
   return OPT_OK;
 }
 
 }  // namespace
+}  // namespace host
+}  // namespace optmi
+
+using namespace optmi;
+using namespace optmi::host;
 
 extern "C" {
 
-const char* opt_last_error(void) { return g_err.c_str(); }
+const char* opt_last_error(void) { return last_error(); }
 
 int opt_energy_channels(int32_t energy) { return energy_channels(energy); }
 
@@ -592,18 +665,7 @@ int opt_problem_create(const opt_problem_desc* desc, void* workspace, size_t wor
                 L.total);
   std::unique_ptr<opt_problem> p(new (std::nothrow) opt_problem());
   if (!p) return fail(OPT_ENOMEM, "host allocation failed");
-  p->desc = *desc;
-  p->sh = sh;
-  p->L = L;
-  p->stream = (hipStream_t)hip_stream;
-  p->ws = (char*)workspace;
-  p->nblk = (int)std::min<long long>(kMaxBlocks, (sh.n + kBlock - 1) / kBlock);
-  if (p->nblk < 1) p->nblk = 1;
-  p->impl = make_impl(p.get());
-  if (!p->impl) return fail(OPT_EUNSUPPORTED, "energy %d is not built", desc->energy);
-  if (sh.graph) TRY(build_incidence(p.get()));
-  k_setup<<<1, 64, 0, p->stream>>>(p->S(), 0.0, 1.0, 0);
-  HIP_LAUNCHED("k_setup");
+  TRY(problem_init(p.get(), desc, sh, workspace, (hipStream_t)hip_stream));
   *out = p.release();
   return OPT_OK;
 }
@@ -618,8 +680,7 @@ int opt_linearize(opt_problem* p, const void* x, double* cost) {
   TRY(p->impl->linearize(x, 0));
   p->last_x = x;
   if (cost) {
-    k_finish_cost<<<1, kBlock, 0, p->stream>>>(p->S(), p->part(P_LIN), p->nblk, nullptr, 0);
-    HIP_LAUNCHED("k_finish_cost");
+    TRY(scalar_kernel(p->stream, FinishArgs{p->S(), p->part(P_LIN), p->nblk, nullptr, 0}, "finish"));
     DevScalars hs;
     TRY(sync_scalars(p, &hs));
     *cost = hs.E_final;
@@ -659,14 +720,29 @@ int opt_pcg(opt_problem* p, const opt_solve_params* sp, double lambda, void* del
   TRY(check_params(sp));
   if (!p->last_x) return fail(OPT_EINVAL, "opt_linearize has not been called");
   PrecondArgs pa{lambda, sp->lm_diag_min, sp->lm_diag_max, sp->use_precond, lambda != 0.0};
-  k_setup<<<1, 64, 0, p->stream>>>(p->S(), lambda, 1.0, 0);
-  HIP_LAUNCHED("k_setup");
+  TRY(scalar_kernel(p->stream, SetupArgs{p->S(), lambda, 1.0, 0, 0.0}, "setup"));
   TRY(p->impl->init(p->last_x, nullptr, 0, pa, 0));
   TRY(run_pcg(p, pa, 0, sp->pcg_iters, sp->pcg_variant));
   if (delta_out) {
     const size_t bytes = (size_t)p->sh.C * p->sh.n * p->sh.tsize;
     HIP_TRY(hipMemcpyAsync(delta_out, p->at(p->L.delta), bytes, hipMemcpyDeviceToDevice, p->stream));
   }
+  return OPT_OK;
+}
+
+int opt_problem_set_tuning(opt_problem* p, const opt_tuning* t) {
+  if (!p || !t) return fail(OPT_EINVAL, "problem or tuning is NULL");
+  if (t->strip_rows < 0 || t->strip_rows > (1 << 20))
+    return fail(OPT_EINVAL, "strip_rows %d outside [0, 2^20]", t->strip_rows);
+  p->tune = *t;
+  return OPT_OK;
+}
+
+int opt_problem_get_tuning(opt_problem* p, opt_tuning* t) {
+  if (!p || !t) return fail(OPT_EINVAL, "problem or tuning is NULL");
+  *t = p->tune;
+  if (t->strip_rows == 0 && !p->sh.graph)
+    t->strip_rows = strip_geom(p->desc.width, p->desc.height, 0).Hs;
   return OPT_OK;
 }
 
@@ -695,8 +771,7 @@ int opt_profile_read(opt_problem* p, double* pcg_ms, int64_t* pcg_iters) {
 int opt_cost(opt_problem* p, const void* x, double* cost) {
   if (!p || !x || !cost) return fail(OPT_EINVAL, "problem, unknowns or cost is NULL");
   TRY(p->impl->cost(x, nullptr, 0));
-  k_finish_cost<<<1, kBlock, 0, p->stream>>>(p->S(), p->part(P_COST), p->nblk, nullptr, 0);
-  HIP_LAUNCHED("k_finish_cost");
+  TRY(scalar_kernel(p->stream, FinishArgs{p->S(), p->part(P_COST), p->nblk, nullptr, 0}, "finish"));
   DevScalars hs;
   TRY(sync_scalars(p, &hs));
   *cost = hs.E_final;
@@ -710,8 +785,7 @@ int opt_solve(opt_problem* p, void* x, const opt_solve_params* sp, opt_solve_rep
   const int K = sp->outer_iters, Lp = sp->pcg_iters;
   const int lm = sp->method == OPT_LM;
   double* trace = p->trace();
-  k_setup<<<1, 64, 0, p->stream>>>(p->S(), 0.0, sp->lm_radius0, lm);
-  HIP_LAUNCHED("k_setup");
+  TRY(scalar_kernel(p->stream, SetupArgs{p->S(), 0.0, sp->lm_radius0, lm, sp->lm_radius_min}, "setup"));
   PrecondArgs pa{0.0, sp->lm_diag_min, sp->lm_diag_max, sp->use_precond, lm != 0};
   LMConsts lc{sp->lm_radius_min, sp->lm_radius_max, sp->lm_min_rel_decrease};
   for (int k = 0; k < K; ++k) {
@@ -726,14 +800,12 @@ int opt_solve(opt_problem* p, void* x, const opt_solve_params* sp, opt_solve_rep
     if (lm) {
       TRY(p->impl->model(x));
       TRY(p->impl->cost(x, p->at(p->L.delta), 1));
-      k_lm_decide<<<1, kBlock, 0, p->stream>>>(p->S(), p->part(P_M), p->part(P_COST), p->nblk, lc);
-      HIP_LAUNCHED("k_lm_decide");
+      TRY(scalar_kernel(p->stream, DecideArgs{p->S(), p->part(P_M), p->part(P_COST), p->nblk, lc}, "decide"));
     }
     TRY(p->impl->apply_step(x, lm));
   }
   TRY(p->impl->cost(x, nullptr, 0));
-  k_finish_cost<<<1, kBlock, 0, p->stream>>>(p->S(), p->part(P_COST), p->nblk, nullptr, 0);
-  HIP_LAUNCHED("k_finish_cost");
+  TRY(scalar_kernel(p->stream, FinishArgs{p->S(), p->part(P_COST), p->nblk, nullptr, 0}, "finish"));
   p->last_x = nullptr;
   if (!rep) return OPT_OK;
   DevScalars hs;

@@ -1,0 +1,418 @@
+// Serving many solves at once (continuous batching).
+//
+// The paper notes that a GPU solver is inefficient on problems with few
+// unknowns (Sec. 8, on the small examples): one problem of a few thousand sites
+// fills a small fraction of the chip, and every kernel launch costs about as
+// much as the work it carries.  The server runs many requests together: each
+// step advances every active request by one outer iteration, and every stage of
+// that iteration is one launch per energy kind covering all requests of that
+// kind (k_batch), each over the block range it would have alone.  Requests join
+// at any step when a slot is free and their workspace fits in the arena, and
+// leave when they finish, so the batch changes from step to step.
+//
+// Each request's arithmetic, partial sums and reduction order are those of the
+// single-problem solve, so a request gives the same bits whether it runs alone
+// or in any batch.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstring>
+#include <map>
+#include <memory>
+#include <new>
+#include <vector>
+
+#include "opt.h"
+#include "host.h"
+
+using namespace optmi;
+using namespace optmi::host;
+
+namespace {
+
+constexpr int kStageKinds = 12;        // table kinds that one step can write
+constexpr int kMaxKinds = 20;          // energy x precision x PCG form
+
+// Arena byte ranges, first fit with coalescing.
+class RangeAlloc {
+ public:
+  void reset(size_t off, size_t bytes) {
+    free_.clear();
+    if (bytes) free_[off] = bytes;
+  }
+  bool alloc(size_t bytes, size_t* off) {
+    for (auto it = free_.begin(); it != free_.end(); ++it) {
+      if (it->second < bytes) continue;
+      *off = it->first;
+      const size_t rest = it->second - bytes, at = it->first + bytes;
+      free_.erase(it);
+      if (rest) free_[at] = rest;
+      return true;
+    }
+    return false;
+  }
+  void release(size_t off, size_t bytes) {
+    auto it = free_.emplace(off, bytes).first;
+    auto nx = std::next(it);
+    if (nx != free_.end() && it->first + it->second == nx->first) {
+      it->second += nx->second;
+      free_.erase(nx);
+    }
+    if (it != free_.begin()) {
+      auto pv = std::prev(it);
+      if (pv->first + pv->second == it->first) {
+        pv->second += it->second;
+        free_.erase(it);
+      }
+    }
+  }
+  size_t free_bytes() const {
+    size_t t = 0;
+    for (auto& kv : free_) t += kv.second;
+    return t;
+  }
+
+ private:
+  std::map<size_t, size_t> free_;
+};
+
+enum class SlotState { EMPTY, NEW, RUN, FIN };
+
+struct Slot {
+  SlotState state = SlotState::EMPTY;
+  int64_t ticket = -1;
+  std::unique_ptr<opt_problem> p;
+  size_t ws_off = 0, ws_bytes = 0;
+  void* x = nullptr;
+  opt_solve_params sp{};
+  int it = 0;             // outer iterations enqueued
+  bool lm_done = false;   // LM radius fell below its minimum (seen after a step)
+  bool fused = false;     // PCG form used
+};
+
+struct TuneEntry {
+  int32_t energy, precision;
+  int64_t min_sites, max_sites;
+  opt_tuning t;
+};
+
+struct Result {
+  opt_solve_report rep{};
+  std::vector<double> trace;
+  bool nonfinite = false;
+};
+
+// Every table kind holds, over all energy kinds, one argument row and one start
+// entry per problem, one block-to-problem entry per block (at most kMaxBlocks
+// per problem), and per kind one extra start entry and three alignment gaps.
+size_t table_area_bytes(int max_slots) {
+  const size_t per_stage = (size_t)max_slots * (kMaxArgBytes + sizeof(int) + sizeof(int) * kMaxBlocks) +
+                           (size_t)kMaxKinds * (sizeof(int) + 3 * kAlign);
+  return align_up((size_t)kStageKinds * per_stage);
+}
+
+size_t gather_bytes(int max_slots) { return align_up((size_t)max_slots * sizeof(DevScalars)); }
+
+}  // namespace
+
+struct opt_server {
+  char* arena = nullptr;
+  size_t arena_bytes = 0;
+  int max_slots = 0;
+  hipStream_t stream = nullptr;
+  Batcher B;
+  DevScalars* dev_gather = nullptr;   // device, one row per slot
+  DevScalars* host_gather = nullptr;  // pinned
+  RangeAlloc ranges;
+  std::vector<Slot> slots;
+  std::map<int64_t, Result> results;
+  std::vector<TuneEntry> tuning;  // later entries take precedence
+  int64_t next_ticket = 1;
+
+  ~opt_server() {
+    if (B.host) (void)hipHostFree(B.host);
+    if (host_gather) (void)hipHostFree(host_gather);
+  }
+};
+
+namespace {
+
+int key_of(const Slot& s) {
+  return (s.p->desc.energy * 2 + s.p->desc.precision) * 2 + (s.fused ? 1 : 0);
+}
+
+SlotRef ref_of(Slot& s) {
+  SlotRef r;
+  r.p = s.p.get();
+  r.x = s.x;
+  const int lm = s.sp.method == OPT_LM;
+  r.pa = PrecondArgs{0.0, s.sp.lm_diag_min, s.sp.lm_diag_max, s.sp.use_precond, lm != 0};
+  r.lm = lm;
+  r.L = s.sp.pcg_iters;
+  r.trace_idx = s.it;
+  return r;
+}
+
+// Record `stage` for the slots listed, one batched launch per energy kind.
+int record_stage(opt_server* sv, Stage st, const std::vector<int>& ids) {
+  std::map<int, std::vector<SlotRef>> groups;
+  for (int i : ids) groups[key_of(sv->slots[(size_t)i])].push_back(ref_of(sv->slots[(size_t)i]));
+  for (auto& kv : groups) {
+    std::vector<SlotRef>& g = kv.second;
+    const bool fused = (kv.first & 1) != 0;
+    TRY(g[0].p->impl->batch(st, g.data(), (int)g.size(), fused, sv->B));
+  }
+  return OPT_OK;
+}
+
+template <class A, class F>
+int record_scalar(opt_server* sv, const std::vector<int>& ids, F make, const char* name) {
+  if (ids.empty()) return OPT_OK;
+  std::vector<A> rows;
+  std::vector<int> grids(ids.size(), 1);
+  for (int i : ids) rows.push_back(make(sv->slots[(size_t)i], i));
+  return batch_record(sv->B, rows.data(), grids.data(), (int)rows.size(), 0, 1, name);
+}
+
+void release_slot(opt_server* sv, Slot& s) {
+  sv->ranges.release(s.ws_off, s.ws_bytes);
+  s = Slot();
+}
+
+}  // namespace
+
+extern "C" {
+
+int opt_server_reserved_bytes(int32_t max_slots, size_t* bytes) {
+  if (!bytes) return fail(OPT_EINVAL, "bytes is NULL");
+  if (max_slots < 1 || max_slots > 4096) return fail(OPT_EINVAL, "max_slots %d outside [1, 4096]", max_slots);
+  *bytes = table_area_bytes(max_slots) + gather_bytes(max_slots);
+  return OPT_OK;
+}
+
+int opt_server_create(void* arena, size_t arena_bytes, int32_t max_slots, void* hip_stream,
+                      opt_server** out) {
+  if (!out) return fail(OPT_EINVAL, "out is NULL");
+  *out = nullptr;
+  size_t reserved = 0;
+  TRY(opt_server_reserved_bytes(max_slots, &reserved));
+  if (!arena) return fail(OPT_EINVAL, "arena is NULL");
+  if (((uintptr_t)arena) % kAlign) return fail(OPT_EINVAL, "arena must be %zu-byte aligned", kAlign);
+  if (arena_bytes < reserved)
+    return fail(OPT_ENOMEM, "arena of %zu bytes is smaller than the %zu the server keeps", arena_bytes,
+                reserved);
+  std::unique_ptr<opt_server> sv(new (std::nothrow) opt_server());
+  if (!sv) return fail(OPT_ENOMEM, "host allocation failed");
+  sv->arena = (char*)arena;
+  sv->arena_bytes = arena_bytes;
+  sv->max_slots = max_slots;
+  sv->stream = (hipStream_t)hip_stream;
+  sv->slots.resize((size_t)max_slots);
+  const size_t tb = table_area_bytes(max_slots), gb = gather_bytes(max_slots);
+  HIP_TRY(hipHostMalloc((void**)&sv->B.host, tb, hipHostMallocDefault));
+  HIP_TRY(hipHostMalloc((void**)&sv->host_gather, gb, hipHostMallocDefault));
+  sv->B.dev = sv->arena;
+  sv->B.cap = tb;
+  sv->B.stream = sv->stream;
+  sv->dev_gather = (DevScalars*)(sv->arena + tb);
+  sv->ranges.reset(tb + gb, (arena_bytes - tb - gb) / kAlign * kAlign);
+  *out = sv.release();
+  return OPT_OK;
+}
+
+int opt_server_destroy(opt_server* sv) {
+  delete sv;
+  return OPT_OK;
+}
+
+int opt_server_submit(opt_server* sv, const opt_problem_desc* desc, void* unknowns,
+                      const opt_solve_params* sp, int64_t* ticket) {
+  if (!sv || !unknowns || !ticket) return fail(OPT_EINVAL, "server, unknowns or ticket is NULL");
+  *ticket = -1;
+  Shape sh;
+  TRY(check_desc(desc, &sh));
+  TRY(check_params(sp));
+  const size_t need = align_up(make_layout(sh).total);
+  size_t slot = (size_t)sv->max_slots;
+  for (size_t k = 0; k < sv->slots.size(); ++k)
+    if (sv->slots[k].state == SlotState::EMPTY) {
+      slot = k;
+      break;
+    }
+  if (slot == (size_t)sv->max_slots) return fail(OPT_EAGAIN, "all %d slots are busy", sv->max_slots);
+  size_t off = 0;
+  if (!sv->ranges.alloc(need, &off))
+    return fail(OPT_EAGAIN, "no free arena range of %zu bytes (%zu free in total)", need,
+                sv->ranges.free_bytes());
+  std::unique_ptr<opt_problem> p(new (std::nothrow) opt_problem());
+  if (!p) {
+    sv->ranges.release(off, need);
+    return fail(OPT_ENOMEM, "host allocation failed");
+  }
+  const int rc = problem_init(p.get(), desc, sh, sv->arena + off, sv->stream);
+  if (rc != OPT_OK) {
+    sv->ranges.release(off, need);
+    return rc;
+  }
+  for (auto it = sv->tuning.rbegin(); it != sv->tuning.rend(); ++it)
+    if (it->energy == desc->energy && it->precision == desc->precision && sh.n >= it->min_sites &&
+        sh.n <= it->max_sites) {
+      p->tune = it->t;
+      break;
+    }
+  Slot& s = sv->slots[slot];
+  s.state = SlotState::NEW;
+  s.ticket = sv->next_ticket++;
+  s.ws_off = off;
+  s.ws_bytes = need;
+  s.x = unknowns;
+  s.sp = *sp;
+  s.it = 0;
+  s.lm_done = false;
+  s.fused = sp->pcg_variant == OPT_PCG_FUSED && p->impl->has_fused();
+  s.p = std::move(p);
+  *ticket = s.ticket;
+  return OPT_OK;
+}
+
+int opt_server_step(opt_server* sv) {
+  if (!sv) return fail(OPT_EINVAL, "server is NULL");
+  sv->B.reset();
+  std::vector<int> fresh, run, lm_run, fin, touched;
+  for (int i = 0; i < sv->max_slots; ++i) {
+    Slot& s = sv->slots[(size_t)i];
+    if (s.state == SlotState::NEW) {
+      fresh.push_back(i);
+      s.state = SlotState::RUN;
+    }
+    if (s.state != SlotState::RUN) continue;
+    touched.push_back(i);
+    if (s.it < s.sp.outer_iters && !s.lm_done) {
+      run.push_back(i);
+      if (s.sp.method == OPT_LM) lm_run.push_back(i);
+    }
+  }
+  if (touched.empty()) return OPT_OK;
+  // solve setup for requests that joined
+  TRY(record_scalar<SetupArgs>(sv, fresh, [](Slot& s, int) {
+    return SetupArgs{s.p->S(), 0.0, s.sp.lm_radius0, s.sp.method == OPT_LM ? 1 : 0, s.sp.lm_radius_min};
+  }, "setup[batch]"));
+  // one outer iteration (Sec. 4) for every running request
+  TRY(record_stage(sv, Stage::LIN, run));
+  TRY(record_stage(sv, Stage::INIT, run));
+  TRY(record_stage(sv, Stage::PCG, run));
+  TRY(record_stage(sv, Stage::MODEL, lm_run));
+  TRY(record_stage(sv, Stage::TRIAL_COST, lm_run));
+  TRY(record_scalar<DecideArgs>(sv, lm_run, [](Slot& s, int) {
+    const LMConsts lc{s.sp.lm_radius_min, s.sp.lm_radius_max, s.sp.lm_min_rel_decrease};
+    return DecideArgs{s.p->S(), s.p->part(P_M), s.p->part(P_COST), s.p->nblk, lc};
+  }, "decide[batch]"));
+  TRY(record_stage(sv, Stage::STEP, run));
+  for (int i : run) sv->slots[(size_t)i].it += 1;
+  // final cost for requests that have finished their iterations
+  for (int i : touched) {
+    const Slot& s = sv->slots[(size_t)i];
+    if (s.it >= s.sp.outer_iters || s.lm_done) fin.push_back(i);
+  }
+  TRY(record_stage(sv, Stage::COST, fin));
+  TRY(record_scalar<FinishArgs>(sv, fin, [](Slot& s, int) {
+    return FinishArgs{s.p->S(), s.p->part(P_COST), s.p->nblk, nullptr, 0};
+  }, "finish[batch]"));
+  DevScalars* dg = sv->dev_gather;
+  TRY(record_scalar<GatherArgs>(sv, touched, [dg](Slot& s, int i) {
+    return GatherArgs{s.p->S(), dg + i};
+  }, "gather[batch]"));
+  // enqueue: tables, launches, read-backs; then wait once
+  if (sv->B.used) HIP_TRY(hipMemcpyAsync(sv->B.dev, sv->B.host, sv->B.used, hipMemcpyHostToDevice, sv->stream));
+  for (auto& f : sv->B.launches) TRY(f());
+  HIP_TRY(hipMemcpyAsync(sv->host_gather, sv->dev_gather, sizeof(DevScalars) * (size_t)sv->max_slots,
+                         hipMemcpyDeviceToHost, sv->stream));
+  std::vector<std::vector<double>> traces(fin.size());
+  for (size_t k = 0; k < fin.size(); ++k) {
+    const Slot& s = sv->slots[(size_t)fin[k]];
+    traces[k].assign((size_t)s.sp.outer_iters + 1, 0.0);
+    if (s.sp.outer_iters > 0)
+      HIP_TRY(hipMemcpyAsync(traces[k].data(), s.p->trace(), sizeof(double) * (size_t)s.sp.outer_iters,
+                             hipMemcpyDeviceToHost, sv->stream));
+  }
+  HIP_TRY(hipStreamSynchronize(sv->stream));
+  for (int i : touched) {
+    Slot& s = sv->slots[(size_t)i];
+    const DevScalars& hs = sv->host_gather[i];
+    if (s.sp.method == OPT_LM && hs.done) s.lm_done = true;
+  }
+  // retire finished requests; the report matches opt_solve's
+  for (size_t k = 0; k < fin.size(); ++k) {
+    Slot& s = sv->slots[(size_t)fin[k]];
+    const DevScalars& hs = sv->host_gather[fin[k]];
+    const int K = s.sp.outer_iters, lm = s.sp.method == OPT_LM;
+    const int done = lm ? hs.outer_done : K;
+    Result r;
+    r.trace = std::move(traces[k]);
+    for (int j = done; j <= K; ++j) r.trace[(size_t)j] = hs.E_final;
+    r.rep.cost_initial = K > 0 ? r.trace[0] : hs.E_final;
+    r.rep.cost_final = hs.E_final;
+    r.rep.outer_done = done;
+    r.rep.steps_accepted = lm ? hs.n_accepted : K;
+    r.rep.cost_trace = nullptr;
+    r.nonfinite = hs.nonfinite != 0;
+    sv->results[s.ticket] = std::move(r);
+    release_slot(sv, s);
+  }
+  return OPT_OK;
+}
+
+int opt_server_poll(opt_server* sv, int64_t ticket, int32_t* done, opt_solve_report* report) {
+  if (!sv || !done) return fail(OPT_EINVAL, "server or done is NULL");
+  *done = 0;
+  auto it = sv->results.find(ticket);
+  if (it == sv->results.end()) {
+    for (const Slot& s : sv->slots)
+      if (s.state != SlotState::EMPTY && s.ticket == ticket) return OPT_OK;
+    return fail(OPT_EINVAL, "ticket %lld is not known (or was already collected)", (long long)ticket);
+  }
+  *done = 1;
+  const Result& r = it->second;
+  const bool nonfinite = r.nonfinite;
+  if (report) {
+    double* dst = report->cost_trace;
+    *report = r.rep;
+    report->cost_trace = dst;
+    if (dst) memcpy(dst, r.trace.data(), sizeof(double) * r.trace.size());
+  }
+  sv->results.erase(it);
+  if (nonfinite) return fail(OPT_ENUMERIC, "a cost was NaN or infinite");
+  return OPT_OK;
+}
+
+int opt_server_cancel(opt_server* sv, int64_t ticket) {
+  if (!sv) return fail(OPT_EINVAL, "server is NULL");
+  if (sv->results.erase(ticket)) return OPT_OK;
+  for (Slot& s : sv->slots)
+    if (s.state != SlotState::EMPTY && s.ticket == ticket) {
+      release_slot(sv, s);
+      return OPT_OK;
+    }
+  return fail(OPT_EINVAL, "ticket %lld is not known", (long long)ticket);
+}
+
+int opt_server_add_tuning(opt_server* sv, int32_t energy, int32_t precision, int64_t min_sites,
+                          int64_t max_sites, const opt_tuning* t) {
+  if (!sv || !t) return fail(OPT_EINVAL, "server or tuning is NULL");
+  if (t->strip_rows < 0 || t->strip_rows > (1 << 20))
+    return fail(OPT_EINVAL, "strip_rows %d outside [0, 2^20]", t->strip_rows);
+  if (min_sites > max_sites) return fail(OPT_EINVAL, "empty site range");
+  sv->tuning.push_back(TuneEntry{energy, precision, min_sites, max_sites, *t});
+  return OPT_OK;
+}
+
+int opt_server_info(opt_server* sv, int32_t* active, size_t* arena_free) {
+  if (!sv) return fail(OPT_EINVAL, "server is NULL");
+  int n = 0;
+  for (const Slot& s : sv->slots) n += s.state != SlotState::EMPTY;
+  if (active) *active = n;
+  if (arena_free) *arena_free = sv->ranges.free_bytes();
+  return OPT_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,128 @@
+"""Autotuner for the launch shape of the fused PCG kernel.
+
+    python -m paper_1604_06525_amd.tune [--out tuning.json] [--quick]
+
+For each energy with a fused kernel (ARAP warp, Poisson, optical flow), each
+precision and each size class (grid sides 128, 256, 512, 1024, 2048), it times
+the PCG phase of a short solve on a seeded synthetic problem for every candidate
+strip height, and keeps the fastest.  The result is a JSON list of entries
+{energy, precision, min_sites, max_sites, strip_rows, iter_us, candidates}; a
+class covers the sites from half its own count up to twice it.  ``apply()``
+feeds the entries to a Server (used at admission) and ``best()`` looks one up for
+a single Problem.  Every choice gives the same iterates; only the speed differs.
+"""
+import argparse
+import json
+import os
+import sys
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+DEFAULT_PATH = os.path.join(HERE, "tuning.json")
+CANDIDATES = (4, 6, 8, 12, 16, 24, 32, 48, 64)
+SIDES = (128, 256, 512, 1024, 2048)
+ENERGIES = ("arap_warp", "poisson", "flow")
+
+
+def _problem(energy, side, precision):
+    import torch
+    import paper_1604_06525_amd as pkg
+    import workloads
+    from workloads.layout import problem_args
+    if energy == "arap_warp":
+        d = workloads.arap_warp(side, side, seed=2)
+    elif energy == "poisson":
+        d = workloads.poisson_edit(side, side, seed=5)
+    else:
+        d = workloads.optical_flow(side, side, seed=4)
+    dt = np.float64 if precision == "fp64" else np.float32
+    name, arrs, params, dims = problem_args(d, dt)
+    dev = torch.device("cuda:0")
+    prob = pkg.Problem(name, [torch.from_numpy(a).to(dev) for a in arrs], params, precision=precision, **dims)
+    x0 = torch.from_numpy(np.ascontiguousarray(np.asarray(d["x0"], dt).reshape(prob.channels, -1))).to(dev)
+    return prob, x0
+
+
+def time_candidate(prob, x0, strip_rows, pcg_iters=50, repeats=3):
+    """Microseconds per PCG iteration (median of repeats) with this strip height."""
+    import paper_1604_06525_amd as pkg
+    prob.set_tuning(strip_rows)
+    sp = pkg.default_params(method="gn", outer_iters=1, pcg_iters=pcg_iters)
+    x = x0.clone()
+    prob.solve(x, params=sp, report=False)  # warm-up
+    prob.profile_enable(True)
+    prob.profile_read()
+    times = []
+    for _ in range(repeats):
+        x.copy_(x0)
+        prob.solve(x, params=sp, report=False)
+        ms, iters = prob.profile_read()
+        times.append(1e3 * ms / iters)
+    prob.profile_enable(False)
+    return float(np.median(times))
+
+
+def autotune(energies=ENERGIES, precisions=("mixed", "fp64"), sides=SIDES, candidates=CANDIDATES,
+             log=sys.stderr):
+    entries = []
+    for energy in energies:
+        for precision in precisions:
+            for side in sides:
+                prob, x0 = _problem(energy, side, precision)
+                res = {}
+                for c in candidates:
+                    if c > side:
+                        continue
+                    res[c] = time_candidate(prob, x0, c)
+                best = min(res, key=res.get)
+                n = side * side
+                entries.append(dict(energy=energy, precision=precision, min_sites=n // 2, max_sites=2 * n,
+                                    side=side, strip_rows=best, iter_us=res[best],
+                                    candidates={str(k): v for k, v in res.items()}))
+                print(f"tune {energy} {precision} {side}^2: strip_rows {best} ({res[best]:.2f} us/iter)",
+                      file=log, flush=True)
+    return entries
+
+
+def save(entries, path=DEFAULT_PATH):
+    with open(path, "w") as f:
+        json.dump(entries, f, indent=1)
+
+
+def load(path=DEFAULT_PATH):
+    if not os.path.exists(path):
+        return []
+    with open(path) as f:
+        return json.load(f)
+
+
+def best(entries, energy, precision, n_sites):
+    """strip_rows of the last matching entry, or 0 (automatic)."""
+    hit = 0
+    for e in entries:
+        if e["energy"] == energy and e["precision"] == precision and e["min_sites"] <= n_sites <= e["max_sites"]:
+            hit = e["strip_rows"]
+    return hit
+
+
+def apply(server, entries):
+    for e in entries:
+        server.add_tuning(e["energy"], e["precision"], e["min_sites"], e["max_sites"], e["strip_rows"])
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--out", default=DEFAULT_PATH)
+    ap.add_argument("--quick", action="store_true", help="mixed precision, ARAP warp only")
+    a = ap.parse_args()
+    if a.quick:
+        entries = autotune(energies=("arap_warp",), precisions=("mixed",))
+    else:
+        entries = autotune()
+    save(entries, a.out)
+    print(json.dumps({"entries": len(entries), "path": a.out}))
+
+
+if __name__ == "__main__":
+    main()

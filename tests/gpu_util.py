@@ -40,3 +40,16 @@ def relmax(a, b):
     s = np.abs(b).max()
     d = np.abs(a - b).max()
     return 0.0 if d == 0 else d / (s if s > 0 else 1.0)
+
+
+def f32_inputs(d):
+    """The workload with every float array rounded to float32 (and back to
+    float64): the data a mixed-precision problem actually holds, so that the FP64
+    oracle can be evaluated on exactly those values."""
+    out = {}
+    for k, v in d.items():
+        if isinstance(v, np.ndarray) and v.dtype.kind == "f":
+            out[k] = v.astype(np.float32).astype(np.float64)
+        else:
+            out[k] = v
+    return out

