@@ -50,6 +50,8 @@ def parse():
     ap.add_argument("--serve", action="store_true")
     ap.add_argument("--serve-requests", type=int, default=200)
     ap.add_argument("--serve-loads", type=str, default="0.25,0.5,0.75,0.9,1.0,1.2")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run device copies of a known size (to scale memory counters)")
     return ap.parse_args()
 
 
@@ -71,6 +73,24 @@ def cpu_baseline(d, pcg_iters):
             "sample": f"one GN outer iteration (explicit Jacobian assembly + {pcg_iters} PCG "
                       f"iterations, FP64, scipy CSR, single thread) of the same 1024x1024 warp; "
                       f"{dt:.1f} s"}
+
+
+COPY_BYTES = 256 << 20
+
+
+def copy_calibration(reps=5):
+    """Device-to-device copies of COPY_BYTES each: a kernel that reads and writes
+    a known number of bytes, against which the memory counters of a profiled run
+    are scaled."""
+    import torch
+    dev = torch.device("cuda:0")
+    a = torch.ones(COPY_BYTES // 4, dtype=torch.float32, device=dev)
+    b = torch.empty_like(a)
+    for _ in range(reps):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_bytes_read": COPY_BYTES, "copy_bytes_written": COPY_BYTES, "reps": reps}),
+          flush=True)
 
 
 SERVE_ARENA = 8 << 30
@@ -232,6 +252,9 @@ def main():
         sys.exit(2)
     if args.serve:
         serve_main(args)
+        return
+    if args.copy_calibration:
+        copy_calibration()
         return
     import torch
     import paper_1604_06525_amd as pkg

@@ -115,29 +115,32 @@ struct Buf {
     b.rs = __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(p), (short)0, (int)bytes, 0x00020000);
     return b;
   }
-  __device__ __forceinline__ T load(unsigned off) const;
-  __device__ __forceinline__ void store(unsigned off, T v) const;
+  // voff: per-lane byte offset (range-checked); soff: wave-uniform byte offset
+  // added to it (a channel plane); voff + soff must stay inside the buffer for
+  // an in-range voff.
+  __device__ __forceinline__ T load(unsigned voff, unsigned soff) const;
+  __device__ __forceinline__ void store(unsigned voff, unsigned soff, T v) const;
 };
 template <>
-__device__ __forceinline__ float Buf<float>::load(unsigned off) const {
-  return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(rs, off, 0, 0));
+__device__ __forceinline__ float Buf<float>::load(unsigned off, unsigned soff) const {
+  return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(rs, off, soff, 0));
 }
 template <>
-__device__ __forceinline__ double Buf<double>::load(unsigned off) const {
-  return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(rs, off, 0, 0));
+__device__ __forceinline__ double Buf<double>::load(unsigned off, unsigned soff) const {
+  return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(rs, off, soff, 0));
 }
 template <>
-__device__ __forceinline__ uint8_t Buf<uint8_t>::load(unsigned off) const {
-  return __builtin_amdgcn_raw_buffer_load_b8(rs, off, 0, 0);
+__device__ __forceinline__ uint8_t Buf<uint8_t>::load(unsigned off, unsigned soff) const {
+  return __builtin_amdgcn_raw_buffer_load_b8(rs, off, soff, 0);
 }
 template <>
-__device__ __forceinline__ void Buf<float>::store(unsigned off, float v) const {
-  __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), rs, off, 0, 0);
+__device__ __forceinline__ void Buf<float>::store(unsigned off, unsigned soff, float v) const {
+  __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), rs, off, soff, 0);
 }
 template <>
-__device__ __forceinline__ void Buf<double>::store(unsigned off, double v) const {
+__device__ __forceinline__ void Buf<double>::store(unsigned off, unsigned soff, double v) const {
   typedef unsigned u2 __attribute__((ext_vector_type(2)));
-  __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u2, v), rs, off, 0, 0);
+  __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u2, v), rs, off, soff, 0);
 }
 
 __device__ __forceinline__ void sincos_t(float v, float* s, float* c) { sincosf(v, s, c); }

@@ -169,6 +169,29 @@ struct ArapWarp {
     g[0] = gx; g[1] = gy; g[2] = gt;
   }
 
+  // sum over the residuals anchored at the centre of (J u)_r^2, u read through
+  // the view U (zero at excluded sites); summed over all sites this is
+  // |J u|^2 = u . (J^T J u).  An excluded centre anchors only constants.
+  template <class PV, class SV, class FV>
+  __device__ __forceinline__ T jsq(PV U, SV S, FV F, int, int) const {
+    if (!(F(0, 0) & ACTIVE)) return T(0);
+    const T c = S(0, 0, 0), sn = S(1, 0, 0), Ux = S(2, 0, 0), Uy = S(3, 0, 0);
+    const T ux = U(0, 0, 0), uy = U(1, 0, 0), ut = U(2, 0, 0);
+    T acc = 0;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      const int di = k == 0 ? 1 : (k == 1 ? -1 : 0), dj = k == 2 ? 1 : (k == 3 ? -1 : 0);
+      const T w = (F(di, dj) & ACTIVE) ? T(1) : T(0);
+      const T dx = Ux - S(2, di, dj), dy = Uy - S(3, di, dj);
+      const T apx = -sn * dx - c * dy, apy = c * dx - sn * dy;
+      const T jx = (ux - U(0, di, dj)) - apx * ut, jy = (uy - U(1, di, dj)) - apy * ut;
+      acc += w * (jx * jx + jy * jy);
+    }
+    acc *= wr * wr;
+    if (F(0, 0) & FIT) acc += wf * wf * (ux * ux + uy * uy);
+    return acc;
+  }
+
   // LM model term of the residuals anchored at s, in FP64:
   //   sum_r (J d)_r (2 F_r + (J d)_r), J and F at X, step Dl.
   template <class XA, class DA>

@@ -127,6 +127,23 @@ struct OpticalFlow {
     g[1] = jv * jp + w2 * sv;
   }
 
+  // sum over the residuals anchored at the centre of (J u)_r^2; summed over all
+  // sites this is |J u|^2.
+  template <class PV, class SV, class FV>
+  __device__ __forceinline__ T jsq(PV U, SV S, FV F, int, int) const {
+    const T uu = U(0, 0, 0), uv = U(1, 0, 0);
+    const T jp = S(0, 0, 0) * uu + S(1, 0, 0) * uv;
+    T acc = 0;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      const int di = k == 0 ? 1 : (k == 1 ? -1 : 0), dj = k == 2 ? 1 : (k == 3 ? -1 : 0);
+      const T w = (F(di, dj) & INGRID) ? T(1) : T(0);
+      const T eu = uu - U(0, di, dj), ev = uv - U(1, di, dj);
+      acc += w * (eu * eu + ev * ev);
+    }
+    return jp * jp + wr * wr * acc;
+  }
+
   template <class XA, class DA>
   __device__ __forceinline__ double model(XA X, DA Dl, int s) const {
     const int i = s % W, j = s / W;

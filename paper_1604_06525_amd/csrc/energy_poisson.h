@@ -102,6 +102,24 @@ struct Poisson {
     for (int c = 0; c < C; ++c) g[c] = T(2) * acc[c];
   }
 
+  // sum over the residuals anchored at the centre of (J u)_r^2 (u is zero at
+  // excluded pixels); summed over all sites this is |J u|^2.
+  template <class PV, class SV, class FV>
+  __device__ __forceinline__ T jsq(PV U, SV, FV F, int, int) const {
+    T acc = 0;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      const int di = k == 0 ? 1 : (k == 1 ? -1 : 0), dj = k == 2 ? 1 : (k == 3 ? -1 : 0);
+      const T w = (F(di, dj) & INGRID) ? T(1) : T(0);
+#pragma unroll
+      for (int c = 0; c < C; ++c) {
+        const T e = U(c, 0, 0) - U(c, di, dj);
+        acc += w * e * e;
+      }
+    }
+    return acc;
+  }
+
   template <class XA, class DA>
   __device__ __forceinline__ double model(XA X, DA Dl, int s) const {
     const int i = s % W, j = s / W;

@@ -31,6 +31,7 @@
 // every later iteration kernel returns at once and d keeps its value.
 #pragma once
 #include <type_traits>
+#include <utility>
 
 #include "common.h"
 
@@ -329,28 +330,28 @@ __device__ __forceinline__ uint32_t from_right(uint32_t v) { return dpp_from_rig
 constexpr int kStripCols = 60;
 
 // One grid row as one lane sees it (its column), for the streaming kernel.
-template <class E>
+template <class E, bool DAMP>
 struct StreamRow {
   using T = typename E::Real;
   static constexpr int C = E::C, NS = E::kStatePlanes > 0 ? E::kStatePlanes : 1;
   T r[C];    // r_i, later r_{i+1}
   T m[C];    // M^-1, later u_{i+1} = M^-1 r_{i+1}
-  T p[C];    // p_i
-  T x[C];    // d (only on produced rows)
-  T dmp[C];  // LM damping (only when damped)
+  T p[C];    // p_{i-1}, later p_i
+  T x[C];    // d (loaded one step before it is updated)
+  T dmp[DAMP ? C : 1];  // LM damping
   T st[NS];
   uint32_t f;
 };
 
-// Apply the energy's operator at the centre row R with rows U (above) and D
-// (below); V selects the vector (p or u).  Horizontal neighbours come from the
-// adjacent lanes.
-template <class E, class VSel>
-__device__ __forceinline__ void stream_apply(const E& e, const StreamRow<E>& U,
-                                             const StreamRow<E>& R, const StreamRow<E>& D,
-                                             VSel V, int col, int row, typename E::Real* g) {
+// Stencil views centred on row R (rows U above and D below); V selects the
+// vector.  Horizontal neighbours come from the adjacent lanes (DPP), vertical
+// ones from the row ring.  NEED_NBR_STATE: whether the operator reads the state
+// of the neighbours (passes that do not skip those lane exchanges).
+template <class E, bool DAMP, class VSel, class Body>
+__device__ __forceinline__ auto with_views(const StreamRow<E, DAMP>& U, const StreamRow<E, DAMP>& R,
+                                           const StreamRow<E, DAMP>& D, VSel V, Body body) {
   using T = typename E::Real;
-  constexpr int C = E::C, NS = StreamRow<E>::NS;
+  constexpr int C = E::C, NS = StreamRow<E, DAMP>::NS;
   T vl[C], vr[C], sl[NS], sr[NS];
 #pragma unroll
   for (int c = 0; c < C; ++c) {
@@ -372,7 +373,7 @@ __device__ __forceinline__ void stream_apply(const E& e, const StreamRow<E>& U,
   auto Fv = [&](int di, int dj) -> uint32_t {
     return dj < 0 ? U.f : dj > 0 ? D.f : di < 0 ? fl : di > 0 ? fr : R.f;
   };
-  e.apply(Pv, Sv, Fv, col, row, g);
+  return body(Pv, Sv, Fv);
 }
 
 // The unit of work of a block, XCD-aware: blocks go to the 8 XCDs round-robin,
@@ -390,12 +391,12 @@ struct FusedBufs {
   T* p[2];         // iteration i writes p_i to p[i & 1], reads p_{i-1} from p[(i + 1) & 1]
   T* x;            // the PCG solution d, updated in place
   const T* minv;
-  const T* damp;   // nullptr: no damping
+  const T* damp;   // LM damping lambda*D (the DAMP form only)
   double* part[2]; // [gamma | delta] partials, kMaxBlocks apart; iteration i writes
                    // part[i & 1] (the priming launch writes part[1]) and reads the other
 };
 
-template <class E>
+template <class E, bool DAMP>
 struct FusedArgs {
   E e;
   FusedBufs<typename E::Real> b;
@@ -406,11 +407,21 @@ struct FusedArgs {
   int L;
 };
 
-template <class E>
-__device__ __forceinline__ void run(const FusedArgs<E>& a, VG g, int iter) {
+// f(integral_constant<int, I>) for each I of the sequence, in order.
+template <int... I, class F>
+__device__ __forceinline__ void unroll_seq(std::integer_sequence<int, I...>, F f) {
+  (f(std::integral_constant<int, I>{}), ...);
+}
+
+// Rows of loads in flight ahead of the row being started.
+constexpr int kPrefetch = 4;
+
+template <class E, bool DAMP>
+__device__ __forceinline__ void run(const FusedArgs<E, DAMP>& a, VG g, int iter) {
   using T = typename E::Real;
-  using Row = StreamRow<E>;
+  using Row = StreamRow<E, DAMP>;
   constexpr int C = E::C, NS = E::kStatePlanes;
+  constexpr int N = kPrefetch + 4;  // ring slots: four rows in use, the rest in flight
   const E& e = a.e;
   DevScalars* S = a.S;
   if (iter >= a.L || S->stopped || (a.lm_gate && S->done)) return;
@@ -436,7 +447,7 @@ __device__ __forceinline__ void run(const FusedArgs<E>& a, VG g, int iter) {
     }
   }
   const T aT = (T)alpha, bT = (T)beta;
-  const bool read_pold = iter > 0, write_out = iter >= 0, damped = a.b.damp != nullptr;
+  const bool read_pold = iter > 0, write_out = iter >= 0;
   const int W = e.W, H = e.H, n = e.n, n_sy = a.n_sy, Hs = a.Hs;
   const int lane = threadIdx.x & 63;
   const int strip = unit_of_block(g) * kWaves + (threadIdx.x >> 6);
@@ -449,109 +460,113 @@ __device__ __forceinline__ void run(const FusedArgs<E>& a, VG g, int iter) {
     const bool colin = col >= 0 && col < W;
     const bool out_lane = colin && lane >= 2 && lane < 2 + kStripCols;
     const int K = (y1 - y0) + 4;  // rows y0-2 .. y1+1
-    // One raw buffer per vector (all channels), per state plane and for the
-    // flags; a lane or row off the strip reads at an out-of-range offset and gets 0.
+    // One raw buffer per vector (all channels; channel c at scalar offset
+    // c * plane), per state plane and for the flags.  A lane or row off the strip
+    // uses an out-of-range offset: its loads return 0, its stores are dropped.
     const size_t vbytes = (size_t)C * n * sizeof(T);
-    const T* r_in = a.b.r[iter < 0 ? 0 : (iter & 1)];
-    T* r_out = a.b.r[(iter + 1) & 1];
-    const Buf<T> Brin = Buf<T>::make(r_in, vbytes), Bm = Buf<T>::make(a.b.minv, vbytes);
-    const Buf<T> Bpin = Buf<T>::make(a.b.p[(iter + 1) & 1], vbytes);
-    const Buf<T> Bx = Buf<T>::make(a.b.x, vbytes);
-    const Buf<T> Bd = Buf<T>::make(a.b.damp, damped ? vbytes : 0);
-    const Buf<T> Brout = Buf<T>::make(r_out, write_out ? vbytes : 0);
+    const unsigned plane = (unsigned)((size_t)n * sizeof(T));
+    const Buf<T> Brin = Buf<T>::make(a.b.r[iter < 0 ? 0 : (iter & 1)], vbytes);
+    const Buf<T> Bm = Buf<T>::make(a.b.minv, vbytes);
+    const Buf<T> Bpin = Buf<T>::make(a.b.p[(iter + 1) & 1], read_pold ? vbytes : 0);
+    const Buf<T> Bx = Buf<T>::make(a.b.x, write_out ? vbytes : 0);
+    const Buf<T> Bd = Buf<T>::make(a.b.damp, DAMP ? vbytes : 0);
+    const Buf<T> Brout = Buf<T>::make(a.b.r[(iter + 1) & 1], write_out ? vbytes : 0);
     const Buf<T> Bpout = Buf<T>::make(a.b.p[iter & 1], write_out ? vbytes : 0);
     Buf<T> Bst[NS > 0 ? NS : 1];
 #pragma unroll
     for (int q = 0; q < NS; ++q) Bst[q] = Buf<T>::make(e.state_plane(q), (size_t)n * sizeof(T));
     const Buf<uint8_t> Bf = Buf<uint8_t>::make(e.flags, (size_t)n);
-    const unsigned plane = (unsigned)((size_t)n * sizeof(T));
-    // Row y0-2+k lives in ring slot k & 7.  Its loads are issued four steps before
-    // it is needed, into its own slot, so their latency overlaps four steps of work.
-    Row ring[8];
+    // Row y0-2+k lives in ring slot k % N; its loads are issued kPrefetch steps
+    // before it is started.
+    Row ring[N];
     auto issue = [&](Row& R, int y) {
       const bool in = colin && y >= 0 && y < H && y <= y1 + 1;
       const unsigned s = (unsigned)(y * W + col);
       const unsigned o = in ? s * (unsigned)sizeof(T) : kBufOutOfRange;
-      const unsigned ox = (in && y >= y0 && y < y1 && write_out) ? o : kBufOutOfRange;
-      const unsigned op = read_pold ? o : kBufOutOfRange;
 #pragma unroll
       for (int c = 0; c < C; ++c) {
-        R.r[c] = Brin.load(o + c * plane);
-        R.m[c] = Bm.load(o + c * plane);
-        R.p[c] = Bpin.load(op + c * plane);
-        R.x[c] = Bx.load(ox + c * plane);
-        R.dmp[c] = Bd.load(o + c * plane);
+        R.r[c] = Brin.load(o, c * plane);
+        R.m[c] = Bm.load(o, c * plane);
+        R.p[c] = Bpin.load(o, c * plane);
+        if constexpr (DAMP) R.dmp[c] = Bd.load(o, c * plane);
       }
 #pragma unroll
-      for (int q = 0; q < NS; ++q) R.st[q] = Bst[q].load(o);
-      R.f = Bf.load(in ? s : kBufOutOfRange);
+      for (int q = 0; q < NS; ++q) R.st[q] = Bst[q].load(o, 0);
+      R.f = Bf.load(in ? s : kBufOutOfRange, 0);
     };
     auto selp = [](const Row& R, int c) { return R.p[c]; };
     auto selu = [](const Row& R, int c) { return R.m[c]; };
 
     auto step = [&](auto PH, int k) {
       constexpr int ph = decltype(PH)::value;
-      Row& R0 = ring[ph];            // row y = y0 - 2 + k
-      Row& R1 = ring[(ph + 7) & 7];  // y - 1
-      Row& R2 = ring[(ph + 6) & 7];  // y - 2
-      Row& R3 = ring[(ph + 5) & 7];  // y - 3
+      Row& R0 = ring[ph];                // row y = y0 - 2 + k
+      Row& R1 = ring[(ph + N - 1) % N];  // y - 1
+      Row& R2 = ring[(ph + N - 2) % N];  // y - 2
+      Row& R3 = ring[(ph + N - 3) % N];  // y - 3
       const int y = y0 - 2 + k;
-      issue(ring[(ph + 4) & 7], y + 4);
-      // p_i = M^-1 r_i + beta p_{i-1} on row y (R0.p holds p_{i-1})
+      issue(ring[(ph + kPrefetch) % N], y + kPrefetch);
+      // p_i = M^-1 r_i + beta p_{i-1} on row y
 #pragma unroll
       for (int c = 0; c < C; ++c) {
         const T u = R0.m[c] * R0.r[c];
         R0.p[c] = read_pold ? fma(bT, R0.p[c], u) : u;
       }
       if (k >= 2) {
-        // s = A p and r_{i+1}, u_{i+1} on row y - 1
+        // s = A p, r_{i+1} = r_i - alpha s, u_{i+1} = M^-1 r_{i+1} on row y - 1;
+        // d of that row is fetched now, to be updated in the next step
         T gv[C];
-        stream_apply(e, R2, R1, R0, selp, col, y - 1, gv);
+        with_views(R2, R1, R0, selp, [&](auto Pv, auto Sv, auto Fv) {
+          e.apply(Pv, Sv, Fv, col, y - 1, gv);
+          return 0;
+        });
         const bool act = R1.f & E::ACTIVE;
+        const bool prod = y - 1 >= y0 && y - 1 < y1;
+        const unsigned ox = (out_lane && prod && act && write_out) ? (unsigned)((y - 1) * W + col) *
+                                                                         (unsigned)sizeof(T)
+                                                                   : kBufOutOfRange;
 #pragma unroll
         for (int c = 0; c < C; ++c) {
-          const T sv = damped ? fma(R1.dmp[c], R1.p[c], gv[c]) : gv[c];
+          R1.x[c] = Bx.load(ox, c * plane);
+          const T sv = DAMP ? fma(R1.dmp[c], R1.p[c], gv[c]) : gv[c];
           R1.r[c] = act ? fma(-aT, sv, R1.r[c]) : T(0);
           R1.m[c] = act ? R1.m[c] * R1.r[c] : T(0);
         }
       }
       if (k >= 4) {
-        // w = A u_{i+1} on row y - 2; partials and outputs
+        // row y - 2 is final: partials of gamma = r.u and delta = u.(A u) =
+        // |J u|^2 (+ u.damp u), and the stores of d, r, p
         const int yo = y - 2;
-        T wv[C];
-        stream_apply(e, R3, R2, R1, selu, col, yo, wv);
+        const T jq = with_views(R3, R2, R1, selu, [&](auto Pv, auto Sv, auto Fv) {
+          return e.jsq(Pv, Sv, Fv, col, yo);
+        });
         const bool act = R2.f & E::ACTIVE;
-        if (out_lane && act) {
+        if (out_lane && (R2.f & E::INGRID)) {
+          T gs = 0, ds = 0;
 #pragma unroll
           for (int c = 0; c < C; ++c) {
-            const T ww = damped ? fma(R2.dmp[c], R2.m[c], wv[c]) : wv[c];
-            g_acc += (double)R2.r[c] * (double)R2.m[c];
-            d_acc += (double)ww * (double)R2.m[c];
+            gs = fma(R2.r[c], R2.m[c], gs);
+            if constexpr (DAMP) ds = fma(R2.dmp[c] * R2.m[c], R2.m[c], ds);
           }
+          g_acc += (double)gs;
+          d_acc += (double)jq + (double)ds;
         }
-        // masked lanes store out of range (dropped)
         const unsigned o = out_lane ? (unsigned)(yo * W + col) * (unsigned)sizeof(T) : kBufOutOfRange;
         const unsigned ox = (act && write_out) ? o : kBufOutOfRange;
 #pragma unroll
         for (int c = 0; c < C; ++c) {
           const T pv = act ? R2.p[c] : T(0);
-          Bx.store(ox + c * plane, fma(aT, pv, R2.x[c]));
-          Brout.store(o + c * plane, R2.r[c]);
-          Bpout.store(o + c * plane, pv);
+          Bx.store(ox, c * plane, fma(aT, pv, R2.x[c]));
+          Brout.store(o, c * plane, R2.r[c]);
+          Bpout.store(o, c * plane, pv);
         }
       }
     };
 #pragma unroll
-    for (int k = 0; k < 4; ++k) issue(ring[k], y0 - 2 + k);
-    for (int k = 0; k < K; k += 8) {
-      step(std::integral_constant<int, 0>{}, k);
-      if (k + 1 < K) step(std::integral_constant<int, 1>{}, k + 1);
-      if (k + 2 < K) step(std::integral_constant<int, 2>{}, k + 2);
-      if (k + 3 < K) step(std::integral_constant<int, 3>{}, k + 3);
-      if (k + 4 < K) step(std::integral_constant<int, 4>{}, k + 4);
-      if (k + 5 < K) step(std::integral_constant<int, 5>{}, k + 5);
-      if (k + 6 < K) step(std::integral_constant<int, 6>{}, k + 6);
-      if (k + 7 < K) step(std::integral_constant<int, 7>{}, k + 7);
+    for (int k = 0; k < kPrefetch; ++k) issue(ring[k], y0 - 2 + k);
+    for (int k = 0; k < K; k += N) {
+      unroll_seq(std::make_integer_sequence<int, N>{}, [&](auto PH) {
+        if (k + decltype(PH)::value < K) step(PH, k + decltype(PH)::value);
+      });
     }
   }
   const double gs = block_sum(g_acc);

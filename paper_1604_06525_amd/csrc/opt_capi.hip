@@ -241,9 +241,10 @@ class ImplT final : public Impl {
     a.L = L;
     return a;
   }
-  FusedArgs<E> fused_args(int L, PrecondArgs pa, int lm, int* grid) const {
+  template <bool DAMP>
+  FusedArgs<E, DAMP> fused_args(int L, PrecondArgs pa, int lm, int* grid) const {
     const StripGeom g = strip_geom(e_.W, e_.H, p_->tune.strip_rows);
-    FusedArgs<E> a;
+    FusedArgs<E, DAMP> a;
     a.e = e_;
     a.b.r[0] = rbuf(0);
     a.b.r[1] = rbuf(1);
@@ -300,8 +301,8 @@ class ImplT final : public Impl {
       return fail(OPT_EUNSUPPORTED, "the fused PCG kernel needs an operator of radius 1");
     } else {
       int grid = 0;
-      const FusedArgs<E> a = fused_args(L, pa, lm, &grid);
-      return go(a, grid, iter, "fused");
+      if (pa.damped) return go(fused_args<true>(L, pa, lm, &grid), grid, iter, "fused");
+      return go(fused_args<false>(L, pa, lm, &grid), grid, iter, "fused");
     }
   }
   int apply_jtj(const void* pin, void* qout, PrecondArgs pa) override {
@@ -351,8 +352,14 @@ class ImplT final : public Impl {
           if constexpr (E::kRadius != 1 || E::kGraph) {
             return fail(OPT_EUNSUPPORTED, "the fused PCG kernel needs an operator of radius 1");
           } else {
-            return rec<FusedArgs<E>>(B, s, n, [](const ImplT& m, const SlotRef& r, int* g) {
-              return m.fused_args(r.L, r.pa, r.lm, g);
+            // one group holds problems of one method (the server keys groups by
+            // it), so the damping form is the same for all
+            if (s[0].pa.damped)
+              return rec<FusedArgs<E, true>>(B, s, n, [](const ImplT& m, const SlotRef& r, int* g) {
+                return m.template fused_args<true>(r.L, r.pa, r.lm, g);
+              }, -1, Lmax, "fused[batch]");
+            return rec<FusedArgs<E, false>>(B, s, n, [](const ImplT& m, const SlotRef& r, int* g) {
+              return m.template fused_args<false>(r.L, r.pa, r.lm, g);
             }, -1, Lmax, "fused[batch]");
           }
         } else {

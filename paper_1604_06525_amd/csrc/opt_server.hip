@@ -31,7 +31,7 @@ using namespace optmi::host;
 namespace {
 
 constexpr int kStageKinds = 12;        // table kinds that one step can write
-constexpr int kMaxKinds = 20;          // energy x precision x PCG form
+constexpr int kMaxKinds = 40;          // energy x precision x method x PCG form
 
 // Arena byte ranges, first fit with coalescing.
 class RangeAlloc {
@@ -137,8 +137,11 @@ struct opt_server {
 
 namespace {
 
+// Requests that can share one launch: same energy, precision, method (the
+// damped and undamped fused kernels differ) and PCG form; bit 0 is the form.
 int key_of(const Slot& s) {
-  return (s.p->desc.energy * 2 + s.p->desc.precision) * 2 + (s.fused ? 1 : 0);
+  return ((s.p->desc.energy * 2 + s.p->desc.precision) * 2 + (s.sp.method == OPT_LM ? 1 : 0)) * 2 +
+         (s.fused ? 1 : 0);
 }
 
 SlotRef ref_of(Slot& s) {

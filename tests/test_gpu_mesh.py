@@ -11,7 +11,7 @@ import torch
 
 import oracle as o
 import workloads as w
-from tests.gpu_util import make_problem, relmax, require_gpu, to_dev, to_np
+from tests.gpu_util import f32_inputs, make_problem, relmax, require_gpu, to_dev, to_np
 
 pytestmark = pytest.mark.gpu
 
@@ -98,15 +98,48 @@ def test_gn_fp64():
     assert np.allclose(rep["cost_trace"], costs, rtol=1e-9, atol=0)
 
 
-def test_lm_mixed_level5():
-    """Config-3 style: 1% handles, LM with 40 PCG iterations, mixed precision."""
-    d = w.arap_mesh(5, seed=3)
+@pytest.mark.parametrize("handle_frac,tol", [(0.05, 1e-4), (0.01, 1e-3)])
+def test_lm_mixed_level5(handle_frac, tol):
+    """LM with 40 PCG iterations, mixed precision, against the FP64 oracle.
+
+    With 5% handles the final cost agrees to 1e-4.  With 1% handles (the
+    icosphere configuration's density) the system is so ill-conditioned that 40
+    PCG iterations from the first, almost undamped LM step end in a different
+    place for any change of FP32 rounding: FP32 emulations of the oracle's PCG
+    that differ only in summation order spread by up to 2.2e-4 in final cost
+    (5e-6 with 5% handles).  There the bound is 1e-3, and both runs must take
+    the same steps."""
+    d = w.arap_mesh(5, seed=3, handle_frac=handle_frac)
     e = o.make_energy(d)
     xo, costs, acc = o.levenberg_marquardt(e, d["x0"], 4, 40)
     prob = make_problem(d, "mixed")
     xt = to_dev(prob, d["x0"])
     rep = prob.solve(xt, method="lm", outer_iters=4, pcg_iters=40)
-    assert abs(rep["cost_final"] - costs[-1]) <= 1e-4 * costs[-1]
+    assert rep["steps_accepted"] == sum(acc)
+    assert abs(rep["cost_final"] - costs[-1]) <= tol * costs[-1]
+
+
+@pytest.mark.parametrize("level", [1, 3])
+def test_operators_mixed(level):
+    """Mixed precision: the FP64 cost of FP32 values is exact; FP32 products
+    agree with the FP64 oracle on the same FP32-rounded inputs to 1e-5 of their
+    largest entry (a vertex sums a few dozen FP32 terms)."""
+    d, x = _mesh(level)
+    d32 = f32_inputs(d)
+    x32 = np.asarray(x, np.float32).astype(np.float64)
+    e = o.make_energy(d32)
+    lin = o.Linearization(e, x32)
+    prob = make_problem(d, "mixed")
+    xt = to_dev(prob, x32)
+    assert abs(prob.cost(xt) - lin.E) <= 1e-12 * lin.E
+    assert abs(prob.linearize(xt) - lin.E) <= 1e-12 * lin.E
+    b, dg = prob.eval_jtf()
+    p = np.random.default_rng(2).normal(size=lin.diag.size)
+    p32 = np.asarray(p, np.float32).astype(np.float64)
+    errs = [relmax(to_np(b), lin.jtf()), relmax(to_np(dg), lin.diag),
+            relmax(to_np(prob.apply_jtj(to_dev(prob, p32))), lin.apply(p32))]
+    print("mesh mixed operator errors", errs)
+    assert max(errs) < 1e-5
 
 
 def test_deterministic_mixed():
