@@ -100,22 +100,28 @@ def cpu_baseline(d, pcg_iters):
                       f"{dt:.1f} s"}
 
 
-COPY_BYTES = 256 << 20
+COPY_BYTES = 2 << 30  # far larger than the 256 MB Infinity Cache
 
 
 def copy_calibration(reps=5):
     """Device-to-device copies of COPY_BYTES each: a kernel that reads and writes
     a known number of bytes, against which the memory counters of a profiled run
-    are scaled."""
+    are scaled.  Also reports the copy's bandwidth (read + write bytes / time)."""
     import torch
     dev = torch.device("cuda:0")
     a = torch.ones(COPY_BYTES // 4, dtype=torch.float32, device=dev)
     b = torch.empty_like(a)
+    b.copy_(a)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
     for _ in range(reps):
         b.copy_(a)
+    e1.record()
     torch.cuda.synchronize()
-    print(json.dumps({"copy_bytes_read": COPY_BYTES, "copy_bytes_written": COPY_BYTES, "reps": reps}),
-          flush=True)
+    ms = e0.elapsed_time(e1) / reps
+    print(json.dumps({"copy_bytes_read": COPY_BYTES, "copy_bytes_written": COPY_BYTES, "reps": reps,
+                      "ms_per_copy": ms, "GB_per_s": 2 * COPY_BYTES / (ms * 1e-3) / 1e9}), flush=True)
 
 
 SERVE_ARENA = 8 << 30

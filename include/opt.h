@@ -218,15 +218,22 @@ int opt_profile_enable(opt_problem* prob, int enable);
 int opt_profile_read(opt_problem* prob, double* pcg_ms, int64_t* pcg_iters);
 
 /*
- * Launch tuning of a problem (no effect on results: every choice computes the
- * same iterates, only the work split changes).
- *   strip_rows: the fused PCG kernel gives each wavefront a strip of 60 columns
- *   and this many rows (0 = automatic: about 1,152 strips per launch).  Shorter
- *   strips mean more wavefronts in flight but more halo rows read twice.
- * opt_problem_get_tuning returns the values in force (strip_rows resolved).
+ * Launch tuning of a problem (no effect on results beyond the order of a few
+ * additions: every choice computes the same iterates up to rounding; only the
+ * work split changes).  The fused PCG kernel gives each wavefront a strip of at
+ * most 60 columns (the grid's width split evenly) and some rows.
+ *   strip_rows > 0: strips of that many rows.
+ *   waves_per_simd > 0 (and strip_rows == 0): about that many strips per SIMD,
+ *     rows split evenly.
+ *   both 0 (automatic): two strips per SIMD, rows split evenly, at least 4
+ *     rows.
+ * Shorter strips mean more wavefronts in flight but more halo rows read twice.
+ * opt_problem_get_tuning returns the values in force (resolved: the largest
+ * strip height and the strips per SIMD, rounded up).
  */
 typedef struct {
   int32_t strip_rows;
+  int32_t waves_per_simd;
 } opt_tuning;
 
 int opt_problem_set_tuning(opt_problem* prob, const opt_tuning* tuning);

@@ -81,6 +81,12 @@ __device__ __forceinline__ double reduce_partials(const double* __restrict__ par
 
 __device__ __forceinline__ bool is_block_leader(VG g) { return g.bid == 0 && threadIdx.x == 0; }
 
+// 1/x: the hardware reciprocal in FP32 (within 1 ulp; every kernel forms M^-1
+// with it, so the preconditioner is the same everywhere), correctly rounded in
+// FP64.
+__device__ __forceinline__ float recip(float x) { return __builtin_amdgcn_rcpf(x); }
+__device__ __forceinline__ double recip(double x) { return 1.0 / x; }
+
 // Jacobi preconditioner entry for an unknown with diagonal d (Sec. 4.1): the
 // inverse of the damped diagonal d + lambda*clamp(d), or 0 when that is not
 // positive (an unknown no residual touches stays where it is).  Without the
@@ -91,10 +97,15 @@ struct Precond {
   T lam, dmin, dmax;
   int use;
   __device__ __forceinline__ T damp(T d) const { return lam * (d < dmin ? dmin : (d > dmax ? dmax : d)); }
+  // the preconditioner's entry M (the damped diagonal, or 1 without it)
+  __device__ __forceinline__ T den(T d) const {
+    if (!use) return T(1);
+    return lam != T(0) ? d + damp(d) : d;
+  }
   __device__ __forceinline__ T minv(T d) const {
     if (!use) return T(1);
-    const T den = lam != T(0) ? d + damp(d) : d;
-    return den > T(0) ? T(1) / den : T(0);
+    const T m = den(d);
+    return m > T(0) ? recip(m) : T(0);
   }
 };
 
@@ -141,6 +152,71 @@ template <>
 __device__ __forceinline__ void Buf<double>::store(unsigned off, unsigned soff, double v) const {
   typedef unsigned u2 __attribute__((ext_vector_type(2)));
   __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u2, v), rs, off, soff, 0);
+}
+
+// K consecutive values at byte offset voff (+ soff) in one or two wide loads
+// (each lane reads 4*K or 8*K contiguous bytes), and the matching store.
+template <int K, typename T>
+__device__ __forceinline__ void buf_loadv(const Buf<T>& b, unsigned voff, unsigned soff, T* out) {
+  typedef unsigned u2 __attribute__((ext_vector_type(2)));
+  typedef unsigned u3 __attribute__((ext_vector_type(3)));
+  typedef unsigned u4 __attribute__((ext_vector_type(4)));
+  constexpr int W = (int)(K * sizeof(T) / 4);  // dwords
+  static_assert(K * sizeof(T) % 4 == 0, "whole dwords");
+  unsigned d[W];
+  int i = 0;
+#pragma unroll
+  for (; i + 4 <= W; i += 4) {
+    const u4 v = __builtin_amdgcn_raw_buffer_load_b128(b.rs, voff + 4 * i, soff, 0);
+    d[i] = v.x; d[i + 1] = v.y; d[i + 2] = v.z; d[i + 3] = v.w;
+  }
+  if constexpr (W % 4 == 3) {
+    const u3 v = __builtin_amdgcn_raw_buffer_load_b96(b.rs, voff + 4 * (W - 3), soff, 0);
+    d[W - 3] = v.x; d[W - 2] = v.y; d[W - 1] = v.z;
+  } else if constexpr (W % 4 == 2) {
+    const u2 v = __builtin_amdgcn_raw_buffer_load_b64(b.rs, voff + 4 * (W - 2), soff, 0);
+    d[W - 2] = v.x; d[W - 1] = v.y;
+  } else if constexpr (W % 4 == 1) {
+    d[W - 1] = __builtin_amdgcn_raw_buffer_load_b32(b.rs, voff + 4 * (W - 1), soff, 0);
+  }
+  (void)i;
+  __builtin_memcpy(out, d, sizeof(d));
+}
+
+template <int K, typename T>
+__device__ __forceinline__ void buf_storev(const Buf<T>& b, unsigned voff, unsigned soff, const T* in) {
+  typedef unsigned u2 __attribute__((ext_vector_type(2)));
+  typedef unsigned u3 __attribute__((ext_vector_type(3)));
+  typedef unsigned u4 __attribute__((ext_vector_type(4)));
+  constexpr int W = (int)(K * sizeof(T) / 4);
+  unsigned d[W];
+  __builtin_memcpy(d, in, sizeof(d));
+  int i = 0;
+#pragma unroll
+  for (; i + 4 <= W; i += 4) {
+    u4 v;
+    v.x = d[i]; v.y = d[i + 1]; v.z = d[i + 2]; v.w = d[i + 3];
+    __builtin_amdgcn_raw_buffer_store_b128(v, b.rs, voff + 4 * i, soff, 0);
+  }
+  if constexpr (W % 4 == 3) {
+    u3 v;
+    v.x = d[W - 3]; v.y = d[W - 2]; v.z = d[W - 1];
+    __builtin_amdgcn_raw_buffer_store_b96(v, b.rs, voff + 4 * (W - 3), soff, 0);
+  } else if constexpr (W % 4 == 2) {
+    u2 v;
+    v.x = d[W - 2]; v.y = d[W - 1];
+    __builtin_amdgcn_raw_buffer_store_b64(v, b.rs, voff + 4 * (W - 2), soff, 0);
+  } else if constexpr (W % 4 == 1) {
+    __builtin_amdgcn_raw_buffer_store_b32(d[W - 1], b.rs, voff + 4 * (W - 1), soff, 0);
+  }
+  (void)i;
+}
+
+// Index of element (channel c, site s) of an internal vector of C channels:
+// the channels of a site are adjacent, so one wide access reads a site.
+template <int C>
+__device__ __forceinline__ size_t vix(int c, int s) {
+  return (size_t)s * C + c;
 }
 
 __device__ __forceinline__ void sincos_t(float v, float* s, float* c) { sincosf(v, s, c); }

@@ -78,21 +78,22 @@ struct ArapMesh {
   const int* __restrict__ nb;    // [2E] neighbour ids
   const T* __restrict__ U;       // [3][n]
   const T* __restrict__ Ct;      // [3][n]
-  T* __restrict__ trig;          // [6][n]
+  T* __restrict__ trig;          // [n][6]: per vertex cos/sin of the three angles
   uint8_t* __restrict__ flags;
   T wf, wr;
   double wf_d, wr_d;
 
-  __device__ __forceinline__ const T* state_plane(int k) const { return trig + (size_t)k * n; }
+  __device__ __forceinline__ T state_at(int k, int v) const { return trig[(size_t)v * 6 + k]; }
 
   __device__ __forceinline__ EulerTrig<T> trig_at(int v) const {
     EulerTrig<T> t;
-    t.cx = trig[v];
-    t.sx = trig[n + v];
-    t.cy = trig[2 * (size_t)n + v];
-    t.sy = trig[3 * (size_t)n + v];
-    t.cz = trig[4 * (size_t)n + v];
-    t.sz = trig[5 * (size_t)n + v];
+    const T* q = trig + (size_t)v * 6;
+    t.cx = q[0];
+    t.sx = q[1];
+    t.cy = q[2];
+    t.sy = q[3];
+    t.cz = q[4];
+    t.sz = q[5];
     return t;
   }
   template <class XA>
@@ -136,8 +137,8 @@ struct ArapMesh {
     for (int k = 0; k < 3; ++k) {
       T s, c;
       sincos_t(x[(size_t)(3 + k) * n + v], &s, &c);
-      trig[(size_t)(2 * k) * n + v] = c;
-      trig[(size_t)(2 * k + 1) * n + v] = s;
+      trig[(size_t)v * 6 + 2 * k] = c;
+      trig[(size_t)v * 6 + 2 * k + 1] = s;
     }
     uint32_t f = ACTIVE | INGRID;
 #pragma unroll

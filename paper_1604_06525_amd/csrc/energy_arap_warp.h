@@ -32,8 +32,8 @@ struct ArapWarp {
   using Real = T;
   static constexpr bool kGraph = false;
   static constexpr int C = 3;             // unknown channels
-  static constexpr int kStatePlanes = 4;  // cos t, sin t, U_x, U_y
-  static constexpr int kOwnState = 2;     // planes the library stores (cos, sin)
+  static constexpr int kStatePlanes = 4;  // per site: cos t, sin t, U_x, U_y
+  static constexpr int kOwnState = 4;     // all four are stored (U copied beside the angle)
   static constexpr int kRadius = 1;       // stencil radius of J^T J
   enum : uint32_t { ACTIVE = 1, INGRID = 2, FIT = 4 };
 
@@ -41,14 +41,13 @@ struct ArapWarp {
   const T* __restrict__ U;    // [2][n]
   const T* __restrict__ Ct;   // [2][n]
   const uint8_t* __restrict__ mask;
-  T* __restrict__ cs;         // [2][n] cos and sin of t at the linearisation point
+  T* __restrict__ st;         // [n][4]: cos t, sin t at the linearisation point, U_x, U_y
   uint8_t* __restrict__ flags;
   T wf, wr;                   // w_fit, w_reg in the bulk type
   double wf_d, wr_d;          // and in double for the cost
 
-  __device__ __forceinline__ const T* state_plane(int k) const {
-    return k < 2 ? cs + (size_t)k * n : U + (size_t)(k - 2) * n;
-  }
+  __device__ __forceinline__ T state_at(int k, int site) const { return st[(size_t)site * 4 + k]; }
+  __device__ __forceinline__ const T* state_base() const { return st; }
 
   // Neighbour k of site (i, j) in the order (1,0), (-1,0), (0,1), (0,-1);
   // its id, or -1 off the grid.
@@ -95,8 +94,11 @@ struct ArapWarp {
   __device__ __forceinline__ void linearize(const T* __restrict__ x, int s) const {
     T sn, c;
     sincos_t(x[2 * (size_t)n + s], &sn, &c);
-    cs[s] = c;
-    cs[n + s] = sn;
+    T* q = st + (size_t)s * 4;
+    q[0] = c;
+    q[1] = sn;
+    q[2] = U[s];
+    q[3] = U[n + s];
     const bool fit = Ct[s] >= T(0) && Ct[n + s] >= T(0);
     flags[s] = (uint8_t)(INGRID | (mask[s] == 0 ? ACTIVE : 0) | (fit ? FIT : 0));
   }
@@ -107,7 +109,7 @@ struct ArapWarp {
   __device__ __forceinline__ void jtf_diag(XV X, SV S, FV F, int s, int, int, T* b, T* d) const {
     const T c = S(0, 0, 0), sn = S(1, 0, 0), Ux = S(2, 0, 0), Uy = S(3, 0, 0);
     const T Ox = X(0, 0, 0), Oy = X(1, 0, 0);
-    T bx = 0, by = 0, bt = 0, dO = 0, dt = 0;
+    T bx = 0, by = 0, bt = 0;
     const T wr2 = wr * wr;
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
@@ -123,17 +125,36 @@ struct ArapWarp {
       bx += wr2 * (f2x - f1x);
       by += wr2 * (f2y - f1y);
       bt += wr2 * (apx * f1x + apy * f1y);
-      dO += T(2) * wr2;
-      dt += wr2 * (apx * apx + apy * apy);
     }
     if (F(0, 0) & FIT) {
       const T wf2 = wf * wf;
       bx -= wf2 * (Ox - Ct[s]);
       by -= wf2 * (Oy - Ct[n + s]);
-      dO += wf2;
     }
     b[0] = bx; b[1] = by; b[2] = bt;
-    d[0] = dO; d[1] = dO; d[2] = dt;
+    diag(S, F, d);
+  }
+
+  // diag(J^T J) at an active centre, from the state and flags alone: 2 w_reg^2
+  // per active neighbour (+ w_fit^2) for the offsets, w_reg^2 |U_p - U_q|^2 per
+  // active neighbour for the angle (|R'(t) d| = |d|).
+  template <class SV, class FV>
+  __device__ __forceinline__ void diag(SV S, FV F, T* d) const {
+    const T Ux = S(2, 0, 0), Uy = S(3, 0, 0);
+    const T wr2 = wr * wr;
+    T nact = 0, dt = 0;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      const int di = k == 0 ? 1 : (k == 1 ? -1 : 0), dj = k == 2 ? 1 : (k == 3 ? -1 : 0);
+      const T w = (F(di, dj) & ACTIVE) ? T(1) : T(0);
+      const T dx = Ux - S(2, di, dj), dy = Uy - S(3, di, dj);
+      nact += w;
+      dt += w * (dx * dx + dy * dy);
+    }
+    const T dO = T(2) * wr2 * nact + ((F(0, 0) & FIT) ? wf * wf : T(0));
+    d[0] = dO;
+    d[1] = dO;
+    d[2] = wr2 * dt;
   }
 
   // g = J^T J P at an active centre site.
@@ -161,12 +182,10 @@ struct ArapWarp {
       gy += w * (j1y - j2y);
       gt -= w * (apx * j1x + apy * j1y);
     }
-    if (F(0, 0) & FIT) {
-      const T wf2 = wf * wf;
-      gx += wf2 * px;
-      gy += wf2 * py;
-    }
-    g[0] = gx; g[1] = gy; g[2] = gt;
+    const T wfit = (F(0, 0) & FIT) ? wf * wf : T(0);
+    g[0] = fma(wfit, px, gx);
+    g[1] = fma(wfit, py, gy);
+    g[2] = gt;
   }
 
   // sum over the residuals anchored at the centre of (J u)_r^2, u read through
@@ -174,7 +193,7 @@ struct ArapWarp {
   // |J u|^2 = u . (J^T J u).  An excluded centre anchors only constants.
   template <class PV, class SV, class FV>
   __device__ __forceinline__ T jsq(PV U, SV S, FV F, int, int) const {
-    if (!(F(0, 0) & ACTIVE)) return T(0);
+    const uint32_t f0 = F(0, 0);
     const T c = S(0, 0, 0), sn = S(1, 0, 0), Ux = S(2, 0, 0), Uy = S(3, 0, 0);
     const T ux = U(0, 0, 0), uy = U(1, 0, 0), ut = U(2, 0, 0);
     T acc = 0;
@@ -187,9 +206,9 @@ struct ArapWarp {
       const T jx = (ux - U(0, di, dj)) - apx * ut, jy = (uy - U(1, di, dj)) - apy * ut;
       acc += w * (jx * jx + jy * jy);
     }
-    acc *= wr * wr;
-    if (F(0, 0) & FIT) acc += wf * wf * (ux * ux + uy * uy);
-    return acc;
+    const T wfit = (f0 & FIT) ? wf * wf : T(0);
+    acc = fma(wr * wr, acc, wfit * (ux * ux + uy * uy));
+    return (f0 & ACTIVE) ? acc : T(0);
   }
 
   // LM model term of the residuals anchored at s, in FP64:

@@ -52,7 +52,8 @@ struct OpticalFlow {
   T wf, wr;
   double wf_d, wr_d;
 
-  __device__ __forceinline__ const T* state_plane(int k) const { return jf + (size_t)k * n; }
+  __device__ __forceinline__ T state_at(int k, int site) const { return jf[(size_t)site * 2 + k]; }
+  __device__ __forceinline__ const T* state_base() const { return jf; }
 
   __device__ __forceinline__ int nbr(int i, int j, int s, int k) const {
     switch (k) {
@@ -82,8 +83,8 @@ struct OpticalFlow {
   __device__ __forceinline__ void linearize(const T* __restrict__ x, int s) const {
     const int i = s % W, j = s / W;
     const double xs = i + (double)x[s], ys = j + (double)x[n + s];
-    jf[s] = (T)(-wf_d * sample_bilinear<double>(Idx, W, H, xs, ys));
-    jf[n + s] = (T)(-wf_d * sample_bilinear<double>(Idy, W, H, xs, ys));
+    jf[(size_t)s * 2] = (T)(-wf_d * sample_bilinear<double>(Idx, W, H, xs, ys));
+    jf[(size_t)s * 2 + 1] = (T)(-wf_d * sample_bilinear<double>(Idy, W, H, xs, ys));
     flags[s] = (uint8_t)(INGRID | ACTIVE);
   }
 
@@ -105,6 +106,20 @@ struct OpticalFlow {
     const T w2 = T(2) * wr * wr;
     b[0] = -ju * f - w2 * su;
     b[1] = -jv * f - w2 * sv;
+    diag(S, F, d);
+  }
+
+  // diag(J^T J) at an active centre, from the state and flags alone.
+  template <class SV, class FV>
+  __device__ __forceinline__ void diag(SV S, FV F, T* d) const {
+    const T ju = S(0, 0, 0), jv = S(1, 0, 0);
+    T cnt = 0;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      const int di = k == 0 ? 1 : (k == 1 ? -1 : 0), dj = k == 2 ? 1 : (k == 3 ? -1 : 0);
+      cnt += (F(di, dj) & INGRID) ? T(1) : T(0);
+    }
+    const T w2 = T(2) * wr * wr;
     d[0] = ju * ju + w2 * cnt;
     d[1] = jv * jv + w2 * cnt;
   }

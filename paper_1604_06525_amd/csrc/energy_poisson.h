@@ -32,7 +32,8 @@ struct Poisson {
   const uint8_t* __restrict__ mask;
   uint8_t* __restrict__ flags;
 
-  __device__ __forceinline__ const T* state_plane(int) const { return nullptr; }
+  __device__ __forceinline__ T state_at(int, int) const { return T(0); }
+  __device__ __forceinline__ const T* state_base() const { return nullptr; }
 
   __device__ __forceinline__ int nbr(int i, int j, int s, int k) const {
     switch (k) {
@@ -82,10 +83,21 @@ struct Poisson {
       cnt += T(2);
     }
 #pragma unroll
-    for (int c = 0; c < C; ++c) {
-      b[c] = T(-2) * acc[c];
-      d[c] = cnt;
+    for (int c = 0; c < C; ++c) b[c] = T(-2) * acc[c];
+    diag(nullptr, F, d);
+  }
+
+  // diag(J^T J) at an active centre: 2 per neighbour on the grid.
+  template <class SV, class FV>
+  __device__ __forceinline__ void diag(SV, FV F, T* d) const {
+    T cnt = 0;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      const int di = k == 0 ? 1 : (k == 1 ? -1 : 0), dj = k == 2 ? 1 : (k == 3 ? -1 : 0);
+      cnt += (F(di, dj) & INGRID) ? T(2) : T(0);
     }
+#pragma unroll
+    for (int c = 0; c < C; ++c) d[c] = cnt;
   }
 
   template <class PV, class SV, class FV>

@@ -59,7 +59,8 @@ struct ShapeFromShading {
   double L[9];
   T sw_pT, sw_sT, sw_gT;
 
-  __device__ __forceinline__ const T* state_plane(int k) const { return st + (size_t)k * n; }
+  __device__ __forceinline__ T state_at(int k, int site) const { return st[(size_t)site * 4 + k]; }
+  __device__ __forceinline__ const T* state_base() const { return st; }
 
   __device__ __forceinline__ bool ibe(int i, int j) const {
     return i >= 1 && i <= W - 2 && j >= 1 && j <= H - 2;
@@ -177,10 +178,11 @@ struct ShapeFromShading {
     auto Xo = [&](int di, int dj) -> T { return x[s + dj * W + di]; };
     T v, g0, gl, gu;
     shading<T>(i, j, Xo, &v, &g0, &gl, &gu);
-    st[s] = v;
-    st[n + s] = g0;
-    st[2 * n + s] = gl;
-    st[3 * n + s] = gu;
+    T* q = st + (size_t)s * 4;
+    q[0] = v;
+    q[1] = g0;
+    q[2] = gl;
+    q[3] = gu;
     uint32_t f = INGRID;
     if (dv(i, j)) f |= ACTIVE;
     if (ibe(i, j)) f |= IBE;

@@ -70,6 +70,7 @@ constexpr int kNumPartBufs = 10;
 Layout make_layout(const Shape& sh);
 int check_desc(const opt_problem_desc* d, Shape* sh);
 int check_params(const opt_solve_params* sp);
+int check_tuning(const opt_tuning* t);
 
 struct PrecondArgs {
   double lam, dmin, dmax;
@@ -118,7 +119,8 @@ class Impl {
  public:
   virtual ~Impl() = default;
   virtual int linearize(const void* x, int lm_gate) = 0;
-  virtual int init(const void* x, double* trace, int idx, PrecondArgs pa, int lm_gate) = 0;
+  // u_form: the fused form follows (write u_0 = M^-1 b where b would go)
+  virtual int init(const void* x, double* trace, int idx, PrecondArgs pa, int lm_gate, int u_form) = 0;
   virtual int pcg_a(int k, int L, PrecondArgs pa, int lm_gate) = 0;
   virtual int pcg_b(int k, int L, PrecondArgs pa, int lm_gate) = 0;
   virtual int fused(int iter, int L, PrecondArgs pa, int lm_gate) = 0;
@@ -127,6 +129,8 @@ class Impl {
   virtual int apply_step(void* x, int lm_gate) = 0;
   virtual int cost(const void* x, const void* delta, int lm_gate) = 0;
   virtual int model(const void* x) = 0;
+  // Copy an internal vector (interleaved) out to channel planes.
+  virtual int to_planes(const void* src, void* dst) = 0;
   // Record one batched launch of `stage` over n problems of this energy and
   // type (the PCG stage records all of its launches); `fused` picks the form.
   virtual int batch(Stage stage, const SlotRef* slots, int n, bool fused, Batcher& B) = 0;
@@ -142,6 +146,7 @@ struct opt_problem {
   hipStream_t stream = nullptr;
   char* ws = nullptr;
   int nblk = 1;
+  int n_simd = 1024;  // SIMDs of the device (fused kernel launch shape)
   const void* last_x = nullptr;
   opt_tuning tune{};
   std::unique_ptr<optmi::host::Impl> impl;

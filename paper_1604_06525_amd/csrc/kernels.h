@@ -20,12 +20,17 @@
 //
 // Fused (one kernel per iteration): the single-reduction recurrence of
 // Chronopoulos and Gear, which gives the same iterates in exact arithmetic.  With
-// u = M^-1 r, w = A u, gamma = r.u and delta = w.u summed by the previous kernel:
+// u = M^-1 r, gamma = r.u and delta = u.(A u) summed by the previous kernel:
 //   beta_i = gamma_i/gamma_{i-1},  alpha_i = gamma_i / (delta_i - beta_i gamma_i/alpha_{i-1})
-//   p_i = u_i + beta_i p_{i-1};  s_i = A p_i;  d += alpha_i p_i;  r_{i+1} = r_i - alpha_i s_i
-//   partials of gamma_{i+1} = r_{i+1}.u_{i+1} and delta_{i+1} = (A u_{i+1}).u_{i+1}.
-// s_i = A p_i is formed exactly (not by its own recurrence).  A first "priming"
-// launch (iter = -1) with alpha = beta = 0 produces gamma_0 and delta_0.
+//   p_i = u_i + beta_i p_{i-1};  s_i = A p_i;  d += alpha_i p_i;
+//   u_{i+1} = u_i - alpha_i M^-1 s_i  (= M^-1 r_{i+1});
+//   partials of gamma_{i+1} = r_{i+1}.u_{i+1} = sum M u_{i+1}^2 and of
+//   delta_{i+1} = |J u_{i+1}|^2 + u_{i+1}.(lambda D) u_{i+1}.
+// The kernel carries u instead of r, and M (the Jacobi diagonal, damped for LM)
+// is recomputed per site from the state and flags it reads anyway, so neither r
+// nor M^-1 is read.  s_i = A p_i is formed exactly (not by its own recurrence).
+// Init writes u_0 = M^-1 b; a first "priming" launch (iter = -1, alpha = beta =
+// 0, no stores) produces gamma_0 and delta_0.
 //
 // If the curvature p.Ap is not positive the solve stops (DevScalars::stopped):
 // every later iteration kernel returns at once and d keeps its value.
@@ -54,7 +59,7 @@ namespace optmi {
     return inb_(di, dj) ? (uint32_t)(e).flags[(s) + dj * (e).W + di] : 0u;            \
   };                                                                                  \
   auto Sg = [&](int k, int di, int dj) -> typename E::Real {                          \
-    return inb_(di, dj) ? (e).state_plane(k)[(s) + dj * (e).W + di] : typename E::Real(0); \
+    return inb_(di, dj) ? (e).state_at(k, (s) + dj * (e).W + di) : typename E::Real(0);  \
   };
 
 // b = -J^T F and diag(J^T J) at an active site s at the linearisation point x.
@@ -139,6 +144,7 @@ struct InitArgs {
   int trace_idx;
   Precond<typename E::Real> pc;
   int lm_gate;
+  int u_form;  // fused form: write u_0 = M^-1 b (not b) to o.r
 };
 
 template <class E>
@@ -175,9 +181,9 @@ __device__ __forceinline__ void run(const InitArgs<E>& a, VG g, int) {
     }
 #pragma unroll
     for (int c = 0; c < C; ++c) {
-      const size_t k = (size_t)c * n + s;
+      const size_t k = vix<C>(c, s);
       const T m = pc.minv(d[c]);
-      a.o.r[k] = b[c];
+      a.o.r[k] = a.u_form ? m * b[c] : b[c];
       a.o.diag[k] = d[c];
       a.o.minv[k] = m;
       if (a.o.damp) a.o.damp[k] = pc.lam != T(0) ? pc.damp(d[c]) : T(0);
@@ -190,7 +196,8 @@ __device__ __forceinline__ void run(const InitArgs<E>& a, VG g, int) {
 
 // ---------------------------------------------------------------- split: pcg_a
 // Iteration k of the split form (MODE 0), or the plain product
-// q = (J^T J + damp) p_in (MODE 1, with p_in in p[0]).
+// q = (J^T J + damp) p_in (MODE 1, with p_in in p[0] and q in the caller's
+// channel-plane layout; the damping vector stays in the internal layout).
 template <typename T>
 struct SplitBufs {
   const T* r;
@@ -229,8 +236,8 @@ __device__ __forceinline__ void run(const SplitAArgs<E, MODE>& a, VG g, int k) {
   const T* pold = MODE == 1 ? b.p[0] : b.p[(k + 1) & 1];
   T* pnew = b.p[k & 1];
   auto Pg = [&](int c, int site) -> T {
-    const size_t o = (size_t)c * n + site;
-    if (MODE == 1) return pold[o];
+    if (MODE == 1) return pold[(size_t)c * n + site];
+    const size_t o = vix<C>(c, site);
     const T z = b.minv[o] * b.r[o];
     return k == 0 ? z : fma(beta, pold[o], z);
   };
@@ -241,7 +248,7 @@ __device__ __forceinline__ void run(const SplitAArgs<E, MODE>& a, VG g, int k) {
     if (act) site_apply(a.e, s, Pg, gv);
 #pragma unroll
     for (int c = 0; c < C; ++c) {
-      const size_t o = (size_t)c * n + s;
+      const size_t o = vix<C>(c, s);
       T pv = T(0), qv = T(0);
       if (act) {
         pv = Pg(c, s);
@@ -249,7 +256,7 @@ __device__ __forceinline__ void run(const SplitAArgs<E, MODE>& a, VG g, int k) {
         if (b.damp) qv += b.damp[o] * pv;
       }
       if (MODE == 0) pnew[o] = pv;
-      b.q[o] = qv;
+      b.q[MODE == 1 ? (size_t)c * n + s : o] = qv;
       pq += (double)pv * (double)qv;
     }
   }
@@ -288,7 +295,7 @@ __device__ __forceinline__ void run(const SplitBArgs<T, C>& a, VG g, int k) {
   OPT_SITE_LOOP(s, a.n, g) {
 #pragma unroll
     for (int c = 0; c < C; ++c) {
-      const size_t o = (size_t)c * a.n + s;
+      const size_t o = vix<C>(c, s);
       a.delta[o] = fma(alpha, p[o], a.delta[o]);
       const T rv = fma(-alpha, a.q[o], a.r[o]);
       a.r[o] = rv;
@@ -334,11 +341,10 @@ template <class E, bool DAMP>
 struct StreamRow {
   using T = typename E::Real;
   static constexpr int C = E::C, NS = E::kStatePlanes > 0 ? E::kStatePlanes : 1;
-  T r[C];    // r_i, later r_{i+1}
-  T m[C];    // M^-1, later u_{i+1} = M^-1 r_{i+1}
+  T u[C];    // u_i, later u_{i+1}
   T p[C];    // p_{i-1}, later p_i
   T x[C];    // d (loaded one step before it is updated)
-  T dmp[DAMP ? C : 1];  // LM damping
+  T dmp[DAMP ? C : 1];  // LM damping lambda*D (computed, not loaded)
   T st[NS];
   uint32_t f;
 };
@@ -387,11 +393,9 @@ __device__ __forceinline__ int unit_of_block(VG g) {
 
 template <typename T>
 struct FusedBufs {
-  T* r[2];         // iteration i reads r_i from r[i & 1], writes r_{i+1} to r[(i + 1) & 1]
+  T* u[2];         // iteration i reads u_i from u[i & 1], writes u_{i+1} to u[(i + 1) & 1]
   T* p[2];         // iteration i writes p_i to p[i & 1], reads p_{i-1} from p[(i + 1) & 1]
   T* x;            // the PCG solution d, updated in place
-  const T* minv;
-  const T* damp;   // LM damping lambda*D (the DAMP form only)
   double* part[2]; // [gamma | delta] partials, kMaxBlocks apart; iteration i writes
                    // part[i & 1] (the priming launch writes part[1]) and reads the other
 };
@@ -400,10 +404,13 @@ template <class E, bool DAMP>
 struct FusedArgs {
   E e;
   FusedBufs<typename E::Real> b;
+  Precond<typename E::Real> pc;  // lam taken from the device scalars when lm_gate
   int n_part;  // blocks of this problem
   DevScalars* S;
   int lm_gate;
-  int n_sx, n_sy, Hs;  // strips across, strips down, rows per strip
+  int n_sx, n_sy;  // strips across, strips down
+  int sw;          // produced columns per strip (<= kStripCols)
+  int rq, rr;      // rows per strip: rq, one more for the first rr strips down
   int L;
 };
 
@@ -424,7 +431,62 @@ __device__ __forceinline__ void run(const FusedArgs<E, DAMP>& a, VG g, int iter)
   constexpr int N = kPrefetch + 4;  // ring slots: four rows in use, the rest in flight
   const E& e = a.e;
   DevScalars* S = a.S;
-  if (iter >= a.L || S->stopped || (a.lm_gate && S->done)) return;
+  if (iter >= a.L) return;
+  const bool read_pold = iter > 0, write_out = iter >= 0;
+  const int W = e.W, H = e.H, n = e.n, n_sy = a.n_sy, sw = a.sw;
+  const int lane = threadIdx.x & 63;
+  const int strip = unit_of_block(g) * kWaves + (threadIdx.x >> 6);
+  const bool has_strip = strip < a.n_sx * n_sy;
+  // Strips are numbered along grid rows, so horizontally adjacent strips run
+  // side by side (and mostly on one XCD).  Vertically adjacent strips walk in
+  // opposite directions, so both reach the halo rows they share at about the
+  // same time and the second read is served by the L2.  The operators treat
+  // the rows above and below a site alike, so a strip walking up only sees the
+  // four neighbour terms in another order.
+  const int sy = strip / a.n_sx, sx = strip % a.n_sx;
+  const int col = sx * sw - 2 + lane;
+  const int y0 = sy * a.rq + min(sy, a.rr), y1 = min(y0 + a.rq + (sy < a.rr ? 1 : 0), H);
+  const int dir = (sy & 1) ? -1 : 1;
+  const int ybeg = dir > 0 ? y0 - 2 : y1 + 1;  // row of step 0
+  const int ylo = max(y0 - 2, 0), yhi = min(y1 + 1, H - 1);
+  const bool colin = has_strip && col >= 0 && col < W;
+  const bool out_lane = colin && lane >= 2 && lane < 2 + sw;
+  const int K = (y1 - y0) + 4;  // rows y0-2 .. y1+1
+  // One raw buffer per vector and for the per-site state and flags.  A site's
+  // channels are adjacent, so each row of a vector is one wide load per lane.
+  // A lane or row off the strip uses an out-of-range offset: its loads return
+  // 0, its stores are dropped.
+  constexpr unsigned VB = C * sizeof(T), SB = (NS > 0 ? NS : 1) * sizeof(T);
+  const size_t vbytes = (size_t)n * VB;
+  const Buf<T> Buin = Buf<T>::make(a.b.u[iter < 0 ? 0 : (iter & 1)], vbytes);
+  const Buf<T> Bpin = Buf<T>::make(a.b.p[(iter + 1) & 1], read_pold ? vbytes : 0);
+  const Buf<T> Bx = Buf<T>::make(a.b.x, write_out ? vbytes : 0);
+  const Buf<T> Buout = Buf<T>::make(a.b.u[(iter + 1) & 1], write_out ? vbytes : 0);
+  const Buf<T> Bpout = Buf<T>::make(a.b.p[iter & 1], write_out ? vbytes : 0);
+  const Buf<T> Bst = Buf<T>::make(e.state_base(), NS > 0 ? (size_t)n * SB : 0);
+  const Buf<uint8_t> Bf = Buf<uint8_t>::make(e.flags, (size_t)n);
+  // The row of step k lives in ring slot k % N; its loads are issued
+  // kPrefetch steps before it is started.
+  Row ring[N];
+  auto issue = [&](Row& R, int y) {
+    const bool in = colin && y >= ylo && y <= yhi;
+    const unsigned s = (unsigned)(y * W + col);
+    const unsigned o = in ? s * VB : kBufOutOfRange;
+    if constexpr (NS > 0) {
+      buf_loadv<NS>(Bst, in ? s * SB : kBufOutOfRange, 0, R.st);
+    } else {
+      R.st[0] = T(0);
+    }
+    R.f = Bf.load(in ? s : kBufOutOfRange, 0);
+    buf_loadv<C>(Buin, o, 0, R.u);
+    buf_loadv<C>(Bpin, o, 0, R.p);
+  };
+  // The first rows do not depend on alpha and beta: fetch them while the
+  // previous launch's partial sums are reduced.
+#pragma unroll
+  for (int k = 0; k < kPrefetch; ++k) issue(ring[k], ybeg + dir * k);
+
+  if (S->stopped || (a.lm_gate && S->done)) return;
   const double* part_in = a.b.part[(iter + 1) & 1];
   double* part_out = a.b.part[iter & 1];
   double alpha = 0.0, beta = 0.0;
@@ -447,122 +509,81 @@ __device__ __forceinline__ void run(const FusedArgs<E, DAMP>& a, VG g, int iter)
     }
   }
   const T aT = (T)alpha, bT = (T)beta;
-  const bool read_pold = iter > 0, write_out = iter >= 0;
-  const int W = e.W, H = e.H, n = e.n, n_sy = a.n_sy, Hs = a.Hs;
-  const int lane = threadIdx.x & 63;
-  const int strip = unit_of_block(g) * kWaves + (threadIdx.x >> 6);
+  Precond<T> pc = a.pc;
+  if (a.lm_gate) pc.lam = (T)S->lambda;
   double g_acc = 0.0, d_acc = 0.0;
 
-  if (strip < a.n_sx * n_sy) {
-    const int sx = strip / n_sy, sy = strip % n_sy;
-    const int col = sx * kStripCols - 2 + lane;
-    const int y0 = sy * Hs, y1 = min(y0 + Hs, H);
-    const bool colin = col >= 0 && col < W;
-    const bool out_lane = colin && lane >= 2 && lane < 2 + kStripCols;
-    const int K = (y1 - y0) + 4;  // rows y0-2 .. y1+1
-    // One raw buffer per vector (all channels; channel c at scalar offset
-    // c * plane), per state plane and for the flags.  A lane or row off the strip
-    // uses an out-of-range offset: its loads return 0, its stores are dropped.
-    const size_t vbytes = (size_t)C * n * sizeof(T);
-    const unsigned plane = (unsigned)((size_t)n * sizeof(T));
-    const Buf<T> Brin = Buf<T>::make(a.b.r[iter < 0 ? 0 : (iter & 1)], vbytes);
-    const Buf<T> Bm = Buf<T>::make(a.b.minv, vbytes);
-    const Buf<T> Bpin = Buf<T>::make(a.b.p[(iter + 1) & 1], read_pold ? vbytes : 0);
-    const Buf<T> Bx = Buf<T>::make(a.b.x, write_out ? vbytes : 0);
-    const Buf<T> Bd = Buf<T>::make(a.b.damp, DAMP ? vbytes : 0);
-    const Buf<T> Brout = Buf<T>::make(a.b.r[(iter + 1) & 1], write_out ? vbytes : 0);
-    const Buf<T> Bpout = Buf<T>::make(a.b.p[iter & 1], write_out ? vbytes : 0);
-    Buf<T> Bst[NS > 0 ? NS : 1];
-#pragma unroll
-    for (int q = 0; q < NS; ++q) Bst[q] = Buf<T>::make(e.state_plane(q), (size_t)n * sizeof(T));
-    const Buf<uint8_t> Bf = Buf<uint8_t>::make(e.flags, (size_t)n);
-    // Row y0-2+k lives in ring slot k % N; its loads are issued kPrefetch steps
-    // before it is started.
-    Row ring[N];
-    auto issue = [&](Row& R, int y) {
-      const bool in = colin && y >= 0 && y < H && y <= y1 + 1;
-      const unsigned s = (unsigned)(y * W + col);
-      const unsigned o = in ? s * (unsigned)sizeof(T) : kBufOutOfRange;
-#pragma unroll
-      for (int c = 0; c < C; ++c) {
-        R.r[c] = Brin.load(o, c * plane);
-        R.m[c] = Bm.load(o, c * plane);
-        R.p[c] = Bpin.load(o, c * plane);
-        if constexpr (DAMP) R.dmp[c] = Bd.load(o, c * plane);
-      }
-#pragma unroll
-      for (int q = 0; q < NS; ++q) R.st[q] = Bst[q].load(o, 0);
-      R.f = Bf.load(in ? s : kBufOutOfRange, 0);
-    };
+  if (has_strip) {
     auto selp = [](const Row& R, int c) { return R.p[c]; };
-    auto selu = [](const Row& R, int c) { return R.m[c]; };
+    auto selu = [](const Row& R, int c) { return R.u[c]; };
 
     auto step = [&](auto PH, int k) {
       constexpr int ph = decltype(PH)::value;
-      Row& R0 = ring[ph];                // row y = y0 - 2 + k
-      Row& R1 = ring[(ph + N - 1) % N];  // y - 1
-      Row& R2 = ring[(ph + N - 2) % N];  // y - 2
-      Row& R3 = ring[(ph + N - 3) % N];  // y - 3
-      const int y = y0 - 2 + k;
-      issue(ring[(ph + kPrefetch) % N], y + kPrefetch);
-      // p_i = M^-1 r_i + beta p_{i-1} on row y
+      Row& R0 = ring[ph];                // row y = ybeg + dir k
+      Row& R1 = ring[(ph + N - 1) % N];  // y - dir
+      Row& R2 = ring[(ph + N - 2) % N];  // y - 2 dir
+      Row& R3 = ring[(ph + N - 3) % N];  // y - 3 dir
+      const int y = ybeg + dir * k;
+      issue(ring[(ph + kPrefetch) % N], y + dir * kPrefetch);
+      // p_i = u_i + beta p_{i-1} on row y
 #pragma unroll
-      for (int c = 0; c < C; ++c) {
-        const T u = R0.m[c] * R0.r[c];
-        R0.p[c] = read_pold ? fma(bT, R0.p[c], u) : u;
-      }
+      for (int c = 0; c < C; ++c) R0.p[c] = read_pold ? fma(bT, R0.p[c], R0.u[c]) : R0.u[c];
       if (k >= 2) {
-        // s = A p, r_{i+1} = r_i - alpha s, u_{i+1} = M^-1 r_{i+1} on row y - 1;
+        // on row y - dir: s = A p (with the LM damping), the diagonal M from the
+        // state, u_{i+1} = u_i - alpha M^-1 s and the partial of gamma = sum M u^2;
         // d of that row is fetched now, to be updated in the next step
-        T gv[C];
+        const int y1r = y - dir;
+        T gv[C], dg[C];
         with_views(R2, R1, R0, selp, [&](auto Pv, auto Sv, auto Fv) {
-          e.apply(Pv, Sv, Fv, col, y - 1, gv);
+          e.apply(Pv, Sv, Fv, col, y1r, gv);
+          e.diag(Sv, Fv, dg);
           return 0;
         });
         const bool act = R1.f & E::ACTIVE;
-        const bool prod = y - 1 >= y0 && y - 1 < y1;
-        const unsigned ox = (out_lane && prod && act && write_out) ? (unsigned)((y - 1) * W + col) *
-                                                                         (unsigned)sizeof(T)
+        const bool prod = y1r >= y0 && y1r < y1;
+        const unsigned ox = (out_lane && prod && act && write_out) ? (unsigned)(y1r * W + col) * VB
                                                                    : kBufOutOfRange;
+        buf_loadv<C>(Bx, ox, 0, R1.x);
+        T gs = 0;
 #pragma unroll
         for (int c = 0; c < C; ++c) {
-          R1.x[c] = Bx.load(ox, c * plane);
-          const T sv = DAMP ? fma(R1.dmp[c], R1.p[c], gv[c]) : gv[c];
-          R1.r[c] = act ? fma(-aT, sv, R1.r[c]) : T(0);
-          R1.m[c] = act ? R1.m[c] * R1.r[c] : T(0);
+          T sv = gv[c];
+          if constexpr (DAMP) {
+            R1.dmp[c] = pc.lam != T(0) ? pc.damp(dg[c]) : T(0);
+            sv = fma(R1.dmp[c], R1.p[c], sv);
+          }
+          R1.u[c] = act ? fma(-aT, pc.minv(dg[c]) * sv, R1.u[c]) : T(0);
+          gs = fma(pc.den(dg[c]) * R1.u[c], R1.u[c], gs);
         }
+        g_acc += (out_lane && prod) ? (double)gs : 0.0;
       }
       if (k >= 4) {
-        // row y - 2 is final: partials of gamma = r.u and delta = u.(A u) =
-        // |J u|^2 (+ u.damp u), and the stores of d, r, p
-        const int yo = y - 2;
+        // row y - 2 dir is final: partial of delta = |J u|^2 (+ u.(lambda D) u),
+        // and the stores of d, u, p
+        const int yo = y - 2 * dir;
         const T jq = with_views(R3, R2, R1, selu, [&](auto Pv, auto Sv, auto Fv) {
           return e.jsq(Pv, Sv, Fv, col, yo);
         });
         const bool act = R2.f & E::ACTIVE;
-        if (out_lane && (R2.f & E::INGRID)) {
-          T gs = 0, ds = 0;
+        T ds = jq;
+        if constexpr (DAMP) {
 #pragma unroll
-          for (int c = 0; c < C; ++c) {
-            gs = fma(R2.r[c], R2.m[c], gs);
-            if constexpr (DAMP) ds = fma(R2.dmp[c] * R2.m[c], R2.m[c], ds);
-          }
-          g_acc += (double)gs;
-          d_acc += (double)jq + (double)ds;
+          for (int c = 0; c < C; ++c) ds = fma(R2.dmp[c] * R2.u[c], R2.u[c], ds);
         }
-        const unsigned o = out_lane ? (unsigned)(yo * W + col) * (unsigned)sizeof(T) : kBufOutOfRange;
+        d_acc += (out_lane && (R2.f & E::INGRID)) ? (double)ds : 0.0;
+        const unsigned o = out_lane ? (unsigned)(yo * W + col) * VB : kBufOutOfRange;
         const unsigned ox = (act && write_out) ? o : kBufOutOfRange;
+        T pv[C], xv[C];
 #pragma unroll
         for (int c = 0; c < C; ++c) {
-          const T pv = act ? R2.p[c] : T(0);
-          Bx.store(ox, c * plane, fma(aT, pv, R2.x[c]));
-          Brout.store(o, c * plane, R2.r[c]);
-          Bpout.store(o, c * plane, pv);
+          pv[c] = act ? R2.p[c] : T(0);
+          xv[c] = fma(aT, pv[c], R2.x[c]);
         }
+        buf_storev<C>(Bx, ox, 0, xv);
+        buf_storev<C>(Buout, o, 0, R2.u);
+        buf_storev<C>(Bpout, o, 0, pv);
       }
     };
-#pragma unroll
-    for (int k = 0; k < kPrefetch; ++k) issue(ring[k], y0 - 2 + k);
     for (int k = 0; k < K; k += N) {
       unroll_seq(std::make_integer_sequence<int, N>{}, [&](auto PH) {
         if (k + decltype(PH)::value < K) step(PH, k + decltype(PH)::value);
@@ -598,7 +619,7 @@ __device__ __forceinline__ void run(const StepArgs<E>& a, VG g, int) {
 #pragma unroll
     for (int c = 0; c < C; ++c) {
       const size_t o = (size_t)c * n + s;
-      a.x[o] = a.x[o] + a.delta[o];
+      a.x[o] = a.x[o] + a.delta[vix<C>(c, s)];
     }
   }
 }
@@ -624,7 +645,7 @@ __device__ __forceinline__ void run(const CostArgs<E>& a, VG g, int) {
   auto X = [&](int c, int s) -> double {
     const size_t o = (size_t)c * n + s;
     if (a.delta == nullptr) return (double)a.x[o];
-    return (double)(T)(a.x[o] + a.delta[o]);
+    return (double)(T)(a.x[o] + a.delta[vix<E::C>(c, s)]);
   };
   double acc = 0.0;
   OPT_SITE_LOOP(s, n, g) acc += a.e.cost(X, s);
@@ -646,7 +667,7 @@ __device__ __forceinline__ void run(const ModelArgs<E>& a, VG g, int) {
   if (a.S->done) return;
   const int n = a.e.n;
   auto X = [&](int c, int s) -> double { return (double)a.x[(size_t)c * n + s]; };
-  auto D = [&](int c, int s) -> double { return (double)a.delta[(size_t)c * n + s]; };
+  auto D = [&](int c, int s) -> double { return (double)a.delta[vix<E::C>(c, s)]; };
   double acc = 0.0;
   OPT_SITE_LOOP(s, n, g) acc += a.e.model(X, D, s);
   block_store(acc, a.part, g);
@@ -747,6 +768,23 @@ __device__ __forceinline__ void run(const FinishArgs& a, VG, int) {
     a.S->E_final = E;
     if (!finite_d(E)) a.S->nonfinite = 1;
     if (a.trace) a.trace[a.trace_idx] = E;
+  }
+}
+
+// An internal vector (sites x C, interleaved) copied out to the caller's layout
+// of C planes of n values.
+template <typename T, int C>
+struct PlanesArgs {
+  const T* src;
+  T* dst;
+  int n;
+};
+
+template <typename T, int C>
+__device__ __forceinline__ void run(const PlanesArgs<T, C>& a, VG g, int) {
+  OPT_SITE_LOOP(s, a.n, g) {
+#pragma unroll
+    for (int c = 0; c < C; ++c) a.dst[(size_t)c * a.n + s] = a.src[vix<C>(c, s)];
   }
 }
 

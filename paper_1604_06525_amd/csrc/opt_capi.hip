@@ -144,26 +144,37 @@ int check_desc(const opt_problem_desc* d, Shape* sh) {
 
 namespace {
 
-// Strips of the fused kernel: about this many waves per launch (4.5 per CU).
-constexpr int kFusedTargetStrips = 1152;
-
 struct StripGeom {
-  int n_sx, n_sy, Hs, grid;
+  int n_sx, n_sy, sw, rq, rr, grid;
 };
 
-// rows > 0 fixes the strip height (a tuned value); 0 picks it for about
-// kFusedTargetStrips strips.
-StripGeom strip_geom(int W, int H, int rows) {
+// Partition of a W x H grid into strips for the fused kernel: n_sx strips
+// across of sw produced columns each (sw <= 60, as even as possible), n_sy
+// strips down of rq or rq + 1 rows.
+//   t.strip_rows > 0: strips of that many rows;
+//   otherwise about w strips per SIMD with the rows split evenly, w =
+//   t.waves_per_simd or, by default, kAutoWavesPerSimd; never under 4 rows.
+// Balance matters: a launch is set by its slowest SIMD, so every SIMD should
+// get the same number of equal strips (measured best: two, which also lets each
+// SIMD overlap one strip's memory waits with the other's arithmetic).
+constexpr int kAutoWavesPerSimd = 2;
+
+StripGeom strip_geom(int W, int H, const opt_tuning& t, int n_simd) {
   StripGeom g;
   g.n_sx = (W + kStripCols - 1) / kStripCols;
-  g.Hs = rows > 0 ? rows : std::max(4, (g.n_sx * H + kFusedTargetStrips - 1) / kFusedTargetStrips);
-  g.n_sy = (H + g.Hs - 1) / g.Hs;
-  const int max_strips = kWaves * kMaxBlocks;
-  if (g.n_sx * g.n_sy > max_strips) {
-    const int n_sy = std::max(1, max_strips / g.n_sx);
-    g.Hs = (H + n_sy - 1) / n_sy;
-    g.n_sy = (H + g.Hs - 1) / g.Hs;
+  g.sw = (W + g.n_sx - 1) / g.n_sx;
+  const int max_sy = std::max(1, H / 4);
+  int n_sy;
+  if (t.strip_rows > 0) {
+    n_sy = (H + t.strip_rows - 1) / t.strip_rows;
+  } else {
+    const int w = t.waves_per_simd > 0 ? t.waves_per_simd : kAutoWavesPerSimd;
+    n_sy = std::min(max_sy, std::max(1, w * n_simd / g.n_sx));
   }
+  n_sy = std::max(1, std::min(n_sy, kWaves * kMaxBlocks / g.n_sx));
+  g.n_sy = n_sy;
+  g.rq = H / n_sy;
+  g.rr = H % n_sy;
   g.grid = (g.n_sx * g.n_sy + kWaves - 1) / kWaves;
   return g;
 }
@@ -192,7 +203,7 @@ class ImplT final : public Impl {
   LinArgs<E> lin_args(const void* x, int lm) const {
     return LinArgs<E>{e_, (const T*)x, p_->part(P_LIN), p_->S(), lm};
   }
-  InitArgs<E> init_args(const void* x, double* trace, int idx, PrecondArgs pa, int lm) const {
+  InitArgs<E> init_args(const void* x, double* trace, int idx, PrecondArgs pa, int lm, int u_form) const {
     InitArgs<E> a;
     a.e = e_;
     a.x = (const T*)x;
@@ -205,6 +216,7 @@ class ImplT final : public Impl {
     a.trace_idx = idx;
     a.pc = pc(pa);
     a.lm_gate = lm;
+    a.u_form = u_form;
     return a;
   }
   SplitBufs<T> split_bufs(PrecondArgs pa) const {
@@ -243,24 +255,25 @@ class ImplT final : public Impl {
   }
   template <bool DAMP>
   FusedArgs<E, DAMP> fused_args(int L, PrecondArgs pa, int lm, int* grid) const {
-    const StripGeom g = strip_geom(e_.W, e_.H, p_->tune.strip_rows);
+    const StripGeom g = strip_geom(e_.W, e_.H, p_->tune, p_->n_simd);
     FusedArgs<E, DAMP> a;
     a.e = e_;
-    a.b.r[0] = rbuf(0);
-    a.b.r[1] = rbuf(1);
+    a.b.u[0] = rbuf(0);
+    a.b.u[1] = rbuf(1);
     a.b.p[0] = pbuf(0);
     a.b.p[1] = pbuf(1);
     a.b.x = vec(p_->L.delta);
-    a.b.minv = vec(p_->L.minv);
-    a.b.damp = damp(pa);
     a.b.part[0] = p_->part(P_F0);
     a.b.part[1] = p_->part(P_F1);
+    a.pc = pc(pa);
     a.n_part = g.grid;
     a.S = p_->S();
     a.lm_gate = lm;
     a.n_sx = g.n_sx;
     a.n_sy = g.n_sy;
-    a.Hs = g.Hs;
+    a.sw = g.sw;
+    a.rq = g.rq;
+    a.rr = g.rr;
     a.L = L;
     *grid = g.grid;
     return a;
@@ -284,8 +297,8 @@ class ImplT final : public Impl {
   }
 
   int linearize(const void* x, int lm) override { return go(lin_args(x, lm), nblk(), 0, "linearize"); }
-  int init(const void* x, double* trace, int idx, PrecondArgs pa, int lm) override {
-    return go(init_args(x, trace, idx, pa, lm), nblk(), 0, "init");
+  int init(const void* x, double* trace, int idx, PrecondArgs pa, int lm, int u_form) override {
+    return go(init_args(x, trace, idx, pa, lm, u_form), nblk(), 0, "init");
   }
   int pcg_a(int k, int L, PrecondArgs pa, int lm) override {
     return go(pcga_args(L, pa, lm), nblk(), k, "pcg_a");
@@ -317,6 +330,9 @@ class ImplT final : public Impl {
     return go(cost_args(x, delta, lm), nblk(), 0, "cost");
   }
   int model(const void* x) override { return go(model_args(x), nblk(), 0, "model"); }
+  int to_planes(const void* src, void* dst) override {
+    return go(PlanesArgs<T, E::C>{(const T*)src, (T*)dst, e_.n}, nblk(), 0, "to_planes");
+  }
 
   // ------------------------------------------------ batched launches
   // Every problem keeps the grid it has alone, so its per-block partials and
@@ -343,9 +359,9 @@ class ImplT final : public Impl {
           return m.lin_args(r.x, r.lm);
         }, 0, 1, "linearize[batch]");
       case Stage::INIT:
-        return rec<InitArgs<E>>(B, s, n, [](const ImplT& m, const SlotRef& r, int* g) {
+        return rec<InitArgs<E>>(B, s, n, [use_fused](const ImplT& m, const SlotRef& r, int* g) {
           *g = m.nblk();
-          return m.init_args(r.x, r.p->trace(), r.trace_idx, r.pa, r.lm);
+          return m.init_args(r.x, r.p->trace(), r.trace_idx, r.pa, r.lm, use_fused ? 1 : 0);
         }, 0, 1, "init[batch]");
       case Stage::PCG:
         if (use_fused) {
@@ -428,7 +444,7 @@ std::unique_ptr<Impl> make_impl_t(opt_problem* p) {
       e.U = (const T*)d.arrays[0];
       e.Ct = (const T*)d.arrays[1];
       e.mask = (const uint8_t*)d.arrays[2];
-      e.cs = (T*)p->at(p->L.state);
+      e.st = (T*)p->at(p->L.state);
       e.flags = (uint8_t*)p->at(p->L.flags);
       e.wf = (T)d.params[0];
       e.wr = (T)d.params[1];
@@ -558,10 +574,22 @@ int problem_init(opt_problem* p, const opt_problem_desc* desc, const Shape& sh, 
   p->ws = (char*)workspace;
   p->nblk = (int)std::min<long long>(kMaxBlocks, (sh.n + kBlock - 1) / kBlock);
   if (p->nblk < 1) p->nblk = 1;
+  int dev = 0, cus = 0;
+  HIP_TRY(hipGetDevice(&dev));
+  HIP_TRY(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+  p->n_simd = std::max(1, cus) * 4;  // four SIMDs per compute unit
   p->impl = make_impl(p);
   if (!p->impl) return fail(OPT_EUNSUPPORTED, "energy %d is not built", desc->energy);
   if (sh.graph) TRY(build_incidence(p));
   TRY(scalar_kernel(p->stream, SetupArgs{p->S(), 0.0, 1.0, 0, 0.0}, "setup"));
+  return OPT_OK;
+}
+
+int check_tuning(const opt_tuning* t) {
+  if (t->strip_rows < 0 || t->strip_rows > (1 << 20))
+    return fail(OPT_EINVAL, "strip_rows %d outside [0, 2^20]", t->strip_rows);
+  if (t->waves_per_simd < 0 || t->waves_per_simd > 64)
+    return fail(OPT_EINVAL, "waves_per_simd %d outside [0, 64]", t->waves_per_simd);
   return OPT_OK;
 }
 
@@ -608,8 +636,13 @@ int record_event(opt_problem* p) {
 // The L iterations of the inner solve after init, in the chosen form.  Energies
 // whose operator reaches further than one site (shape from shading) always use
 // the split form.
+// Whether the inner solve runs in the fused form (which starts from u_0 = M^-1 b).
+int uses_fused(opt_problem* p, int variant) {
+  return variant == OPT_PCG_FUSED && p->impl->has_fused() ? 1 : 0;
+}
+
 int run_pcg(opt_problem* p, PrecondArgs pa, int lm, int L, int variant) {
-  if (variant == OPT_PCG_FUSED && p->impl->has_fused()) {
+  if (uses_fused(p, variant)) {
     if (L > 0) TRY(p->impl->fused(-1, L, pa, lm));
     for (int i = 0; i < L; ++i) TRY(p->impl->fused(i, L, pa, lm));
   } else {
@@ -700,11 +733,9 @@ int opt_eval_jtf(opt_problem* p, void* b_out, void* diag_out) {
   if (!p) return fail(OPT_EINVAL, "problem is NULL");
   if (!p->last_x) return fail(OPT_EINVAL, "opt_linearize has not been called");
   PrecondArgs pa{0.0, 0.0, 0.0, 1, false};
-  TRY(p->impl->init(p->last_x, nullptr, 0, pa, 0));
-  const size_t bytes = (size_t)p->sh.C * p->sh.n * p->sh.tsize;
-  if (b_out) HIP_TRY(hipMemcpyAsync(b_out, p->at(p->L.r0), bytes, hipMemcpyDeviceToDevice, p->stream));
-  if (diag_out)
-    HIP_TRY(hipMemcpyAsync(diag_out, p->at(p->L.diag), bytes, hipMemcpyDeviceToDevice, p->stream));
+  TRY(p->impl->init(p->last_x, nullptr, 0, pa, 0, 0));
+  if (b_out) TRY(p->impl->to_planes(p->at(p->L.r0), b_out));
+  if (diag_out) TRY(p->impl->to_planes(p->at(p->L.diag), diag_out));
   return OPT_OK;
 }
 
@@ -717,7 +748,7 @@ int opt_apply_jtj(opt_problem* p, const void* pin, void* qout, double lambda,
   if (lambda != 0.0) {
     if (!sp) return fail(OPT_EINVAL, "params are needed when lambda != 0");
     pa = PrecondArgs{lambda, sp->lm_diag_min, sp->lm_diag_max, 1, true};
-    TRY(p->impl->init(p->last_x, nullptr, 0, pa, 0));
+    TRY(p->impl->init(p->last_x, nullptr, 0, pa, 0, 0));
   }
   return p->impl->apply_jtj(pin, qout, pa);
 }
@@ -728,19 +759,15 @@ int opt_pcg(opt_problem* p, const opt_solve_params* sp, double lambda, void* del
   if (!p->last_x) return fail(OPT_EINVAL, "opt_linearize has not been called");
   PrecondArgs pa{lambda, sp->lm_diag_min, sp->lm_diag_max, sp->use_precond, lambda != 0.0};
   TRY(scalar_kernel(p->stream, SetupArgs{p->S(), lambda, 1.0, 0, 0.0}, "setup"));
-  TRY(p->impl->init(p->last_x, nullptr, 0, pa, 0));
+  TRY(p->impl->init(p->last_x, nullptr, 0, pa, 0, uses_fused(p, sp->pcg_variant)));
   TRY(run_pcg(p, pa, 0, sp->pcg_iters, sp->pcg_variant));
-  if (delta_out) {
-    const size_t bytes = (size_t)p->sh.C * p->sh.n * p->sh.tsize;
-    HIP_TRY(hipMemcpyAsync(delta_out, p->at(p->L.delta), bytes, hipMemcpyDeviceToDevice, p->stream));
-  }
+  if (delta_out) TRY(p->impl->to_planes(p->at(p->L.delta), delta_out));
   return OPT_OK;
 }
 
 int opt_problem_set_tuning(opt_problem* p, const opt_tuning* t) {
   if (!p || !t) return fail(OPT_EINVAL, "problem or tuning is NULL");
-  if (t->strip_rows < 0 || t->strip_rows > (1 << 20))
-    return fail(OPT_EINVAL, "strip_rows %d outside [0, 2^20]", t->strip_rows);
+  TRY(check_tuning(t));
   p->tune = *t;
   return OPT_OK;
 }
@@ -748,8 +775,11 @@ int opt_problem_set_tuning(opt_problem* p, const opt_tuning* t) {
 int opt_problem_get_tuning(opt_problem* p, opt_tuning* t) {
   if (!p || !t) return fail(OPT_EINVAL, "problem or tuning is NULL");
   *t = p->tune;
-  if (t->strip_rows == 0 && !p->sh.graph)
-    t->strip_rows = strip_geom(p->desc.width, p->desc.height, 0).Hs;
+  if (!p->sh.graph) {
+    const StripGeom g = strip_geom(p->desc.width, p->desc.height, p->tune, p->n_simd);
+    t->strip_rows = g.rq + (g.rr > 0 ? 1 : 0);
+    t->waves_per_simd = (g.n_sx * g.n_sy + p->n_simd - 1) / p->n_simd;
+  }
   return OPT_OK;
 }
 
@@ -797,7 +827,7 @@ int opt_solve(opt_problem* p, void* x, const opt_solve_params* sp, opt_solve_rep
   LMConsts lc{sp->lm_radius_min, sp->lm_radius_max, sp->lm_min_rel_decrease};
   for (int k = 0; k < K; ++k) {
     TRY(p->impl->linearize(x, lm));
-    TRY(p->impl->init(x, trace, k, pa, lm));
+    TRY(p->impl->init(x, trace, k, pa, lm, uses_fused(p, sp->pcg_variant)));
     if (p->profile) TRY(record_event(p));
     TRY(run_pcg(p, pa, lm, Lp, sp->pcg_variant));
     if (p->profile) {

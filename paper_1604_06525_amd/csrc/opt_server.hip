@@ -402,8 +402,7 @@ int opt_server_cancel(opt_server* sv, int64_t ticket) {
 int opt_server_add_tuning(opt_server* sv, int32_t energy, int32_t precision, int64_t min_sites,
                           int64_t max_sites, const opt_tuning* t) {
   if (!sv || !t) return fail(OPT_EINVAL, "server or tuning is NULL");
-  if (t->strip_rows < 0 || t->strip_rows > (1 << 20))
-    return fail(OPT_EINVAL, "strip_rows %d outside [0, 2^20]", t->strip_rows);
+  TRY(check_tuning(t));
   if (min_sites > max_sites) return fail(OPT_EINVAL, "empty site range");
   sv->tuning.push_back(TuneEntry{energy, precision, min_sites, max_sites, *t});
   return OPT_OK;

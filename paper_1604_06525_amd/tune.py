@@ -5,9 +5,10 @@
 For each energy with a fused kernel (ARAP warp, Poisson, optical flow), each
 precision and each size class (grid sides 128, 256, 512, 1024, 2048), it times
 the PCG phase of a short solve on a seeded synthetic problem for every candidate
-strip height, and keeps the fastest.  The result is a JSON list of entries
-{energy, precision, min_sites, max_sites, strip_rows, iter_us, candidates}; a
-class covers the sites from half its own count up to twice it.  ``apply()``
+launch shape (fixed strip heights, and balanced partitions with 1 to 4 strips
+per SIMD), and keeps the fastest.  The result is a JSON list of entries
+{energy, precision, min_sites, max_sites, strip_rows, waves_per_simd, iter_us,
+candidates}; a class covers the sites from half its own count up to twice it.  ``apply()``
 feeds the entries to a Server (used at admission) and ``best()`` looks one up for
 a single Problem.  Every choice gives the same iterates; only the speed differs.
 """
@@ -20,7 +21,8 @@ import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 DEFAULT_PATH = os.path.join(HERE, "tuning.json")
-CANDIDATES = (4, 6, 8, 12, 16, 24, 32, 48, 64)
+CANDIDATES = tuple(("rows", r) for r in (4, 6, 8, 12, 16, 24, 32)) + \
+    tuple(("waves", w) for w in (1, 2, 3, 4)) + (("auto", 0),)
 SIDES = (128, 256, 512, 1024, 2048)
 ENERGIES = ("arap_warp", "poisson", "flow")
 
@@ -44,10 +46,15 @@ def _problem(energy, side, precision):
     return prob, x0
 
 
-def time_candidate(prob, x0, strip_rows, pcg_iters=50, repeats=3):
-    """Microseconds per PCG iteration (median of repeats) with this strip height."""
+def _fields(cand):
+    kind, v = cand
+    return {"strip_rows": v if kind == "rows" else 0, "waves_per_simd": v if kind == "waves" else 0}
+
+
+def time_candidate(prob, x0, cand, pcg_iters=50, repeats=3):
+    """Microseconds per PCG iteration (median of repeats) with this launch shape."""
     import paper_1604_06525_amd as pkg
-    prob.set_tuning(strip_rows)
+    prob.set_tuning(**_fields(cand))
     sp = pkg.default_params(method="gn", outer_iters=1, pcg_iters=pcg_iters)
     x = x0.clone()
     prob.solve(x, params=sp, report=False)  # warm-up
@@ -72,15 +79,15 @@ def autotune(energies=ENERGIES, precisions=("mixed", "fp64"), sides=SIDES, candi
                 prob, x0 = _problem(energy, side, precision)
                 res = {}
                 for c in candidates:
-                    if c > side:
+                    if c[0] == "rows" and c[1] > side:
                         continue
                     res[c] = time_candidate(prob, x0, c)
                 best = min(res, key=res.get)
                 n = side * side
                 entries.append(dict(energy=energy, precision=precision, min_sites=n // 2, max_sites=2 * n,
-                                    side=side, strip_rows=best, iter_us=res[best],
-                                    candidates={str(k): v for k, v in res.items()}))
-                print(f"tune {energy} {precision} {side}^2: strip_rows {best} ({res[best]:.2f} us/iter)",
+                                    side=side, **_fields(best), iter_us=res[best],
+                                    candidates={f"{k[0]}={k[1]}": v for k, v in res.items()}))
+                print(f"tune {energy} {precision} {side}^2: {best[0]}={best[1]} ({res[best]:.2f} us/iter)",
                       file=log, flush=True)
     return entries
 
@@ -98,17 +105,18 @@ def load(path=DEFAULT_PATH):
 
 
 def best(entries, energy, precision, n_sites):
-    """strip_rows of the last matching entry, or 0 (automatic)."""
-    hit = 0
+    """Tuning fields of the last matching entry, or the automatic choice."""
+    hit = {"strip_rows": 0, "waves_per_simd": 0}
     for e in entries:
         if e["energy"] == energy and e["precision"] == precision and e["min_sites"] <= n_sites <= e["max_sites"]:
-            hit = e["strip_rows"]
+            hit = {"strip_rows": e.get("strip_rows", 0), "waves_per_simd": e.get("waves_per_simd", 0)}
     return hit
 
 
 def apply(server, entries):
     for e in entries:
-        server.add_tuning(e["energy"], e["precision"], e["min_sites"], e["max_sites"], e["strip_rows"])
+        server.add_tuning(e["energy"], e["precision"], e["min_sites"], e["max_sites"],
+                          e.get("strip_rows", 0), e.get("waves_per_simd", 0))
 
 
 def main():

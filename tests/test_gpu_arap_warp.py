@@ -210,3 +210,24 @@ def test_zero_iterations_and_tiny_grid():
     rep = prob.solve(xt, method="gn", outer_iters=2, pcg_iters=3)
     xo, costs = o.gauss_newton(o.make_energy(d), d["x0"], 2, 3)
     assert np.allclose(rep["cost_trace"], costs, rtol=1e-12, atol=1e-300)
+
+
+@pytest.mark.parametrize("tuning", [dict(strip_rows=4), dict(strip_rows=7), dict(strip_rows=200),
+                                    dict(waves_per_simd=1), dict(waves_per_simd=3)])
+def test_launch_shapes_agree(tuning):
+    """Every strip partition of the fused kernel gives the oracle's PCG iterates
+    (strips walk in alternating directions and end in ragged partial strips)."""
+    d, x = _case(130, 97, "random")
+    e = o.make_energy(d)
+    lin = o.Linearization(e, x)
+    ref, _ = o.pcg(lin.apply, lin.jtf(), lin.minv(True), 20)
+    prob = make_problem(d, "fp64")
+    prob.set_tuning(**tuning)
+    t = prob.get_tuning()
+    assert t["strip_rows"] >= 1 and t["waves_per_simd"] >= 1
+    if tuning.get("strip_rows"):
+        assert t["strip_rows"] == min(tuning["strip_rows"], 97)
+    xt = to_dev(prob, x)
+    prob.linearize(xt)
+    got = to_np(prob.pcg(20, variant="fused"))
+    assert relmax(got, ref) < 1e-9
