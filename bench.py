@@ -58,7 +58,7 @@ def parse():
 TRAFFIC_RECORD = os.path.join(ROOT, "profiles", "fused_arap_warp_1024_mixed_counters.md")
 
 
-def measured_traffic(strip_rows):
+def measured_traffic(tuning):
     """HBM bytes per fused launch from the committed counter summary (FETCH_SIZE
     and WRITE_SIZE, each scaled by a plain copy's reading), or None when the
     kernel sources or the launch shape differ from those the counters were
@@ -70,7 +70,7 @@ def measured_traffic(strip_rows):
     for line in open(TRAFFIC_RECORD):
         if line.strip().startswith("traffic-record:"):
             rec = json.loads(line.split("traffic-record:", 1)[1])
-    if rec is None or rec.get("strip_rows") != strip_rows:
+    if rec is None or rec.get("tuning") != tuning:
         return None
     h = hashlib.sha256()
     for f in rec["sources"]:
@@ -346,11 +346,12 @@ def main():
         "dtype": "f32",
         "data": "synthetic",
         "config": {"workload": "arap_warp_1024x1024_gn10x50_mixed", "grid": [WARP["W"], WARP["H"]],
+                   "launch": prob.get_tuning(),
                    "unknowns": 3 * n, "outer_iters": WARP["outer"], "pcg_iters": WARP["pcg"],
                    "precision": "mixed: FP32 bulk, FP64 dot products and costs", "seed": WARP["seed"]},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS,
-                     "traffic": measured_traffic(prob.get_tuning()["strip_rows"]),
+                     "traffic": measured_traffic(prob.get_tuning()),
                      "unit_of_work": "one PCG iteration = one k_fused launch",
                      "bytes_per_iter": bpi, "iter_us": iter_us, "launch_avg_us": launch_avg_us},
         "pcg_phase_iters_per_s": pcg_iters / (pcg_ms / 1e3),

@@ -171,7 +171,7 @@ class Problem:
     """
 
     def __init__(self, energy, arrays, params=(), precision="mixed", width=0, height=0,
-                 n_vertices=0, edges=None, stream=None, workspace=None):
+                 n_vertices=0, edges=None, stream=None, workspace=None, tuning="auto"):
         self.energy = energy
         self.precision = precision
         self.dtype = torch.float64 if precision == "fp64" else torch.float32
@@ -195,6 +195,13 @@ class Problem:
                                        ctypes.c_void_p(self.stream.cuda_stream), ctypes.byref(h)),
                "opt_problem_create")
         self.handle = h
+        if tuning == "auto" and not n_vertices:
+            from . import tune
+            t = tune.best(tune.load(), energy, precision, self.n_sites)
+            if t["strip_rows"] or t["waves_per_simd"]:
+                self.set_tuning(**t)
+        elif isinstance(tuning, dict):
+            self.set_tuning(**tuning)
 
     def __del__(self):
         h = getattr(self, "handle", None)
@@ -304,7 +311,7 @@ class Server:
     handed to the library: it is the memory budget of the requests held at once.
     """
 
-    def __init__(self, arena_bytes, max_slots=64, device="cuda", stream=None):
+    def __init__(self, arena_bytes, max_slots=64, device="cuda", stream=None, tuning="auto"):
         self.stream = stream if stream is not None else torch.cuda.current_stream(device)
         self.arena = torch.empty(int(arena_bytes), dtype=torch.uint8, device=device)
         h = ctypes.c_void_p(0)
@@ -313,6 +320,9 @@ class Server:
                "opt_server_create")
         self.handle = h
         self._held = {}  # ticket -> (desc, tensors, outer_iters), kept alive until collected
+        if tuning == "auto":
+            from . import tune
+            tune.apply(self, tune.load())
 
     @staticmethod
     def reserved_bytes(max_slots):

@@ -114,6 +114,11 @@ struct SlotRef {
 
 enum class Stage { LIN, INIT, PCG, MODEL, TRIAL_COST, STEP, COST };
 
+// Strip partition of a grid for the fused kernel (opt_capi.hip: strip_geom).
+struct StripGeom {
+  int n_sx, n_sy, sw, rq, rr, grid;
+};
+
 // Launch sequence for one energy and bulk type.
 class Impl {
  public:
@@ -131,6 +136,8 @@ class Impl {
   virtual int model(const void* x) = 0;
   // Copy an internal vector (interleaved) out to channel planes.
   virtual int to_planes(const void* src, void* dst) = 0;
+  // Fused-kernel strip partition in force (grid energies).
+  virtual StripGeom strip_geometry(bool damped) const = 0;
   // Record one batched launch of `stage` over n problems of this energy and
   // type (the PCG stage records all of its launches); `fused` picks the form.
   virtual int batch(Stage stage, const SlotRef* slots, int n, bool fused, Batcher& B) = 0;

@@ -382,13 +382,14 @@ __device__ __forceinline__ auto with_views(const StreamRow<E, DAMP>& U, const St
   return body(Pv, Sv, Fv);
 }
 
-// The unit of work of a block, XCD-aware: blocks go to the 8 XCDs round-robin,
-// and each XCD takes one contiguous run of units so neighbouring strips share its
-// L2.  (In a batch the hardware placement differs; only speed depends on it.)
+// The unit of work of a block, XCD-aware: blocks go to the 8 XCDs round-robin
+// (block b to XCD b % 8), and each XCD takes one contiguous run of units, so
+// neighbouring strips share its L2.  XCD x holds q + (x < r) of the nb blocks
+// (q = nb / 8, r = nb % 8); the map is a bijection of [0, nb).  (In a batch the
+// hardware placement differs; only speed depends on it.)
 __device__ __forceinline__ int unit_of_block(VG g) {
-  if (g.nb % 8 != 0) return g.bid;
-  const int per = g.nb / 8;
-  return (g.bid % 8) * per + g.bid / 8;
+  const int q = g.nb >> 3, r = g.nb & 7, x = g.bid & 7;
+  return x * q + min(x, r) + (g.bid >> 3);
 }
 
 template <typename T>

@@ -144,22 +144,19 @@ int check_desc(const opt_problem_desc* d, Shape* sh) {
 
 namespace {
 
-struct StripGeom {
-  int n_sx, n_sy, sw, rq, rr, grid;
-};
-
 // Partition of a W x H grid into strips for the fused kernel: n_sx strips
 // across of sw produced columns each (sw <= 60, as even as possible), n_sy
 // strips down of rq or rq + 1 rows.
 //   t.strip_rows > 0: strips of that many rows;
 //   otherwise about w strips per SIMD with the rows split evenly, w =
-//   t.waves_per_simd or, by default, kAutoWavesPerSimd; never under 4 rows.
+//   t.waves_per_simd or, by default, min(kAutoWavesPerSimd, the kernel's
+//   occupancy in waves per SIMD); never under 4 rows.
 // Balance matters: a launch is set by its slowest SIMD, so every SIMD should
-// get the same number of equal strips (measured best: two, which also lets each
-// SIMD overlap one strip's memory waits with the other's arithmetic).
+// get the same number of equal strips (measured best: two where two fit, which
+// lets each SIMD overlap one strip's memory waits with the other's arithmetic).
 constexpr int kAutoWavesPerSimd = 2;
 
-StripGeom strip_geom(int W, int H, const opt_tuning& t, int n_simd) {
+StripGeom strip_geom(int W, int H, const opt_tuning& t, int n_simd, int occupancy) {
   StripGeom g;
   g.n_sx = (W + kStripCols - 1) / kStripCols;
   g.sw = (W + g.n_sx - 1) / g.n_sx;
@@ -168,7 +165,8 @@ StripGeom strip_geom(int W, int H, const opt_tuning& t, int n_simd) {
   if (t.strip_rows > 0) {
     n_sy = (H + t.strip_rows - 1) / t.strip_rows;
   } else {
-    const int w = t.waves_per_simd > 0 ? t.waves_per_simd : kAutoWavesPerSimd;
+    const int w = t.waves_per_simd > 0 ? t.waves_per_simd
+                                       : std::max(1, std::min(kAutoWavesPerSimd, occupancy));
     n_sy = std::min(max_sy, std::max(1, w * n_simd / g.n_sx));
   }
   n_sy = std::max(1, std::min(n_sy, kWaves * kMaxBlocks / g.n_sx));
@@ -253,9 +251,34 @@ class ImplT final : public Impl {
     a.L = L;
     return a;
   }
+  // Waves per SIMD the fused kernel can hold (blocks per CU of four waves).
+  template <bool DAMP>
+  static int fused_occupancy() {
+    static const int occ = [] {
+      int blocks = 0;
+      if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, k_solo<FusedArgs<E, DAMP>>, kBlock, 0) !=
+          hipSuccess)
+        return 1;
+      return std::max(1, blocks * kWaves / 4);
+    }();
+    return occ;
+  }
+  StripGeom geom(bool damped) const {
+    if constexpr (E::kGraph) {
+      (void)damped;
+      return StripGeom{};
+    } else if constexpr (E::kRadius != 1) {
+      (void)damped;
+      return strip_geom(e_.W, e_.H, p_->tune, p_->n_simd, 1);
+    } else {
+      return strip_geom(e_.W, e_.H, p_->tune, p_->n_simd,
+                        damped ? fused_occupancy<true>() : fused_occupancy<false>());
+    }
+  }
+
   template <bool DAMP>
   FusedArgs<E, DAMP> fused_args(int L, PrecondArgs pa, int lm, int* grid) const {
-    const StripGeom g = strip_geom(e_.W, e_.H, p_->tune, p_->n_simd);
+    const StripGeom g = geom(DAMP);
     FusedArgs<E, DAMP> a;
     a.e = e_;
     a.b.u[0] = rbuf(0);
@@ -330,6 +353,7 @@ class ImplT final : public Impl {
     return go(cost_args(x, delta, lm), nblk(), 0, "cost");
   }
   int model(const void* x) override { return go(model_args(x), nblk(), 0, "model"); }
+  StripGeom strip_geometry(bool damped) const override { return geom(damped); }
   int to_planes(const void* src, void* dst) override {
     return go(PlanesArgs<T, E::C>{(const T*)src, (T*)dst, e_.n}, nblk(), 0, "to_planes");
   }
@@ -776,7 +800,7 @@ int opt_problem_get_tuning(opt_problem* p, opt_tuning* t) {
   if (!p || !t) return fail(OPT_EINVAL, "problem or tuning is NULL");
   *t = p->tune;
   if (!p->sh.graph) {
-    const StripGeom g = strip_geom(p->desc.width, p->desc.height, p->tune, p->n_simd);
+    const StripGeom g = p->impl->strip_geometry(false);
     t->strip_rows = g.rq + (g.rr > 0 ? 1 : 0);
     t->waves_per_simd = (g.n_sx * g.n_sy + p->n_simd - 1) / p->n_simd;
   }
