@@ -267,26 +267,37 @@ int opt_energy_channels(int32_t energy);
  *   request may be submitted again after a step has retired others.  A graph's
  *   edges are read at submission (this synchronises the stream).  *ticket names
  *   the request.
- * opt_server_step: one quantum: requests admitted since the last step start;
- *   every running request does one outer iteration (linearise, PCG init, its
- *   pcg_iters PCG iterations, LM decision, update); requests that reach their
- *   outer_iters (or whose LM radius fell below the minimum) get their final cost
- *   and leave.  Synchronises the stream once.  A request's unknowns are written
- *   in place.
+ * opt_server_step: enqueue one quantum: admitted requests start, in admission
+ *   order, while the running set's estimated GPU fill (the share of the device's
+ *   wavefront slots its launches occupy, each at most 1) stays within the fill
+ *   budget (default 1.0; at least one request always runs); every running
+ *   request does one outer iteration (linearise, PCG init, its pcg_iters PCG
+ *   iterations, LM decision, update); requests that reach their outer_iters (or
+ *   whose LM radius is known to have fallen below the minimum) get their final
+ *   cost and leave.  Steps are pipelined: the call returns once the work is
+ *   enqueued, with up to 3 steps in flight (it waits for the oldest when 3 are);
+ *   completed steps are processed whenever the server is called.  With nothing
+ *   to enqueue it waits for the oldest step in flight.  A request's unknowns are
+ *   written in place; they are final once poll reports it done.
+ * opt_server_wait: wait until every enqueued step has completed.
+ * opt_server_set_fill_budget: the fill budget (>= 0; 0 runs one request at a
+ *   time, a large value runs every admitted request at once).
  * opt_server_poll: *done = 1 once the request has left; then the report (as
  *   opt_solve's; cost_trace, if not NULL, must hold outer_iters + 1 entries) is
  *   filled and the ticket is forgotten.  Returns OPT_ENUMERIC (report filled) if
  *   a cost was NaN or infinite.  *done = 0 while it runs.  OPT_EINVAL for a
  *   ticket that is unknown or already collected.
- * opt_server_cancel: drop a running request (its unknowns are left part-way) or
- *   an uncollected result.
+ * opt_server_cancel: drop a running request (its unknowns are left part-way;
+ *   its arena range is reused once its enqueued work has completed) or an
+ *   uncollected result.
  * opt_server_info: requests held (running or admitted) and free arena bytes.
  * opt_server_add_tuning: launch tuning (opt_tuning) applied at admission to
  *   requests of that energy and precision whose site count lies in
  *   [min_sites, max_sites]; a later entry overrides an earlier one.
  *
- * A server is not thread-safe: calls on one server must not overlap.  The
- * server's stream must not be used for other work while a step runs.
+ * A server is not thread-safe: calls on one server must not overlap.  Work the
+ * caller puts on the server's stream is ordered with the steps (for example a
+ * copy of initial unknowns before their submission).
  */
 typedef struct opt_server opt_server;
 
@@ -297,6 +308,8 @@ int opt_server_destroy(opt_server* server);
 int opt_server_submit(opt_server* server, const opt_problem_desc* desc, void* unknowns,
                       const opt_solve_params* params, int64_t* ticket);
 int opt_server_step(opt_server* server);
+int opt_server_wait(opt_server* server);
+int opt_server_set_fill_budget(opt_server* server, double budget);
 int opt_server_poll(opt_server* server, int64_t ticket, int32_t* done, opt_solve_report* report);
 int opt_server_cancel(opt_server* server, int64_t ticket);
 int opt_server_info(opt_server* server, int32_t* active, size_t* arena_free);

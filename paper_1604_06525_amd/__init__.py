@@ -74,6 +74,8 @@ _proto = {
     "opt_server_submit": (ctypes.c_int, [_P, ctypes.POINTER(opt_problem_desc), _P,
                                          ctypes.POINTER(opt_solve_params), ctypes.POINTER(ctypes.c_int64)]),
     "opt_server_step": (ctypes.c_int, [_P]),
+    "opt_server_wait": (ctypes.c_int, [_P]),
+    "opt_server_set_fill_budget": (ctypes.c_int, [_P, ctypes.c_double]),
     "opt_server_poll": (ctypes.c_int, [_P, ctypes.c_int64, ctypes.POINTER(ctypes.c_int32),
                                        ctypes.POINTER(opt_solve_report)]),
     "opt_server_cancel": (ctypes.c_int, [_P, ctypes.c_int64]),
@@ -195,6 +197,7 @@ class Problem:
                                        ctypes.c_void_p(self.stream.cuda_stream), ctypes.byref(h)),
                "opt_problem_create")
         self.handle = h
+        self._lib = lib()
         if tuning == "auto" and not n_vertices:
             from . import tune
             t = tune.best(tune.load(), energy, precision, self.n_sites)
@@ -204,9 +207,12 @@ class Problem:
             self.set_tuning(**tuning)
 
     def __del__(self):
+        # at interpreter exit the module globals may already be gone; the
+        # library handle kept on the instance still works
         h = getattr(self, "handle", None)
-        if h is not None and h.value:
-            lib().opt_problem_destroy(h)
+        L = getattr(self, "_lib", None)
+        if h is not None and h.value and L is not None:
+            L.opt_problem_destroy(h)
             self.handle = None
 
     def _vec(self, t, name):
@@ -319,6 +325,7 @@ class Server:
                                       ctypes.c_void_p(self.stream.cuda_stream), ctypes.byref(h)),
                "opt_server_create")
         self.handle = h
+        self._lib = lib()
         self._held = {}  # ticket -> (desc, tensors, outer_iters), kept alive until collected
         if tuning == "auto":
             from . import tune
@@ -331,9 +338,12 @@ class Server:
         return b.value
 
     def __del__(self):
+        # at interpreter exit the module globals may already be gone; the
+        # library handle kept on the instance still works
         h = getattr(self, "handle", None)
-        if h is not None and h.value:
-            lib().opt_server_destroy(h)
+        L = getattr(self, "_lib", None)
+        if h is not None and h.value and L is not None:
+            L.opt_server_destroy(h)
             self.handle = None
 
     def submit(self, energy, arrays, x, params=(), precision="mixed", width=0, height=0,
@@ -353,6 +363,12 @@ class Server:
 
     def step(self):
         _check(lib().opt_server_step(self.handle), "opt_server_step")
+
+    def wait(self):
+        _check(lib().opt_server_wait(self.handle), "opt_server_wait")
+
+    def set_fill_budget(self, budget):
+        _check(lib().opt_server_set_fill_budget(self.handle, float(budget)), "opt_server_set_fill_budget")
 
     def poll(self, ticket):
         """None while the request runs; its report (a dict) once it has left."""

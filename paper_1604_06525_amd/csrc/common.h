@@ -31,7 +31,7 @@ struct DevScalars {
   int32_t n_accepted;
   int32_t outer_done;
   int32_t nonfinite; // a cost was NaN or infinite
-  int32_t pad;
+  int32_t trace_k;   // next cost-trace entry (one per outer iteration that linearises)
 };
 
 // Sum of v over the block in a fixed order: a shuffle tree inside each wave,

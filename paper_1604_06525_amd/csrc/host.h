@@ -5,6 +5,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cstddef>
+#include <cstring>
 #include <functional>
 #include <memory>
 #include <vector>
@@ -60,7 +61,14 @@ struct Shape {
 
 // Byte offsets of every region of a problem's workspace.
 struct Layout {
-  size_t r0, r1, p0, p1, q, diag, minv, damp, delta, state, flags, csr, parts, scal, trace, total;
+  size_t r0, r1, p0, p1, q, diag, minv, damp, delta, state, flags, csr, parts, scal, trace, rows, total;
+};
+
+// Argument rows a single problem launches with, one device slot of kMaxArgBytes
+// each in its workspace (the batching server keeps its own tables).
+enum RowKind {
+  ROW_SETUP, ROW_LIN, ROW_INIT, ROW_PCGA, ROW_APPLY, ROW_PCGB, ROW_FUSED, ROW_STEP, ROW_COST,
+  ROW_TRIAL, ROW_MODEL, ROW_DECIDE, ROW_FINISH, ROW_PLANES, kNumRows
 };
 
 // Partial-sum buffers of kMaxBlocks doubles each; the fused form uses two pairs.
@@ -109,7 +117,6 @@ struct SlotRef {
   PrecondArgs pa;
   int lm;
   int L;          // PCG iterations
-  int trace_idx;  // outer iteration
 };
 
 enum class Stage { LIN, INIT, PCG, MODEL, TRIAL_COST, STEP, COST };
@@ -125,7 +132,7 @@ class Impl {
   virtual ~Impl() = default;
   virtual int linearize(const void* x, int lm_gate) = 0;
   // u_form: the fused form follows (write u_0 = M^-1 b where b would go)
-  virtual int init(const void* x, double* trace, int idx, PrecondArgs pa, int lm_gate, int u_form) = 0;
+  virtual int init(const void* x, double* trace, PrecondArgs pa, int lm_gate, int u_form) = 0;
   virtual int pcg_a(int k, int L, PrecondArgs pa, int lm_gate) = 0;
   virtual int pcg_b(int k, int L, PrecondArgs pa, int lm_gate) = 0;
   virtual int fused(int iter, int L, PrecondArgs pa, int lm_gate) = 0;
@@ -138,6 +145,9 @@ class Impl {
   virtual int to_planes(const void* src, void* dst) = 0;
   // Fused-kernel strip partition in force (grid energies).
   virtual StripGeom strip_geometry(bool damped) const = 0;
+  // Estimated share of the GPU one PCG launch of this problem occupies (its
+  // wavefronts over those the device holds at the kernel's occupancy), <= 1.
+  virtual double gpu_fill(bool fused, bool damped) const = 0;
   // Record one batched launch of `stage` over n problems of this energy and
   // type (the PCG stage records all of its launches); `fused` picks the form.
   virtual int batch(Stage stage, const SlotRef* slots, int n, bool fused, Batcher& B) = 0;
@@ -155,6 +165,10 @@ struct opt_problem {
   int nblk = 1;
   int n_simd = 1024;  // SIMDs of the device (fused kernel launch shape)
   const void* last_x = nullptr;
+  // last bytes stored in each device argument row (a row is stored again only
+  // when it changes)
+  std::vector<std::vector<unsigned char>> row_cache =
+      std::vector<std::vector<unsigned char>>(optmi::host::kNumRows);
   opt_tuning tune{};
   std::unique_ptr<optmi::host::Impl> impl;
   // PCG-phase timing (opt_profile_enable)
@@ -181,21 +195,74 @@ namespace host {
 int problem_init(opt_problem* p, const opt_problem_desc* desc, const Shape& sh, void* workspace,
                  hipStream_t stream);
 
-// A one-block scalar kernel on the problem's stream.
+// An argument struct with every byte zero (padding included) before its fields
+// are set, so equal arguments compare equal byte for byte.
 template <class A>
-int scalar_kernel(hipStream_t st, const A& a, const char* name) {
-  k_solo<A><<<1, kBlock, 0, st>>>(a, 0);
+A blank() {
+  A a;
+  std::memset(static_cast<void*>(&a), 0, sizeof(A));
+  return a;
+}
+
+// Argument rows of the one-block scalar stages.
+inline SetupArgs setup_args(DevScalars* S, double lambda, double radius0, int lm, double radius_min) {
+  SetupArgs a = blank<SetupArgs>();
+  a.S = S;
+  a.lambda = lambda;
+  a.radius0 = radius0;
+  a.lm = lm;
+  a.radius_min = radius_min;
+  return a;
+}
+inline FinishArgs finish_args(DevScalars* S, const double* part, int nb) {
+  FinishArgs a = blank<FinishArgs>();
+  a.S = S;
+  a.part = part;
+  a.nb = nb;
+  return a;
+}
+inline DecideArgs decide_args(DevScalars* S, const double* m_part, const double* c_part, int nb,
+                              const opt_solve_params& sp) {
+  DecideArgs a = blank<DecideArgs>();
+  a.S = S;
+  a.m_part = m_part;
+  a.c_part = c_part;
+  a.nb = nb;
+  a.lc.radius_min = sp.lm_radius_min;
+  a.lc.radius_max = sp.lm_radius_max;
+  a.lc.min_rel_decrease = sp.lm_min_rel_decrease;
+  return a;
+}
+
+// Launch one stage of a single problem: store its argument row in the problem's
+// workspace (only if it changed since the last store) and run the stage kernel
+// over `grid` blocks, in the problem's stream.
+template <class A>
+int launch_row(opt_problem* p, int kind, const A& a, int grid, int iter, const char* name) {
+  static_assert(sizeof(A) <= kMaxArgBytes, "argument row larger than its slot");
+  A* dev = (A*)(p->ws + p->L.rows + (size_t)kind * kMaxArgBytes);
+  std::vector<unsigned char>& c = p->row_cache[(size_t)kind];
+  if (c.size() != sizeof(A) || std::memcmp(c.data(), &a, sizeof(A)) != 0) {
+    k_put<A><<<1, 64, 0, p->stream>>>(dev, a);
+    HIP_LAUNCHED(name);
+    c.assign((const unsigned char*)&a, (const unsigned char*)&a + sizeof(A));
+  }
+  k_batch<A><<<grid, kBlock, 0, p->stream>>>(dev, nullptr, nullptr, 1, iter);
   HIP_LAUNCHED(name);
   return OPT_OK;
 }
 
 // A batched argument table in the staging area: one row per problem and the
 // first block of each problem's range.
+// Each problem's blocks start at a multiple of kXcdCount (the hardware deals
+// blocks to the XCDs round-robin), so they fall on the XCDs as when alone.
+constexpr int kXcdCount = 8;
+
 template <class A>
 struct BatchTable {
   const A* rows = nullptr;      // device, one per problem
-  const int* start = nullptr;   // device, n + 1 entries: first block of each problem
-  const int* slot_of = nullptr; // device, problem of each block
+  const int* start = nullptr;   // device, 2n entries: first block and grid of each problem
+  const int* slot_of = nullptr; // device, problem of each block (-1: idle)
   int n = 0, total = 0;         // problems, blocks
 };
 
@@ -203,9 +270,11 @@ template <class A>
 int batch_table(Batcher& B, const A* rows, const int* grids, int n, BatchTable<A>* t) {
   static_assert(sizeof(A) <= kMaxArgBytes, "argument row larger than the table area allows");
   long long total = 0;
-  for (int k = 0; k < n; ++k) total += grids[k];
-  if (total > (long long)n * kMaxBlocks) return fail(OPT_EINVAL, "batched grid of %lld blocks", total);
-  const size_t tbytes = sizeof(A) * (size_t)n, sbytes = sizeof(int) * ((size_t)n + 1);
+  for (int k = 0; k < n; ++k) {
+    if (grids[k] < 1 || grids[k] > kMaxBlocks) return fail(OPT_EINVAL, "grid of %d blocks", grids[k]);
+    total = (total + kXcdCount - 1) / kXcdCount * kXcdCount + grids[k];
+  }
+  const size_t tbytes = sizeof(A) * (size_t)n, sbytes = sizeof(int) * 2 * (size_t)n;
   const long long ot = B.reserve(tbytes), os = B.reserve(sbytes), om = B.reserve(sizeof(int) * total);
   if (ot < 0 || os < 0 || om < 0) return fail(OPT_ENOMEM, "server table area is full");
   A* ht = (A*)(B.host + ot);
@@ -213,12 +282,14 @@ int batch_table(Batcher& B, const A* rows, const int* grids, int n, BatchTable<A
   int* hm = (int*)(B.host + om);
   int b = 0;
   for (int k = 0; k < n; ++k) {
+    const int b0 = (b + kXcdCount - 1) / kXcdCount * kXcdCount;
+    for (; b < b0; ++b) hm[b] = -1;
     ht[k] = rows[k];
-    hs[k] = b;
-    for (int q = 0; q < grids[k]; ++q) hm[b + q] = k;
-    b += grids[k];
+    hs[2 * k] = b0;
+    hs[2 * k + 1] = grids[k];
+    for (int q = 0; q < grids[k]; ++q) hm[b0 + q] = k;
+    b = b0 + grids[k];
   }
-  hs[n] = b;
   t->rows = (const A*)(B.dev + ot);
   t->start = (const int*)(B.dev + os);
   t->slot_of = (const int*)(B.dev + om);
@@ -229,7 +300,7 @@ int batch_table(Batcher& B, const A* rows, const int* grids, int n, BatchTable<A
 
 template <class A>
 int batch_launch(const BatchTable<A>& t, int iter, hipStream_t st, const char* name) {
-  k_batch<A><<<t.total, kBlock, 0, st>>>(t.rows, t.start, t.slot_of, iter);
+  k_batch<A><<<t.total, kBlock, 0, st>>>(t.rows, t.start, t.slot_of, t.n, iter);
   HIP_LAUNCHED(name);
   return OPT_OK;
 }

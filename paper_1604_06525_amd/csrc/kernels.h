@@ -1,9 +1,9 @@
 // Kernels of one solve, generic over the energy.
 //
 // Each stage is an argument struct plus a device function run(args, grid, iter).
-// k_solo launches one problem; k_batch launches many problems of one kind at
-// once, each over its own contiguous range of blocks, and gives every block the
-// grid it would have had alone, so results do not depend on the batch.
+// k_batch launches one problem, or many problems of one kind at once, each over
+// its own contiguous range of blocks, and gives every block the grid it would
+// have had alone, so results do not depend on the batch.
 //
 // Kernel boundaries are the only grid-wide synchronisation.  A scalar that
 // needs a sum over the whole problem is produced as per-block FP64 partials by
@@ -41,6 +41,14 @@
 #include "common.h"
 
 namespace optmi {
+
+// Element i (0 or 1) of a pair held in kernel arguments.  A select rather than
+// an index: a runtime index into an argument struct copied to a local would put
+// the whole struct in scratch memory.
+template <typename P>
+__device__ __forceinline__ P pick(P const (&pair)[2], int i) {
+  return i ? pair[1] : pair[0];
+}
 
 // Grid-stride loop over sites with a fixed per-thread order (the grid size
 // depends only on n), so the partial sums are reproducible.
@@ -140,8 +148,7 @@ struct InitArgs {
   int n_lin;
   double* rz_part;
   DevScalars* S;
-  double* trace;
-  int trace_idx;
+  double* trace;  // cost trace (entry S->trace_k), or nullptr
   Precond<typename E::Real> pc;
   int lm_gate;
   int u_form;  // fused form: write u_0 = M^-1 b (not b) to o.r
@@ -164,7 +171,10 @@ __device__ __forceinline__ void run(const InitArgs<E>& a, VG g, int) {
     } else {
       E0 = S->E0;
     }
-    if (a.trace) a.trace[a.trace_idx] = E0;
+    if (a.trace) {
+      a.trace[S->trace_k] = E0;
+      S->trace_k += 1;
+    }
     S->stopped = 0;
   }
   Precond<T> pc = a.pc;
@@ -229,12 +239,12 @@ __device__ __forceinline__ void run(const SplitAArgs<E, MODE>& a, VG g, int k) {
   T beta = T(0);
   if (MODE == 0) {
     if (k >= a.L || S->stopped || (a.lm_gate && S->done)) return;
-    const double rz = reduce_partials(b.rz_part[k & 1], a.n_part);
+    const double rz = reduce_partials(pick(b.rz_part, k & 1), a.n_part);
     if (k > 0) beta = (T)(rz / S->rz[(k - 1) & 1]);
     if (is_block_leader(g)) S->rz[k & 1] = rz;
   }
-  const T* pold = MODE == 1 ? b.p[0] : b.p[(k + 1) & 1];
-  T* pnew = b.p[k & 1];
+  const T* pold = MODE == 1 ? b.p[0] : pick(b.p, (k + 1) & 1);
+  T* pnew = pick(b.p, k & 1);
   auto Pg = [&](int c, int site) -> T {
     if (MODE == 1) return pold[(size_t)c * n + site];
     const size_t o = vix<C>(c, site);
@@ -290,7 +300,7 @@ __device__ __forceinline__ void run(const SplitBArgs<T, C>& a, VG g, int k) {
     return;
   }
   const T alpha = (T)(S->rz[k & 1] / pq);
-  const T* p = a.p[k & 1];
+  const T* p = pick(a.p, k & 1);
   double rz = 0.0;
   OPT_SITE_LOOP(s, a.n, g) {
 #pragma unroll
@@ -302,7 +312,7 @@ __device__ __forceinline__ void run(const SplitBArgs<T, C>& a, VG g, int k) {
       rz += (double)rv * (double)(a.minv[o] * rv);
     }
   }
-  block_store(rz, a.rz_part[(k + 1) & 1], g);
+  block_store(rz, pick(a.rz_part, (k + 1) & 1), g);
 }
 
 // ---------------------------------------------------------------- fused iteration
@@ -459,11 +469,11 @@ __device__ __forceinline__ void run(const FusedArgs<E, DAMP>& a, VG g, int iter)
   // 0, its stores are dropped.
   constexpr unsigned VB = C * sizeof(T), SB = (NS > 0 ? NS : 1) * sizeof(T);
   const size_t vbytes = (size_t)n * VB;
-  const Buf<T> Buin = Buf<T>::make(a.b.u[iter < 0 ? 0 : (iter & 1)], vbytes);
-  const Buf<T> Bpin = Buf<T>::make(a.b.p[(iter + 1) & 1], read_pold ? vbytes : 0);
+  const Buf<T> Buin = Buf<T>::make(pick(a.b.u, iter < 0 ? 0 : (iter & 1)), vbytes);
+  const Buf<T> Bpin = Buf<T>::make(pick(a.b.p, (iter + 1) & 1), read_pold ? vbytes : 0);
   const Buf<T> Bx = Buf<T>::make(a.b.x, write_out ? vbytes : 0);
-  const Buf<T> Buout = Buf<T>::make(a.b.u[(iter + 1) & 1], write_out ? vbytes : 0);
-  const Buf<T> Bpout = Buf<T>::make(a.b.p[iter & 1], write_out ? vbytes : 0);
+  const Buf<T> Buout = Buf<T>::make(pick(a.b.u, (iter + 1) & 1), write_out ? vbytes : 0);
+  const Buf<T> Bpout = Buf<T>::make(pick(a.b.p, iter & 1), write_out ? vbytes : 0);
   const Buf<T> Bst = Buf<T>::make(e.state_base(), NS > 0 ? (size_t)n * SB : 0);
   const Buf<uint8_t> Bf = Buf<uint8_t>::make(e.flags, (size_t)n);
   // The row of step k lives in ring slot k % N; its loads are issued
@@ -488,8 +498,8 @@ __device__ __forceinline__ void run(const FusedArgs<E, DAMP>& a, VG g, int iter)
   for (int k = 0; k < kPrefetch; ++k) issue(ring[k], ybeg + dir * k);
 
   if (S->stopped || (a.lm_gate && S->done)) return;
-  const double* part_in = a.b.part[(iter + 1) & 1];
-  double* part_out = a.b.part[iter & 1];
+  const double* part_in = pick(a.b.part, (iter + 1) & 1);
+  double* part_out = pick(a.b.part, iter & 1);
   double alpha = 0.0, beta = 0.0;
   if (iter >= 0) {
     const double gam = reduce_partials(part_in, a.n_part);
@@ -705,6 +715,7 @@ __device__ __forceinline__ void run(const SetupArgs& a, VG, int) {
     S->n_accepted = 0;
     S->outer_done = 0;
     S->nonfinite = 0;
+    S->trace_k = 0;
   }
 }
 
@@ -754,13 +765,11 @@ __device__ __forceinline__ void run(const DecideArgs& a, VG, int) {
   }
 }
 
-// Finish a cost reduction into E_final (and optionally a trace slot).
+// Finish a cost reduction into E_final.
 struct FinishArgs {
   DevScalars* S;
   const double* part;
   int nb;
-  double* trace;
-  int trace_idx;
 };
 
 __device__ __forceinline__ void run(const FinishArgs& a, VG, int) {
@@ -768,7 +777,6 @@ __device__ __forceinline__ void run(const FinishArgs& a, VG, int) {
   if (threadIdx.x == 0) {
     a.S->E_final = E;
     if (!finite_d(E)) a.S->nonfinite = 1;
-    if (a.trace) a.trace[a.trace_idx] = E;
   }
 }
 
@@ -800,22 +808,35 @@ __device__ __forceinline__ void run(const GatherArgs& a, VG, int) {
 }
 
 // ---------------------------------------------------------------- launchers
-template <class A>
-__global__ void __launch_bounds__(kBlock) k_solo(A a, int iter) {
-  run(a, VG{(int)blockIdx.x, (int)gridDim.x}, iter);
-}
-
-// Many problems of one kind in one launch: problem j owns blocks
-// [start[j], start[j+1]), slot_of[b] names the problem of block b, and its
-// arguments are table[j].
+// Every stage runs through this one kernel per argument type, alone (n == 1:
+// the problem's own argument row, the hardware grid) or batched: problem j owns
+// blocks [start[2j], start[2j] + start[2j+1]), slot_of[b] names the problem of
+// block b (-1: an idle block), and its arguments are table[j].  Each batched
+// range starts at a multiple of 8, so a problem's block i runs on XCD i mod 8 as
+// it would alone.  One kernel binary for both means a problem computes the same
+// bits alone and in any batch.
 template <class A>
 __global__ void __launch_bounds__(kBlock) k_batch(const A* __restrict__ table,
                                                   const int* __restrict__ start,
-                                                  const int* __restrict__ slot_of, int iter) {
+                                                  const int* __restrict__ slot_of, int n, int iter) {
   const int b = blockIdx.x;
-  const int j = slot_of[b];
-  const A a = table[j];
-  run(a, VG{b - start[j], start[j + 1] - start[j]}, iter);
+  int j = 0;
+  VG g{b, (int)gridDim.x};
+  if (n != 1) {
+    j = slot_of[b];
+    if (j < 0) return;
+    g = VG{b - start[2 * j], start[2 * j + 1]};
+  }
+  // read in place: the row's fields are loaded where used (uniform addresses,
+  // scalar loads); a local copy of the whole row would be kept in scratch memory
+  const A& a = table[j];
+  run(a, g, iter);
+}
+
+// Store one argument row in device memory, in stream order.
+template <class A>
+__global__ void k_put(A* __restrict__ dst, A a) {
+  if (threadIdx.x == 0) *dst = a;
 }
 
 }  // namespace optmi

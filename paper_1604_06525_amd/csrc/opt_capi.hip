@@ -51,6 +51,7 @@ Layout make_layout(const Shape& sh) {
   L.parts = off; off += align_up(kNumPartBufs * (size_t)kMaxBlocks * sizeof(double));
   L.scal = off; off += align_up(sizeof(DevScalars));
   L.trace = off; off += align_up((size_t)kTraceCap * sizeof(double));
+  L.rows = off; off += align_up((size_t)kNumRows * kMaxArgBytes);
   L.total = off;
   return L;
 }
@@ -184,7 +185,7 @@ class ImplT final : public Impl {
   ImplT(opt_problem* p, const E& e) : p_(p), e_(e) {}
 
   Precond<T> pc(PrecondArgs a) const {
-    Precond<T> c;
+    Precond<T> c = blank<Precond<T>>();
     c.lam = (T)a.lam;
     c.dmin = (T)a.dmin;
     c.use = a.use;
@@ -199,10 +200,16 @@ class ImplT final : public Impl {
 
   // ------------------------------------------------ argument builders
   LinArgs<E> lin_args(const void* x, int lm) const {
-    return LinArgs<E>{e_, (const T*)x, p_->part(P_LIN), p_->S(), lm};
+    LinArgs<E> a = blank<LinArgs<E>>();
+    a.e = e_;
+    a.x = (const T*)x;
+    a.part = p_->part(P_LIN);
+    a.S = p_->S();
+    a.lm_gate = lm;
+    return a;
   }
-  InitArgs<E> init_args(const void* x, double* trace, int idx, PrecondArgs pa, int lm, int u_form) const {
-    InitArgs<E> a;
+  InitArgs<E> init_args(const void* x, double* trace, PrecondArgs pa, int lm, int u_form) const {
+    InitArgs<E> a = blank<InitArgs<E>>();
     a.e = e_;
     a.x = (const T*)x;
     a.o = InitOut<T>{rbuf(0), vec(p_->L.diag), vec(p_->L.minv), damp(pa), vec(p_->L.delta)};
@@ -211,14 +218,13 @@ class ImplT final : public Impl {
     a.rz_part = p_->part(P_RZ0);
     a.S = p_->S();
     a.trace = trace;
-    a.trace_idx = idx;
     a.pc = pc(pa);
     a.lm_gate = lm;
     a.u_form = u_form;
     return a;
   }
   SplitBufs<T> split_bufs(PrecondArgs pa) const {
-    SplitBufs<T> b;
+    SplitBufs<T> b = blank<SplitBufs<T>>();
     b.r = rbuf(0);
     b.minv = vec(p_->L.minv);
     b.damp = damp(pa);
@@ -230,11 +236,22 @@ class ImplT final : public Impl {
     b.pq_part = p_->part(P_PQ);
     return b;
   }
+  template <int MODE>
+  SplitAArgs<E, MODE> split_a_args(const SplitBufs<T>& b, int L, int lm) const {
+    SplitAArgs<E, MODE> a = blank<SplitAArgs<E, MODE>>();
+    a.e = e_;
+    a.b = b;
+    a.n_part = p_->nblk;
+    a.S = p_->S();
+    a.lm_gate = lm;
+    a.L = L;
+    return a;
+  }
   SplitAArgs<E, 0> pcga_args(int L, PrecondArgs pa, int lm) const {
-    return SplitAArgs<E, 0>{e_, split_bufs(pa), p_->nblk, p_->S(), lm, L};
+    return split_a_args<0>(split_bufs(pa), L, lm);
   }
   SplitBArgs<T, E::C> pcgb_args(int L, int lm) const {
-    SplitBArgs<T, E::C> a;
+    SplitBArgs<T, E::C> a = blank<SplitBArgs<T, E::C>>();
     a.n = e_.n;
     a.delta = vec(p_->L.delta);
     a.r = rbuf(0);
@@ -256,7 +273,7 @@ class ImplT final : public Impl {
   static int fused_occupancy() {
     static const int occ = [] {
       int blocks = 0;
-      if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, k_solo<FusedArgs<E, DAMP>>, kBlock, 0) !=
+      if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, k_batch<FusedArgs<E, DAMP>>, kBlock, 0) !=
           hipSuccess)
         return 1;
       return std::max(1, blocks * kWaves / 4);
@@ -279,7 +296,7 @@ class ImplT final : public Impl {
   template <bool DAMP>
   FusedArgs<E, DAMP> fused_args(int L, PrecondArgs pa, int lm, int* grid) const {
     const StripGeom g = geom(DAMP);
-    FusedArgs<E, DAMP> a;
+    FusedArgs<E, DAMP> a = blank<FusedArgs<E, DAMP>>();
     a.e = e_;
     a.b.u[0] = rbuf(0);
     a.b.u[1] = rbuf(1);
@@ -302,31 +319,52 @@ class ImplT final : public Impl {
     return a;
   }
   StepArgs<E> step_args(void* x, int lm) const {
-    return StepArgs<E>{e_, (T*)x, vec(p_->L.delta), p_->S(), lm};
+    StepArgs<E> a = blank<StepArgs<E>>();
+    a.e = e_;
+    a.x = (T*)x;
+    a.delta = vec(p_->L.delta);
+    a.S = p_->S();
+    a.lm_gate = lm;
+    return a;
   }
   CostArgs<E> cost_args(const void* x, const void* delta, int lm) const {
-    return CostArgs<E>{e_, (const T*)x, (const T*)delta, p_->part(P_COST), p_->S(), lm};
+    CostArgs<E> a = blank<CostArgs<E>>();
+    a.e = e_;
+    a.x = (const T*)x;
+    a.delta = (const T*)delta;
+    a.part = p_->part(P_COST);
+    a.S = p_->S();
+    a.lm_gate = lm;
+    return a;
   }
   ModelArgs<E> model_args(const void* x) const {
-    return ModelArgs<E>{e_, (const T*)x, vec(p_->L.delta), p_->part(P_M), p_->S()};
+    ModelArgs<E> a = blank<ModelArgs<E>>();
+    a.e = e_;
+    a.x = (const T*)x;
+    a.delta = vec(p_->L.delta);
+    a.part = p_->part(P_M);
+    a.S = p_->S();
+    return a;
   }
 
   // ------------------------------------------------ single-problem launches
   template <class A>
-  int go(const A& a, int grid, int iter, const char* name) {
-    k_solo<A><<<grid, kBlock, 0, p_->stream>>>(a, iter);
-    HIP_LAUNCHED(name);
-    return OPT_OK;
+  int go(int kind, const A& a, int grid, int iter, const char* name) {
+    return launch_row(p_, kind, a, grid, iter, name);
   }
 
-  int linearize(const void* x, int lm) override { return go(lin_args(x, lm), nblk(), 0, "linearize"); }
-  int init(const void* x, double* trace, int idx, PrecondArgs pa, int lm, int u_form) override {
-    return go(init_args(x, trace, idx, pa, lm, u_form), nblk(), 0, "init");
+  int linearize(const void* x, int lm) override {
+    return go(ROW_LIN, lin_args(x, lm), nblk(), 0, "linearize");
+  }
+  int init(const void* x, double* trace, PrecondArgs pa, int lm, int u_form) override {
+    return go(ROW_INIT, init_args(x, trace, pa, lm, u_form), nblk(), 0, "init");
   }
   int pcg_a(int k, int L, PrecondArgs pa, int lm) override {
-    return go(pcga_args(L, pa, lm), nblk(), k, "pcg_a");
+    return go(ROW_PCGA, pcga_args(L, pa, lm), nblk(), k, "pcg_a");
   }
-  int pcg_b(int k, int L, PrecondArgs, int lm) override { return go(pcgb_args(L, lm), nblk(), k, "pcg_b"); }
+  int pcg_b(int k, int L, PrecondArgs, int lm) override {
+    return go(ROW_PCGB, pcgb_args(L, lm), nblk(), k, "pcg_b");
+  }
   // The fused kernel addresses each vector through a raw buffer of < 256 MB.
   bool has_fused() const override {
     return E::kRadius == 1 && !E::kGraph && (size_t)E::C * e_.n * sizeof(T) <= (size_t(1) << 28);
@@ -337,25 +375,43 @@ class ImplT final : public Impl {
       return fail(OPT_EUNSUPPORTED, "the fused PCG kernel needs an operator of radius 1");
     } else {
       int grid = 0;
-      if (pa.damped) return go(fused_args<true>(L, pa, lm, &grid), grid, iter, "fused");
-      return go(fused_args<false>(L, pa, lm, &grid), grid, iter, "fused");
+      if (pa.damped) return go(ROW_FUSED, fused_args<true>(L, pa, lm, &grid), grid, iter, "fused");
+      return go(ROW_FUSED, fused_args<false>(L, pa, lm, &grid), grid, iter, "fused");
     }
   }
   int apply_jtj(const void* pin, void* qout, PrecondArgs pa) override {
-    SplitBufs<T> b{};
+    SplitBufs<T> b = blank<SplitBufs<T>>();
     b.damp = damp(pa);
     b.p[0] = (T*)pin;
     b.q = (T*)qout;
-    return go(SplitAArgs<E, 1>{e_, b, 0, p_->S(), 0, 1}, nblk(), 0, "apply");
+    SplitAArgs<E, 1> a = split_a_args<1>(b, 1, 0);
+    a.n_part = 0;
+    return go(ROW_APPLY, a, nblk(), 0, "apply");
   }
-  int apply_step(void* x, int lm) override { return go(step_args(x, lm), nblk(), 0, "step"); }
+  int apply_step(void* x, int lm) override { return go(ROW_STEP, step_args(x, lm), nblk(), 0, "step"); }
   int cost(const void* x, const void* delta, int lm) override {
-    return go(cost_args(x, delta, lm), nblk(), 0, "cost");
+    return go(delta ? ROW_TRIAL : ROW_COST, cost_args(x, delta, lm), nblk(), 0, "cost");
   }
-  int model(const void* x) override { return go(model_args(x), nblk(), 0, "model"); }
+  int model(const void* x) override { return go(ROW_MODEL, model_args(x), nblk(), 0, "model"); }
   StripGeom strip_geometry(bool damped) const override { return geom(damped); }
+  double gpu_fill(bool use_fused, bool damped) const override {
+    double waves = (double)nblk() * kWaves;
+    int occ = 2;
+    if constexpr (E::kRadius == 1 && !E::kGraph) {
+      if (use_fused && has_fused()) {
+        const StripGeom g = geom(damped);
+        waves = (double)g.n_sx * g.n_sy;
+        occ = damped ? fused_occupancy<true>() : fused_occupancy<false>();
+      }
+    }
+    return std::min(1.0, waves / ((double)occ * p_->n_simd));
+  }
   int to_planes(const void* src, void* dst) override {
-    return go(PlanesArgs<T, E::C>{(const T*)src, (T*)dst, e_.n}, nblk(), 0, "to_planes");
+    PlanesArgs<T, E::C> a = blank<PlanesArgs<T, E::C>>();
+    a.src = (const T*)src;
+    a.dst = (T*)dst;
+    a.n = e_.n;
+    return go(ROW_PLANES, a, nblk(), 0, "to_planes");
   }
 
   // ------------------------------------------------ batched launches
@@ -385,7 +441,7 @@ class ImplT final : public Impl {
       case Stage::INIT:
         return rec<InitArgs<E>>(B, s, n, [use_fused](const ImplT& m, const SlotRef& r, int* g) {
           *g = m.nblk();
-          return m.init_args(r.x, r.p->trace(), r.trace_idx, r.pa, r.lm, use_fused ? 1 : 0);
+          return m.init_args(r.x, r.p->trace(), r.pa, r.lm, use_fused ? 1 : 0);
         }, 0, 1, "init[batch]");
       case Stage::PCG:
         if (use_fused) {
@@ -605,7 +661,7 @@ int problem_init(opt_problem* p, const opt_problem_desc* desc, const Shape& sh, 
   p->impl = make_impl(p);
   if (!p->impl) return fail(OPT_EUNSUPPORTED, "energy %d is not built", desc->energy);
   if (sh.graph) TRY(build_incidence(p));
-  TRY(scalar_kernel(p->stream, SetupArgs{p->S(), 0.0, 1.0, 0, 0.0}, "setup"));
+  TRY(launch_row(p, ROW_SETUP, setup_args(p->S(), 0.0, 1.0, 0, 0.0), 1, 0, "setup"));
   return OPT_OK;
 }
 
@@ -744,7 +800,7 @@ int opt_linearize(opt_problem* p, const void* x, double* cost) {
   TRY(p->impl->linearize(x, 0));
   p->last_x = x;
   if (cost) {
-    TRY(scalar_kernel(p->stream, FinishArgs{p->S(), p->part(P_LIN), p->nblk, nullptr, 0}, "finish"));
+    TRY(launch_row(p, ROW_FINISH, finish_args(p->S(), p->part(P_LIN), p->nblk), 1, 0, "finish"));
     DevScalars hs;
     TRY(sync_scalars(p, &hs));
     *cost = hs.E_final;
@@ -757,7 +813,7 @@ int opt_eval_jtf(opt_problem* p, void* b_out, void* diag_out) {
   if (!p) return fail(OPT_EINVAL, "problem is NULL");
   if (!p->last_x) return fail(OPT_EINVAL, "opt_linearize has not been called");
   PrecondArgs pa{0.0, 0.0, 0.0, 1, false};
-  TRY(p->impl->init(p->last_x, nullptr, 0, pa, 0, 0));
+  TRY(p->impl->init(p->last_x, nullptr, pa, 0, 0));
   if (b_out) TRY(p->impl->to_planes(p->at(p->L.r0), b_out));
   if (diag_out) TRY(p->impl->to_planes(p->at(p->L.diag), diag_out));
   return OPT_OK;
@@ -772,7 +828,7 @@ int opt_apply_jtj(opt_problem* p, const void* pin, void* qout, double lambda,
   if (lambda != 0.0) {
     if (!sp) return fail(OPT_EINVAL, "params are needed when lambda != 0");
     pa = PrecondArgs{lambda, sp->lm_diag_min, sp->lm_diag_max, 1, true};
-    TRY(p->impl->init(p->last_x, nullptr, 0, pa, 0, 0));
+    TRY(p->impl->init(p->last_x, nullptr, pa, 0, 0));
   }
   return p->impl->apply_jtj(pin, qout, pa);
 }
@@ -782,8 +838,8 @@ int opt_pcg(opt_problem* p, const opt_solve_params* sp, double lambda, void* del
   TRY(check_params(sp));
   if (!p->last_x) return fail(OPT_EINVAL, "opt_linearize has not been called");
   PrecondArgs pa{lambda, sp->lm_diag_min, sp->lm_diag_max, sp->use_precond, lambda != 0.0};
-  TRY(scalar_kernel(p->stream, SetupArgs{p->S(), lambda, 1.0, 0, 0.0}, "setup"));
-  TRY(p->impl->init(p->last_x, nullptr, 0, pa, 0, uses_fused(p, sp->pcg_variant)));
+  TRY(launch_row(p, ROW_SETUP, setup_args(p->S(), lambda, 1.0, 0, 0.0), 1, 0, "setup"));
+  TRY(p->impl->init(p->last_x, nullptr, pa, 0, uses_fused(p, sp->pcg_variant)));
   TRY(run_pcg(p, pa, 0, sp->pcg_iters, sp->pcg_variant));
   if (delta_out) TRY(p->impl->to_planes(p->at(p->L.delta), delta_out));
   return OPT_OK;
@@ -832,7 +888,7 @@ int opt_profile_read(opt_problem* p, double* pcg_ms, int64_t* pcg_iters) {
 int opt_cost(opt_problem* p, const void* x, double* cost) {
   if (!p || !x || !cost) return fail(OPT_EINVAL, "problem, unknowns or cost is NULL");
   TRY(p->impl->cost(x, nullptr, 0));
-  TRY(scalar_kernel(p->stream, FinishArgs{p->S(), p->part(P_COST), p->nblk, nullptr, 0}, "finish"));
+  TRY(launch_row(p, ROW_FINISH, finish_args(p->S(), p->part(P_COST), p->nblk), 1, 0, "finish"));
   DevScalars hs;
   TRY(sync_scalars(p, &hs));
   *cost = hs.E_final;
@@ -846,12 +902,11 @@ int opt_solve(opt_problem* p, void* x, const opt_solve_params* sp, opt_solve_rep
   const int K = sp->outer_iters, Lp = sp->pcg_iters;
   const int lm = sp->method == OPT_LM;
   double* trace = p->trace();
-  TRY(scalar_kernel(p->stream, SetupArgs{p->S(), 0.0, sp->lm_radius0, lm, sp->lm_radius_min}, "setup"));
+  TRY(launch_row(p, ROW_SETUP, setup_args(p->S(), 0.0, sp->lm_radius0, lm, sp->lm_radius_min), 1, 0, "setup"));
   PrecondArgs pa{0.0, sp->lm_diag_min, sp->lm_diag_max, sp->use_precond, lm != 0};
-  LMConsts lc{sp->lm_radius_min, sp->lm_radius_max, sp->lm_min_rel_decrease};
   for (int k = 0; k < K; ++k) {
     TRY(p->impl->linearize(x, lm));
-    TRY(p->impl->init(x, trace, k, pa, lm, uses_fused(p, sp->pcg_variant)));
+    TRY(p->impl->init(x, trace, pa, lm, uses_fused(p, sp->pcg_variant)));
     if (p->profile) TRY(record_event(p));
     TRY(run_pcg(p, pa, lm, Lp, sp->pcg_variant));
     if (p->profile) {
@@ -861,12 +916,13 @@ int opt_solve(opt_problem* p, void* x, const opt_solve_params* sp, opt_solve_rep
     if (lm) {
       TRY(p->impl->model(x));
       TRY(p->impl->cost(x, p->at(p->L.delta), 1));
-      TRY(scalar_kernel(p->stream, DecideArgs{p->S(), p->part(P_M), p->part(P_COST), p->nblk, lc}, "decide"));
+      TRY(launch_row(p, ROW_DECIDE, decide_args(p->S(), p->part(P_M), p->part(P_COST), p->nblk, *sp), 1, 0,
+                      "decide"));
     }
     TRY(p->impl->apply_step(x, lm));
   }
   TRY(p->impl->cost(x, nullptr, 0));
-  TRY(scalar_kernel(p->stream, FinishArgs{p->S(), p->part(P_COST), p->nblk, nullptr, 0}, "finish"));
+  TRY(launch_row(p, ROW_FINISH, finish_args(p->S(), p->part(P_COST), p->nblk), 1, 0, "finish"));
   p->last_x = nullptr;
   if (!rep) return OPT_OK;
   DevScalars hs;

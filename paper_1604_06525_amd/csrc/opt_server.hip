@@ -4,11 +4,18 @@
 // unknowns (Sec. 8, on the small examples): one problem of a few thousand sites
 // fills a small fraction of the chip, and every kernel launch costs about as
 // much as the work it carries.  The server runs many requests together: each
-// step advances every active request by one outer iteration, and every stage of
+// step advances every running request by one outer iteration, and every stage of
 // that iteration is one launch per energy kind covering all requests of that
-// kind (k_batch), each over the block range it would have alone.  Requests join
-// at any step when a slot is free and their workspace fits in the arena, and
-// leave when they finish, so the batch changes from step to step.
+// kind (k_batch), each over the block range it would have alone.
+//
+// Scheduling.  Requests are admitted (workspace carved from the arena) when a
+// slot and a range are free, and started in admission order while the running
+// set's estimated GPU fill stays within a budget: a request that fills the GPU
+// by itself runs alone, as in a plain first-in first-out solver, and small
+// requests share steps.  Steps are pipelined: a step is enqueued without
+// waiting for the GPU (up to kDepth in flight); its scalars and results come back
+// through pinned memory behind an event, and the host harvests completed steps
+// whenever it calls in.
 //
 // Each request's arithmetic, partial sums and reduction order are those of the
 // single-problem solve, so a request gives the same bits whether it runs alone
@@ -30,8 +37,9 @@ using namespace optmi::host;
 
 namespace {
 
-constexpr int kStageKinds = 12;        // table kinds that one step can write
-constexpr int kMaxKinds = 40;          // energy x precision x method x PCG form
+constexpr int kStageKinds = 12;  // table kinds that one step can write
+constexpr int kMaxKinds = 40;    // energy x precision x method x PCG form
+constexpr int kDepth = 3;        // steps in flight
 
 // Arena byte ranges, first fit with coalescing.
 class RangeAlloc {
@@ -76,7 +84,10 @@ class RangeAlloc {
   std::map<size_t, size_t> free_;
 };
 
-enum class SlotState { EMPTY, NEW, RUN, FIN };
+// NEW: admitted, not started.  RUN: in the running set.  DRAIN: its last work
+// is enqueued (final cost, or it was cancelled); the slot is released once the
+// step that carries that work has completed.
+enum class SlotState { EMPTY, NEW, RUN, DRAIN };
 
 struct Slot {
   SlotState state = SlotState::EMPTY;
@@ -86,8 +97,17 @@ struct Slot {
   void* x = nullptr;
   opt_solve_params sp{};
   int it = 0;             // outer iterations enqueued
-  bool lm_done = false;   // LM radius fell below its minimum (seen after a step)
+  bool lm_done = false;   // LM radius fell below its minimum (seen in a completed step)
   bool fused = false;     // PCG form used
+  bool cancelled = false;
+  double fill = 1.0;      // estimated share of the GPU that one of its launches occupies
+  int64_t last_step = -1; // last step that enqueued work for it
+};
+
+// Pinned per-slot landing area for a finished request.
+struct ResultArea {
+  DevScalars scal;
+  double trace[kTraceCap];
 };
 
 struct TuneEntry {
@@ -102,12 +122,20 @@ struct Result {
   bool nonfinite = false;
 };
 
-// Every table kind holds, over all energy kinds, one argument row and one start
-// entry per problem, one block-to-problem entry per block (at most kMaxBlocks
-// per problem), and per kind one extra start entry and three alignment gaps.
+struct StepRec {
+  hipEvent_t ev = nullptr;
+  std::vector<int> gathered;  // LM slots whose scalars this step reads back
+  std::vector<int> retiring;  // slots whose final cost this step computes
+};
+
+// Every table kind holds, over all energy kinds, one argument row and two start
+// entries per problem, one block-to-problem entry per block (at most kMaxBlocks
+// per problem, plus up to kXcdCount - 1 idle blocks before it), and per kind
+// three alignment gaps.
 size_t table_area_bytes(int max_slots) {
-  const size_t per_stage = (size_t)max_slots * (kMaxArgBytes + sizeof(int) + sizeof(int) * kMaxBlocks) +
-                           (size_t)kMaxKinds * (sizeof(int) + 3 * kAlign);
+  const size_t per_stage =
+      (size_t)max_slots * (kMaxArgBytes + 2 * sizeof(int) + sizeof(int) * (kMaxBlocks + kXcdCount)) +
+      (size_t)kMaxKinds * 3 * kAlign;
   return align_up((size_t)kStageKinds * per_stage);
 }
 
@@ -120,9 +148,14 @@ struct opt_server {
   size_t arena_bytes = 0;
   int max_slots = 0;
   hipStream_t stream = nullptr;
+  double fill_budget = 1.0;
   Batcher B;
-  DevScalars* dev_gather = nullptr;   // device, one row per slot
-  DevScalars* host_gather = nullptr;  // pinned
+  char* staging[kDepth] = {};           // pinned argument tables, one per step in flight
+  DevScalars* dev_gather = nullptr;     // device, one row per slot
+  DevScalars* host_gather[kDepth] = {}; // pinned, one per step in flight
+  ResultArea* res = nullptr;            // pinned, one per slot
+  StepRec steps[kDepth];
+  int64_t n_steps = 0, n_done = 0;      // steps enqueued, steps completed and harvested
   RangeAlloc ranges;
   std::vector<Slot> slots;
   std::map<int64_t, Result> results;
@@ -130,8 +163,13 @@ struct opt_server {
   int64_t next_ticket = 1;
 
   ~opt_server() {
-    if (B.host) (void)hipHostFree(B.host);
-    if (host_gather) (void)hipHostFree(host_gather);
+    if (n_steps > n_done) (void)hipStreamSynchronize(stream);
+    for (int k = 0; k < kDepth; ++k) {
+      if (staging[k]) (void)hipHostFree(staging[k]);
+      if (host_gather[k]) (void)hipHostFree(host_gather[k]);
+      if (steps[k].ev) (void)hipEventDestroy(steps[k].ev);
+    }
+    if (res) (void)hipHostFree(res);
   }
 };
 
@@ -152,7 +190,6 @@ SlotRef ref_of(Slot& s) {
   r.pa = PrecondArgs{0.0, s.sp.lm_diag_min, s.sp.lm_diag_max, s.sp.use_precond, lm != 0};
   r.lm = lm;
   r.L = s.sp.pcg_iters;
-  r.trace_idx = s.it;
   return r;
 }
 
@@ -180,6 +217,56 @@ int record_scalar(opt_server* sv, const std::vector<int>& ids, F make, const cha
 void release_slot(opt_server* sv, Slot& s) {
   sv->ranges.release(s.ws_off, s.ws_bytes);
   s = Slot();
+}
+
+// The report of a finished request, as opt_solve fills it.
+void finish_result(opt_server* sv, int i) {
+  Slot& s = sv->slots[(size_t)i];
+  const ResultArea& ra = sv->res[i];
+  const DevScalars& hs = ra.scal;
+  const int K = s.sp.outer_iters, lm = s.sp.method == OPT_LM;
+  const int done = lm ? hs.outer_done : K;
+  Result r;
+  r.trace.assign(ra.trace, ra.trace + K + 1);
+  for (int j = done; j <= K; ++j) r.trace[(size_t)j] = hs.E_final;
+  r.rep.cost_initial = K > 0 ? r.trace[0] : hs.E_final;
+  r.rep.cost_final = hs.E_final;
+  r.rep.outer_done = done;
+  r.rep.steps_accepted = lm ? hs.n_accepted : K;
+  r.rep.cost_trace = nullptr;
+  r.nonfinite = hs.nonfinite != 0;
+  sv->results[s.ticket] = std::move(r);
+}
+
+// Process completed steps in order.  block: wait for the oldest one in flight.
+int harvest(opt_server* sv, bool block) {
+  bool first = true;
+  while (sv->n_done < sv->n_steps) {
+    const int ring = (int)(sv->n_done % kDepth);
+    StepRec& r = sv->steps[ring];
+    if (block && first) {
+      HIP_TRY(hipEventSynchronize(r.ev));
+    } else {
+      const hipError_t q = hipEventQuery(r.ev);
+      if (q == hipErrorNotReady) break;
+      if (q != hipSuccess) return fail(OPT_EHIP, "hipEventQuery failed: %s", hipGetErrorString(q));
+    }
+    first = false;
+    for (int i : r.gathered) {
+      Slot& s = sv->slots[(size_t)i];
+      if (s.state == SlotState::RUN && sv->host_gather[ring][i].done) s.lm_done = true;
+    }
+    for (int i : r.retiring)
+      if (!sv->slots[(size_t)i].cancelled) finish_result(sv, i);
+    sv->n_done++;
+    for (Slot& s : sv->slots)
+      if (s.state == SlotState::DRAIN && s.last_step < sv->n_done) release_slot(sv, s);
+  }
+  return OPT_OK;
+}
+
+bool runnable(const Slot& s) {
+  return s.state == SlotState::RUN && !s.cancelled && s.it < s.sp.outer_iters && !s.lm_done;
 }
 
 }  // namespace
@@ -212,8 +299,12 @@ int opt_server_create(void* arena, size_t arena_bytes, int32_t max_slots, void* 
   sv->stream = (hipStream_t)hip_stream;
   sv->slots.resize((size_t)max_slots);
   const size_t tb = table_area_bytes(max_slots), gb = gather_bytes(max_slots);
-  HIP_TRY(hipHostMalloc((void**)&sv->B.host, tb, hipHostMallocDefault));
-  HIP_TRY(hipHostMalloc((void**)&sv->host_gather, gb, hipHostMallocDefault));
+  for (int k = 0; k < kDepth; ++k) {
+    HIP_TRY(hipHostMalloc((void**)&sv->staging[k], tb, hipHostMallocDefault));
+    HIP_TRY(hipHostMalloc((void**)&sv->host_gather[k], gb, hipHostMallocDefault));
+    HIP_TRY(hipEventCreateWithFlags(&sv->steps[k].ev, hipEventDisableTiming));
+  }
+  HIP_TRY(hipHostMalloc((void**)&sv->res, sizeof(ResultArea) * (size_t)max_slots, hipHostMallocDefault));
   sv->B.dev = sv->arena;
   sv->B.cap = tb;
   sv->B.stream = sv->stream;
@@ -228,6 +319,13 @@ int opt_server_destroy(opt_server* sv) {
   return OPT_OK;
 }
 
+int opt_server_set_fill_budget(opt_server* sv, double budget) {
+  if (!sv) return fail(OPT_EINVAL, "server is NULL");
+  if (!(budget >= 0.0)) return fail(OPT_EINVAL, "fill budget %g must be >= 0", budget);
+  sv->fill_budget = budget;
+  return OPT_OK;
+}
+
 int opt_server_submit(opt_server* sv, const opt_problem_desc* desc, void* unknowns,
                       const opt_solve_params* sp, int64_t* ticket) {
   if (!sv || !unknowns || !ticket) return fail(OPT_EINVAL, "server, unknowns or ticket is NULL");
@@ -235,6 +333,7 @@ int opt_server_submit(opt_server* sv, const opt_problem_desc* desc, void* unknow
   Shape sh;
   TRY(check_desc(desc, &sh));
   TRY(check_params(sp));
+  TRY(harvest(sv, false));
   const size_t need = align_up(make_layout(sh).total);
   size_t slot = (size_t)sv->max_slots;
   for (size_t k = 0; k < sv->slots.size(); ++k)
@@ -264,15 +363,15 @@ int opt_server_submit(opt_server* sv, const opt_problem_desc* desc, void* unknow
       break;
     }
   Slot& s = sv->slots[slot];
+  s = Slot();
   s.state = SlotState::NEW;
   s.ticket = sv->next_ticket++;
   s.ws_off = off;
   s.ws_bytes = need;
   s.x = unknowns;
   s.sp = *sp;
-  s.it = 0;
-  s.lm_done = false;
   s.fused = sp->pcg_variant == OPT_PCG_FUSED && p->impl->has_fused();
+  s.fill = p->impl->gpu_fill(s.fused, sp->method == OPT_LM);
   s.p = std::move(p);
   *ticket = s.ticket;
   return OPT_OK;
@@ -280,25 +379,53 @@ int opt_server_submit(opt_server* sv, const opt_problem_desc* desc, void* unknow
 
 int opt_server_step(opt_server* sv) {
   if (!sv) return fail(OPT_EINVAL, "server is NULL");
-  sv->B.reset();
-  std::vector<int> fresh, run, lm_run, fin, touched;
-  for (int i = 0; i < sv->max_slots; ++i) {
+  TRY(harvest(sv, false));
+  if (sv->n_steps - sv->n_done >= kDepth) TRY(harvest(sv, true));
+  // start admitted requests in admission order while the running set's fill
+  // stays within the budget (at least one request always runs)
+  double running = 0.0;
+  for (const Slot& s : sv->slots)
+    if (runnable(s)) running += s.fill;
+  std::vector<int> order;
+  for (int i = 0; i < sv->max_slots; ++i)
+    if (sv->slots[(size_t)i].state == SlotState::NEW) order.push_back(i);
+  std::sort(order.begin(), order.end(),
+            [&](int a, int b) { return sv->slots[(size_t)a].ticket < sv->slots[(size_t)b].ticket; });
+  std::vector<int> fresh;
+  for (int i : order) {
     Slot& s = sv->slots[(size_t)i];
-    if (s.state == SlotState::NEW) {
-      fresh.push_back(i);
-      s.state = SlotState::RUN;
-    }
-    if (s.state != SlotState::RUN) continue;
-    touched.push_back(i);
-    if (s.it < s.sp.outer_iters && !s.lm_done) {
-      run.push_back(i);
-      if (s.sp.method == OPT_LM) lm_run.push_back(i);
-    }
+    if (running > 0.0 && running + s.fill > sv->fill_budget) break;
+    s.state = SlotState::RUN;
+    running += s.fill;
+    fresh.push_back(i);
   }
-  if (touched.empty()) return OPT_OK;
-  // solve setup for requests that joined
+  // this step: one outer iteration for every runnable request; the final cost
+  // for requests whose iterations are then all enqueued (or whose LM solve has
+  // stopped)
+  std::vector<int> run, lm_run, fin;
+  for (int i = 0; i < sv->max_slots; ++i) {
+    const Slot& s = sv->slots[(size_t)i];
+    if (!runnable(s)) continue;
+    run.push_back(i);
+    if (s.sp.method == OPT_LM) lm_run.push_back(i);
+  }
+  for (int i = 0; i < sv->max_slots; ++i) {
+    const Slot& s = sv->slots[(size_t)i];
+    if (s.state != SlotState::RUN || s.cancelled) continue;
+    const int after = s.it + (runnable(s) ? 1 : 0);
+    if (after >= s.sp.outer_iters || s.lm_done) fin.push_back(i);
+  }
+  if (fresh.empty() && run.empty() && fin.empty()) {
+    // nothing to enqueue: wait for the oldest step in flight, if any
+    if (sv->n_steps > sv->n_done) TRY(harvest(sv, true));
+    return OPT_OK;
+  }
+
+  const int ring = (int)(sv->n_steps % kDepth);
+  sv->B.reset();
+  sv->B.host = sv->staging[ring];
   TRY(record_scalar<SetupArgs>(sv, fresh, [](Slot& s, int) {
-    return SetupArgs{s.p->S(), 0.0, s.sp.lm_radius0, s.sp.method == OPT_LM ? 1 : 0, s.sp.lm_radius_min};
+    return setup_args(s.p->S(), 0.0, s.sp.lm_radius0, s.sp.method == OPT_LM ? 1 : 0, s.sp.lm_radius_min);
   }, "setup[batch]"));
   // one outer iteration (Sec. 4) for every running request
   TRY(record_stage(sv, Stage::LIN, run));
@@ -307,60 +434,42 @@ int opt_server_step(opt_server* sv) {
   TRY(record_stage(sv, Stage::MODEL, lm_run));
   TRY(record_stage(sv, Stage::TRIAL_COST, lm_run));
   TRY(record_scalar<DecideArgs>(sv, lm_run, [](Slot& s, int) {
-    const LMConsts lc{s.sp.lm_radius_min, s.sp.lm_radius_max, s.sp.lm_min_rel_decrease};
-    return DecideArgs{s.p->S(), s.p->part(P_M), s.p->part(P_COST), s.p->nblk, lc};
+    return decide_args(s.p->S(), s.p->part(P_M), s.p->part(P_COST), s.p->nblk, s.sp);
   }, "decide[batch]"));
   TRY(record_stage(sv, Stage::STEP, run));
-  for (int i : run) sv->slots[(size_t)i].it += 1;
-  // final cost for requests that have finished their iterations
-  for (int i : touched) {
-    const Slot& s = sv->slots[(size_t)i];
-    if (s.it >= s.sp.outer_iters || s.lm_done) fin.push_back(i);
-  }
   TRY(record_stage(sv, Stage::COST, fin));
   TRY(record_scalar<FinishArgs>(sv, fin, [](Slot& s, int) {
-    return FinishArgs{s.p->S(), s.p->part(P_COST), s.p->nblk, nullptr, 0};
+    return finish_args(s.p->S(), s.p->part(P_COST), s.p->nblk);
   }, "finish[batch]"));
   DevScalars* dg = sv->dev_gather;
-  TRY(record_scalar<GatherArgs>(sv, touched, [dg](Slot& s, int i) {
+  TRY(record_scalar<GatherArgs>(sv, lm_run, [dg](Slot& s, int i) {
     return GatherArgs{s.p->S(), dg + i};
   }, "gather[batch]"));
-  // enqueue: tables, launches, read-backs; then wait once
+  // enqueue: tables, launches, read-backs, event; no wait
   if (sv->B.used) HIP_TRY(hipMemcpyAsync(sv->B.dev, sv->B.host, sv->B.used, hipMemcpyHostToDevice, sv->stream));
   for (auto& f : sv->B.launches) TRY(f());
-  HIP_TRY(hipMemcpyAsync(sv->host_gather, sv->dev_gather, sizeof(DevScalars) * (size_t)sv->max_slots,
-                         hipMemcpyDeviceToHost, sv->stream));
-  std::vector<std::vector<double>> traces(fin.size());
-  for (size_t k = 0; k < fin.size(); ++k) {
-    const Slot& s = sv->slots[(size_t)fin[k]];
-    traces[k].assign((size_t)s.sp.outer_iters + 1, 0.0);
+  if (!lm_run.empty())
+    HIP_TRY(hipMemcpyAsync(sv->host_gather[ring], sv->dev_gather, sizeof(DevScalars) * (size_t)sv->max_slots,
+                           hipMemcpyDeviceToHost, sv->stream));
+  for (int i : fin) {
+    Slot& s = sv->slots[(size_t)i];
+    HIP_TRY(hipMemcpyAsync(&sv->res[i].scal, s.p->S(), sizeof(DevScalars), hipMemcpyDeviceToHost, sv->stream));
     if (s.sp.outer_iters > 0)
-      HIP_TRY(hipMemcpyAsync(traces[k].data(), s.p->trace(), sizeof(double) * (size_t)s.sp.outer_iters,
+      HIP_TRY(hipMemcpyAsync(sv->res[i].trace, s.p->trace(), sizeof(double) * (size_t)s.sp.outer_iters,
                              hipMemcpyDeviceToHost, sv->stream));
   }
-  HIP_TRY(hipStreamSynchronize(sv->stream));
-  for (int i : touched) {
+  StepRec& rec = sv->steps[ring];
+  rec.gathered = lm_run;
+  rec.retiring = fin;
+  HIP_TRY(hipEventRecord(rec.ev, sv->stream));
+  const int64_t idx = sv->n_steps++;
+  for (int i : run) sv->slots[(size_t)i].it += 1;
+  for (int i : fresh) sv->slots[(size_t)i].last_step = idx;
+  for (int i : run) sv->slots[(size_t)i].last_step = idx;
+  for (int i : fin) {
     Slot& s = sv->slots[(size_t)i];
-    const DevScalars& hs = sv->host_gather[i];
-    if (s.sp.method == OPT_LM && hs.done) s.lm_done = true;
-  }
-  // retire finished requests; the report matches opt_solve's
-  for (size_t k = 0; k < fin.size(); ++k) {
-    Slot& s = sv->slots[(size_t)fin[k]];
-    const DevScalars& hs = sv->host_gather[fin[k]];
-    const int K = s.sp.outer_iters, lm = s.sp.method == OPT_LM;
-    const int done = lm ? hs.outer_done : K;
-    Result r;
-    r.trace = std::move(traces[k]);
-    for (int j = done; j <= K; ++j) r.trace[(size_t)j] = hs.E_final;
-    r.rep.cost_initial = K > 0 ? r.trace[0] : hs.E_final;
-    r.rep.cost_final = hs.E_final;
-    r.rep.outer_done = done;
-    r.rep.steps_accepted = lm ? hs.n_accepted : K;
-    r.rep.cost_trace = nullptr;
-    r.nonfinite = hs.nonfinite != 0;
-    sv->results[s.ticket] = std::move(r);
-    release_slot(sv, s);
+    s.last_step = idx;
+    s.state = SlotState::DRAIN;
   }
   return OPT_OK;
 }
@@ -368,10 +477,11 @@ int opt_server_step(opt_server* sv) {
 int opt_server_poll(opt_server* sv, int64_t ticket, int32_t* done, opt_solve_report* report) {
   if (!sv || !done) return fail(OPT_EINVAL, "server or done is NULL");
   *done = 0;
+  TRY(harvest(sv, false));
   auto it = sv->results.find(ticket);
   if (it == sv->results.end()) {
     for (const Slot& s : sv->slots)
-      if (s.state != SlotState::EMPTY && s.ticket == ticket) return OPT_OK;
+      if (s.state != SlotState::EMPTY && s.ticket == ticket && !s.cancelled) return OPT_OK;
     return fail(OPT_EINVAL, "ticket %lld is not known (or was already collected)", (long long)ticket);
   }
   *done = 1;
@@ -392,11 +502,23 @@ int opt_server_cancel(opt_server* sv, int64_t ticket) {
   if (!sv) return fail(OPT_EINVAL, "server is NULL");
   if (sv->results.erase(ticket)) return OPT_OK;
   for (Slot& s : sv->slots)
-    if (s.state != SlotState::EMPTY && s.ticket == ticket) {
-      release_slot(sv, s);
+    if (s.state != SlotState::EMPTY && s.ticket == ticket && !s.cancelled) {
+      // work already enqueued for it must complete before its range is reused
+      s.cancelled = true;
+      if (s.last_step < sv->n_done) {
+        release_slot(sv, s);
+      } else {
+        s.state = SlotState::DRAIN;
+      }
       return OPT_OK;
     }
   return fail(OPT_EINVAL, "ticket %lld is not known", (long long)ticket);
+}
+
+int opt_server_wait(opt_server* sv) {
+  if (!sv) return fail(OPT_EINVAL, "server is NULL");
+  while (sv->n_done < sv->n_steps) TRY(harvest(sv, true));
+  return OPT_OK;
 }
 
 int opt_server_add_tuning(opt_server* sv, int32_t energy, int32_t precision, int64_t min_sites,
@@ -410,8 +532,9 @@ int opt_server_add_tuning(opt_server* sv, int32_t energy, int32_t precision, int
 
 int opt_server_info(opt_server* sv, int32_t* active, size_t* arena_free) {
   if (!sv) return fail(OPT_EINVAL, "server is NULL");
+  TRY(harvest(sv, false));
   int n = 0;
-  for (const Slot& s : sv->slots) n += s.state != SlotState::EMPTY;
+  for (const Slot& s : sv->slots) n += s.state != SlotState::EMPTY && !s.cancelled;
   if (active) *active = n;
   if (arena_free) *arena_free = sv->ranges.free_bytes();
   return OPT_OK;

@@ -165,6 +165,7 @@ def test_cancel_and_unknown_ticket():
     held, free_before = sv.info()
     assert held == 3
     sv.cancel(subs[1][0])
+    sv.wait()
     held, free_after = sv.info()
     assert held == 2 and free_after > free_before
     out = _run_until_done(sv, [subs[0][0], subs[2][0]])
