@@ -157,9 +157,22 @@ struct ArapWarp {
     d[2] = wr2 * dt;
   }
 
+  // Per-site edge geometry that apply computes and jsq reuses: for each
+  // neighbour k, a_p = R'(t_p)(U_p - U_q).
+  struct JCache {
+    T ax[4], ay[4];
+  };
+
   // g = J^T J P at an active centre site.
   template <class PV, class SV, class FV>
-  __device__ __forceinline__ void apply(PV P, SV S, FV F, int, int, T* g) const {
+  __device__ __forceinline__ void apply(PV P, SV S, FV F, int i, int j, T* g) const {
+    JCache jc;
+    apply_c(P, S, F, i, j, g, jc);
+  }
+
+  // apply, also filling the edge geometry of the centre.
+  template <class PV, class SV, class FV>
+  __device__ __forceinline__ void apply_c(PV P, SV S, FV F, int, int, T* g, JCache& jc) const {
     const T c = S(0, 0, 0), sn = S(1, 0, 0), Ux = S(2, 0, 0), Uy = S(3, 0, 0);
     const T px = P(0, 0, 0), py = P(1, 0, 0), pt = P(2, 0, 0);
     T gx = 0, gy = 0, gt = 0;
@@ -181,6 +194,8 @@ struct ArapWarp {
       gx += w * (j1x - j2x);
       gy += w * (j1y - j2y);
       gt -= w * (apx * j1x + apy * j1y);
+      jc.ax[k] = apx;
+      jc.ay[k] = apy;
     }
     const T wfit = (F(0, 0) & FIT) ? wf * wf : T(0);
     g[0] = fma(wfit, px, gx);
@@ -208,6 +223,23 @@ struct ArapWarp {
     }
     const T wfit = (f0 & FIT) ? wf * wf : T(0);
     acc = fma(wr * wr, acc, wfit * (ux * ux + uy * uy));
+    return (f0 & ACTIVE) ? acc : T(0);
+  }
+
+  // jsq from the edge geometry that apply_c left for this centre: only the
+  // vector (through U) and the centre's flags are read.
+  template <class PV, class FV>
+  __device__ __forceinline__ T jsq_c(PV U, FV F, const JCache& jc) const {
+    const uint32_t f0 = F(0, 0);
+    const T ux = U(0, 0, 0), uy = U(1, 0, 0), ut = U(2, 0, 0);
+    T acc = (f0 & FIT) ? wf * wf * (ux * ux + uy * uy) : T(0);
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      const int di = k == 0 ? 1 : (k == 1 ? -1 : 0), dj = k == 2 ? 1 : (k == 3 ? -1 : 0);
+      const T w = (F(di, dj) & ACTIVE) ? wr * wr : T(0);
+      const T jx = (ux - U(0, di, dj)) - jc.ax[k] * ut, jy = (uy - U(1, di, dj)) - jc.ay[k] * ut;
+      acc = fma(w, jx * jx + jy * jy, acc);
+    }
     return (f0 & ACTIVE) ? acc : T(0);
   }
 

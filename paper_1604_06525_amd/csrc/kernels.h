@@ -346,6 +346,19 @@ __device__ __forceinline__ uint32_t from_right(uint32_t v) { return dpp_from_rig
 // One wave per strip of 64 columns: 60 produced, 2 halo columns on each side.
 constexpr int kStripCols = 60;
 
+// Edge geometry an energy may keep from apply (on a row) for jsq (on the same
+// row one step later): E::JCache with apply_c and jsq_c, else nothing.
+template <class E, class = void>
+struct JCacheOf {
+  struct type {};
+  static constexpr bool kOn = false;
+};
+template <class E>
+struct JCacheOf<E, std::void_t<typename E::JCache>> {
+  using type = typename E::JCache;
+  static constexpr bool kOn = true;
+};
+
 // One grid row as one lane sees it (its column), for the streaming kernel.
 template <class E, bool DAMP>
 struct StreamRow {
@@ -354,9 +367,10 @@ struct StreamRow {
   T u[C];    // u_i, later u_{i+1}
   T p[C];    // p_{i-1}, later p_i
   T x[C];    // d (loaded one step before it is updated)
-  T dmp[DAMP ? C : 1];  // LM damping lambda*D (computed, not loaded)
+  T po[C];   // p_{i-1}, kept for the deferred update of d
   T st[NS];
   uint32_t f;
+  typename JCacheOf<E>::type jc;  // set by apply on this row, read by its jsq
 };
 
 // Stencil views centred on row R (rows U above and D below); V selects the
@@ -444,9 +458,16 @@ __device__ __forceinline__ void run(const FusedArgs<E, DAMP>& a, VG g, int iter)
   DevScalars* S = a.S;
   if (iter >= a.L) return;
   const bool read_pold = iter > 0, write_out = iter >= 0;
+  // d = sum_i alpha_i p_i is updated every second iteration: an odd iteration
+  // adds alpha_{i-1} p_{i-1} (the p it reads) and then alpha_i p_i, rounding as
+  // two successive updates would; an even one leaves d alone unless it is the
+  // last.  That halves the traffic of d.
+  const bool xupd = write_out && ((iter & 1) || iter == a.L - 1);
+  const bool xtwo = xupd && (iter & 1);
   const int W = e.W, H = e.H, n = e.n, n_sy = a.n_sy, sw = a.sw;
   const int lane = threadIdx.x & 63;
-  const int strip = unit_of_block(g) * kWaves + (threadIdx.x >> 6);
+  // the wave's strip and every row quantity below are wave-uniform (scalar)
+  const int strip = unit_of_block(g) * kWaves + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const bool has_strip = strip < a.n_sx * n_sy;
   // Strips are numbered along grid rows, so horizontally adjacent strips run
   // side by side (and mostly on one XCD).  Vertically adjacent strips walk in
@@ -471,24 +492,31 @@ __device__ __forceinline__ void run(const FusedArgs<E, DAMP>& a, VG g, int iter)
   const size_t vbytes = (size_t)n * VB;
   const Buf<T> Buin = Buf<T>::make(pick(a.b.u, iter < 0 ? 0 : (iter & 1)), vbytes);
   const Buf<T> Bpin = Buf<T>::make(pick(a.b.p, (iter + 1) & 1), read_pold ? vbytes : 0);
-  const Buf<T> Bx = Buf<T>::make(a.b.x, write_out ? vbytes : 0);
+  const Buf<T> Bx = Buf<T>::make(a.b.x, xupd ? vbytes : 0);
   const Buf<T> Buout = Buf<T>::make(pick(a.b.u, (iter + 1) & 1), write_out ? vbytes : 0);
   const Buf<T> Bpout = Buf<T>::make(pick(a.b.p, iter & 1), write_out ? vbytes : 0);
   const Buf<T> Bst = Buf<T>::make(e.state_base(), NS > 0 ? (size_t)n * SB : 0);
   const Buf<uint8_t> Bf = Buf<uint8_t>::make(e.flags, (size_t)n);
+  // Byte offsets are a per-lane column part plus a scalar row part.  Either
+  // part may be kBufOutOfRange; the sum then stays at or above 2^28 (no part
+  // in range reaches 2^28), so the access is out of range as required.
+  const unsigned lane_v = colin ? (unsigned)col * VB : kBufOutOfRange;
+  const unsigned lane_s = colin ? (unsigned)col * SB : kBufOutOfRange;
+  const unsigned lane_f = colin ? (unsigned)col : kBufOutOfRange;
+  const unsigned lane_o = out_lane ? (unsigned)col * VB : kBufOutOfRange;
   // The row of step k lives in ring slot k % N; its loads are issued
   // kPrefetch steps before it is started.
   Row ring[N];
   auto issue = [&](Row& R, int y) {
-    const bool in = colin && y >= ylo && y <= yhi;
-    const unsigned s = (unsigned)(y * W + col);
-    const unsigned o = in ? s * VB : kBufOutOfRange;
+    const bool in = y >= ylo && y <= yhi;
+    const unsigned rs = (unsigned)(y * W);
     if constexpr (NS > 0) {
-      buf_loadv<NS>(Bst, in ? s * SB : kBufOutOfRange, 0, R.st);
+      buf_loadv<NS>(Bst, lane_s + (in ? rs * SB : kBufOutOfRange), 0, R.st);
     } else {
       R.st[0] = T(0);
     }
-    R.f = Bf.load(in ? s : kBufOutOfRange, 0);
+    R.f = Bf.load(lane_f + (in ? rs : kBufOutOfRange), 0);
+    const unsigned o = lane_v + (in ? rs * VB : kBufOutOfRange);
     buf_loadv<C>(Buin, o, 0, R.u);
     buf_loadv<C>(Bpin, o, 0, R.p);
   };
@@ -497,10 +525,13 @@ __device__ __forceinline__ void run(const FusedArgs<E, DAMP>& a, VG g, int iter)
 #pragma unroll
   for (int k = 0; k < kPrefetch; ++k) issue(ring[k], ybeg + dir * k);
 
-  if (S->stopped || (a.lm_gate && S->done)) return;
+  // S->stopped holds 1 + the iteration at which the PCG stopped; the blocks of
+  // that launch all take the stop path (a sibling may already have set it).
+  const int stopped_at = S->stopped;
+  if ((stopped_at != 0 && stopped_at != iter + 1) || (a.lm_gate && S->done)) return;
   const double* part_in = pick(a.b.part, (iter + 1) & 1);
   double* part_out = pick(a.b.part, iter & 1);
-  double alpha = 0.0, beta = 0.0;
+  double alpha = 0.0, beta = 0.0, alpha_prev = 0.0;
   if (iter >= 0) {
     const double gam = reduce_partials(part_in, a.n_part);
     const double del = reduce_partials(part_in + kMaxBlocks, a.n_part);
@@ -509,8 +540,23 @@ __device__ __forceinline__ void run(const FusedArgs<E, DAMP>& a, VG g, int iter)
       beta = gam / S->gam[(iter - 1) & 1];
       den = del - beta * gam / S->alpha[(iter - 1) & 1];
     }
+    if (iter & 1) alpha_prev = S->alpha[(iter - 1) & 1];
     if (!(den > 0.0)) {
-      if (is_block_leader(g)) S->stopped = 1;
+      if (is_block_leader(g)) S->stopped = iter + 1;
+      if ((iter & 1) && out_lane) {
+        // the update alpha_{i-1} p_{i-1} deferred from the previous iteration
+        const T ap = (T)alpha_prev;
+        for (int y = y0; y < y1; ++y) {
+          const unsigned s = (unsigned)(y * W + col);
+          if (!(Bf.load(s, 0) & E::ACTIVE)) continue;
+          T pv[C], xv[C];
+          buf_loadv<C>(Bpin, s * VB, 0, pv);
+          buf_loadv<C>(Bx, s * VB, 0, xv);
+#pragma unroll
+          for (int c = 0; c < C; ++c) xv[c] = fma(ap, pv[c], xv[c]);
+          buf_storev<C>(Bx, s * VB, 0, xv);
+        }
+      }
       return;
     }
     alpha = gam / den;
@@ -519,7 +565,7 @@ __device__ __forceinline__ void run(const FusedArgs<E, DAMP>& a, VG g, int iter)
       S->alpha[iter & 1] = alpha;
     }
   }
-  const T aT = (T)alpha, bT = (T)beta;
+  const T aT = (T)alpha, bT = (T)beta, apT = (T)alpha_prev;
   Precond<T> pc = a.pc;
   if (a.lm_gate) pc.lam = (T)S->lambda;
   double g_acc = 0.0, d_acc = 0.0;
@@ -538,7 +584,10 @@ __device__ __forceinline__ void run(const FusedArgs<E, DAMP>& a, VG g, int iter)
       issue(ring[(ph + kPrefetch) % N], y + dir * kPrefetch);
       // p_i = u_i + beta p_{i-1} on row y
 #pragma unroll
-      for (int c = 0; c < C; ++c) R0.p[c] = read_pold ? fma(bT, R0.p[c], R0.u[c]) : R0.u[c];
+      for (int c = 0; c < C; ++c) {
+        R0.po[c] = R0.p[c];
+        R0.p[c] = read_pold ? fma(bT, R0.p[c], R0.u[c]) : R0.u[c];
+      }
       if (k >= 2) {
         // on row y - dir: s = A p (with the LM damping), the diagonal M from the
         // state, u_{i+1} = u_i - alpha M^-1 s and the partial of gamma = sum M u^2;
@@ -546,49 +595,64 @@ __device__ __forceinline__ void run(const FusedArgs<E, DAMP>& a, VG g, int iter)
         const int y1r = y - dir;
         T gv[C], dg[C];
         with_views(R2, R1, R0, selp, [&](auto Pv, auto Sv, auto Fv) {
-          e.apply(Pv, Sv, Fv, col, y1r, gv);
+          if constexpr (JCacheOf<E>::kOn) {
+            e.apply_c(Pv, Sv, Fv, col, y1r, gv, R1.jc);
+          } else {
+            e.apply(Pv, Sv, Fv, col, y1r, gv);
+          }
           e.diag(Sv, Fv, dg);
           return 0;
         });
         const bool act = R1.f & E::ACTIVE;
-        const bool prod = y1r >= y0 && y1r < y1;
-        const unsigned ox = (out_lane && prod && act && write_out) ? (unsigned)(y1r * W + col) * VB
-                                                                   : kBufOutOfRange;
+        const bool prod = y1r >= y0 && y1r < y1;  // uniform
+        const unsigned ox = act ? lane_o + ((prod && xupd) ? (unsigned)(y1r * W) * VB : kBufOutOfRange)
+                                : kBufOutOfRange;
         buf_loadv<C>(Bx, ox, 0, R1.x);
-        T gs = 0;
+        T gs = 0, dd = 0;
 #pragma unroll
         for (int c = 0; c < C; ++c) {
           T sv = gv[c];
+          T dmp = T(0);
           if constexpr (DAMP) {
-            R1.dmp[c] = pc.lam != T(0) ? pc.damp(dg[c]) : T(0);
-            sv = fma(R1.dmp[c], R1.p[c], sv);
+            dmp = pc.lam != T(0) ? pc.damp(dg[c]) : T(0);
+            sv = fma(dmp, R1.p[c], sv);
           }
-          R1.u[c] = act ? fma(-aT, pc.minv(dg[c]) * sv, R1.u[c]) : T(0);
-          gs = fma(pc.den(dg[c]) * R1.u[c], R1.u[c], gs);
+          // M and M^-1 as Precond gives them (without damping, lam is 0)
+          // (branch-free: the reciprocal is taken even where it is not used)
+          const T m = DAMP ? pc.den(dg[c]) : (pc.use ? dg[c] : T(1));
+          const T rm = recip(m);
+          const T mi = pc.use ? (m > T(0) ? rm : T(0)) : T(1);
+          R1.u[c] = act ? fma(-aT, mi * sv, R1.u[c]) : T(0);
+          gs = fma(m * R1.u[c], R1.u[c], gs);
+          if constexpr (DAMP) dd = fma(dmp * R1.u[c], R1.u[c], dd);
         }
-        g_acc += (out_lane && prod) ? (double)gs : 0.0;
+        if (prod) {
+          g_acc += (double)(out_lane ? gs : T(0));
+          // the damping part of delta, u.(lambda D) u, is pointwise: taken here
+          if constexpr (DAMP) d_acc += (double)((out_lane && (R1.f & E::INGRID)) ? dd : T(0));
+        }
       }
       if (k >= 4) {
         // row y - 2 dir is final: partial of delta = |J u|^2 (+ u.(lambda D) u),
         // and the stores of d, u, p
         const int yo = y - 2 * dir;
         const T jq = with_views(R3, R2, R1, selu, [&](auto Pv, auto Sv, auto Fv) {
-          return e.jsq(Pv, Sv, Fv, col, yo);
+          if constexpr (JCacheOf<E>::kOn) {
+            return e.jsq_c(Pv, Fv, R2.jc);
+          } else {
+            return e.jsq(Pv, Sv, Fv, col, yo);
+          }
         });
         const bool act = R2.f & E::ACTIVE;
-        T ds = jq;
-        if constexpr (DAMP) {
-#pragma unroll
-          for (int c = 0; c < C; ++c) ds = fma(R2.dmp[c] * R2.u[c], R2.u[c], ds);
-        }
-        d_acc += (out_lane && (R2.f & E::INGRID)) ? (double)ds : 0.0;
-        const unsigned o = out_lane ? (unsigned)(yo * W + col) * VB : kBufOutOfRange;
-        const unsigned ox = (act && write_out) ? o : kBufOutOfRange;
+        d_acc += (double)((out_lane && (R2.f & E::INGRID)) ? jq : T(0));
+        const unsigned o = lane_o + (unsigned)(yo * W) * VB;
+        const unsigned ox = (act && xupd) ? o : kBufOutOfRange;
         T pv[C], xv[C];
 #pragma unroll
         for (int c = 0; c < C; ++c) {
           pv[c] = act ? R2.p[c] : T(0);
-          xv[c] = fma(aT, pv[c], R2.x[c]);
+          const T xo = xtwo ? fma(apT, R2.po[c], R2.x[c]) : R2.x[c];
+          xv[c] = fma(aT, pv[c], xo);
         }
         buf_storev<C>(Bx, ox, 0, xv);
         buf_storev<C>(Buout, o, 0, R2.u);

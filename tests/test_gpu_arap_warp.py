@@ -93,7 +93,7 @@ def test_pcg(W, H, mask, precond, variant):
     xt = to_dev(prob, x)
     prob.linearize(xt)
     A = (lin.JT @ lin.J).tocsr()
-    for L in (1, 7, 25):
+    for L in (1, 7, 8, 25):  # odd and even counts end d's paired updates both ways
         ref, _ = o.pcg(lin.apply, lin.jtf(), lin.minv(precond), L)
         # Once CG loses orthogonality its iterates depend on rounding order; the
         # oracle's own spread between J^T(Jp) and (J^T J)p bounds what can agree.
@@ -231,3 +231,34 @@ def test_launch_shapes_agree(tuning):
     prob.linearize(xt)
     got = to_np(prob.pcg(20, variant="fused"))
     assert relmax(got, ref) < 1e-9
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+@pytest.mark.parametrize("pcg_iters", [1, 2, 3, 6])
+def test_pcg_exact_stop_keeps_last_update(precision, pcg_iters):
+    """Isolated active pixels with fit terms only: J^T J is w_fit I on their
+    positions (the angles have no term), so Jacobi-PCG reaches the exact Newton
+    step after one iteration, and with dyadic data every product and sum is
+    exact.  The second iteration then finds gamma = delta = 0 and stops; the
+    step of the first iteration must still reach d, so one GN iteration puts
+    every constrained pixel on its target (cost 0), as the oracle does."""
+    W, H = 18, 14
+    d = w.arap_warp(W, H, seed=1, n_constraints=1, margin=0, w_fit=4.0, w_reg=1.0)
+    i, j = np.meshgrid(np.arange(W), np.arange(H))
+    act = (i % 2 == 0) & (j % 2 == 0)
+    d["mask"] = np.where(act, 0, 1).astype(np.uint8)
+    rng = np.random.default_rng(4)
+    C = -np.ones((2, H, W))
+    tgt = act & (rng.random((H, W)) < 0.7)
+    off = rng.integers(0, 4, size=(2, H, W)).astype(np.float64)
+    C[:, tgt] = d["U"][:, tgt] + off[:, tgt]
+    d["C"] = C
+    e = o.make_energy(d)
+    xo, costs = o.gauss_newton(e, d["x0"], 1, pcg_iters)
+    assert costs[-1] == 0.0 and costs[0] > 0.0
+    prob = make_problem(d, precision)
+    xt = to_dev(prob, d["x0"])
+    rep = prob.solve(xt, method="gn", outer_iters=1, pcg_iters=pcg_iters)
+    assert rep["cost_trace"][0] == costs[0]
+    assert rep["cost_final"] == 0.0
+    assert np.array_equal(to_np(xt).reshape(3, H, W), np.asarray(xo).reshape(3, H, W))
