@@ -226,6 +226,70 @@ struct ArapWarp {
     return (f0 & ACTIVE) ? acc : T(0);
   }
 
+  // Streaming apply (the fused kernel walks rows in order).  Each regulariser
+  // residual (J P)_r / w_reg is formed once, by its anchor, and handed to the
+  // other end of its edge: across lanes by a lane shift, and from one row step
+  // to the next through a Carry.  The sums are those of apply, term for term.
+  struct Res {
+    T jx, jy;  // (P_a - P_b) - a_a P^t_a, anchored at a toward b
+    T ax, ay;  // a_a = R'(t_a)(U_a - U_b)
+  };
+  __device__ __forceinline__ static Res own_res(T c, T sn, T dx, T dy, T pax, T pay, T pat, T pbx, T pby) {
+    Res r;
+    r.ax = -sn * dx - c * dy;
+    r.ay = c * dx - sn * dy;
+    r.jx = (pax - pbx) - r.ax * pat;
+    r.jy = (pay - pby) - r.ay * pat;
+    return r;
+  }
+  // The two residuals of the edge between a row A and the row B after it in
+  // the walk: A's toward B (with A's a) and B's toward A (with B's a).
+  struct Carry {
+    Res a, b;
+  };
+  template <class Row>
+  __device__ __forceinline__ Carry edge_next(const Row& A, const Row& B) const {
+    const T dx = A.st[2] - B.st[2], dy = A.st[3] - B.st[3];
+    Carry e;
+    e.a = own_res(A.st[0], A.st[1], dx, dy, A.p[0], A.p[1], A.p[2], B.p[0], B.p[1]);
+    e.b = own_res(B.st[0], B.st[1], -dx, -dy, B.p[0], B.p[1], B.p[2], A.p[0], A.p[1]);
+    return e;
+  }
+  // g = J^T J P at the centre row, from its horizontal edges (formed here; the
+  // neighbours' halves arrive through Hs(v, di), the value v of lane +di) and
+  // its vertical edges: prev (previous row in the walk, dj = -1 in the views)
+  // and next (dj = +1).  Fills the edge geometry for jsq_c.
+  template <class PV, class SV, class FV, class HS>
+  __device__ __forceinline__ void apply_stream(PV P, SV S, FV F, HS Hs, const Carry& prev, const Carry& next,
+                                               T* g, JCache& jc) const {
+    const T c = S(0, 0, 0), sn = S(1, 0, 0), Ux = S(2, 0, 0), Uy = S(3, 0, 0);
+    const T px = P(0, 0, 0), py = P(1, 0, 0), pt = P(2, 0, 0);
+    const Res rp = own_res(c, sn, Ux - S(2, 1, 0), Uy - S(3, 1, 0), px, py, pt, P(0, 1, 0), P(1, 1, 0));
+    const Res rm = own_res(c, sn, Ux - S(2, -1, 0), Uy - S(3, -1, 0), px, py, pt, P(0, -1, 0), P(1, -1, 0));
+    // neighbour +x holds its residual toward -x (this site), and the reverse
+    const T bpx = Hs(rm.jx, 1), bpy = Hs(rm.jy, 1);
+    const T bmx = Hs(rp.jx, -1), bmy = Hs(rp.jy, -1);
+    const Res own[4] = {rp, rm, next.a, prev.b};
+    const T bx[4] = {bpx, bmx, next.b.jx, prev.a.jx};
+    const T by[4] = {bpy, bmy, next.b.jy, prev.a.jy};
+    T gx = 0, gy = 0, gt = 0;
+    const T wr2 = wr * wr;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      const int di = k == 0 ? 1 : (k == 1 ? -1 : 0), dj = k == 2 ? 1 : (k == 3 ? -1 : 0);
+      const T w = (F(di, dj) & ACTIVE) ? wr2 : T(0);
+      gx += w * (own[k].jx - bx[k]);
+      gy += w * (own[k].jy - by[k]);
+      gt -= w * (own[k].ax * own[k].jx + own[k].ay * own[k].jy);
+      jc.ax[k] = own[k].ax;
+      jc.ay[k] = own[k].ay;
+    }
+    const T wfit = (F(0, 0) & FIT) ? wf * wf : T(0);
+    g[0] = fma(wfit, px, gx);
+    g[1] = fma(wfit, py, gy);
+    g[2] = gt;
+  }
+
   // jsq from the edge geometry that apply_c left for this centre: only the
   // vector (through U) and the centre's flags are read.
   template <class PV, class FV>

@@ -359,6 +359,20 @@ struct JCacheOf<E, std::void_t<typename E::JCache>> {
   static constexpr bool kOn = true;
 };
 
+// An energy may form J^T J p row by row in the streaming kernel, passing each
+// residual of an edge between rows to the next step (E::Carry, edge_next and
+// apply_stream); else the fused kernel uses apply.
+template <class E, class = void>
+struct StreamApplyOf {
+  struct Carry {};
+  static constexpr bool kOn = false;
+};
+template <class E>
+struct StreamApplyOf<E, std::void_t<typename E::Carry>> {
+  using Carry = typename E::Carry;
+  static constexpr bool kOn = true;
+};
+
 // One grid row as one lane sees it (its column), for the streaming kernel.
 template <class E, bool DAMP>
 struct StreamRow {
@@ -574,6 +588,9 @@ __device__ __forceinline__ void run(const FusedArgs<E, DAMP>& a, VG g, int iter)
     auto selp = [](const Row& R, int c) { return R.p[c]; };
     auto selu = [](const Row& R, int c) { return R.u[c]; };
 
+    using SA = StreamApplyOf<E>;
+    typename SA::Carry cprev{};  // residuals of the edge (y - 2 dir, y - dir)
+    auto shift = [](T v, int di) { return di > 0 ? from_right(v) : from_left(v); };
     auto step = [&](auto PH, int k) {
       constexpr int ph = decltype(PH)::value;
       Row& R0 = ring[ph];                // row y = ybeg + dir k
@@ -585,8 +602,14 @@ __device__ __forceinline__ void run(const FusedArgs<E, DAMP>& a, VG g, int iter)
       // p_i = u_i + beta p_{i-1} on row y
 #pragma unroll
       for (int c = 0; c < C; ++c) {
+        // at iteration 0 (and in the priming launch) beta is 0 and p_{i-1}
+        // reads as 0, so this is p_0 = u_0 exactly
         R0.po[c] = R0.p[c];
-        R0.p[c] = read_pold ? fma(bT, R0.p[c], R0.u[c]) : R0.u[c];
+        R0.p[c] = fma(bT, R0.p[c], R0.u[c]);
+      }
+      typename SA::Carry cnext{};  // residuals of the edge (y - dir, y)
+      if constexpr (SA::kOn) {
+        if (k >= 1) cnext = e.edge_next(R1, R0);
       }
       if (k >= 2) {
         // on row y - dir: s = A p (with the LM damping), the diagonal M from the
@@ -595,7 +618,9 @@ __device__ __forceinline__ void run(const FusedArgs<E, DAMP>& a, VG g, int iter)
         const int y1r = y - dir;
         T gv[C], dg[C];
         with_views(R2, R1, R0, selp, [&](auto Pv, auto Sv, auto Fv) {
-          if constexpr (JCacheOf<E>::kOn) {
+          if constexpr (SA::kOn) {
+            e.apply_stream(Pv, Sv, Fv, shift, cprev, cnext, gv, R1.jc);
+          } else if constexpr (JCacheOf<E>::kOn) {
             e.apply_c(Pv, Sv, Fv, col, y1r, gv, R1.jc);
           } else {
             e.apply(Pv, Sv, Fv, col, y1r, gv);
@@ -626,12 +651,11 @@ __device__ __forceinline__ void run(const FusedArgs<E, DAMP>& a, VG g, int iter)
           gs = fma(m * R1.u[c], R1.u[c], gs);
           if constexpr (DAMP) dd = fma(dmp * R1.u[c], R1.u[c], dd);
         }
-        if (prod) {
-          g_acc += (double)(out_lane ? gs : T(0));
-          // the damping part of delta, u.(lambda D) u, is pointwise: taken here
-          if constexpr (DAMP) d_acc += (double)((out_lane && (R1.f & E::INGRID)) ? dd : T(0));
-        }
+        g_acc += (double)((out_lane && prod) ? gs : T(0));
+        // the damping part of delta, u.(lambda D) u, is pointwise: taken here
+        if constexpr (DAMP) d_acc += (double)((out_lane && prod && (R1.f & E::INGRID)) ? dd : T(0));
       }
+      if constexpr (SA::kOn) cprev = cnext;
       if (k >= 4) {
         // row y - 2 dir is final: partial of delta = |J u|^2 (+ u.(lambda D) u),
         // and the stores of d, u, p
