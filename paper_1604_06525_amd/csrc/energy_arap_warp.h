@@ -259,9 +259,9 @@ struct ArapWarp {
   // neighbours' halves arrive through Hs(v, di), the value v of lane +di) and
   // its vertical edges: prev (previous row in the walk, dj = -1 in the views)
   // and next (dj = +1).  Fills the edge geometry for jsq_c.
-  template <class PV, class SV, class FV, class HS>
-  __device__ __forceinline__ void apply_stream(PV P, SV S, FV F, HS Hs, const Carry& prev, const Carry& next,
-                                               T* g, JCache& jc) const {
+  template <class PV, class SV, class FV, class AV, class HS>
+  __device__ __forceinline__ void apply_stream(PV P, SV S, FV F, AV A, HS Hs, const Carry& prev,
+                                               const Carry& next, T* g, JCache& jc) const {
     const T c = S(0, 0, 0), sn = S(1, 0, 0), Ux = S(2, 0, 0), Uy = S(3, 0, 0);
     const T px = P(0, 0, 0), py = P(1, 0, 0), pt = P(2, 0, 0);
     const Res rp = own_res(c, sn, Ux - S(2, 1, 0), Uy - S(3, 1, 0), px, py, pt, P(0, 1, 0), P(1, 1, 0));
@@ -277,7 +277,7 @@ struct ArapWarp {
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
       const int di = k == 0 ? 1 : (k == 1 ? -1 : 0), dj = k == 2 ? 1 : (k == 3 ? -1 : 0);
-      const T w = (F(di, dj) & ACTIVE) ? wr2 : T(0);
+      const T w = wr2 * A(di, dj);
       gx += w * (own[k].jx - bx[k]);
       gy += w * (own[k].jy - by[k]);
       gt -= w * (own[k].ax * own[k].jx + own[k].ay * own[k].jy);
@@ -290,17 +290,37 @@ struct ArapWarp {
     g[2] = gt;
   }
 
+  // diag as above, with the neighbours' activity as weights A (1 or 0).
+  template <class SV, class FV, class AV>
+  __device__ __forceinline__ void diag_stream(SV S, FV F, AV A, T* d) const {
+    const T Ux = S(2, 0, 0), Uy = S(3, 0, 0);
+    const T wr2 = wr * wr;
+    T nact = 0, dt = 0;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      const int di = k == 0 ? 1 : (k == 1 ? -1 : 0), dj = k == 2 ? 1 : (k == 3 ? -1 : 0);
+      const T w = A(di, dj);
+      const T dx = Ux - S(2, di, dj), dy = Uy - S(3, di, dj);
+      nact += w;
+      dt += w * (dx * dx + dy * dy);
+    }
+    const T dO = T(2) * wr2 * nact + ((F(0, 0) & FIT) ? wf * wf : T(0));
+    d[0] = dO;
+    d[1] = dO;
+    d[2] = wr2 * dt;
+  }
+
   // jsq from the edge geometry that apply_c left for this centre: only the
-  // vector (through U) and the centre's flags are read.
-  template <class PV, class FV>
-  __device__ __forceinline__ T jsq_c(PV U, FV F, const JCache& jc) const {
+  // vector (through U), the centre's flags and the activity weights are read.
+  template <class PV, class FV, class AV>
+  __device__ __forceinline__ T jsq_c(PV U, FV F, AV A, const JCache& jc) const {
     const uint32_t f0 = F(0, 0);
     const T ux = U(0, 0, 0), uy = U(1, 0, 0), ut = U(2, 0, 0);
     T acc = (f0 & FIT) ? wf * wf * (ux * ux + uy * uy) : T(0);
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
       const int di = k == 0 ? 1 : (k == 1 ? -1 : 0), dj = k == 2 ? 1 : (k == 3 ? -1 : 0);
-      const T w = (F(di, dj) & ACTIVE) ? wr * wr : T(0);
+      const T w = wr * wr * A(di, dj);
       const T jx = (ux - U(0, di, dj)) - jc.ax[k] * ut, jy = (uy - U(1, di, dj)) - jc.ay[k] * ut;
       acc = fma(w, jx * jx + jy * jy, acc);
     }

@@ -384,13 +384,15 @@ struct StreamRow {
   T po[C];   // p_{i-1}, kept for the deferred update of d
   T st[NS];
   uint32_t f;
+  T aw;  // 1 where the site is active, else 0 (set with p)
   typename JCacheOf<E>::type jc;  // set by apply on this row, read by its jsq
 };
 
-// Stencil views centred on row R (rows U above and D below); V selects the
-// vector.  Horizontal neighbours come from the adjacent lanes (DPP), vertical
-// ones from the row ring.  NEED_NBR_STATE: whether the operator reads the state
-// of the neighbours (passes that do not skip those lane exchanges).
+// Stencil views centred on row R (rows U before and D after it in the walk); V
+// selects the vector.  Horizontal neighbours come from the adjacent lanes
+// (DPP), vertical ones from the row ring.  Views: P (vector), S (state), F
+// (flags), A (active weight).  Lane exchanges whose values the body does not
+// read are dropped by the compiler.
 template <class E, bool DAMP, class VSel, class Body>
 __device__ __forceinline__ auto with_views(const StreamRow<E, DAMP>& U, const StreamRow<E, DAMP>& R,
                                            const StreamRow<E, DAMP>& D, VSel V, Body body) {
@@ -408,6 +410,7 @@ __device__ __forceinline__ auto with_views(const StreamRow<E, DAMP>& U, const St
     sr[q] = from_right(R.st[q]);
   }
   const uint32_t fl = from_left(R.f), fr = from_right(R.f);
+  const T al = from_left(R.aw), ar = from_right(R.aw);
   auto Pv = [&](int c, int di, int dj) -> T {
     return dj < 0 ? V(U, c) : dj > 0 ? V(D, c) : di < 0 ? vl[c] : di > 0 ? vr[c] : V(R, c);
   };
@@ -417,7 +420,10 @@ __device__ __forceinline__ auto with_views(const StreamRow<E, DAMP>& U, const St
   auto Fv = [&](int di, int dj) -> uint32_t {
     return dj < 0 ? U.f : dj > 0 ? D.f : di < 0 ? fl : di > 0 ? fr : R.f;
   };
-  return body(Pv, Sv, Fv);
+  auto Av = [&](int di, int dj) -> T {
+    return dj < 0 ? U.aw : dj > 0 ? D.aw : di < 0 ? al : di > 0 ? ar : R.aw;
+  };
+  return body(Pv, Sv, Fv, Av);
 }
 
 // The unit of work of a block, XCD-aware: blocks go to the 8 XCDs round-robin
@@ -459,14 +465,17 @@ __device__ __forceinline__ void unroll_seq(std::integer_sequence<int, I...>, F f
   (f(std::integral_constant<int, I>{}), ...);
 }
 
-// Rows of loads in flight ahead of the row being started.
-constexpr int kPrefetch = 4;
+// Rows of loads in flight ahead of the row being started (FP64 rows are twice
+// as large, so fewer fit in registers).
+template <typename T>
+constexpr int kPrefetchOf = sizeof(T) > 4 ? 2 : 4;
 
 template <class E, bool DAMP>
 __device__ __forceinline__ void run(const FusedArgs<E, DAMP>& a, VG g, int iter) {
   using T = typename E::Real;
   using Row = StreamRow<E, DAMP>;
   constexpr int C = E::C, NS = E::kStatePlanes;
+  constexpr int kPrefetch = kPrefetchOf<T>;
   constexpr int N = kPrefetch + 4;  // ring slots: four rows in use, the rest in flight
   const E& e = a.e;
   DevScalars* S = a.S;
@@ -607,6 +616,7 @@ __device__ __forceinline__ void run(const FusedArgs<E, DAMP>& a, VG g, int iter)
         R0.po[c] = R0.p[c];
         R0.p[c] = fma(bT, R0.p[c], R0.u[c]);
       }
+      R0.aw = (R0.f & E::ACTIVE) ? T(1) : T(0);
       typename SA::Carry cnext{};  // residuals of the edge (y - dir, y)
       if constexpr (SA::kOn) {
         if (k >= 1) cnext = e.edge_next(R1, R0);
@@ -617,15 +627,18 @@ __device__ __forceinline__ void run(const FusedArgs<E, DAMP>& a, VG g, int iter)
         // d of that row is fetched now, to be updated in the next step
         const int y1r = y - dir;
         T gv[C], dg[C];
-        with_views(R2, R1, R0, selp, [&](auto Pv, auto Sv, auto Fv) {
+        with_views(R2, R1, R0, selp, [&](auto Pv, auto Sv, auto Fv, auto Av) {
           if constexpr (SA::kOn) {
-            e.apply_stream(Pv, Sv, Fv, shift, cprev, cnext, gv, R1.jc);
-          } else if constexpr (JCacheOf<E>::kOn) {
-            e.apply_c(Pv, Sv, Fv, col, y1r, gv, R1.jc);
+            e.apply_stream(Pv, Sv, Fv, Av, shift, cprev, cnext, gv, R1.jc);
+            e.diag_stream(Sv, Fv, Av, dg);
           } else {
-            e.apply(Pv, Sv, Fv, col, y1r, gv);
+            if constexpr (JCacheOf<E>::kOn) {
+              e.apply_c(Pv, Sv, Fv, col, y1r, gv, R1.jc);
+            } else {
+              e.apply(Pv, Sv, Fv, col, y1r, gv);
+            }
+            e.diag(Sv, Fv, dg);
           }
-          e.diag(Sv, Fv, dg);
           return 0;
         });
         const bool act = R1.f & E::ACTIVE;
@@ -660,9 +673,9 @@ __device__ __forceinline__ void run(const FusedArgs<E, DAMP>& a, VG g, int iter)
         // row y - 2 dir is final: partial of delta = |J u|^2 (+ u.(lambda D) u),
         // and the stores of d, u, p
         const int yo = y - 2 * dir;
-        const T jq = with_views(R3, R2, R1, selu, [&](auto Pv, auto Sv, auto Fv) {
+        const T jq = with_views(R3, R2, R1, selu, [&](auto Pv, auto Sv, auto Fv, auto Av) {
           if constexpr (JCacheOf<E>::kOn) {
-            return e.jsq_c(Pv, Fv, R2.jc);
+            return e.jsq_c(Pv, Fv, Av, R2.jc);
           } else {
             return e.jsq(Pv, Sv, Fv, col, yo);
           }
