@@ -79,6 +79,56 @@ __device__ __forceinline__ double reduce_partials(const double* __restrict__ par
   return total;
 }
 
+// block_sum of two values at once (one pair of barriers); each result has the
+// bits block_sum gives it alone.  Valid in thread 0 only.
+__device__ __forceinline__ void block_sum2(double a, double b, double* ta, double* tb) {
+  __shared__ double wsum[2][kWaves];
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) {
+    a += __shfl_down(a, off, 64);
+    b += __shfl_down(b, off, 64);
+  }
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  if (lane == 0) {
+    wsum[0][w] = a;
+    wsum[1][w] = b;
+  }
+  __syncthreads();
+  double sa = 0.0, sb = 0.0;
+  if (threadIdx.x == 0) {
+#pragma unroll
+    for (int k = 0; k < kWaves; ++k) {
+      sa += wsum[0][k];
+      sb += wsum[1][k];
+    }
+  }
+  __syncthreads();
+  *ta = sa;
+  *tb = sb;
+}
+
+// reduce_partials of two arrays in one pass (their loads are issued together);
+// each result has the bits reduce_partials gives it alone.  Returned to every
+// thread of the block.
+__device__ __forceinline__ void reduce_partials2(const double* __restrict__ pa, const double* __restrict__ pb,
+                                                 int n, double* ta, double* tb) {
+  __shared__ double total[2];
+  double a = 0.0, b = 0.0;
+  for (int k = threadIdx.x; k < n; k += kBlock) {
+    a += pa[k];
+    b += pb[k];
+  }
+  double sa, sb;
+  block_sum2(a, b, &sa, &sb);
+  if (threadIdx.x == 0) {
+    total[0] = sa;
+    total[1] = sb;
+  }
+  __syncthreads();
+  *ta = total[0];
+  *tb = total[1];
+}
+
 __device__ __forceinline__ bool is_block_leader(VG g) { return g.bid == 0 && threadIdx.x == 0; }
 
 // 1/x: the hardware reciprocal in FP32 (within 1 ulp; every kernel forms M^-1

@@ -556,8 +556,8 @@ __device__ __forceinline__ void run(const FusedArgs<E, DAMP>& a, VG g, int iter)
   double* part_out = pick(a.b.part, iter & 1);
   double alpha = 0.0, beta = 0.0, alpha_prev = 0.0;
   if (iter >= 0) {
-    const double gam = reduce_partials(part_in, a.n_part);
-    const double del = reduce_partials(part_in + kMaxBlocks, a.n_part);
+    double gam, del;
+    reduce_partials2(part_in, part_in + kMaxBlocks, a.n_part, &gam, &del);
     double den = del;
     if (iter > 0) {
       beta = gam / S->gam[(iter - 1) & 1];
@@ -702,8 +702,8 @@ __device__ __forceinline__ void run(const FusedArgs<E, DAMP>& a, VG g, int iter)
       });
     }
   }
-  const double gs = block_sum(g_acc);
-  const double ds = block_sum(d_acc);
+  double gs, ds;
+  block_sum2(g_acc, d_acc, &gs, &ds);
   if (threadIdx.x == 0) {
     part_out[g.bid] = gs;
     part_out[kMaxBlocks + g.bid] = ds;
