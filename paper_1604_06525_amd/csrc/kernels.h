@@ -548,22 +548,28 @@ __device__ __forceinline__ void run(const FusedArgs<E, DAMP>& a, VG g, int iter)
 #pragma unroll
   for (int k = 0; k < kPrefetch; ++k) issue(ring[k], ybeg + dir * k);
 
+  // The scalars that earlier launches left, read together up front.
   // S->stopped holds 1 + the iteration at which the PCG stopped; the blocks of
-  // that launch all take the stop path (a sibling may already have set it).
+  // that launch all take the stop path (a sibling may already have set it, so
+  // a block only returns here for a stop of an earlier launch).
   const int stopped_at = S->stopped;
-  if ((stopped_at != 0 && stopped_at != iter + 1) || (a.lm_gate && S->done)) return;
+  const int lm_done = a.lm_gate ? S->done : 0;
+  const double gam_old = iter > 0 ? S->gam[(iter - 1) & 1] : 1.0;
+  const double alpha_old = iter > 0 ? S->alpha[(iter - 1) & 1] : 1.0;
+  const double lam_now = a.lm_gate ? S->lambda : 0.0;
+  if ((stopped_at != 0 && stopped_at != iter + 1) || lm_done) return;
   const double* part_in = pick(a.b.part, (iter + 1) & 1);
   double* part_out = pick(a.b.part, iter & 1);
-  double alpha = 0.0, beta = 0.0, alpha_prev = 0.0;
+  double alpha = 0.0, beta = 0.0;
+  const double alpha_prev = (iter & 1) ? alpha_old : 0.0;
   if (iter >= 0) {
     double gam, del;
     reduce_partials2(part_in, part_in + kMaxBlocks, a.n_part, &gam, &del);
     double den = del;
     if (iter > 0) {
-      beta = gam / S->gam[(iter - 1) & 1];
-      den = del - beta * gam / S->alpha[(iter - 1) & 1];
+      beta = gam / gam_old;
+      den = del - beta * gam / alpha_old;
     }
-    if (iter & 1) alpha_prev = S->alpha[(iter - 1) & 1];
     if (!(den > 0.0)) {
       if (is_block_leader(g)) S->stopped = iter + 1;
       if ((iter & 1) && out_lane) {
@@ -590,7 +596,7 @@ __device__ __forceinline__ void run(const FusedArgs<E, DAMP>& a, VG g, int iter)
   }
   const T aT = (T)alpha, bT = (T)beta, apT = (T)alpha_prev;
   Precond<T> pc = a.pc;
-  if (a.lm_gate) pc.lam = (T)S->lambda;
+  if (a.lm_gate) pc.lam = (T)lam_now;
   double g_acc = 0.0, d_acc = 0.0;
 
   if (has_strip) {
