@@ -233,7 +233,8 @@ __device__ __forceinline__ void buf_loadv(const Buf<T>& b, unsigned voff, unsign
   __builtin_memcpy(out, d, sizeof(d));
 }
 
-template <int K, typename T>
+// AUX: the cache-policy bits of the store instruction (0: default).
+template <int K, int AUX = 0, typename T>
 __device__ __forceinline__ void buf_storev(const Buf<T>& b, unsigned voff, unsigned soff, const T* in) {
   typedef unsigned u2 __attribute__((ext_vector_type(2)));
   typedef unsigned u3 __attribute__((ext_vector_type(3)));
@@ -246,18 +247,18 @@ __device__ __forceinline__ void buf_storev(const Buf<T>& b, unsigned voff, unsig
   for (; i + 4 <= W; i += 4) {
     u4 v;
     v.x = d[i]; v.y = d[i + 1]; v.z = d[i + 2]; v.w = d[i + 3];
-    __builtin_amdgcn_raw_buffer_store_b128(v, b.rs, voff + 4 * i, soff, 0);
+    __builtin_amdgcn_raw_buffer_store_b128(v, b.rs, voff + 4 * i, soff, AUX);
   }
   if constexpr (W % 4 == 3) {
     u3 v;
     v.x = d[W - 3]; v.y = d[W - 2]; v.z = d[W - 1];
-    __builtin_amdgcn_raw_buffer_store_b96(v, b.rs, voff + 4 * (W - 3), soff, 0);
+    __builtin_amdgcn_raw_buffer_store_b96(v, b.rs, voff + 4 * (W - 3), soff, AUX);
   } else if constexpr (W % 4 == 2) {
     u2 v;
     v.x = d[W - 2]; v.y = d[W - 1];
-    __builtin_amdgcn_raw_buffer_store_b64(v, b.rs, voff + 4 * (W - 2), soff, 0);
+    __builtin_amdgcn_raw_buffer_store_b64(v, b.rs, voff + 4 * (W - 2), soff, AUX);
   } else if constexpr (W % 4 == 1) {
-    __builtin_amdgcn_raw_buffer_store_b32(d[W - 1], b.rs, voff + 4 * (W - 1), soff, 0);
+    __builtin_amdgcn_raw_buffer_store_b32(d[W - 1], b.rs, voff + 4 * (W - 1), soff, AUX);
   }
   (void)i;
 }

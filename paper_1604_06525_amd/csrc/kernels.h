@@ -460,6 +460,15 @@ struct FusedArgs {
 };
 
 // f(integral_constant<int, I>) for each I of the sequence, in order.
+// Cache policy of the fused kernel's vector stores: device scope (the stores
+// write through to the level every XCD sees, so little is left to write back
+// when the kernel ends; measured about 1% faster than the default, while the
+// non-temporal hint was 10% slower).
+#ifndef OPT_FUSED_STORE_AUX
+#define OPT_FUSED_STORE_AUX 16
+#endif
+constexpr int kFusedStoreAux = OPT_FUSED_STORE_AUX;
+
 template <int... I, class F>
 __device__ __forceinline__ void unroll_seq(std::integer_sequence<int, I...>, F f) {
   (f(std::integral_constant<int, I>{}), ...);
@@ -697,9 +706,9 @@ __device__ __forceinline__ void run(const FusedArgs<E, DAMP>& a, VG g, int iter)
           const T xo = xtwo ? fma(apT, R2.po[c], R2.x[c]) : R2.x[c];
           xv[c] = fma(aT, pv[c], xo);
         }
-        buf_storev<C>(Bx, ox, 0, xv);
-        buf_storev<C>(Buout, o, 0, R2.u);
-        buf_storev<C>(Bpout, o, 0, pv);
+        buf_storev<C, kFusedStoreAux>(Bx, ox, 0, xv);
+        buf_storev<C, kFusedStoreAux>(Buout, o, 0, R2.u);
+        buf_storev<C, kFusedStoreAux>(Bpout, o, 0, pv);
       }
     };
     for (int k = 0; k < K; k += N) {
