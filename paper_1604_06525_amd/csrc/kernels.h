@@ -460,14 +460,13 @@ struct FusedArgs {
 };
 
 // f(integral_constant<int, I>) for each I of the sequence, in order.
-// Cache policy of the fused kernel's vector stores: device scope (the stores
-// write through to the level every XCD sees, so little is left to write back
-// when the kernel ends; measured about 1% faster than the default, while the
-// non-temporal hint was 10% slower).
-#ifndef OPT_FUSED_STORE_AUX
-#define OPT_FUSED_STORE_AUX 16
-#endif
-constexpr int kFusedStoreAux = OPT_FUSED_STORE_AUX;
+// Cache policy of the fused kernel's vector stores.  FP32 rows: device scope
+// (the stores write through to the level every XCD sees, so little is left to
+// write back when the kernel ends; measured 1-9% faster than the default, the
+// non-temporal hint 10% slower).  FP64 rows: the default (device scope made
+// those launches 40-70% slower).
+template <typename T>
+constexpr int kFusedStoreAux = sizeof(T) == 4 ? 16 : 0;
 
 template <int... I, class F>
 __device__ __forceinline__ void unroll_seq(std::integer_sequence<int, I...>, F f) {
@@ -706,9 +705,9 @@ __device__ __forceinline__ void run(const FusedArgs<E, DAMP>& a, VG g, int iter)
           const T xo = xtwo ? fma(apT, R2.po[c], R2.x[c]) : R2.x[c];
           xv[c] = fma(aT, pv[c], xo);
         }
-        buf_storev<C, kFusedStoreAux>(Bx, ox, 0, xv);
-        buf_storev<C, kFusedStoreAux>(Buout, o, 0, R2.u);
-        buf_storev<C, kFusedStoreAux>(Bpout, o, 0, pv);
+        buf_storev<C, kFusedStoreAux<T>>(Bx, ox, 0, xv);
+        buf_storev<C, kFusedStoreAux<T>>(Buout, o, 0, R2.u);
+        buf_storev<C, kFusedStoreAux<T>>(Bpout, o, 0, pv);
       }
     };
     for (int k = 0; k < K; k += N) {
