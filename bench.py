@@ -2,6 +2,7 @@
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
     python bench.py --serve [--serve-requests N]
+    python bench.py --configs all
 
 A step is one whole solve: ARAP image warping on a 1024 x 1024 pixel grid
 (3 unknowns per pixel, 8,192 positional constraints), Gauss-Newton 10 outer x 50
@@ -16,6 +17,11 @@ algorithmic bytes of an iteration (p, d and r each read and written once per
 unknown, plus the per-pixel angle, rest position and flags).  ``cpu_baseline`` is the
 FP64 oracle (explicit sparse Jacobian, scipy) on one outer iteration of the same
 workload on the host.
+
+``--configs all`` measures every configuration of the measurement table instead
+(ARAP warp 64^2 FP64 and 1024^2 mixed/FP64, shape from shading 1024^2, ARAP
+icosphere meshes of levels 7 and 8, optical flow 1920x1080 mixed/FP64, Poisson
+1024^2): one JSON line each, not the contract line.
 
 ``--serve`` measures the batching server instead: a seeded Poisson-arrival
 stream of mixed requests (ARAP warps and Poisson edits on grids of side
@@ -50,6 +56,8 @@ def parse():
     ap.add_argument("--serve", action="store_true")
     ap.add_argument("--serve-requests", type=int, default=200)
     ap.add_argument("--serve-loads", type=str, default="0.25,0.5,0.75,0.9,1.0,1.2")
+    ap.add_argument("--configs", type=str, default="",
+                    help="'all' or a comma list: per-configuration PCG rates instead of the headline line")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run device copies of a known size (to scale memory counters)")
     return ap.parse_args()
@@ -275,6 +283,88 @@ def serve_main(args):
     print(json.dumps(out), flush=True)
 
 
+# The configurations of the measurement table (besides the headline warp run):
+# name, generator, precision, method, outer, inner, algorithmic bytes per PCG
+# iteration as (bytes per unknown, bytes per site) for FP32 bulk; FP64 doubles
+# the per-unknown part.
+CONFIGS = [
+    ("warp_64x64_gn5x20_fp64", lambda w: w.arap_warp(64, 64, seed=1), "fp64", "gn", 5, 20, (24, 13)),
+    ("warp_1024x1024_gn10x50_mixed", lambda w: w.arap_warp(1024, 1024, seed=2), "mixed", "gn", 10, 50, (24, 13)),
+    ("warp_1024x1024_gn10x50_fp64", lambda w: w.arap_warp(1024, 1024, seed=2), "fp64", "gn", 10, 50, (24, 13)),
+    ("sfs_1024x1024_gn10x50_mixed", lambda w: w.shape_from_shading(1024, 1024, seed=2), "mixed", "gn", 10, 50, (24, 13)),
+    ("mesh_icosphere7_lm10x40_mixed", lambda w: w.arap_mesh(7, seed=3), "mixed", "lm", 10, 40, (24, 52)),
+    ("mesh_icosphere8_lm10x40_mixed", lambda w: w.arap_mesh(8, seed=3), "mixed", "lm", 10, 40, (24, 52)),
+    ("flow_1920x1080_gn10x50_mixed", lambda w: w.optical_flow(1920, 1080, seed=4), "mixed", "gn", 10, 50, (24, 8)),
+    ("flow_1920x1080_gn10x50_fp64", lambda w: w.optical_flow(1920, 1080, seed=4), "fp64", "gn", 10, 50, (24, 8)),
+    ("poisson_1024x1024_gn10x50_mixed", lambda w: w.poisson_edit(1024, 1024, seed=5), "mixed", "gn", 10, 50, (24, 1)),
+]
+
+
+def pcg_form(energy, channels, n, prec):
+    """Which PCG form the library runs by default: a fused kernel for grid
+    energies (each internal vector under 256 MB), the split form for graphs."""
+    tsize = 8 if prec == "fp64" else 4
+    ok = energy in ("arap_warp", "poisson", "flow", "laplacian", "sfs") and channels * n * tsize <= (1 << 28)
+    return "fused" if ok else "split"
+
+
+def configs_main(args):
+    """One JSON line per configuration: PCG iterations/s over the PCG phases,
+    the per-iteration time against the algorithmic bytes, and the whole-solve
+    time (median of `steps` solves after `warmup`)."""
+    import torch
+    import paper_1604_06525_amd as pkg
+    import workloads
+    from workloads.layout import problem_args
+    dev = torch.device("cuda:0")
+    only = set(args.configs.split(",")) if args.configs != "all" else None
+    for name, gen, prec, method, outer, inner, (bu, bs) in CONFIGS:
+        if only and name not in only:
+            continue
+        d = gen(workloads)
+        dt = np.float64 if prec == "fp64" else np.float32
+        energy, arrs, params, dims = problem_args(d, dt)
+        if "edges" in dims:
+            dims = dict(dims, edges=torch.from_numpy(dims["edges"]).to(dev))
+        prob = pkg.Problem(energy, [torch.from_numpy(a).to(dev) for a in arrs], params, precision=prec, **dims)
+        x0 = torch.from_numpy(np.ascontiguousarray(np.asarray(d["x0"], dt).reshape(prob.channels, -1))).to(dev)
+        sp = pkg.default_params(method=method, outer_iters=outer, pcg_iters=inner)
+        x = x0.clone()
+        for _ in range(args.warmup):
+            x.copy_(x0)
+            prob.solve(x, params=sp, report=False)
+        torch.cuda.synchronize()
+        prob.profile_enable(True)
+        prob.profile_read()
+        solve_ms = []
+        stream = torch.cuda.current_stream()
+        for _ in range(args.steps):
+            x.copy_(x0)
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            prob.solve(x, params=sp, report=False)
+            e1.record(stream)
+            torch.cuda.synchronize()
+            solve_ms.append(e0.elapsed_time(e1))
+        pcg_ms, pcg_iters = prob.profile_read()
+        prob.profile_enable(False)
+        n = prob.n_sites
+        N = n * prob.channels
+        per_unknown = bu * (2 if prec == "fp64" else 1)
+        bpi = per_unknown * N + bs * n
+        iter_us = 1e3 * pcg_ms / pcg_iters
+        achieved = bpi / (iter_us * 1e-6) / 1e9
+        rep = prob.solve(x.copy_(x0), params=sp)
+        print(json.dumps({"config": name, "sites": n, "unknowns": N, "precision": prec, "method": method,
+                          "outer_iters": outer, "pcg_iters": inner, "pcg_form": pcg_form(energy, prob.channels, n, prec),
+                          "pcg_iters_per_s": pcg_iters / (pcg_ms / 1e3), "iter_us": iter_us,
+                          "bytes_per_iter": bpi, "achieved_GBs": achieved, "frac_of_8TBs": achieved / HBM_PEAK_GBS,
+                          "solve_ms_median": float(np.median(solve_ms)), "cost_initial": rep["cost_initial"],
+                          "cost_final": rep["cost_final"], "launch": prob.get_tuning()}), flush=True)
+        del prob
+        torch.cuda.synchronize()
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -286,6 +376,9 @@ def main():
         return
     if args.copy_calibration:
         copy_calibration()
+        return
+    if args.configs:
+        configs_main(args)
         return
     import torch
     import paper_1604_06525_amd as pkg

@@ -443,6 +443,7 @@ struct FusedBufs {
   T* x;            // the PCG solution d, updated in place
   double* part[2]; // [gamma | delta] partials, kMaxBlocks apart; iteration i writes
                    // part[i & 1] (the priming launch writes part[1]) and reads the other
+  const T* diag;   // diag(J^T J) from init (read by energies that do not recompute it)
 };
 
 template <class E, bool DAMP>

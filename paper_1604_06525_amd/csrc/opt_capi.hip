@@ -16,6 +16,7 @@
 #include "opt.h"
 #include "host.h"
 #include "energies.h"
+#include "fused_sfs.h"
 
 namespace optmi {
 namespace host {
@@ -115,8 +116,9 @@ int check_desc(const opt_problem_desc* d, Shape* sh) {
     if (!grid_energy) return fail(OPT_EUNSUPPORTED, "energy %d needs the graph domain", d->energy);
     if (d->width < 1 || d->height < 1)
       return fail(OPT_EINVAL, "grid size %d x %d must be positive", d->width, d->height);
-    if (d->width > kStripCols * kWaves * kMaxBlocks)
-      return fail(OPT_EINVAL, "grid width %d exceeds %d", d->width, kStripCols * kWaves * kMaxBlocks);
+    // (every fused kernel's strips of one grid row fit in the partial-sum buffers)
+    if (d->width > kSfsCols * kWaves * kMaxBlocks)
+      return fail(OPT_EINVAL, "grid width %d exceeds %d", d->width, kSfsCols * kWaves * kMaxBlocks);
     if ((long long)d->width * d->height > (1LL << 30))
       return fail(OPT_EINVAL, "grid of %lld sites is too large", (long long)d->width * d->height);
     sh->n = d->width * d->height;
@@ -157,9 +159,9 @@ namespace {
 // lets each SIMD overlap one strip's memory waits with the other's arithmetic).
 constexpr int kAutoWavesPerSimd = 2;
 
-StripGeom strip_geom(int W, int H, const opt_tuning& t, int n_simd, int occupancy) {
+StripGeom strip_geom(int W, int H, const opt_tuning& t, int n_simd, int occupancy, int cols) {
   StripGeom g;
-  g.n_sx = (W + kStripCols - 1) / kStripCols;
+  g.n_sx = (W + cols - 1) / cols;
   g.sw = (W + g.n_sx - 1) / g.n_sx;
   const int max_sy = std::max(1, H / 4);
   int n_sy;
@@ -182,6 +184,11 @@ template <class E>
 class ImplT final : public Impl {
  public:
   using T = typename E::Real;
+  // fused PCG kernels: the generic one (grid operators of radius 1) and the
+  // residual-streaming one for shape from shading (radius 2)
+  static constexpr bool kSfs = std::is_same_v<E, ShapeFromShading<T>>;
+  static constexpr bool kFusedOk = !E::kGraph && (E::kRadius == 1 || kSfs);
+  static constexpr int kCols = kSfs ? kSfsCols : kStripCols;
   ImplT(opt_problem* p, const E& e) : p_(p), e_(e) {}
 
   Precond<T> pc(PrecondArgs a) const {
@@ -284,12 +291,12 @@ class ImplT final : public Impl {
     if constexpr (E::kGraph) {
       (void)damped;
       return StripGeom{};
-    } else if constexpr (E::kRadius != 1) {
+    } else if constexpr (!kFusedOk) {
       (void)damped;
-      return strip_geom(e_.W, e_.H, p_->tune, p_->n_simd, 1);
+      return strip_geom(e_.W, e_.H, p_->tune, p_->n_simd, 1, kStripCols);
     } else {
       return strip_geom(e_.W, e_.H, p_->tune, p_->n_simd,
-                        damped ? fused_occupancy<true>() : fused_occupancy<false>());
+                        damped ? fused_occupancy<true>() : fused_occupancy<false>(), kCols);
     }
   }
 
@@ -305,6 +312,7 @@ class ImplT final : public Impl {
     a.b.x = vec(p_->L.delta);
     a.b.part[0] = p_->part(P_F0);
     a.b.part[1] = p_->part(P_F1);
+    a.b.diag = vec(p_->L.diag);
     a.pc = pc(pa);
     a.n_part = g.grid;
     a.S = p_->S();
@@ -367,12 +375,12 @@ class ImplT final : public Impl {
   }
   // The fused kernel addresses each vector through a raw buffer of < 256 MB.
   bool has_fused() const override {
-    return E::kRadius == 1 && !E::kGraph && (size_t)E::C * e_.n * sizeof(T) <= (size_t(1) << 28);
+    return kFusedOk && (size_t)E::C * e_.n * sizeof(T) <= (size_t(1) << 28);
   }
   // iter = -1 is the priming launch (it writes only partials).
   int fused(int iter, int L, PrecondArgs pa, int lm) override {
-    if constexpr (E::kRadius != 1 || E::kGraph) {
-      return fail(OPT_EUNSUPPORTED, "the fused PCG kernel needs an operator of radius 1");
+    if constexpr (!kFusedOk) {
+      return fail(OPT_EUNSUPPORTED, "no fused PCG kernel for this energy");
     } else {
       int grid = 0;
       if (pa.damped) return go(ROW_FUSED, fused_args<true>(L, pa, lm, &grid), grid, iter, "fused");
@@ -397,7 +405,7 @@ class ImplT final : public Impl {
   double gpu_fill(bool use_fused, bool damped) const override {
     double waves = (double)nblk() * kWaves;
     int occ = 2;
-    if constexpr (E::kRadius == 1 && !E::kGraph) {
+    if constexpr (kFusedOk) {
       if (use_fused && has_fused()) {
         const StripGeom g = geom(damped);
         waves = (double)g.n_sx * g.n_sy;
@@ -445,8 +453,8 @@ class ImplT final : public Impl {
         }, 0, 1, "init[batch]");
       case Stage::PCG:
         if (use_fused) {
-          if constexpr (E::kRadius != 1 || E::kGraph) {
-            return fail(OPT_EUNSUPPORTED, "the fused PCG kernel needs an operator of radius 1");
+          if constexpr (!kFusedOk) {
+            return fail(OPT_EUNSUPPORTED, "no fused PCG kernel for this energy");
           } else {
             // one group holds problems of one method (the server keys groups by
             // it), so the damping form is the same for all
