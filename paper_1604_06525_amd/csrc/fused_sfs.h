@@ -38,6 +38,7 @@ struct SfsRow {
   T JB, gh, gv, G;    // shading terms along p
   T s0, s1, s2;       // smoothness J p (0 where that residual is not valid)
   T JBu;              // shading derivative along u_{i+1}
+  T ky;               // k_y of this row (one FP64 division per row)
 };
 
 template <typename T, bool DAMP>
@@ -85,7 +86,7 @@ __device__ __forceinline__ void run(const FusedArgs<ShapeFromShading<T>, DAMP>& 
     Row& R = ring[k];
     R.u = R.p = R.po = R.x = R.dg = R.dB0 = R.dBl = R.dBu = T(0);
     R.f = 0;
-    R.JB = R.gh = R.gv = R.G = R.s0 = R.s1 = R.s2 = R.JBu = T(0);
+    R.JB = R.gh = R.gv = R.G = R.s0 = R.s1 = R.s2 = R.JBu = R.ky = T(0);
   }
   auto issue = [&](Row& R, int y) {
     const bool in = y >= ylo && y <= yhi;
@@ -161,24 +162,26 @@ __device__ __forceinline__ void run(const FusedArgs<ShapeFromShading<T>, DAMP>& 
       Row& R4 = ring[(ph + N - 4) % N];  // y - 4
       const int y = y0 - 3 + k;
       issue(ring[(ph + kPrefetch) % N], y + kPrefetch);
+      // Each part runs only on the rows the produced rows need (uniform tests).
       // row y: p_i = u_i + beta p_{i-1} (beta is 0 and p_{i-1} reads 0 at
-      // iteration 0), JB and gh
+      // iteration 0), JB and gh (rows y0-2 .. y1+2)
       R0.po = R0.p;
       R0.p = fma(bT, R0.p, R0.u);
-      R0.JB = fma(R0.dB0, R0.p, fma(R0.dBl, from_left(R0.p), R0.dBu * R1.p));
-      {
+      R0.ky = kyT(y);
+      if (k >= 1) {
+        R0.JB = fma(R0.dB0, R0.p, fma(R0.dBl, from_left(R0.p), R0.dBu * R1.p));
         const uint32_t f = R0.f;
         const T eh = ((f & E::IBE) && (f & E::ER)) ? T(1) : T(0);
         R0.gh = eh * (R0.JB - from_right(R0.JB));
       }
-      if (k >= 1) {
+      if (k >= 2) {
         // row y - 1: gv, G, smoothness J p
         const uint32_t f = R1.f;
         const T ev = ((f & E::IBE) && (f & E::EC)) ? T(1) : T(0);
         R1.gv = ev * (R1.JB - R0.JB);
         R1.G = (R1.gh - from_left(R1.gh)) + (R1.gv - R2.gv);
         const T p0 = R1.p, pl = from_left(R1.p), pr = from_right(R1.p), pu = R2.p, pd = R0.p;
-        const T kyb = kyT(y - 1), kyu = kyT(y - 2), kyd = kyT(y);
+        const T kyb = R1.ky, kyu = R2.ky, kyd = R0.ky;
         const bool vs = f & E::VS;
         R1.s0 = vs ? T(4) * kxc * p0 - kxl * pl - kxc * pu - kxr * pr - kxc * pd : T(0);
         R1.s1 = vs ? T(4) * kyb * p0 - kyb * pl - kyu * pu - kyb * pr - kyd * pd : T(0);
@@ -190,10 +193,11 @@ __device__ __forceinline__ void run(const FusedArgs<ShapeFromShading<T>, DAMP>& 
                                  : kBufOutOfRange;
         R1.x = Bx.load(ox, 0);
       }
-      if (k >= 2) {
-        // row y - 2: q = J^T J p (+ lambda D p), u_{i+1}, gamma, stores
+      if (k >= 4) {
+        // row y - 2 (rows y0-1 .. y1): q = J^T J p (+ lambda D p), u_{i+1},
+        // gamma, stores
         const int y2 = y - 2;
-        const T ky = kyT(y2);
+        const T ky = R2.ky;
         const T sh = fma(R2.dB0, R2.G, fma(R1.dBu, R1.G, from_right(R2.dBl * R2.G)));
         const T sl0 = from_left(R2.s0), sr0 = from_right(R2.s0);
         const T sl1 = from_left(R2.s1), sr1 = from_right(R2.s1);
@@ -225,8 +229,9 @@ __device__ __forceinline__ void run(const FusedArgs<ShapeFromShading<T>, DAMP>& 
         buf_storev<1, kFusedStoreAux<T>>(Buout, o, 0, &R2.u);
         buf_storev<1, kFusedStoreAux<T>>(Bpout, o, 0, &pv);
       }
-      if (k >= 3) {
-        // row y - 3 is final: partial of delta = |J u|^2 over its residuals
+      if (k >= 6) {
+        // row y - 3 (a produced row) is final: partial of delta = |J u|^2 over
+        // its residuals
         const int y3 = y - 3;
         const bool prod = y3 >= y0 && y3 < y1;  // uniform
         const uint32_t f = R3.f;
@@ -235,7 +240,7 @@ __device__ __forceinline__ void run(const FusedArgs<ShapeFromShading<T>, DAMP>& 
         const T ghu = eh * (R3.JBu - from_right(R3.JBu));
         const T gvu = ev * (R3.JBu - R2.JBu);
         const T u0 = R3.u, ul = from_left(R3.u), ur = from_right(R3.u), uu = R4.u, ud = R2.u;
-        const T kyb = kyT(y3), kyu = kyT(y3 - 1), kyd = kyT(y3 + 1);
+        const T kyb = R3.ky, kyu = R4.ky, kyd = R2.ky;
         const bool vs = f & E::VS;
         const T t0 = T(4) * kxc * u0 - kxl * ul - kxc * uu - kxr * ur - kxc * ud;
         const T t1 = T(4) * kyb * u0 - kyb * ul - kyu * uu - kyb * ur - kyd * ud;
