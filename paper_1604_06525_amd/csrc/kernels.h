@@ -50,10 +50,22 @@ __device__ __forceinline__ P pick(P const (&pair)[2], int i) {
   return i ? pair[1] : pair[0];
 }
 
+// The unit of work of a block, XCD-aware: blocks go to the 8 XCDs round-robin
+// (block b to XCD b % 8), and each XCD takes one contiguous run of units, so
+// neighbouring sites (grid rows, Morton-ordered graph vertices) share its L2.
+// XCD x holds q + (x < r) of the nb blocks (q = nb / 8, r = nb % 8); the map is
+// a bijection of [0, nb).  (In a batch the hardware placement differs; only
+// speed depends on it.)
+__device__ __forceinline__ int unit_of_block(VG g) {
+  const int q = g.nb >> 3, r = g.nb & 7, x = g.bid & 7;
+  return x * q + min(x, r) + (g.bid >> 3);
+}
+
 // Grid-stride loop over sites with a fixed per-thread order (the grid size
-// depends only on n), so the partial sums are reproducible.
+// depends only on n), so the partial sums are reproducible; block b takes the
+// chunks unit_of_block(b), + nb, ...
 #define OPT_SITE_LOOP(s, n, g) \
-  for (int s = (g).bid * kBlock + threadIdx.x; s < (n); s += (g).nb * kBlock)
+  for (int s = unit_of_block(g) * kBlock + threadIdx.x; s < (n); s += (g).nb * kBlock)
 
 // Views over global memory centred at site s = (vi_, vj_) of a W x H grid; every
 // read off the grid returns 0 (flags 0: not on the grid).
@@ -426,15 +438,6 @@ __device__ __forceinline__ auto with_views(const StreamRow<E, DAMP>& U, const St
   return body(Pv, Sv, Fv, Av);
 }
 
-// The unit of work of a block, XCD-aware: blocks go to the 8 XCDs round-robin
-// (block b to XCD b % 8), and each XCD takes one contiguous run of units, so
-// neighbouring strips share its L2.  XCD x holds q + (x < r) of the nb blocks
-// (q = nb / 8, r = nb % 8); the map is a bijection of [0, nb).  (In a batch the
-// hardware placement differs; only speed depends on it.)
-__device__ __forceinline__ int unit_of_block(VG g) {
-  const int q = g.nb >> 3, r = g.nb & 7, x = g.bid & 7;
-  return x * q + min(x, r) + (g.bid >> 3);
-}
 
 template <typename T>
 struct FusedBufs {
