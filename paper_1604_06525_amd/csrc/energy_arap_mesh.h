@@ -85,9 +85,10 @@ struct ArapMesh {
 
   __device__ __forceinline__ T state_at(int k, int v) const { return trig[(size_t)v * 6 + k]; }
 
-  __device__ __forceinline__ EulerTrig<T> trig_at(int v) const {
+  __device__ __forceinline__ EulerTrig<T> trig_at(int v) const { return trig_from(trig + (size_t)v * 6); }
+  // the six state values of a vertex (cos, sin of a_x, a_y, a_z) at q
+  __device__ __forceinline__ static EulerTrig<T> trig_from(const T* q) {
     EulerTrig<T> t;
-    const T* q = trig + (size_t)v * 6;
     t.cx = q[0];
     t.sx = q[1];
     t.cy = q[2];
@@ -195,7 +196,14 @@ struct ArapMesh {
   // g = J^T J P at vertex v; P(c, site) reads the direction.
   template <class PA>
   __device__ __forceinline__ void apply_site(PA P, int v, T* g) const {
-    const EulerTrig<T> tv = trig_at(v);
+    apply_site_v(P, [&](int u) { return trig_at(u); }, [&](int c, int u) { return U[(size_t)c * n + u]; }, v, g);
+  }
+
+  // apply_site with the neighbours' state and rest positions read through
+  // TA(u) (an EulerTrig) and UA(c, u) (a staged copy, say).
+  template <class PA, class TA, class UA>
+  __device__ __forceinline__ void apply_site_v(PA P, TA Tr, UA Uv, int v, T* g) const {
+    const EulerTrig<T> tv = Tr(v);
     T pO[3], pa[3];
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
@@ -206,10 +214,10 @@ struct ArapMesh {
     const T wr2 = wr * wr;
     for (int k = rp[v]; k < rp[v + 1]; ++k) {
       const int u = nb[k];
-      const EulerTrig<T> tu = trig_at(u);
+      const EulerTrig<T> tu = Tr(u);
       T d[3], Rv[3], Gv[3][3], Ru[3], Gu[3][3];
 #pragma unroll
-      for (int c = 0; c < 3; ++c) d[c] = U[(size_t)c * n + v] - U[(size_t)c * n + u];
+      for (int c = 0; c < 3; ++c) d[c] = Uv(c, v) - Uv(c, u);
       euler_rot_grad(tv, d, Rv, Gv);
       euler_rot_grad(tu, d, Ru, Gu);
       T qa[3];

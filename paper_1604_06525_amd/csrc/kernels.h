@@ -264,22 +264,69 @@ __device__ __forceinline__ void run(const SplitAArgs<E, MODE>& a, VG g, int k) {
     return k == 0 ? z : fma(beta, pold[o], z);
   };
   double pq = 0.0;
-  OPT_SITE_LOOP(s, n, g) {
-    T gv[C];
-    const bool act = a.e.flags[s] & E::ACTIVE;
-    if (act) site_apply(a.e, s, Pg, gv);
+  // p, q and the partial of p.q at site s, given its p (pv) and (J^T J p)_s
+  auto finish = [&](int s, bool act, const T* pv_in, const T* gv) {
 #pragma unroll
     for (int c = 0; c < C; ++c) {
       const size_t o = vix<C>(c, s);
       T pv = T(0), qv = T(0);
       if (act) {
-        pv = Pg(c, s);
+        pv = pv_in[c];
         qv = gv[c];
         if (b.damp) qv += b.damp[o] * pv;
       }
       if (MODE == 0) pnew[o] = pv;
       b.q[MODE == 1 ? (size_t)c * n + s : o] = qv;
       pq += (double)pv * (double)qv;
+    }
+  };
+  if constexpr (E::kGraph) {
+    // The block's chunk of vertices is staged in LDS first (their p, the
+    // per-vertex state and the rest positions); a neighbour inside the chunk
+    // (about 87% of the edges of a Morton-ordered icosphere at 256 vertices
+    // per chunk) is read from there, the others from global memory.
+    constexpr int NS = E::kStatePlanes;
+    __shared__ T sp[kBlock][C];
+    __shared__ T sst[kBlock][NS];
+    __shared__ T su[kBlock][3];
+    for (int chunk = unit_of_block(g); chunk * kBlock < n; chunk += g.nb) {
+      const int v0 = chunk * kBlock, t = threadIdx.x, v = v0 + t;
+      const bool in = v < n;
+      T pv[C];
+#pragma unroll
+      for (int c = 0; c < C; ++c) pv[c] = in ? Pg(c, v) : T(0);
+      if (in) {
+#pragma unroll
+        for (int c = 0; c < C; ++c) sp[t][c] = pv[c];
+#pragma unroll
+        for (int k2 = 0; k2 < NS; ++k2) sst[t][k2] = a.e.state_at(k2, v);
+#pragma unroll
+        for (int c = 0; c < 3; ++c) su[t][c] = a.e.U[(size_t)c * n + v];
+      }
+      __syncthreads();
+      auto inb = [&](int u) { return u >= v0 && u < v0 + kBlock; };
+      auto Pl = [&](int c, int u) -> T { return inb(u) ? sp[u - v0][c] : Pg(c, u); };
+      auto Tl = [&](int u) {
+        if (!inb(u)) return a.e.trig_at(u);
+        return E::trig_from(sst[u - v0]);
+      };
+      auto Ul = [&](int c, int u) -> T { return inb(u) ? su[u - v0][c] : a.e.U[(size_t)c * n + u]; };
+      const bool act = in && (a.e.flags[v] & E::ACTIVE);
+      T gv[C];
+      if (act) a.e.apply_site_v(Pl, Tl, Ul, v, gv);
+      if (in) finish(v, act, pv, gv);
+      __syncthreads();  // the next chunk reuses the stage
+    }
+  } else {
+    OPT_SITE_LOOP(s, n, g) {
+      T gv[C], pv[C];
+      const bool act = a.e.flags[s] & E::ACTIVE;
+      if (act) {
+        site_apply(a.e, s, Pg, gv);
+#pragma unroll
+        for (int c = 0; c < C; ++c) pv[c] = Pg(c, s);
+      }
+      finish(s, act, pv, gv);
     }
   }
   if (MODE == 0) block_store(pq, b.pq_part, g);
