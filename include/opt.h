@@ -98,6 +98,9 @@ typedef enum { OPT_GN = 0, OPT_LM = 1 } opt_method;
  * OPT_PCG_FUSED: one kernel per iteration, the single-reduction recurrence of
  *   Chronopoulos and Gear (alpha and beta from r.z and (A z).z of the previous
  *   iteration), with A p evaluated exactly; r, p and d each cross HBM once.
+ *   Available for the grid energies (ARAP warp, Poisson, flow; shape
+ *   from shading with its own residual-streaming kernel); a graph problem
+ *   asking for it runs the split form.
  * OPT_PCG_SPLIT: the textbook recurrence (alpha = r.z / p.Ap, then beta), two
  *   kernels per iteration.
  */
@@ -221,7 +224,8 @@ int opt_profile_read(opt_problem* prob, double* pcg_ms, int64_t* pcg_iters);
  * Launch tuning of a problem (no effect on results beyond the order of a few
  * additions: every choice computes the same iterates up to rounding; only the
  * work split changes).  The fused PCG kernel gives each wavefront a strip of at
- * most 60 columns (the grid's width split evenly) and some rows.
+ * most 60 columns (58 for shape from shading; the grid's width split evenly)
+ * and some rows.
  *   strip_rows > 0: strips of that many rows.
  *   waves_per_simd > 0 (and strip_rows == 0): about that many strips per SIMD,
  *     rows split evenly.
