@@ -190,3 +190,29 @@ def test_poisson_one_step_exact():
     xo, costs = o.gauss_newton(e, d["x0"], 1, 400)
     assert abs(rep["cost_trace"][1] - costs[1]) <= 1e-10 * costs[1]
     assert abs(rep["cost_trace"][2] - rep["cost_trace"][1]) <= 1e-10 * rep["cost_trace"][1]
+
+
+@pytest.mark.parametrize("tuning", [dict(strip_rows=1), dict(strip_rows=5), dict(strip_rows=300),
+                                    dict(waves_per_simd=1), dict(waves_per_simd=3)])
+def test_sfs_fused_launch_shapes(tuning):
+    """The shape-from-shading fused kernel walks strips of 58 columns with 3
+    halo rows above and 2 below: every strip partition (one-row strips, strips
+    taller than the grid, ragged last strips) gives the oracle's PCG iterates,
+    plain and with LM damping."""
+    d, x = _sfs(190, 83)
+    e = o.make_energy(d)
+    lin = o.Linearization(e, x)
+    prob = make_problem(d, "fp64")
+    prob.set_tuning(**tuning)
+    xt = to_dev(prob, x)
+    prob.linearize(xt)
+    JTJ = (lin.JT @ lin.J).tocsr()
+    for lam in (0.0, 0.3):
+        D = lin.damping() if lam else np.zeros(lin.diag.size)
+        Mi = lin.minv(True, lam, D) if lam else lin.minv(True)
+        ref, _ = o.pcg(lambda v: lin.apply(v, lam, D) if lam else lin.apply(v), lin.jtf(), Mi, 14)
+        # the oracle's own spread between two evaluation orders bounds what can agree
+        ref2, _ = o.pcg(lambda v: JTJ @ v + lam * D * v, lin.jtf(), Mi, 14)
+        tol = max(1e-9, 100 * relmax(ref2, ref))
+        got = to_np(prob.pcg(14, lam=lam, variant="fused"))
+        assert relmax(got, ref) < tol, (tuning, lam, tol)
