@@ -21,7 +21,8 @@ workload on the host.
 ``--configs all`` measures every configuration of the measurement table instead
 (ARAP warp 64^2 FP64 and 1024^2 mixed/FP64, shape from shading 1024^2, ARAP
 icosphere meshes of levels 7 and 8, optical flow 1920x1080 mixed/FP64, Poisson
-1024^2): one JSON line each, not the contract line.
+1024^2, and the 1024^2 warp with implicit grid vs explicit graph connectivity):
+one JSON line each, not the contract line.
 
 ``--serve`` measures the batching server instead: a seeded Poisson-arrival
 stream of mixed requests (ARAP warps and Poisson edits on grids of side
@@ -297,14 +298,26 @@ CONFIGS = [
     ("flow_1920x1080_gn10x50_mixed", lambda w: w.optical_flow(1920, 1080, seed=4), "mixed", "gn", 10, 50, (24, 8)),
     ("flow_1920x1080_gn10x50_fp64", lambda w: w.optical_flow(1920, 1080, seed=4), "fp64", "gn", 10, 50, (24, 8)),
     ("poisson_1024x1024_gn10x50_mixed", lambda w: w.poisson_edit(1024, 1024, seed=5), "mixed", "gn", 10, 50, (24, 1)),
+    # the warp with explicit connectivity (the lattice's 4-neighbour edge list):
+    # the implicit vs explicit comparison of the paper (Fig. 18, GN 8 x 100)
+    ("warp_1024x1024_gn8x100_mixed", lambda w: w.arap_warp(1024, 1024, seed=2), "mixed", "gn", 8, 100, (24, 13)),
+    ("warp_graph_1024x1024_gn8x100_mixed", lambda w: _as_graph(w.arap_warp(1024, 1024, seed=2)), "mixed", "gn",
+     8, 100, (24, 13)),
 ]
 
 
-def pcg_form(energy, channels, n, prec):
+def _as_graph(d):
+    """A grid workload as a graph: vertex j*W+i, the lattice's 4-neighbour edges."""
+    from workloads.mesh import grid_edges
+    return dict(d, V=d["W"] * d["H"], edges=grid_edges(d["W"], d["H"]))
+
+
+def pcg_form(energy, channels, n, prec, graph=False):
     """Which PCG form the library runs by default: a fused kernel for grid
     energies (each internal vector under 256 MB), the split form for graphs."""
     tsize = 8 if prec == "fp64" else 4
-    ok = energy in ("arap_warp", "poisson", "flow", "laplacian", "sfs") and channels * n * tsize <= (1 << 28)
+    ok = (energy in ("arap_warp", "poisson", "flow", "sfs") and not graph
+          and channels * n * tsize <= (1 << 28))
     return "fused" if ok else "split"
 
 
@@ -356,7 +369,7 @@ def configs_main(args):
         achieved = bpi / (iter_us * 1e-6) / 1e9
         rep = prob.solve(x.copy_(x0), params=sp)
         print(json.dumps({"config": name, "sites": n, "unknowns": N, "precision": prec, "method": method,
-                          "outer_iters": outer, "pcg_iters": inner, "pcg_form": pcg_form(energy, prob.channels, n, prec),
+                          "outer_iters": outer, "pcg_iters": inner, "pcg_form": pcg_form(energy, prob.channels, n, prec, "V" in d),
                           "pcg_iters_per_s": pcg_iters / (pcg_ms / 1e3), "iter_us": iter_us,
                           "bytes_per_iter": bpi, "achieved_GBs": achieved, "frac_of_8TBs": achieved / HBM_PEAK_GBS,
                           "solve_ms_median": float(np.median(solve_ms)), "cost_initial": rep["cost_initial"],

@@ -2,6 +2,7 @@
 #pragma once
 #include "energy_arap_mesh.h"
 #include "energy_arap_warp.h"
+#include "energy_arap_warp_graph.h"
 #include "energy_flow.h"
 #include "energy_poisson.h"
 #include "energy_sfs.h"

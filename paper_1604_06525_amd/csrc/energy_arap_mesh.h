@@ -72,6 +72,7 @@ struct ArapMesh {
   static constexpr int kOwnState = 6;
   static constexpr int kRadius = 1;
   enum : uint32_t { ACTIVE = 1, INGRID = 2, FIT0 = 4 };  // FIT0 << k: component k
+  static constexpr bool kStaged = true;  // pcg_a stages a vertex chunk in LDS (apply_site_v)
 
   int n;                         // vertices
   const int* __restrict__ rp;    // [n+1] CSR offsets

@@ -231,6 +231,12 @@ struct SplitBufs {
   double* pq_part;
 };
 
+// Graph energies whose pcg_a stages a chunk of vertices in LDS (E::kStaged).
+template <class E, class = void>
+struct StagedOf : std::false_type {};
+template <class E>
+struct StagedOf<E, std::void_t<decltype(E::kStaged)>> : std::bool_constant<E::kStaged> {};
+
 template <class E, int MODE>
 struct SplitAArgs {
   E e;
@@ -280,7 +286,7 @@ __device__ __forceinline__ void run(const SplitAArgs<E, MODE>& a, VG g, int k) {
       pq += (double)pv * (double)qv;
     }
   };
-  if constexpr (E::kGraph) {
+  if constexpr (StagedOf<E>::value) {
     // The block's chunk of vertices is staged in LDS first (their p, the
     // per-vertex state and the rest positions); a neighbour inside the chunk
     // (about 87% of the edges of a Morton-ordered icosphere at 256 vertices

@@ -112,6 +112,8 @@ int check_desc(const opt_problem_desc* d, Shape* sh) {
   const int C = energy_channels(d->energy);
   if (C == 0) return fail(OPT_EUNSUPPORTED, "energy %d is not built", d->energy);
   const bool grid_energy = d->energy != OPT_E_ARAP_MESH;
+  // ARAP warping runs on either domain (the graph form takes an edge list)
+  const bool both = d->energy == OPT_E_ARAP_WARP;
   if (d->domain == OPT_GRID2D) {
     if (!grid_energy) return fail(OPT_EUNSUPPORTED, "energy %d needs the graph domain", d->energy);
     if (d->width < 1 || d->height < 1)
@@ -123,7 +125,7 @@ int check_desc(const opt_problem_desc* d, Shape* sh) {
       return fail(OPT_EINVAL, "grid of %lld sites is too large", (long long)d->width * d->height);
     sh->n = d->width * d->height;
   } else if (d->domain == OPT_GRAPH) {
-    if (grid_energy) return fail(OPT_EUNSUPPORTED, "energy %d needs the grid domain", d->energy);
+    if (grid_energy && !both) return fail(OPT_EUNSUPPORTED, "energy %d needs the grid domain", d->energy);
     if (d->n_vertices < 1 || d->n_edges < 0)
       return fail(OPT_EINVAL, "graph of %d vertices and %d edges", d->n_vertices, d->n_edges);
     if (d->n_edges > (1 << 29)) return fail(OPT_EINVAL, "%d edges is too many", d->n_edges);
@@ -525,6 +527,22 @@ std::unique_ptr<Impl> make_impl_t(opt_problem* p) {
   const opt_problem_desc& d = p->desc;
   switch (d.energy) {
     case OPT_E_ARAP_WARP: {
+      if (d.domain == OPT_GRAPH) {
+        ArapWarpGraph<T> e;
+        e.n = p->sh.n;
+        e.rp = (const int*)p->at(p->L.csr);
+        e.nb = e.rp + (p->sh.n + 1);
+        e.U = (const T*)d.arrays[0];
+        e.Ct = (const T*)d.arrays[1];
+        e.mask = (const uint8_t*)d.arrays[2];
+        e.st = (T*)p->at(p->L.state);
+        e.flags = (uint8_t*)p->at(p->L.flags);
+        e.wf = (T)d.params[0];
+        e.wr = (T)d.params[1];
+        e.wf_d = d.params[0];
+        e.wr_d = d.params[1];
+        return std::unique_ptr<Impl>(new ImplT<ArapWarpGraph<T>>(p, e));
+      }
       ArapWarp<T> e;
       e.W = d.width;
       e.H = d.height;

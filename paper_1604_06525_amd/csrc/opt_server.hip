@@ -38,7 +38,7 @@ using namespace optmi::host;
 namespace {
 
 constexpr int kStageKinds = 12;  // table kinds that one step can write
-constexpr int kMaxKinds = 40;    // energy x precision x method x PCG form
+constexpr int kMaxKinds = 56;    // energy form (7) x precision x method x PCG form
 constexpr int kDepth = 3;        // steps in flight
 
 // Arena byte ranges, first fit with coalescing.
@@ -175,10 +175,12 @@ struct opt_server {
 
 namespace {
 
-// Requests that can share one launch: same energy, precision, method (the
-// damped and undamped fused kernels differ) and PCG form; bit 0 is the form.
+// Requests that can share one launch: same energy, domain (ARAP warping has a
+// grid and a graph form), precision, method (the damped and undamped fused
+// kernels differ) and PCG form; bit 0 is the form.
 int key_of(const Slot& s) {
-  return ((s.p->desc.energy * 2 + s.p->desc.precision) * 2 + (s.sp.method == OPT_LM ? 1 : 0)) * 2 +
+  const int dom = s.p->desc.domain == OPT_GRAPH ? 1 : 0;
+  return (((s.p->desc.energy * 2 + dom) * 2 + s.p->desc.precision) * 2 + (s.sp.method == OPT_LM ? 1 : 0)) * 2 +
          (s.fused ? 1 : 0);
 }
 

@@ -63,6 +63,14 @@ def _ws(lib, d):
     return rc, b.value
 
 
+def test_warp_takes_either_domain(lib):
+    """ARAP warping has a grid form and a graph form (an edge list)."""
+    rc, grid = _ws(lib, _desc())
+    assert rc == pkg.OPT_OK
+    rc, graph = _ws(lib, _desc(domain=pkg.GRAPH, V=64 * 48, E=10))
+    assert rc == pkg.OPT_OK and graph > 0
+
+
 def test_workspace_size_valid_and_monotone(lib):
     sizes = []
     for W in (1, 63, 64, 1024):
@@ -86,7 +94,7 @@ def test_workspace_size_valid_and_monotone(lib):
     (dict(n_params=17), pkg.OPT_EINVAL),
     (dict(energy="laplacian", arrays=0), pkg.OPT_EUNSUPPORTED),
     (dict(energy="arap_mesh", arrays=2), pkg.OPT_EUNSUPPORTED),      # graph energy on a grid
-    (dict(domain=pkg.GRAPH, V=10, E=0), pkg.OPT_EUNSUPPORTED),       # grid energy on a graph
+    (dict(energy="poisson", arrays=2, domain=pkg.GRAPH, V=10, E=0), pkg.OPT_EUNSUPPORTED),  # grid-only energy on a graph
     (dict(domain=7), pkg.OPT_EINVAL),
     (dict(W=60 * 4 * 1024 + 1, H=1), pkg.OPT_EINVAL),
     (dict(W=40000, H=40000), pkg.OPT_EINVAL),
