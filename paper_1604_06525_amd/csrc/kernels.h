@@ -368,13 +368,28 @@ __device__ __forceinline__ void run(const SplitBArgs<T, C>& a, VG g, int k) {
   const T* p = pick(a.p, k & 1);
   double rz = 0.0;
   OPT_SITE_LOOP(s, a.n, g) {
+    // all loads of the site before its stores (the arrays may alias as far as
+    // the compiler knows, so interleaving would serialise them)
+    T pv[C], dv[C], qv[C], rv[C], mv[C];
+    const size_t o0 = vix<C>(0, s);
 #pragma unroll
     for (int c = 0; c < C; ++c) {
-      const size_t o = vix<C>(c, s);
-      a.delta[o] = fma(alpha, p[o], a.delta[o]);
-      const T rv = fma(-alpha, a.q[o], a.r[o]);
-      a.r[o] = rv;
-      rz += (double)rv * (double)(a.minv[o] * rv);
+      pv[c] = p[o0 + c];
+      dv[c] = a.delta[o0 + c];
+      qv[c] = a.q[o0 + c];
+      rv[c] = a.r[o0 + c];
+      mv[c] = a.minv[o0 + c];
+    }
+#pragma unroll
+    for (int c = 0; c < C; ++c) {
+      dv[c] = fma(alpha, pv[c], dv[c]);
+      rv[c] = fma(-alpha, qv[c], rv[c]);
+      rz += (double)rv[c] * (double)(mv[c] * rv[c]);
+    }
+#pragma unroll
+    for (int c = 0; c < C; ++c) {
+      a.delta[o0 + c] = dv[c];
+      a.r[o0 + c] = rv[c];
     }
   }
   block_store(rz, pick(a.rz_part, (k + 1) & 1), g);
