@@ -12,6 +12,11 @@ constexpr int kWaves = kBlock / 64;
 constexpr int kMaxBlocks = 1024; // cap on the grid of every site kernel; also the
                                  // length of each partial-sum buffer
 
+// Graph domain: the vertices are cut into chunks of kBlock consecutive ids, and
+// for each chunk up to halo_cap(sizeof bulk type) distinct outside neighbours are
+// listed so that pcg_a can stage them in LDS next to the chunk itself.
+constexpr int halo_cap(size_t tsize) { return tsize > 4 ? 128 : 256; }
+
 // Solver scalars that live on the device for the whole solve, so that the host
 // never waits inside the loop.  Written by block 0 of one kernel and read by the
 // kernels that follow it in stream order.

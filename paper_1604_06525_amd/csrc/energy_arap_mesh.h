@@ -77,6 +77,9 @@ struct ArapMesh {
   int n;                         // vertices
   const int* __restrict__ rp;    // [n+1] CSR offsets
   const int* __restrict__ nb;    // [2E] neighbour ids
+  const int* __restrict__ nbl;   // [2E] neighbour LDS slots of pcg_a's staging
+  const int* __restrict__ hrp;   // [chunks+1] offsets of each chunk's staged halo
+  const int* __restrict__ hid;   // staged halo vertex ids
   const T* __restrict__ U;       // [3][n]
   const T* __restrict__ Ct;      // [3][n]
   T* __restrict__ trig;          // [n][6]: per vertex cos/sin of the three angles
@@ -197,28 +200,32 @@ struct ArapMesh {
   // g = J^T J P at vertex v; P(c, site) reads the direction.
   template <class PA>
   __device__ __forceinline__ void apply_site(PA P, int v, T* g) const {
-    apply_site_v(P, [&](int u) { return trig_at(u); }, [&](int c, int u) { return U[(size_t)c * n + u]; }, v, g);
+    apply_site_v(P, [&](int u) { return trig_at(u); }, [&](int c, int u) { return U[(size_t)c * n + u]; },
+                 nb, v, v, g);
   }
 
-  // apply_site with the neighbours' state and rest positions read through
-  // TA(u) (an EulerTrig) and UA(c, u) (a staged copy, say).
+  // apply_site with every vertex named by a slot: vs for v itself, nbs[k] for
+  // its neighbours, and the direction, state and rest positions read through
+  // P(c, slot), TA(slot) (an EulerTrig) and UA(c, slot) (a staged copy, say).
   template <class PA, class TA, class UA>
-  __device__ __forceinline__ void apply_site_v(PA P, TA Tr, UA Uv, int v, T* g) const {
-    const EulerTrig<T> tv = Tr(v);
-    T pO[3], pa[3];
+  __device__ __forceinline__ void apply_site_v(PA P, TA Tr, UA Uv, const int* __restrict__ nbs, int vs,
+                                               int v, T* g) const {
+    const EulerTrig<T> tv = Tr(vs);
+    T pO[3], pa[3], Uo[3];
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
-      pO[c] = P(c, v);
-      pa[c] = P(3 + c, v);
+      pO[c] = P(c, vs);
+      pa[c] = P(3 + c, vs);
+      Uo[c] = Uv(c, vs);
     }
     T gO[3] = {}, ga[3] = {};
     const T wr2 = wr * wr;
     for (int k = rp[v]; k < rp[v + 1]; ++k) {
-      const int u = nb[k];
+      const int u = nbs[k];
       const EulerTrig<T> tu = Tr(u);
       T d[3], Rv[3], Gv[3][3], Ru[3], Gu[3][3];
 #pragma unroll
-      for (int c = 0; c < 3; ++c) d[c] = Uv(c, v) - Uv(c, u);
+      for (int c = 0; c < 3; ++c) d[c] = Uo[c] - Uv(c, u);
       euler_rot_grad(tv, d, Rv, Gv);
       euler_rot_grad(tu, d, Ru, Gu);
       T qa[3];

@@ -61,7 +61,8 @@ struct Shape {
 
 // Byte offsets of every region of a problem's workspace.
 struct Layout {
-  size_t r0, r1, p0, p1, q, diag, minv, damp, delta, state, flags, csr, parts, scal, trace, rows, total;
+  size_t r0, r1, p0, p1, q, diag, minv, damp, delta, state, flags, csr, halo, parts, scal, trace,
+      rows, total;
 };
 
 // Argument rows a single problem launches with, one device slot of kMaxArgBytes

@@ -288,13 +288,15 @@ __device__ __forceinline__ void run(const SplitAArgs<E, MODE>& a, VG g, int k) {
   };
   if constexpr (StagedOf<E>::value) {
     // The block's chunk of vertices is staged in LDS first (their p, the
-    // per-vertex state and the rest positions); a neighbour inside the chunk
-    // (about 87% of the edges of a Morton-ordered icosphere at 256 vertices
-    // per chunk) is read from there, the others from global memory.
-    constexpr int NS = E::kStatePlanes;
-    __shared__ T sp[kBlock][C];
-    __shared__ T sst[kBlock][NS];
-    __shared__ T su[kBlock][3];
+    // per-vertex state and the rest positions), and after it the chunk's halo:
+    // the outside neighbours listed for it when the problem was created (about
+    // 13% of the edges of a Morton-ordered icosphere at 256 vertices per chunk
+    // leave it).  Every neighbour is then read from LDS, except those of a
+    // chunk whose halo overflowed the cap (read from global memory).
+    constexpr int NS = E::kStatePlanes, H = halo_cap(sizeof(T));
+    __shared__ T sp[kBlock + H][C];
+    __shared__ T sst[kBlock + H][NS];
+    __shared__ T su[kBlock + H][3];
     for (int chunk = unit_of_block(g); chunk * kBlock < n; chunk += g.nb) {
       const int v0 = chunk * kBlock, t = threadIdx.x, v = v0 + t;
       const bool in = v < n;
@@ -309,17 +311,27 @@ __device__ __forceinline__ void run(const SplitAArgs<E, MODE>& a, VG g, int k) {
 #pragma unroll
         for (int c = 0; c < 3; ++c) su[t][c] = a.e.U[(size_t)c * n + v];
       }
+      const int h0 = a.e.hrp[chunk], nh = a.e.hrp[chunk + 1] - h0;
+      for (int j = t; j < nh; j += kBlock) {
+        const int u = a.e.hid[h0 + j];
+#pragma unroll
+        for (int c = 0; c < C; ++c) sp[kBlock + j][c] = Pg(c, u);
+#pragma unroll
+        for (int k2 = 0; k2 < NS; ++k2) sst[kBlock + j][k2] = a.e.state_at(k2, u);
+#pragma unroll
+        for (int c = 0; c < 3; ++c) su[kBlock + j][c] = a.e.U[(size_t)c * n + u];
+      }
       __syncthreads();
-      auto inb = [&](int u) { return u >= v0 && u < v0 + kBlock; };
-      auto Pl = [&](int c, int u) -> T { return inb(u) ? sp[u - v0][c] : Pg(c, u); };
-      auto Tl = [&](int u) {
-        if (!inb(u)) return a.e.trig_at(u);
-        return E::trig_from(sst[u - v0]);
+      // slot s >= 0: LDS; s < 0: vertex -s - 1 in global memory
+      auto Pl = [&](int c, int s) -> T { return s >= 0 ? sp[s][c] : Pg(c, -s - 1); };
+      auto Tl = [&](int s) {
+        if (s < 0) return a.e.trig_at(-s - 1);
+        return E::trig_from(sst[s]);
       };
-      auto Ul = [&](int c, int u) -> T { return inb(u) ? su[u - v0][c] : a.e.U[(size_t)c * n + u]; };
+      auto Ul = [&](int c, int s) -> T { return s >= 0 ? su[s][c] : a.e.U[(size_t)c * n + (-s - 1)]; };
       const bool act = in && (a.e.flags[v] & E::ACTIVE);
       T gv[C];
-      if (act) a.e.apply_site_v(Pl, Tl, Ul, v, gv);
+      if (act) a.e.apply_site_v(Pl, Tl, Ul, a.e.nbl, t, v, gv);
       if (in) finish(v, act, pv, gv);
       __syncthreads();  // the next chunk reuses the stage
     }

@@ -49,6 +49,9 @@ Layout make_layout(const Shape& sh) {
   L.flags = off; off += align_up((size_t)sh.n);
   L.csr = off;  // graph: row offsets [n+1], then neighbour ids [2E]
   if (sh.graph) off += align_up(sizeof(int) * ((size_t)sh.n + 1 + 2 * (size_t)sh.n_edges));
+  L.halo = off;  // graph: chunk-local neighbour slots [2E], halo offsets [chunks+1], halo ids [<= 2E]
+  if (sh.graph)
+    off += align_up(sizeof(int) * (4 * (size_t)sh.n_edges + (size_t)(sh.n + kBlock - 1) / kBlock + 1));
   L.parts = off; off += align_up(kNumPartBufs * (size_t)kMaxBlocks * sizeof(double));
   L.scal = off; off += align_up(sizeof(DevScalars));
   L.trace = off; off += align_up((size_t)kTraceCap * sizeof(double));
@@ -614,6 +617,9 @@ std::unique_ptr<Impl> make_impl_t(opt_problem* p) {
       e.n = p->sh.n;
       e.rp = (const int*)p->at(p->L.csr);
       e.nb = e.rp + (p->sh.n + 1);
+      e.nbl = (const int*)p->at(p->L.halo);
+      e.hrp = e.nbl + 2 * (size_t)p->sh.n_edges;
+      e.hid = e.hrp + (p->sh.n + kBlock - 1) / kBlock + 1;
       e.U = (const T*)d.arrays[0];
       e.Ct = (const T*)d.arrays[1];
       e.trig = (T*)p->at(p->L.state);
@@ -660,11 +666,45 @@ int build_incidence(opt_problem* p) {
     nb[(size_t)pos[a]++] = b;
     nb[(size_t)pos[b]++] = a;
   }
+  // Per chunk of kBlock consecutive vertices: its outside neighbours in order of
+  // first reference, the first halo_cap of them staged.  nbl names a neighbour by
+  // its LDS slot: u - chunk start inside the chunk, kBlock + halo index for a
+  // staged outside one, -(u + 1) for one past the cap (read from global memory).
+  const int nch = (V + kBlock - 1) / kBlock, cap = halo_cap(p->sh.tsize);
+  std::vector<int> nbl(nb.size()), hrp((size_t)nch + 1, 0), hid, seen((size_t)V, -1), slot((size_t)V, -1);
+  for (int c = 0; c < nch; ++c) {
+    hrp[c] = (int)hid.size();
+    int nh = 0;
+    for (int v = c * kBlock; v < std::min(V, (c + 1) * kBlock); ++v)
+      for (int k = rp[v]; k < rp[(size_t)v + 1]; ++k) {
+        const int u = nb[k];
+        if (u / kBlock == c) {
+          nbl[k] = u - c * kBlock;
+          continue;
+        }
+        if (seen[u] != c) {
+          seen[u] = c;
+          slot[u] = nh < cap ? nh : -1;
+          if (nh < cap) hid.push_back(u);
+          ++nh;
+        }
+        nbl[k] = slot[u] >= 0 ? kBlock + slot[u] : -(u + 1);
+      }
+  }
+  hrp[nch] = (int)hid.size();
   int* dst = (int*)p->at(p->L.csr);
   HIP_TRY(hipMemcpyAsync(dst, rp.data(), sizeof(int) * rp.size(), hipMemcpyHostToDevice, p->stream));
-  if (E > 0)
+  int* hl = (int*)p->at(p->L.halo);
+  HIP_TRY(hipMemcpyAsync(hl + nbl.size(), hrp.data(), sizeof(int) * hrp.size(), hipMemcpyHostToDevice,
+                         p->stream));
+  if (E > 0) {
     HIP_TRY(hipMemcpyAsync(dst + V + 1, nb.data(), sizeof(int) * nb.size(), hipMemcpyHostToDevice,
                            p->stream));
+    HIP_TRY(hipMemcpyAsync(hl, nbl.data(), sizeof(int) * nbl.size(), hipMemcpyHostToDevice, p->stream));
+  }
+  if (!hid.empty())
+    HIP_TRY(hipMemcpyAsync(hl + nbl.size() + hrp.size(), hid.data(), sizeof(int) * hid.size(),
+                           hipMemcpyHostToDevice, p->stream));
   HIP_TRY(hipStreamSynchronize(p->stream));
   return OPT_OK;
 }

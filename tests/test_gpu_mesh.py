@@ -161,3 +161,38 @@ def test_bad_edge_rejected():
     with pytest.raises(pkg.OptError) as err:
         make_problem(d, "mixed")
     assert err.value.code == pkg.OPT_EINVAL
+
+
+def _scrambled(level, seed=3):
+    """The ARAP mesh workload with its vertex ids randomly relabelled: almost
+    every edge then leaves its chunk of 256 consecutive ids, so the per-chunk
+    halos overflow their LDS cap and pcg_a reads the rest from global memory."""
+    d, x = _mesh(level, seed=seed)
+    V = d["V"]
+    perm = np.random.default_rng(seed + 100).permutation(V)  # new id k holds old vertex perm[k]
+    inv = np.empty_like(perm)
+    inv[perm] = np.arange(V)
+    d = dict(d, U=d["U"][:, perm].copy(), C=d["C"][:, perm].copy(), x0=d["x0"][:, perm].copy(),
+             edges=inv[d["edges"]].astype(np.int32), handles=np.sort(inv[d["handles"]]))
+    return d, x[:, perm].copy()
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_scrambled_ids_halo_overflow(prec):
+    d, x = _scrambled(4)
+    if prec == "mixed":
+        d = f32_inputs(d)
+        x = np.asarray(x, np.float32).astype(np.float64)
+    e = o.make_energy(d)
+    lin = o.Linearization(e, x)
+    prob = make_problem(d, prec)
+    xt = to_dev(prob, x)
+    prob.linearize(xt)
+    tol = 1e-12 if prec == "fp64" else 1e-5
+    p = np.random.default_rng(7).normal(size=lin.diag.size)
+    if prec == "mixed":
+        p = np.asarray(p, np.float32).astype(np.float64)
+    assert relmax(to_np(prob.apply_jtj(to_dev(prob, p))), lin.apply(p)) < tol
+    if prec == "fp64":
+        ref, _ = o.pcg(lin.apply, lin.jtf(), lin.minv(True), 20)
+        assert relmax(to_np(prob.pcg(20, variant="split")), ref) < 1e-9
