@@ -13,9 +13,32 @@ constexpr int kMaxBlocks = 1024; // cap on the grid of every site kernel; also t
                                  // length of each partial-sum buffer
 
 // Graph domain: the vertices are cut into chunks of kBlock consecutive ids, and
-// for each chunk up to halo_cap(sizeof bulk type) distinct outside neighbours are
-// listed so that pcg_a can stage them in LDS next to the chunk itself.
-constexpr int halo_cap(size_t tsize) { return tsize > 4 ? 128 : 256; }
+// for each chunk up to halo_cap distinct outside neighbours are listed so that
+// pcg_a can stage them in LDS next to the chunk itself.  The cap fills an LDS
+// budget (30 KiB for FP32, 45 KiB for FP64) with the chunk and its halo at
+// `width` values per vertex (p plus the energy's staged values), a multiple of 32.
+constexpr int halo_cap(size_t tsize, int width) {
+  const int h = (tsize > 4 ? 46080 : 30720) / (width * (int)tsize) - kBlock;
+  return h < 0 ? 0 : h / 32 * 32;
+}
+// ... and up to this many of the chunk's neighbour slots are staged as well.
+constexpr int nbl_cap(size_t tsize) { return tsize > 4 ? 1024 : 1536; }
+
+// Chunk-local neighbour slots and halo lists of a graph problem: nbl[k] names the
+// neighbour of incidence-list entry k by its LDS slot (u - chunk start inside the
+// chunk, kBlock + halo index for a staged outside vertex, -(u + 1) for one past
+// the cap); chunk c stages the vertices hid[hrp[c] .. hrp[c+1]).
+struct Halo {
+  const int* __restrict__ nbl;
+  const int* __restrict__ hrp;
+  const int* __restrict__ hid;
+};
+
+// The per-vertex values a staged graph energy reads for a neighbour.
+template <typename T, int N>
+struct Vals {
+  T v[N];
+};
 
 // Solver scalars that live on the device for the whole solve, so that the host
 // never waits inside the loop.  Written by block 0 of one kernel and read by the

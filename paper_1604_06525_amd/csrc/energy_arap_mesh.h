@@ -72,14 +72,13 @@ struct ArapMesh {
   static constexpr int kOwnState = 6;
   static constexpr int kRadius = 1;
   enum : uint32_t { ACTIVE = 1, INGRID = 2, FIT0 = 4 };  // FIT0 << k: component k
-  static constexpr bool kStaged = true;  // pcg_a stages a vertex chunk in LDS (apply_site_v)
+  static constexpr bool kStaged = true;  // pcg_a stages a vertex chunk in LDS (apply_staged)
+  static constexpr int kStageVals = 9;   // staged per vertex: cos/sin of the angles, U
 
   int n;                         // vertices
   const int* __restrict__ rp;    // [n+1] CSR offsets
   const int* __restrict__ nb;    // [2E] neighbour ids
-  const int* __restrict__ nbl;   // [2E] neighbour LDS slots of pcg_a's staging
-  const int* __restrict__ hrp;   // [chunks+1] offsets of each chunk's staged halo
-  const int* __restrict__ hid;   // staged halo vertex ids
+  Halo halo;                     // pcg_a's staging lists
   const T* __restrict__ U;       // [3][n]
   const T* __restrict__ Ct;      // [3][n]
   T* __restrict__ trig;          // [n][6]: per vertex cos/sin of the three angles
@@ -200,32 +199,41 @@ struct ArapMesh {
   // g = J^T J P at vertex v; P(c, site) reads the direction.
   template <class PA>
   __device__ __forceinline__ void apply_site(PA P, int v, T* g) const {
-    apply_site_v(P, [&](int u) { return trig_at(u); }, [&](int c, int u) { return U[(size_t)c * n + u]; },
-                 nb, v, v, g);
+    apply_staged(P, [&](int u) { return stage_vals(u); }, [&](int k) { return nb[k]; }, v, v, g);
   }
 
-  // apply_site with every vertex named by a slot: vs for v itself, nbs[k] for
-  // its neighbours, and the direction, state and rest positions read through
-  // P(c, slot), TA(slot) (an EulerTrig) and UA(c, slot) (a staged copy, say).
-  template <class PA, class TA, class UA>
-  __device__ __forceinline__ void apply_site_v(PA P, TA Tr, UA Uv, const int* __restrict__ nbs, int vs,
-                                               int v, T* g) const {
-    const EulerTrig<T> tv = Tr(vs);
-    T pO[3], pa[3], Uo[3];
+  // The staged values of vertex u: cos/sin of its angles, then U.
+  __device__ __forceinline__ Vals<T, 9> stage_vals(int u) const {
+    Vals<T, 9> r;
+#pragma unroll
+    for (int k = 0; k < 6; ++k) r.v[k] = trig[(size_t)u * 6 + k];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) r.v[6 + c] = U[(size_t)c * n + u];
+    return r;
+  }
+
+  // apply_site with every vertex named by a slot: vs for v itself, NB(k) for
+  // the neighbour of incidence entry k; P(c, slot) reads the direction and
+  // SA(slot) the staged values.
+  template <class PA, class SA, class NA>
+  __device__ __forceinline__ void apply_staged(PA P, SA Sv, NA NB, int vs, int v, T* g) const {
+    const Vals<T, 9> sv = Sv(vs);
+    const EulerTrig<T> tv = trig_from(sv.v);
+    T pO[3], pa[3];
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
       pO[c] = P(c, vs);
       pa[c] = P(3 + c, vs);
-      Uo[c] = Uv(c, vs);
     }
     T gO[3] = {}, ga[3] = {};
     const T wr2 = wr * wr;
     for (int k = rp[v]; k < rp[v + 1]; ++k) {
-      const int u = nbs[k];
-      const EulerTrig<T> tu = Tr(u);
+      const int u = NB(k);
+      const Vals<T, 9> su = Sv(u);
+      const EulerTrig<T> tu = trig_from(su.v);
       T d[3], Rv[3], Gv[3][3], Ru[3], Gu[3][3];
 #pragma unroll
-      for (int c = 0; c < 3; ++c) d[c] = Uo[c] - Uv(c, u);
+      for (int c = 0; c < 3; ++c) d[c] = sv.v[6 + c] - su.v[6 + c];
       euler_rot_grad(tv, d, Rv, Gv);
       euler_rot_grad(tu, d, Ru, Gu);
       T qa[3];

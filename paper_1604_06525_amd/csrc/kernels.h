@@ -287,16 +287,18 @@ __device__ __forceinline__ void run(const SplitAArgs<E, MODE>& a, VG g, int k) {
     }
   };
   if constexpr (StagedOf<E>::value) {
-    // The block's chunk of vertices is staged in LDS first (their p, the
-    // per-vertex state and the rest positions), and after it the chunk's halo:
-    // the outside neighbours listed for it when the problem was created (about
-    // 13% of the edges of a Morton-ordered icosphere at 256 vertices per chunk
-    // leave it).  Every neighbour is then read from LDS, except those of a
-    // chunk whose halo overflowed the cap (read from global memory).
-    constexpr int NS = E::kStatePlanes, H = halo_cap(sizeof(T));
+    // The block's chunk of vertices is staged in LDS first (their p and the
+    // values the energy reads of a neighbour), after it the chunk's halo: the
+    // outside neighbours listed for it when the problem was created (about 13%
+    // of the edges of a Morton-ordered icosphere at 256 vertices per chunk
+    // leave it), and the chunk's neighbour slots.  Every neighbour is then read
+    // from LDS, except those of a chunk whose halo overflowed the cap (read
+    // from global memory).
+    constexpr int NS = E::kStageVals, H = halo_cap(sizeof(T), C + NS), NBC = nbl_cap(sizeof(T));
     __shared__ T sp[kBlock + H][C];
     __shared__ T sst[kBlock + H][NS];
-    __shared__ T su[kBlock + H][3];
+    __shared__ int snb[NBC];
+    const Halo& hl = a.e.halo;
     for (int chunk = unit_of_block(g); chunk * kBlock < n; chunk += g.nb) {
       const int v0 = chunk * kBlock, t = threadIdx.x, v = v0 + t;
       const bool in = v < n;
@@ -306,32 +308,35 @@ __device__ __forceinline__ void run(const SplitAArgs<E, MODE>& a, VG g, int k) {
       if (in) {
 #pragma unroll
         for (int c = 0; c < C; ++c) sp[t][c] = pv[c];
+        const Vals<T, NS> sv = a.e.stage_vals(v);
 #pragma unroll
-        for (int k2 = 0; k2 < NS; ++k2) sst[t][k2] = a.e.state_at(k2, v);
-#pragma unroll
-        for (int c = 0; c < 3; ++c) su[t][c] = a.e.U[(size_t)c * n + v];
+        for (int k2 = 0; k2 < NS; ++k2) sst[t][k2] = sv.v[k2];
       }
-      const int h0 = a.e.hrp[chunk], nh = a.e.hrp[chunk + 1] - h0;
+      const int h0 = hl.hrp[chunk], nh = hl.hrp[chunk + 1] - h0;
       for (int j = t; j < nh; j += kBlock) {
-        const int u = a.e.hid[h0 + j];
+        const int u = hl.hid[h0 + j];
 #pragma unroll
         for (int c = 0; c < C; ++c) sp[kBlock + j][c] = Pg(c, u);
+        const Vals<T, NS> sv = a.e.stage_vals(u);
 #pragma unroll
-        for (int k2 = 0; k2 < NS; ++k2) sst[kBlock + j][k2] = a.e.state_at(k2, u);
-#pragma unroll
-        for (int c = 0; c < 3; ++c) su[kBlock + j][c] = a.e.U[(size_t)c * n + u];
+        for (int k2 = 0; k2 < NS; ++k2) sst[kBlock + j][k2] = sv.v[k2];
       }
+      const int kb = a.e.rp[v0], nk = min(a.e.rp[min(v0 + kBlock, n)] - kb, NBC);
+      for (int j = t; j < nk; j += kBlock) snb[j] = hl.nbl[kb + j];
       __syncthreads();
       // slot s >= 0: LDS; s < 0: vertex -s - 1 in global memory
       auto Pl = [&](int c, int s) -> T { return s >= 0 ? sp[s][c] : Pg(c, -s - 1); };
-      auto Tl = [&](int s) {
-        if (s < 0) return a.e.trig_at(-s - 1);
-        return E::trig_from(sst[s]);
+      auto Sl = [&](int s) {
+        if (s < 0) return a.e.stage_vals(-s - 1);
+        Vals<T, NS> r;
+#pragma unroll
+        for (int k2 = 0; k2 < NS; ++k2) r.v[k2] = sst[s][k2];
+        return r;
       };
-      auto Ul = [&](int c, int s) -> T { return s >= 0 ? su[s][c] : a.e.U[(size_t)c * n + (-s - 1)]; };
+      auto NBl = [&](int k) { return k - kb < nk ? snb[k - kb] : hl.nbl[k]; };
       const bool act = in && (a.e.flags[v] & E::ACTIVE);
       T gv[C];
-      if (act) a.e.apply_site_v(Pl, Tl, Ul, a.e.nbl, t, v, gv);
+      if (act) a.e.apply_staged(Pl, Sl, NBl, t, v, gv);
       if (in) finish(v, act, pv, gv);
       __syncthreads();  // the next chunk reuses the stage
     }

@@ -84,6 +84,15 @@ int energy_state_planes(int e) {
   }
 }
 
+// Values per vertex pcg_a stages for a graph energy: p and the energy's own.
+int stage_width(int e) {
+  switch (e) {
+    case OPT_E_ARAP_WARP: return ArapWarpGraph<float>::C + ArapWarpGraph<float>::kStageVals;
+    case OPT_E_ARAP_MESH: return ArapMesh<float>::C + ArapMesh<float>::kStageVals;
+    default: return 1;  // not staged: the lists are built but unused
+  }
+}
+
 int n_params_needed(int e) {
   switch (e) {
     case OPT_E_ARAP_WARP: return 2;
@@ -525,6 +534,15 @@ class ImplT final : public Impl {
   E e_;
 };
 
+// The staging lists build_incidence writes after the incidence list.
+Halo halo_of(const opt_problem* p) {
+  Halo h;
+  h.nbl = (const int*)p->at(p->L.halo);
+  h.hrp = h.nbl + 2 * (size_t)p->sh.n_edges;
+  h.hid = h.hrp + (p->sh.n + kBlock - 1) / kBlock + 1;
+  return h;
+}
+
 template <typename T>
 std::unique_ptr<Impl> make_impl_t(opt_problem* p) {
   const opt_problem_desc& d = p->desc;
@@ -540,6 +558,7 @@ std::unique_ptr<Impl> make_impl_t(opt_problem* p) {
         e.mask = (const uint8_t*)d.arrays[2];
         e.st = (T*)p->at(p->L.state);
         e.flags = (uint8_t*)p->at(p->L.flags);
+        e.halo = halo_of(p);
         e.wf = (T)d.params[0];
         e.wr = (T)d.params[1];
         e.wf_d = d.params[0];
@@ -617,9 +636,7 @@ std::unique_ptr<Impl> make_impl_t(opt_problem* p) {
       e.n = p->sh.n;
       e.rp = (const int*)p->at(p->L.csr);
       e.nb = e.rp + (p->sh.n + 1);
-      e.nbl = (const int*)p->at(p->L.halo);
-      e.hrp = e.nbl + 2 * (size_t)p->sh.n_edges;
-      e.hid = e.hrp + (p->sh.n + kBlock - 1) / kBlock + 1;
+      e.halo = halo_of(p);
       e.U = (const T*)d.arrays[0];
       e.Ct = (const T*)d.arrays[1];
       e.trig = (T*)p->at(p->L.state);
@@ -670,7 +687,7 @@ int build_incidence(opt_problem* p) {
   // first reference, the first halo_cap of them staged.  nbl names a neighbour by
   // its LDS slot: u - chunk start inside the chunk, kBlock + halo index for a
   // staged outside one, -(u + 1) for one past the cap (read from global memory).
-  const int nch = (V + kBlock - 1) / kBlock, cap = halo_cap(p->sh.tsize);
+  const int nch = (V + kBlock - 1) / kBlock, cap = halo_cap(p->sh.tsize, stage_width(p->desc.energy));
   std::vector<int> nbl(nb.size()), hrp((size_t)nch + 1, 0), hid, seen((size_t)V, -1), slot((size_t)V, -1);
   for (int c = 0; c < nch; ++c) {
     hrp[c] = (int)hid.size();
