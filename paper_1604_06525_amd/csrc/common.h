@@ -17,8 +17,9 @@ constexpr int kMaxBlocks = 1024; // cap on the grid of every site kernel; also t
 // pcg_a can stage them in LDS next to the chunk itself.  The cap fills an LDS
 // budget (30 KiB for FP32, 45 KiB for FP64) with the chunk and its halo at
 // `width` values per vertex (p plus the energy's staged values), a multiple of 32.
+// Width 0: the energy is not staged and no halo is listed.
 constexpr int halo_cap(size_t tsize, int width) {
-  const int h = (tsize > 4 ? 46080 : 30720) / (width * (int)tsize) - kBlock;
+  const int h = width > 0 ? (tsize > 4 ? 46080 : 30720) / (width * (int)tsize) - kBlock : 0;
   return h < 0 ? 0 : h / 32 * 32;
 }
 // ... and up to this many of the chunk's neighbour slots are staged as well.
@@ -27,10 +28,11 @@ constexpr int nbl_cap(size_t tsize) { return tsize > 4 ? 1024 : 1536; }
 // Chunk-local neighbour slots and halo lists of a graph problem: nbl[k] names the
 // neighbour of incidence-list entry k by its LDS slot (u - chunk start inside the
 // chunk, kBlock + halo index for a staged outside vertex, -(u + 1) for one past
-// the cap); chunk c stages the vertices hid[hrp[c] .. hrp[c+1]).
+// the cap); chunk c stages the hcnt[c] vertices hid[c * cap ...] (rows of a fixed
+// stride, so that a count and the ids can be read at once).
 struct Halo {
   const int* __restrict__ nbl;
-  const int* __restrict__ hrp;
+  const int* __restrict__ hcnt;
   const int* __restrict__ hid;
 };
 

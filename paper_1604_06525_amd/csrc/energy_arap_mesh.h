@@ -199,7 +199,8 @@ struct ArapMesh {
   // g = J^T J P at vertex v; P(c, site) reads the direction.
   template <class PA>
   __device__ __forceinline__ void apply_site(PA P, int v, T* g) const {
-    apply_staged(P, [&](int u) { return stage_vals(u); }, [&](int k) { return nb[k]; }, v, v, g);
+    apply_staged(P, [&](int u) { return stage_vals(u); }, [&](int k) { return nb[k]; }, v, rp[v], rp[v + 1],
+                 (uint32_t)flags[v], g);
   }
 
   // The staged values of vertex u: cos/sin of its angles, then U.
@@ -212,11 +213,12 @@ struct ArapMesh {
     return r;
   }
 
-  // apply_site with every vertex named by a slot: vs for v itself, NB(k) for
-  // the neighbour of incidence entry k; P(c, slot) reads the direction and
-  // SA(slot) the staged values.
+  // apply_site with every vertex named by a slot: vs for the vertex itself,
+  // NB(k) for the neighbour of its incidence entries k0 <= k < k1; P(c, slot)
+  // reads the direction, SA(slot) the staged values; fl is its flags byte.
   template <class PA, class SA, class NA>
-  __device__ __forceinline__ void apply_staged(PA P, SA Sv, NA NB, int vs, int v, T* g) const {
+  __device__ __forceinline__ void apply_staged(PA P, SA Sv, NA NB, int vs, int k0, int k1, uint32_t fl,
+                                               T* g) const {
     const Vals<T, 9> sv = Sv(vs);
     const EulerTrig<T> tv = trig_from(sv.v);
     T pO[3], pa[3];
@@ -227,7 +229,7 @@ struct ArapMesh {
     }
     T gO[3] = {}, ga[3] = {};
     const T wr2 = wr * wr;
-    for (int k = rp[v]; k < rp[v + 1]; ++k) {
+    for (int k = k0; k < k1; ++k) {
       const int u = NB(k);
       const Vals<T, 9> su = Sv(u);
       const EulerTrig<T> tu = trig_from(su.v);
@@ -251,7 +253,6 @@ struct ArapMesh {
       for (int q = 0; q < 3; ++q)
         ga[q] -= wr2 * (Gv[q][0] * j1[0] + Gv[q][1] * j1[1] + Gv[q][2] * j1[2]);
     }
-    const uint32_t fl = flags[v];
     const T wf2 = wf * wf;
 #pragma unroll
     for (int c = 0; c < 3; ++c) {

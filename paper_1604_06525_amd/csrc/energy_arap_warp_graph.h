@@ -125,7 +125,8 @@ struct ArapWarpGraph {
   // g = J^T J P at an active vertex v; P(c, site) reads the direction.
   template <class PA>
   __device__ __forceinline__ void apply_site(PA P, int v, T* g) const {
-    apply_staged(P, [&](int u) { return stage_vals(u); }, [&](int k) { return nb[k]; }, v, v, g);
+    apply_staged(P, [&](int u) { return stage_vals(u); }, [&](int k) { return nb[k]; }, v, rp[v], rp[v + 1],
+                 (uint32_t)flags[v], g);
   }
 
   // The staged values of vertex u: its state, then 1 when it is active, else 0.
@@ -137,17 +138,18 @@ struct ArapWarpGraph {
     return r;
   }
 
-  // apply_site with every vertex named by a slot: vs for v itself, NB(k) for
-  // the neighbour of incidence entry k; P(c, slot) reads the direction and
-  // SA(slot) the staged values.
+  // apply_site with every vertex named by a slot: vs for the vertex itself,
+  // NB(k) for the neighbour of its incidence entries k0 <= k < k1; P(c, slot)
+  // reads the direction, SA(slot) the staged values; fl is its flags byte.
   template <class PA, class SA, class NA>
-  __device__ __forceinline__ void apply_staged(PA P, SA Sv, NA NB, int vs, int v, T* g) const {
+  __device__ __forceinline__ void apply_staged(PA P, SA Sv, NA NB, int vs, int k0, int k1, uint32_t fl,
+                                               T* g) const {
     const Vals<T, 5> sv = Sv(vs);
     const T c = sv.v[0], sn = sv.v[1], Ux = sv.v[2], Uy = sv.v[3];
     const T px = P(0, vs), py = P(1, vs), pt = P(2, vs);
     T gx = 0, gy = 0, gt = 0;
     const T wr2 = wr * wr;
-    for (int k = rp[v]; k < rp[v + 1]; ++k) {
+    for (int k = k0; k < k1; ++k) {
       const int u = NB(k);
       const Vals<T, 5> su = Sv(u);
       const T w = su.v[4] * wr2;
@@ -163,7 +165,7 @@ struct ArapWarpGraph {
       gy += w * (j1y - j2y);
       gt -= w * (apx * j1x + apy * j1y);
     }
-    const T wfit = (flags[v] & FIT) ? wf * wf : T(0);
+    const T wfit = (fl & FIT) ? wf * wf : T(0);
     g[0] = fma(wfit, px, gx);
     g[1] = fma(wfit, py, gy);
     g[2] = gt;

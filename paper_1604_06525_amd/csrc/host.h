@@ -56,6 +56,7 @@ struct Shape {
   int n = 0;           // sites
   size_t tsize = 0;    // bytes of the bulk type
   int n_edges = 0;     // graph: listed undirected edges
+  int stage_w = 0;     // graph: values per vertex pcg_a stages (0: not staged)
   bool graph = false;
 };
 

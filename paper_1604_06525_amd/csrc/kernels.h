@@ -302,6 +302,14 @@ __device__ __forceinline__ void run(const SplitAArgs<E, MODE>& a, VG g, int k) {
     for (int chunk = unit_of_block(g); chunk * kBlock < n; chunk += g.nb) {
       const int v0 = chunk * kBlock, t = threadIdx.x, v = v0 + t;
       const bool in = v < n;
+      // Every index the chunk needs is requested before any load that depends
+      // on one: the halo count and the halo row (a fixed-stride row, read
+      // whole), the chunk's and the vertex's incidence ranges, the flags.
+      const int nh = hl.hcnt[chunk];
+      const int* hrow = hl.hid + (size_t)chunk * H;
+      const int kb = a.e.rp[v0], ke = a.e.rp[min(v0 + kBlock, n)];
+      const int k0 = in ? a.e.rp[v] : 0, k1 = in ? a.e.rp[v + 1] : 0;
+      const uint32_t fl = in ? (uint32_t)a.e.flags[v] : 0u;
       T pv[C];
 #pragma unroll
       for (int c = 0; c < C; ++c) pv[c] = in ? Pg(c, v) : T(0);
@@ -312,16 +320,17 @@ __device__ __forceinline__ void run(const SplitAArgs<E, MODE>& a, VG g, int k) {
 #pragma unroll
         for (int k2 = 0; k2 < NS; ++k2) sst[t][k2] = sv.v[k2];
       }
-      const int h0 = hl.hrp[chunk], nh = hl.hrp[chunk + 1] - h0;
-      for (int j = t; j < nh; j += kBlock) {
-        const int u = hl.hid[h0 + j];
+      for (int j = t; j < H; j += kBlock) {
+        const int u = hrow[j];
+        if (j < nh) {
 #pragma unroll
-        for (int c = 0; c < C; ++c) sp[kBlock + j][c] = Pg(c, u);
-        const Vals<T, NS> sv = a.e.stage_vals(u);
+          for (int c = 0; c < C; ++c) sp[kBlock + j][c] = Pg(c, u);
+          const Vals<T, NS> sv = a.e.stage_vals(u);
 #pragma unroll
-        for (int k2 = 0; k2 < NS; ++k2) sst[kBlock + j][k2] = sv.v[k2];
+          for (int k2 = 0; k2 < NS; ++k2) sst[kBlock + j][k2] = sv.v[k2];
+        }
       }
-      const int kb = a.e.rp[v0], nk = min(a.e.rp[min(v0 + kBlock, n)] - kb, NBC);
+      const int nk = min(ke - kb, NBC);
       for (int j = t; j < nk; j += kBlock) snb[j] = hl.nbl[kb + j];
       __syncthreads();
       // slot s >= 0: LDS; s < 0: vertex -s - 1 in global memory
@@ -334,9 +343,9 @@ __device__ __forceinline__ void run(const SplitAArgs<E, MODE>& a, VG g, int k) {
         return r;
       };
       auto NBl = [&](int k) { return k - kb < nk ? snb[k - kb] : hl.nbl[k]; };
-      const bool act = in && (a.e.flags[v] & E::ACTIVE);
+      const bool act = in && (fl & E::ACTIVE);
       T gv[C];
-      if (act) a.e.apply_staged(Pl, Sl, NBl, t, v, gv);
+      if (act) a.e.apply_staged(Pl, Sl, NBl, t, k0, k1, fl, gv);
       if (in) finish(v, act, pv, gv);
       __syncthreads();  // the next chunk reuses the stage
     }

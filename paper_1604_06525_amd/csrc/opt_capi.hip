@@ -49,9 +49,10 @@ Layout make_layout(const Shape& sh) {
   L.flags = off; off += align_up((size_t)sh.n);
   L.csr = off;  // graph: row offsets [n+1], then neighbour ids [2E]
   if (sh.graph) off += align_up(sizeof(int) * ((size_t)sh.n + 1 + 2 * (size_t)sh.n_edges));
-  L.halo = off;  // graph: chunk-local neighbour slots [2E], halo offsets [chunks+1], halo ids [<= 2E]
+  L.halo = off;  // graph: chunk-local neighbour slots [2E], halo counts [chunks], halo ids [chunks][cap]
   if (sh.graph)
-    off += align_up(sizeof(int) * (4 * (size_t)sh.n_edges + (size_t)(sh.n + kBlock - 1) / kBlock + 1));
+    off += align_up(sizeof(int) * (2 * (size_t)sh.n_edges + (size_t)(sh.n + kBlock - 1) / kBlock *
+                                                                  (1 + (size_t)halo_cap(sh.tsize, sh.stage_w))));
   L.parts = off; off += align_up(kNumPartBufs * (size_t)kMaxBlocks * sizeof(double));
   L.scal = off; off += align_up(sizeof(DevScalars));
   L.trace = off; off += align_up((size_t)kTraceCap * sizeof(double));
@@ -84,12 +85,19 @@ int energy_state_planes(int e) {
   }
 }
 
-// Values per vertex pcg_a stages for a graph energy: p and the energy's own.
+// Values per vertex pcg_a stages for a graph energy: p and the energy's own
+// (0: the energy is not staged).
+template <class E>
+constexpr int stage_width_of() {
+  if constexpr (optmi::StagedOf<E>::value) return E::C + E::kStageVals;
+  return 0;
+}
+
 int stage_width(int e) {
   switch (e) {
-    case OPT_E_ARAP_WARP: return ArapWarpGraph<float>::C + ArapWarpGraph<float>::kStageVals;
-    case OPT_E_ARAP_MESH: return ArapMesh<float>::C + ArapMesh<float>::kStageVals;
-    default: return 1;  // not staged: the lists are built but unused
+    case OPT_E_ARAP_WARP: return stage_width_of<ArapWarpGraph<float>>();
+    case OPT_E_ARAP_MESH: return stage_width_of<ArapMesh<float>>();
+    default: return 0;
   }
 }
 
@@ -145,6 +153,7 @@ int check_desc(const opt_problem_desc* d, Shape* sh) {
     sh->n = d->n_vertices;
     sh->n_edges = d->n_edges;
     sh->graph = true;
+    sh->stage_w = stage_width(d->energy);
   } else {
     return fail(OPT_EINVAL, "domain %d is not OPT_GRID2D or OPT_GRAPH", d->domain);
   }
@@ -538,8 +547,8 @@ class ImplT final : public Impl {
 Halo halo_of(const opt_problem* p) {
   Halo h;
   h.nbl = (const int*)p->at(p->L.halo);
-  h.hrp = h.nbl + 2 * (size_t)p->sh.n_edges;
-  h.hid = h.hrp + (p->sh.n + kBlock - 1) / kBlock + 1;
+  h.hcnt = h.nbl + 2 * (size_t)p->sh.n_edges;
+  h.hid = h.hcnt + (p->sh.n + kBlock - 1) / kBlock;
   return h;
 }
 
@@ -687,10 +696,11 @@ int build_incidence(opt_problem* p) {
   // first reference, the first halo_cap of them staged.  nbl names a neighbour by
   // its LDS slot: u - chunk start inside the chunk, kBlock + halo index for a
   // staged outside one, -(u + 1) for one past the cap (read from global memory).
-  const int nch = (V + kBlock - 1) / kBlock, cap = halo_cap(p->sh.tsize, stage_width(p->desc.energy));
-  std::vector<int> nbl(nb.size()), hrp((size_t)nch + 1, 0), hid, seen((size_t)V, -1), slot((size_t)V, -1);
+  // An energy that is not staged gets cap 0 and every outside slot negative.
+  const int nch = (V + kBlock - 1) / kBlock, cap = halo_cap(p->sh.tsize, p->sh.stage_w);
+  std::vector<int> nbl(nb.size()), hcnt((size_t)nch, 0), hid((size_t)nch * cap, 0), seen((size_t)V, -1),
+      slot((size_t)V, -1);
   for (int c = 0; c < nch; ++c) {
-    hrp[c] = (int)hid.size();
     int nh = 0;
     for (int v = c * kBlock; v < std::min(V, (c + 1) * kBlock); ++v)
       for (int k = rp[v]; k < rp[(size_t)v + 1]; ++k) {
@@ -702,17 +712,16 @@ int build_incidence(opt_problem* p) {
         if (seen[u] != c) {
           seen[u] = c;
           slot[u] = nh < cap ? nh : -1;
-          if (nh < cap) hid.push_back(u);
-          ++nh;
+          if (nh < cap) hid[(size_t)c * cap + nh++] = u;
         }
         nbl[k] = slot[u] >= 0 ? kBlock + slot[u] : -(u + 1);
       }
+    hcnt[c] = nh;
   }
-  hrp[nch] = (int)hid.size();
   int* dst = (int*)p->at(p->L.csr);
   HIP_TRY(hipMemcpyAsync(dst, rp.data(), sizeof(int) * rp.size(), hipMemcpyHostToDevice, p->stream));
   int* hl = (int*)p->at(p->L.halo);
-  HIP_TRY(hipMemcpyAsync(hl + nbl.size(), hrp.data(), sizeof(int) * hrp.size(), hipMemcpyHostToDevice,
+  HIP_TRY(hipMemcpyAsync(hl + nbl.size(), hcnt.data(), sizeof(int) * hcnt.size(), hipMemcpyHostToDevice,
                          p->stream));
   if (E > 0) {
     HIP_TRY(hipMemcpyAsync(dst + V + 1, nb.data(), sizeof(int) * nb.size(), hipMemcpyHostToDevice,
@@ -720,7 +729,7 @@ int build_incidence(opt_problem* p) {
     HIP_TRY(hipMemcpyAsync(hl, nbl.data(), sizeof(int) * nbl.size(), hipMemcpyHostToDevice, p->stream));
   }
   if (!hid.empty())
-    HIP_TRY(hipMemcpyAsync(hl + nbl.size() + hrp.size(), hid.data(), sizeof(int) * hid.size(),
+    HIP_TRY(hipMemcpyAsync(hl + nbl.size() + hcnt.size(), hid.data(), sizeof(int) * hid.size(),
                            hipMemcpyHostToDevice, p->stream));
   HIP_TRY(hipStreamSynchronize(p->stream));
   return OPT_OK;
