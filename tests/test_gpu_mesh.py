@@ -196,3 +196,57 @@ def test_scrambled_ids_halo_overflow(prec):
     if prec == "fp64":
         ref, _ = o.pcg(lin.apply, lin.jtf(), lin.minv(True), 20)
         assert relmax(to_np(prob.pcg(20, variant="split")), ref) < 1e-9
+
+
+def _custom_mesh(U, edges, handles, seed=9):
+    """An ARAP mesh problem on any vertex set and edge list (fit targets at the
+    handles, U + N(0, 0.05^2); unknowns start at (U, 0) plus noise)."""
+    V = U.shape[1]
+    rng = np.random.default_rng(seed)
+    C = np.full((3, V), -1e7)
+    C[:, handles] = U[:, handles] + rng.normal(0.0, 0.05, (3, len(handles)))
+    x0 = np.concatenate([U, np.zeros((3, V))])
+    d = dict(energy="arap_mesh", V=V, edges=np.asarray(edges, np.int32).reshape(-1, 2), U=U, C=C, x0=x0,
+             handles=np.sort(handles), params=dict(w_fit=10.0, w_reg=1.0))
+    return d, x0 + 0.2 * rng.normal(size=x0.shape)
+
+
+def _degenerate(kind):
+    rng = np.random.default_rng(11)
+    if kind == "hub":
+        # vertex 0 joined to every other vertex (degree 2999, more incidence
+        # entries than a chunk stages) plus a ring through the rest
+        V = 3000
+        e = [(0, v) for v in range(1, V)] + [(v, v + 1) for v in range(1, V - 1)]
+        U = rng.normal(size=(3, V))
+        return _custom_mesh(U, e, rng.choice(V, 30, replace=False))
+    if kind == "isolated":
+        # a level-2 icosphere followed by 200 vertices with no edge
+        v, _, e = w.icosphere(2)
+        V = len(v) + 200
+        U = np.concatenate([v.T, rng.normal(size=(3, 200))], axis=1)
+        return _custom_mesh(U, e, rng.choice(V, 20, replace=False))
+    # no edges at all: only the fit terms of the handles remain
+    V = 300
+    return _custom_mesh(rng.normal(size=(3, V)), np.zeros((0, 2), np.int32), rng.choice(V, 25, replace=False))
+
+
+@pytest.mark.parametrize("kind", ["hub", "isolated", "no_edges"])
+def test_degenerate_graphs_fp64(kind):
+    """Graphs the staged gather must also handle: a vertex of very high degree
+    (its chunk's incidence slice overflows the staged slots and its halo the
+    cap), vertices without edges (zero diagonal, M^-1 = 0), no edges at all."""
+    d, x = _degenerate(kind)
+    e = o.make_energy(d)
+    lin = o.Linearization(e, x)
+    prob = make_problem(d, "fp64")
+    xt = to_dev(prob, x)
+    assert abs(prob.linearize(xt) - lin.E) <= 1e-12 * lin.E
+    b, dg = prob.eval_jtf()
+    assert relmax(to_np(b), lin.jtf()) < 1e-12
+    assert relmax(to_np(dg), lin.diag) < 1e-12
+    p = np.random.default_rng(3).normal(size=lin.diag.size)
+    assert relmax(to_np(prob.apply_jtj(to_dev(prob, p))), lin.apply(p)) < 1e-12
+    ref, _ = o.pcg(lin.apply, lin.jtf(), lin.minv(True), 15)
+    for variant in ("split", "fused"):
+        assert relmax(to_np(prob.pcg(15, variant=variant)), ref) < 1e-9, variant
