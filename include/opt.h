@@ -132,8 +132,13 @@ int opt_workspace_size(const opt_problem_desc* desc, size_t* bytes);
  * collapse into one call).  `workspace` is caller-owned device memory of at least
  * opt_workspace_size() bytes, 256-byte aligned, that must outlive the handle.
  * `hip_stream` is a hipStream_t (NULL = the null stream).  For a graph the edge
- * list is sorted into a per-vertex incidence list inside the workspace (this
- * synchronises the stream once).  On failure *out is set to NULL.
+ * list is sorted into a per-vertex incidence list inside the workspace, and for
+ * an energy whose product stages vertices in LDS (ARAP mesh) each chunk of 256
+ * consecutive vertex ids gets a list of its outside neighbours there too; the
+ * host builds both in O(V + E) and copies them (this synchronises the stream
+ * once).  Results do not depend on the vertex numbering beyond summation order,
+ * but neighbours with nearby ids (a spatial ordering) make the products faster.
+ * On failure *out is set to NULL.
  */
 int opt_problem_create(const opt_problem_desc* desc, void* workspace, size_t workspace_bytes,
                        void* hip_stream, opt_problem** out);
