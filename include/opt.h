@@ -3,7 +3,7 @@
  * solver for MI355X (gfx950), after Opt (DeVito et al., arXiv 1604.06525).
  *
  * The solver minimises E(x) = sum_r f_r(x)^2 (Sec. 4) for a fixed set of energies
- * written by hand (the energy listings of Appendix C), on a 2D pixel grid or on
+ * written by hand (the energies defined in Appendix C), on a 2D pixel grid or on
  * a graph.  Every outer iteration linearises F at x and solves the normal
  * equations J^T J d = -J^T F (Sec. 4; the factor 2 on both sides cancels) with a
  * Jacobi-preconditioned conjugate gradient started from d = 0 (Sec. 4.1), whose

@@ -6,7 +6,7 @@ package: only ``tests/``, ``__graft_entry__.smoke()`` and the ``cpu_baseline`` l
 
 What it computes (Opt, arXiv 1604.06525):
 
-* residual vectors F(x) of each energy, written from the energy listings of
+* residual vectors F(x) of each energy, written from the energies defined in
   Appendix C (Figs. 24-27, 30; Laplacian of Figs. 3 and 5), in plain vectorised
   numpy, FP64 (``energies``);
 * an explicit sparse Jacobian J(x) (scipy CSR).  Entries come from complex-step

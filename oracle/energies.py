@@ -1,6 +1,6 @@
-"""Residual definitions of the energies, FP64, from the paper's listings.
+"""Residual definitions of the energies, FP64, written from the energies the paper defines.
 
-Conventions (Sec. 3 and the listings of Appendix C):
+Conventions (Sec. 3 and the energy definitions of Appendix C):
 
 * A grid site is (i, j): i runs along the width W (first dimension), j along the
   height H.  Arrays are [c, H, W]; the unknown vector is the planes flattened,
