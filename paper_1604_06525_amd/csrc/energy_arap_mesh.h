@@ -68,8 +68,10 @@ struct ArapMesh {
   using Real = T;
   static constexpr bool kGraph = true;
   static constexpr int C = 6;
-  static constexpr int kStatePlanes = 6;  // cos/sin of a_x, a_y, a_z
-  static constexpr int kOwnState = 6;
+  // per vertex: cos/sin of a_x, a_y, a_z, then U (copied at linearisation so
+  // that everything a neighbour's product term reads is one 36-byte record)
+  static constexpr int kStatePlanes = 9;
+  static constexpr int kOwnState = 9;
   static constexpr int kRadius = 1;
   enum : uint32_t { ACTIVE = 1, INGRID = 2, FIT0 = 4 };  // FIT0 << k: component k
   static constexpr bool kStaged = true;  // pcg_a stages a vertex chunk in LDS (apply_staged)
@@ -81,14 +83,14 @@ struct ArapMesh {
   Halo halo;                     // pcg_a's staging lists
   const T* __restrict__ U;       // [3][n]
   const T* __restrict__ Ct;      // [3][n]
-  T* __restrict__ trig;          // [n][6]: per vertex cos/sin of the three angles
+  T* __restrict__ trig;          // [n][9]: per vertex cos/sin of the three angles, U
   uint8_t* __restrict__ flags;
   T wf, wr;
   double wf_d, wr_d;
 
-  __device__ __forceinline__ T state_at(int k, int v) const { return trig[(size_t)v * 6 + k]; }
+  __device__ __forceinline__ T state_at(int k, int v) const { return trig[(size_t)v * 9 + k]; }
 
-  __device__ __forceinline__ EulerTrig<T> trig_at(int v) const { return trig_from(trig + (size_t)v * 6); }
+  __device__ __forceinline__ EulerTrig<T> trig_at(int v) const { return trig_from(trig + (size_t)v * 9); }
   // the six state values of a vertex (cos, sin of a_x, a_y, a_z) at q
   __device__ __forceinline__ static EulerTrig<T> trig_from(const T* q) {
     EulerTrig<T> t;
@@ -141,8 +143,9 @@ struct ArapMesh {
     for (int k = 0; k < 3; ++k) {
       T s, c;
       sincos_t(x[(size_t)(3 + k) * n + v], &s, &c);
-      trig[(size_t)v * 6 + 2 * k] = c;
-      trig[(size_t)v * 6 + 2 * k + 1] = s;
+      trig[(size_t)v * 9 + 2 * k] = c;
+      trig[(size_t)v * 9 + 2 * k + 1] = s;
+      trig[(size_t)v * 9 + 6 + k] = U[(size_t)k * n + v];
     }
     uint32_t f = ACTIVE | INGRID;
 #pragma unroll
@@ -203,13 +206,11 @@ struct ArapMesh {
                  (uint32_t)flags[v], g);
   }
 
-  // The staged values of vertex u: cos/sin of its angles, then U.
+  // The staged values of vertex u: its state record (cos/sin of its angles, U).
   __device__ __forceinline__ Vals<T, 9> stage_vals(int u) const {
     Vals<T, 9> r;
 #pragma unroll
-    for (int k = 0; k < 6; ++k) r.v[k] = trig[(size_t)u * 6 + k];
-#pragma unroll
-    for (int c = 0; c < 3; ++c) r.v[6 + c] = U[(size_t)c * n + u];
+    for (int k = 0; k < 9; ++k) r.v[k] = trig[(size_t)u * 9 + k];
     return r;
   }
 
