@@ -298,6 +298,11 @@ CONFIGS = [
     ("flow_1920x1080_gn10x50_mixed", lambda w: w.optical_flow(1920, 1080, seed=4), "mixed", "gn", 10, 50, (24, 8)),
     ("flow_1920x1080_gn10x50_fp64", lambda w: w.optical_flow(1920, 1080, seed=4), "fp64", "gn", 10, 50, (24, 8)),
     ("poisson_1024x1024_gn10x50_mixed", lambda w: w.poisson_edit(1024, 1024, seed=5), "mixed", "gn", 10, 50, (24, 1)),
+    # large grids: 4096^2 still takes the fused kernel; at 8192^2 a vector
+    # (805 MB) exceeds the fused kernel's 256 MB buffer range and the split
+    # form runs
+    ("warp_4096x4096_gn10x50_mixed", lambda w: w.arap_warp(4096, 4096, seed=6), "mixed", "gn", 10, 50, (24, 13)),
+    ("warp_8192x8192_gn5x50_mixed", lambda w: w.arap_warp(8192, 8192, seed=7), "mixed", "gn", 5, 50, (24, 13)),
     # the warp with explicit connectivity (the lattice's 4-neighbour edge list):
     # the implicit vs explicit comparison of the paper (Fig. 18, GN 8 x 100)
     ("warp_1024x1024_gn8x100_mixed", lambda w: w.arap_warp(1024, 1024, seed=2), "mixed", "gn", 8, 100, (24, 13)),
