@@ -298,9 +298,8 @@ CONFIGS = [
     ("flow_1920x1080_gn10x50_mixed", lambda w: w.optical_flow(1920, 1080, seed=4), "mixed", "gn", 10, 50, (24, 8)),
     ("flow_1920x1080_gn10x50_fp64", lambda w: w.optical_flow(1920, 1080, seed=4), "fp64", "gn", 10, 50, (24, 8)),
     ("poisson_1024x1024_gn10x50_mixed", lambda w: w.poisson_edit(1024, 1024, seed=5), "mixed", "gn", 10, 50, (24, 1)),
-    # large grids: 4096^2 still takes the fused kernel; at 8192^2 a vector
-    # (805 MB) exceeds the fused kernel's 256 MB buffer range and the split
-    # form runs
+    # large grids: at 8192^2 a vector (805 MB) is past the regular fused
+    # instantiation's 256 MB buffer range and its large-grid instantiation runs
     ("warp_4096x4096_gn10x50_mixed", lambda w: w.arap_warp(4096, 4096, seed=6), "mixed", "gn", 10, 50, (24, 13)),
     ("warp_8192x8192_gn5x50_mixed", lambda w: w.arap_warp(8192, 8192, seed=7), "mixed", "gn", 5, 50, (24, 13)),
     # the warp with explicit connectivity (the lattice's 4-neighbour edge list):
@@ -319,11 +318,15 @@ def _as_graph(d):
 
 def pcg_form(energy, channels, n, prec, graph=False):
     """Which PCG form the library runs by default: a fused kernel for grid
-    energies (each internal vector under 256 MB), the split form for graphs."""
+    energies, the split form for graphs.  The shape-from-shading kernel needs
+    its vectors and state under 256 MB; the radius-1 kernel has an
+    instantiation for larger grids (buffers based at each strip's first row)."""
     tsize = 8 if prec == "fp64" else 4
-    ok = (energy in ("arap_warp", "poisson", "flow", "sfs") and not graph
-          and channels * n * tsize <= (1 << 28))
-    return "fused" if ok else "split"
+    if graph or energy not in ("arap_warp", "poisson", "flow", "sfs"):
+        return "split"
+    if energy == "sfs" and 4 * n * tsize > (1 << 28):
+        return "split"
+    return "fused"
 
 
 def configs_main(args):

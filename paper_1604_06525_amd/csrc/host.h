@@ -139,6 +139,9 @@ class Impl {
   virtual int pcg_b(int k, int L, PrecondArgs pa, int lm_gate) = 0;
   virtual int fused(int iter, int L, PrecondArgs pa, int lm_gate) = 0;
   virtual bool has_fused() const = 0;
+  // the fused form runs the instantiation for vectors past 256 MB (solo only:
+  // the server runs such problems in the split form)
+  virtual bool fused_is_big() const { return false; }
   virtual int apply_jtj(const void* p, void* q, PrecondArgs pa) = 0;
   virtual int apply_step(void* x, int lm_gate) = 0;
   virtual int cost(const void* x, const void* delta, int lm_gate) = 0;

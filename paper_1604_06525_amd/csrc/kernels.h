@@ -543,7 +543,9 @@ struct FusedBufs {
   const T* diag;   // diag(J^T J) from init (read by energies that do not recompute it)
 };
 
-template <class E, bool DAMP>
+// BIG: the instantiation for grids whose internal vectors pass 256 MB; its
+// raw buffers are based at each strip's first row (see run).
+template <class E, bool DAMP, bool BIG = false>
 struct FusedArgs {
   E e;
   FusedBufs<typename E::Real> b;
@@ -576,8 +578,8 @@ __device__ __forceinline__ void unroll_seq(std::integer_sequence<int, I...>, F f
 template <typename T>
 constexpr int kPrefetchOf = sizeof(T) > 4 ? 2 : 4;
 
-template <class E, bool DAMP>
-__device__ __forceinline__ void run(const FusedArgs<E, DAMP>& a, VG g, int iter) {
+template <class E, bool DAMP, bool BIG>
+__device__ __forceinline__ void run(const FusedArgs<E, DAMP, BIG>& a, VG g, int iter) {
   using T = typename E::Real;
   using Row = StreamRow<E, DAMP>;
   constexpr int C = E::C, NS = E::kStatePlanes;
@@ -616,19 +618,26 @@ __device__ __forceinline__ void run(const FusedArgs<E, DAMP>& a, VG g, int iter)
   // One raw buffer per vector and for the per-site state and flags.  A site's
   // channels are adjacent, so each row of a vector is one wide load per lane.
   // A lane or row off the strip uses an out-of-range offset: its loads return
-  // 0, its stores are dropped.
+  // 0, its stores are dropped.  The BIG instantiation bases every buffer at
+  // the first row the strip touches (yb) and covers only its rows ylo..yhi, so
+  // that offsets stay small however large the grid is (the other keeps whole
+  // vectors: fewer live registers, which the FP32 warp kernel needs).
   constexpr unsigned VB = C * sizeof(T), SB = (NS > 0 ? NS : 1) * sizeof(T);
-  const size_t vbytes = (size_t)n * VB;
-  const Buf<T> Buin = Buf<T>::make(pick(a.b.u, iter < 0 ? 0 : (iter & 1)), vbytes);
-  const Buf<T> Bpin = Buf<T>::make(pick(a.b.p, (iter + 1) & 1), read_pold ? vbytes : 0);
-  const Buf<T> Bx = Buf<T>::make(a.b.x, xupd ? vbytes : 0);
-  const Buf<T> Buout = Buf<T>::make(pick(a.b.u, (iter + 1) & 1), write_out ? vbytes : 0);
-  const Buf<T> Bpout = Buf<T>::make(pick(a.b.p, iter & 1), write_out ? vbytes : 0);
-  const Buf<T> Bst = Buf<T>::make(e.state_base(), NS > 0 ? (size_t)n * SB : 0);
-  const Buf<uint8_t> Bf = Buf<uint8_t>::make(e.flags, (size_t)n);
-  // Byte offsets are a per-lane column part plus a scalar row part.  Either
-  // part may be kBufOutOfRange; the sum then stays at or above 2^28 (no part
-  // in range reaches 2^28), so the access is out of range as required.
+  const int yb = BIG ? ylo : 0;
+  const size_t span = BIG ? (has_strip ? (size_t)(yhi - ylo + 1) * W : 0) : (size_t)n;  // sites
+  const size_t rb = BIG && has_strip ? (size_t)yb * W : 0;                               // first site
+  const size_t vbytes = span * VB;
+  const Buf<T> Buin = Buf<T>::make(pick(a.b.u, iter < 0 ? 0 : (iter & 1)) + rb * C, vbytes);
+  const Buf<T> Bpin = Buf<T>::make(pick(a.b.p, (iter + 1) & 1) + rb * C, read_pold ? vbytes : 0);
+  const Buf<T> Bx = Buf<T>::make(a.b.x + rb * C, xupd ? vbytes : 0);
+  const Buf<T> Buout = Buf<T>::make(pick(a.b.u, (iter + 1) & 1) + rb * C, write_out ? vbytes : 0);
+  const Buf<T> Bpout = Buf<T>::make(pick(a.b.p, iter & 1) + rb * C, write_out ? vbytes : 0);
+  const Buf<T> Bst = Buf<T>::make(e.state_base() + (NS > 0 ? rb * NS : 0), NS > 0 ? span * SB : 0);
+  const Buf<uint8_t> Bf = Buf<uint8_t>::make(e.flags + rb, span);
+  // Byte offsets are a per-lane column part plus a scalar row part (rows
+  // counted from yb).  Either part may be kBufOutOfRange; the sum then stays at
+  // or above 2^28 (no part in range reaches 2^28: the host launches a form
+  // only where that holds), so the access is out of range as required.
   const unsigned lane_v = colin ? (unsigned)col * VB : kBufOutOfRange;
   const unsigned lane_s = colin ? (unsigned)col * SB : kBufOutOfRange;
   const unsigned lane_f = colin ? (unsigned)col : kBufOutOfRange;
@@ -638,7 +647,7 @@ __device__ __forceinline__ void run(const FusedArgs<E, DAMP>& a, VG g, int iter)
   Row ring[N];
   auto issue = [&](Row& R, int y) {
     const bool in = y >= ylo && y <= yhi;
-    const unsigned rs = (unsigned)(y * W);
+    const unsigned rs = (unsigned)((y - yb) * W);
     if constexpr (NS > 0) {
       buf_loadv<NS>(Bst, lane_s + (in ? rs * SB : kBufOutOfRange), 0, R.st);
     } else {
@@ -682,7 +691,7 @@ __device__ __forceinline__ void run(const FusedArgs<E, DAMP>& a, VG g, int iter)
         // the update alpha_{i-1} p_{i-1} deferred from the previous iteration
         const T ap = (T)alpha_prev;
         for (int y = y0; y < y1; ++y) {
-          const unsigned s = (unsigned)(y * W + col);
+          const unsigned s = (unsigned)((y - yb) * W + col);
           if (!(Bf.load(s, 0) & E::ACTIVE)) continue;
           T pv[C], xv[C];
           buf_loadv<C>(Bpin, s * VB, 0, pv);
@@ -755,7 +764,7 @@ __device__ __forceinline__ void run(const FusedArgs<E, DAMP>& a, VG g, int iter)
         });
         const bool act = R1.f & E::ACTIVE;
         const bool prod = y1r >= y0 && y1r < y1;  // uniform
-        const unsigned ox = act ? lane_o + ((prod && xupd) ? (unsigned)(y1r * W) * VB : kBufOutOfRange)
+        const unsigned ox = act ? lane_o + ((prod && xupd) ? (unsigned)((y1r - yb) * W) * VB : kBufOutOfRange)
                                 : kBufOutOfRange;
         buf_loadv<C>(Bx, ox, 0, R1.x);
         T gs = 0, dd = 0;
@@ -794,7 +803,7 @@ __device__ __forceinline__ void run(const FusedArgs<E, DAMP>& a, VG g, int iter)
         });
         const bool act = R2.f & E::ACTIVE;
         d_acc += (double)((out_lane && (R2.f & E::INGRID)) ? jq : T(0));
-        const unsigned o = lane_o + (unsigned)(yo * W) * VB;
+        const unsigned o = lane_o + (unsigned)((yo - yb) * W) * VB;
         const unsigned ox = (act && xupd) ? o : kBufOutOfRange;
         T pv[C], xv[C];
 #pragma unroll
@@ -1028,8 +1037,20 @@ __device__ __forceinline__ void run(const GatherArgs& a, VG, int) {
 // range starts at a multiple of 8, so a problem's block i runs on XCD i mod 8 as
 // it would alone.  One kernel binary for both means a problem computes the same
 // bits alone and in any batch.
+// The BIG FP32 fused iteration is held to the registers of two waves per SIMD
+// (its per-strip buffer bases cost two spills instead of a third register bank).
 template <class A>
-__global__ void __launch_bounds__(kBlock) k_batch(const A* __restrict__ table,
+struct MinWavesOf {
+  static constexpr int value = 1;
+};
+template <class E, bool DAMP>
+struct MinWavesOf<FusedArgs<E, DAMP, true>> {
+  static constexpr int value = sizeof(typename E::Real) == 4 ? 2 : 1;
+};
+
+template <class A>
+__global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(MinWavesOf<A>::value)))
+k_batch(const A* __restrict__ table,
                                                   const int* __restrict__ start,
                                                   const int* __restrict__ slot_of, int n, int iter) {
   const int b = blockIdx.x;

@@ -323,10 +323,10 @@ class ImplT final : public Impl {
     }
   }
 
-  template <bool DAMP>
-  FusedArgs<E, DAMP> fused_args(int L, PrecondArgs pa, int lm, int* grid) const {
+  template <bool DAMP, bool BIG = false>
+  FusedArgs<E, DAMP, BIG> fused_args(int L, PrecondArgs pa, int lm, int* grid) const {
     const StripGeom g = geom(DAMP);
-    FusedArgs<E, DAMP> a = blank<FusedArgs<E, DAMP>>();
+    FusedArgs<E, DAMP, BIG> a = blank<FusedArgs<E, DAMP, BIG>>();
     a.e = e_;
     a.b.u[0] = rbuf(0);
     a.b.u[1] = rbuf(1);
@@ -396,16 +396,47 @@ class ImplT final : public Impl {
   int pcg_b(int k, int L, PrecondArgs, int lm) override {
     return go(ROW_PCGB, pcgb_args(L, lm), nblk(), k, "pcg_b");
   }
-  // The fused kernel addresses each vector through a raw buffer of < 256 MB.
-  bool has_fused() const override {
-    return kFusedOk && (size_t)E::C * e_.n * sizeof(T) <= (size_t(1) << 28);
+  // The fused kernels address memory through raw buffers whose in-range byte
+  // offsets stay under 2^28.  Whole vectors (and the state) of at most 256 MB:
+  // the regular instantiation.  Past that the radius-1 kernel's BIG
+  // instantiation bases its buffers at each strip's first row, so only the
+  // rows one strip touches (its own plus two halo rows each side) must span
+  // less; the shape-from-shading kernel has no such form.
+  bool whole_fits() const {
+    const size_t rec = std::max<size_t>((size_t)E::C, (size_t)std::max(E::kStatePlanes, 1)) * sizeof(T);
+    return rec * e_.n <= (size_t(1) << 28);
   }
+  bool span_fits() const {
+    const size_t rec = std::max<size_t>((size_t)E::C, (size_t)std::max(E::kStatePlanes, 1)) * sizeof(T);
+    for (bool damped : {false, true}) {
+      const StripGeom g = geom(damped);
+      const size_t rows = (size_t)g.rq + (g.rr > 0 ? 1 : 0) + 4;
+      if (rows * (size_t)e_.W * rec >= (size_t(1) << 28)) return false;
+    }
+    return true;
+  }
+  bool has_fused() const override {
+    if constexpr (!kFusedOk) {
+      return false;
+    } else if constexpr (kSfs) {
+      return whole_fits();
+    } else {
+      return whole_fits() || span_fits();
+    }
+  }
+  bool fused_is_big() const override { return has_fused() && !whole_fits(); }
   // iter = -1 is the priming launch (it writes only partials).
   int fused(int iter, int L, PrecondArgs pa, int lm) override {
     if constexpr (!kFusedOk) {
       return fail(OPT_EUNSUPPORTED, "no fused PCG kernel for this energy");
     } else {
       int grid = 0;
+      if constexpr (!kSfs) {
+        if (fused_is_big()) {
+          if (pa.damped) return go(ROW_FUSED, fused_args<true, true>(L, pa, lm, &grid), grid, iter, "fused");
+          return go(ROW_FUSED, fused_args<false, true>(L, pa, lm, &grid), grid, iter, "fused");
+        }
+      }
       if (pa.damped) return go(ROW_FUSED, fused_args<true>(L, pa, lm, &grid), grid, iter, "fused");
       return go(ROW_FUSED, fused_args<false>(L, pa, lm, &grid), grid, iter, "fused");
     }

@@ -372,7 +372,7 @@ int opt_server_submit(opt_server* sv, const opt_problem_desc* desc, void* unknow
   s.ws_bytes = need;
   s.x = unknowns;
   s.sp = *sp;
-  s.fused = sp->pcg_variant == OPT_PCG_FUSED && p->impl->has_fused();
+  s.fused = sp->pcg_variant == OPT_PCG_FUSED && p->impl->has_fused() && !p->impl->fused_is_big();
   s.fill = p->impl->gpu_fill(s.fused, sp->method == OPT_LM);
   s.p = std::move(p);
   *ticket = s.ticket;

@@ -262,3 +262,19 @@ def test_pcg_exact_stop_keeps_last_update(precision, pcg_iters):
     assert rep["cost_trace"][0] == costs[0]
     assert rep["cost_final"] == 0.0
     assert np.array_equal(to_np(xt).reshape(3, H, W), np.asarray(xo).reshape(3, H, W))
+
+
+def test_fused_beyond_256mb_vectors_matches_split():
+    """FP64 warp on 3400 x 3400 sites: each internal vector is 277 MB and the
+    state 370 MB, past the 2^28-byte offsets of a whole-vector raw buffer, so
+    the fused form runs its instantiation with buffers based at each strip's
+    first row.  Its PCG iterates must equal the split (textbook) form's, which
+    is parity-tested against the oracle at smaller sizes, to the FP64
+    tolerance."""
+    d = w.arap_warp(3400, 3400, seed=12)
+    prob = make_problem(d, "fp64")
+    xt = to_dev(prob, d["x0"])
+    prob.linearize(xt)
+    fused = to_np(prob.pcg(12, variant="fused"))
+    split = to_np(prob.pcg(12, variant="split"))
+    assert relmax(fused, split) < 1e-9
