@@ -260,7 +260,10 @@ int opt_energy_channels(int32_t energy);
  * runs each stage of that iteration as one launch per energy kind covering all
  * of its requests.  Each request keeps the arithmetic and reduction order of
  * opt_solve with the same parameters, so its result is bit-identical to solving
- * it alone, whatever else runs beside it.
+ * it alone, whatever else runs beside it.  One exception: a grid problem whose
+ * internal vectors pass 256 MB runs the fused PCG form alone but the split form
+ * in a server (the server batches only the regular fused instantiation); its
+ * served result then equals opt_solve with OPT_PCG_SPLIT bit for bit.
  *
  * Memory: the caller hands the server one device arena (256-byte aligned).  The
  * first opt_server_reserved_bytes(max_slots) bytes hold the server's argument
