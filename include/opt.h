@@ -237,12 +237,19 @@ int opt_profile_read(opt_problem* prob, double* pcg_ms, int64_t* pcg_iters);
  *   both 0 (automatic): two strips per SIMD, rows split evenly, at least 4
  *     rows.
  * Shorter strips mean more wavefronts in flight but more halo rows read twice.
+ *   large_grid_form = 1: run the fused kernel's large-grid form (each strip
+ *     addresses its rows from its own first row; the form a grid whose
+ *     vectors pass 256 MB always runs) even on a grid that does not need it.
+ *     Same iterates up to rounding; for checking and timing that form.  0: the
+ *     form is chosen by size.  Ignored by shape from shading, which has no
+ *     such form.
  * opt_problem_get_tuning returns the values in force (resolved: the largest
  * strip height and the strips per SIMD, rounded up).
  */
 typedef struct {
   int32_t strip_rows;
   int32_t waves_per_simd;
+  int32_t large_grid_form;
 } opt_tuning;
 
 int opt_problem_set_tuning(opt_problem* prob, const opt_tuning* tuning);

@@ -129,9 +129,12 @@ class LMParams:
     min_rel_decrease: float = 1e-3
 
 
-def levenberg_marquardt(energy, x0, outer, inner, prm=LMParams(), use_precond=True):
+def levenberg_marquardt(energy, x0, outer, inner, prm=LMParams(), use_precond=True, history=None):
     """Returns (x, costs, accepted): costs[k] = E at the start of iteration k, plus
-    the final cost; accepted[k] tells whether iteration k took its step."""
+    the final cost; accepted[k] tells whether iteration k took its step.  If
+    ``history`` is a list, one dict per iteration is appended to it: the radius
+    the iteration used, its gain ratio rho and model decrease m, whether it
+    accepted, and the radius and nu it left."""
     x = np.asarray(x0, float).ravel().copy()
     radius, nu = prm.radius0, 2.0
     costs, accepted = [], []
@@ -160,5 +163,8 @@ def levenberg_marquardt(energy, x0, outer, inner, prm=LMParams(), use_precond=Tr
             radius = radius / nu
             nu = 2.0 * nu
             accepted.append(False)
+        if history is not None:
+            history.append(dict(radius_used=1.0 / lam, lam=lam, rho=rho, m=m, accepted=accepted[-1],
+                                radius=radius, nu=nu))
     costs.append(cost(energy, x))
     return x, costs, accepted

@@ -40,7 +40,8 @@ class opt_solve_params(ctypes.Structure):
 
 
 class opt_tuning(ctypes.Structure):
-    _fields_ = [("strip_rows", ctypes.c_int32), ("waves_per_simd", ctypes.c_int32)]
+    _fields_ = [("strip_rows", ctypes.c_int32), ("waves_per_simd", ctypes.c_int32),
+                ("large_grid_form", ctypes.c_int32)]
 
 
 class opt_solve_report(ctypes.Structure):
@@ -273,16 +274,22 @@ class Problem:
                "opt_apply_jtj")
         return q
 
-    def set_tuning(self, strip_rows=0, waves_per_simd=0):
+    def set_tuning(self, strip_rows=0, waves_per_simd=0, large_grid_form=0):
         t = opt_tuning()
         t.strip_rows = int(strip_rows)
         t.waves_per_simd = int(waves_per_simd)
+        t.large_grid_form = int(large_grid_form)
         _check(lib().opt_problem_set_tuning(self.handle, ctypes.byref(t)), "opt_problem_set_tuning")
 
     def get_tuning(self):
+        """The launch shape in force: strip_rows and waves_per_simd (resolved),
+        plus large_grid_form when it was asked for."""
         t = opt_tuning()
         _check(lib().opt_problem_get_tuning(self.handle, ctypes.byref(t)), "opt_problem_get_tuning")
-        return {"strip_rows": t.strip_rows, "waves_per_simd": t.waves_per_simd}
+        out = {"strip_rows": t.strip_rows, "waves_per_simd": t.waves_per_simd}
+        if t.large_grid_form:
+            out["large_grid_form"] = 1
+        return out
 
     def profile_enable(self, on=True):
         _check(lib().opt_profile_enable(self.handle, int(on)), "opt_profile_enable")
@@ -391,10 +398,12 @@ class Server:
         _check(lib().opt_server_cancel(self.handle, int(ticket)), "opt_server_cancel")
         self._held.pop(ticket, None)
 
-    def add_tuning(self, energy, precision, min_sites, max_sites, strip_rows=0, waves_per_simd=0):
+    def add_tuning(self, energy, precision, min_sites, max_sites, strip_rows=0, waves_per_simd=0,
+                   large_grid_form=0):
         t = opt_tuning()
         t.strip_rows = int(strip_rows)
         t.waves_per_simd = int(waves_per_simd)
+        t.large_grid_form = int(large_grid_form)
         _check(lib().opt_server_add_tuning(self.handle, ENERGIES[energy], PRECISIONS[precision],
                                            int(min_sites), int(max_sites), ctypes.byref(t)),
                "opt_server_add_tuning")

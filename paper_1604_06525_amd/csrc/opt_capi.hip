@@ -424,7 +424,13 @@ class ImplT final : public Impl {
       return whole_fits() || span_fits();
     }
   }
-  bool fused_is_big() const override { return has_fused() && !whole_fits(); }
+  bool fused_is_big() const override {
+    if constexpr (!kFusedOk || kSfs) {
+      return false;
+    } else {
+      return has_fused() && (!whole_fits() || (p_->tune.large_grid_form && span_fits()));
+    }
+  }
   // iter = -1 is the priming launch (it writes only partials).
   int fused(int iter, int L, PrecondArgs pa, int lm) override {
     if constexpr (!kFusedOk) {
@@ -793,6 +799,8 @@ int check_tuning(const opt_tuning* t) {
     return fail(OPT_EINVAL, "strip_rows %d outside [0, 2^20]", t->strip_rows);
   if (t->waves_per_simd < 0 || t->waves_per_simd > 64)
     return fail(OPT_EINVAL, "waves_per_simd %d outside [0, 64]", t->waves_per_simd);
+  if (t->large_grid_form != 0 && t->large_grid_form != 1)
+    return fail(OPT_EINVAL, "large_grid_form %d is not 0 or 1", t->large_grid_form);
   return OPT_OK;
 }
 

@@ -53,3 +53,20 @@ def f32_inputs(d):
         else:
             out[k] = v
     return out
+
+
+PCG_TOL_CAP = 1e-6
+PCG_SPREAD_MAX = 1e-8
+
+
+def pcg_tol(ref, ref2):
+    """Tolerance for PCG iterates against the oracle: 100x the oracle's own
+    spread between two valid evaluation orders of the same product (J^T(J p) and
+    (J^T J) p), at least 1e-9.  A case where CG has lost orthogonality (spread
+    above 1e-8) could not tell a wrong product from rounding, so it is refused
+    instead of being compared loosely: the tolerance never exceeds 1e-6."""
+    spread = relmax(ref2, ref)
+    assert spread <= PCG_SPREAD_MAX, f"oracle spread {spread:.2e}: this PCG case is rounding-dominated"
+    tol = max(1e-9, 100 * spread)
+    assert tol <= PCG_TOL_CAP
+    return tol

@@ -11,7 +11,7 @@ import pytest
 
 import oracle as o
 import workloads as w
-from tests.gpu_util import make_problem, relmax, require_gpu, to_dev, to_np
+from tests.gpu_util import f32_inputs, make_problem, pcg_tol, relmax, require_gpu, to_dev, to_np
 
 pytestmark = pytest.mark.gpu
 
@@ -93,12 +93,14 @@ def test_pcg(W, H, mask, precond, variant):
     xt = to_dev(prob, x)
     prob.linearize(xt)
     A = (lin.JT @ lin.J).tocsr()
-    for L in (1, 7, 8, 25):  # odd and even counts end d's paired updates both ways
+    # odd and even counts end d's paired updates both ways; without the
+    # preconditioner the 8 x 8 lattice loses orthogonality past about 20
+    # iterations (its iterates then depend on rounding order), so it stops at 15
+    Ls = (1, 7, 8, 25) if (precond or W * H > 100) else (1, 7, 8, 15)
+    for L in Ls:
         ref, _ = o.pcg(lin.apply, lin.jtf(), lin.minv(precond), L)
-        # Once CG loses orthogonality its iterates depend on rounding order; the
-        # oracle's own spread between J^T(Jp) and (J^T J)p bounds what can agree.
         ref2, _ = o.pcg(lambda v: A @ v, lin.jtf(), lin.minv(precond), L)
-        tol = max(1e-9, 100 * relmax(ref2, ref))
+        tol = pcg_tol(ref, ref2)
         got = to_np(prob.pcg(L, use_precond=precond, variant=variant))
         assert relmax(got, ref) < tol, (L, tol)
 
@@ -278,3 +280,94 @@ def test_fused_beyond_256mb_vectors_matches_split():
     fused = to_np(prob.pcg(12, variant="fused"))
     split = to_np(prob.pcg(12, variant="split"))
     assert relmax(fused, split) < 1e-9
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+@pytest.mark.parametrize("lam", [0.0, 0.3])
+def test_large_grid_form_matches_oracle(precision, lam):
+    """The fused kernel's large-grid form (every buffer based at the strip's
+    first row; in FP32 held to two waves per SIMD, with register spills), forced
+    on a small grid, gives the oracle's PCG iterates, undamped and with LM
+    damping, for odd and even iteration counts.  FP64 to the PCG tolerance;
+    FP32 against the FP64 oracle on the same FP32-rounded inputs, and against
+    the regular form."""
+    d, x = _case(70, 65, "hole")
+    if precision == "mixed":
+        d = f32_inputs(d)
+        x = np.asarray(x, np.float32).astype(np.float64)
+    e = o.make_energy(d)
+    lin = o.Linearization(e, x)
+    D = lin.damping()
+    prob = make_problem(d, precision)
+    prob.set_tuning(large_grid_form=1)
+    assert prob.get_tuning().get("large_grid_form") == 1
+    reg = make_problem(d, precision)
+    xt = to_dev(prob, x)
+    prob.linearize(xt)
+    xr = to_dev(reg, x)
+    reg.linearize(xr)
+    A = (lin.JT @ lin.J).tocsr()
+    Ls = (1, 7, 8, 25) if precision == "fp64" else (1, 7, 8)
+    for L in Ls:
+        Mi = lin.minv(True, lam, D) if lam else lin.minv(True)
+        ref, _ = o.pcg(lambda v: lin.apply(v, lam, D) if lam else lin.apply(v), lin.jtf(), Mi, L)
+        got = to_np(prob.pcg(L, lam=lam, variant="fused"))
+        if precision == "fp64":
+            ref2, _ = o.pcg(lambda v: A @ v + lam * D * v, lin.jtf(), Mi, L)
+            assert relmax(got, ref) < pcg_tol(ref, ref2), L
+        else:
+            assert relmax(got, ref) < 2e-4, (L, relmax(got, ref))
+            assert relmax(got, to_np(reg.pcg(L, lam=lam, variant="fused"))) < 1e-5, L
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_large_grid_form_solves(precision):
+    """GN and LM solves in the large-grid form agree with the oracle (FP64: cost
+    traces to 1e-9; mixed: final cost to 1e-4 and the same accepted steps)."""
+    d = w.arap_warp(64, 64, seed=1)
+    e = o.make_energy(d)
+    xo, costs = o.gauss_newton(e, d["x0"], 5, 20)
+    xl, costs_l, acc = o.levenberg_marquardt(e, d["x0"], 5, 20)
+    prob = make_problem(d, precision)
+    prob.set_tuning(large_grid_form=1)
+    xt = to_dev(prob, d["x0"])
+    rep = prob.solve(xt, method="gn", outer_iters=5, pcg_iters=20)
+    xt2 = to_dev(prob, d["x0"])
+    rep_l = prob.solve(xt2, method="lm", outer_iters=5, pcg_iters=20)
+    assert rep_l["steps_accepted"] == sum(acc)
+    if precision == "fp64":
+        assert np.allclose(rep["cost_trace"], costs, rtol=1e-9, atol=0)
+        assert np.allclose(rep_l["cost_trace"][:len(costs_l)], costs_l, rtol=1e-9, atol=0)
+    else:
+        assert abs(rep["cost_final"] - costs[-1]) <= 1e-4 * costs[-1]
+        assert abs(rep_l["cost_final"] - costs_l[-1]) <= 1e-4 * costs_l[-1]
+
+
+@pytest.mark.parametrize("variant", ["fused", "split"])
+def test_lm_step_control_closed_form(variant):
+    """LM step control on a problem whose only residuals are linear (the
+    centre pixel of a masked 3 x 3 warp, fit terms only): the gain ratio is 1, so
+    every step is taken and the radius triples; from radius 1 the damping is
+    lambda = 1, 1/3, 1/9, 1/27 and x - C shrinks by (1/2)(1/4)(1/10)(1/28).
+    With an acceptance threshold above 1 every step is rejected, x does not
+    move, and from radius 1e-30 the radius (halved, then divided by 4, 8, 16)
+    falls below 1e-32 after four iterations."""
+    from tests.test_oracle_pins import _one_pixel_warp
+    d = _one_pixel_warp()
+    prob = make_problem(d, "fp64")
+    xt = to_dev(prob, d["x0"])
+    rep = prob.solve(xt, method="lm", outer_iters=4, pcg_iters=3, lm_radius0=1.0, pcg_variant=variant)
+    assert rep["steps_accepted"] == 4 and rep["outer_done"] == 4
+    xs = to_np(xt).reshape(3, 3, 3)
+    assert np.allclose([xs[0, 1, 1] - 20.0, xs[1, 1, 1] - 30.0], np.array([2.0, -1.5]) / 2240.0,
+                       rtol=0, atol=1e-13)
+    wf2 = d["params"]["w_fit"] ** 2
+    assert rep["cost_final"] == pytest.approx(wf2 * (2.0 ** 2 + 1.5 ** 2) / 2240.0 ** 2, rel=1e-9)
+    xt = to_dev(prob, d["x0"])
+    rep = prob.solve(xt, method="lm", outer_iters=5, pcg_iters=3, lm_radius0=1.0, lm_min_rel_decrease=2.0,
+                     pcg_variant=variant)
+    assert rep["steps_accepted"] == 0 and rep["outer_done"] == 5
+    assert np.array_equal(to_np(xt), d["x0"].ravel())
+    rep = prob.solve(xt, method="lm", outer_iters=10, pcg_iters=3, lm_radius0=1e-30, lm_radius_min=1e-32,
+                     lm_min_rel_decrease=2.0, pcg_variant=variant)
+    assert rep["outer_done"] == 4 and rep["steps_accepted"] == 0

@@ -3,7 +3,8 @@ warp) against the FP64 oracle, through the C ABI.
 
 Tolerances: FP64 operator products (J^T F, diag, J^T J p) agree to 1e-12 of
 their largest entry; FP64 PCG iterates to 1e-9 (or 100x the oracle's own spread
-between two valid evaluation orders, once CG has lost orthogonality); FP64 GN and
+between two valid evaluation orders, never above 1e-6: cases where CG has lost
+orthogonality are not compared); FP64 GN and
 LM cost traces to 1e-9 relative; mixed precision to 1e-4 relative final cost.
 Sizes span several 64 x 16 tiles and end in ragged partial tiles.
 """
@@ -12,7 +13,7 @@ import pytest
 
 import oracle as o
 import workloads as w
-from tests.gpu_util import f32_inputs, make_problem, relmax, require_gpu, to_dev, to_np
+from tests.gpu_util import pcg_tol, f32_inputs, make_problem, relmax, require_gpu, to_dev, to_np
 
 pytestmark = pytest.mark.gpu
 
@@ -44,9 +45,19 @@ def _warp(W, H, seed=3):
     return d, np.where((d["mask"] == 0)[None], x, d["x0"])
 
 
+# Shape-from-shading cases use distinct focal lengths and centre coordinates and
+# nine distinct non-zero lighting coefficients, so that a swapped intrinsic, a
+# swapped normal component or a wrong lighting derivative changes the result.
+SFS_LIGHT = (0.5, 0.07, -0.3, 0.04, 0.03, -0.02, 0.05, 0.06, -0.04)
+
+
+def _sfs_general(W, H, seed=2, **kw):
+    return w.shape_from_shading(W, H, seed=seed, focal=(0.95 * W, 1.1 * W),
+                                center=((W - 1) / 2 + 1.3, (H - 1) / 2 - 0.7), lighting=SFS_LIGHT, **kw)
+
+
 def _sfs(W, H, seed=2):
-    d = w.shape_from_shading(W, H, seed=seed, invalid="hole" if W > 20 else "none",
-                             edge_zero_frac=0.1)
+    d = _sfs_general(W, H, seed=seed, invalid="hole" if W > 20 else "none", edge_zero_frac=0.1)
     rng = np.random.default_rng(seed)
     x = d["x0"] + 1e-4 * rng.normal(size=d["x0"].shape)
     return d, np.where((d["D"] > 0)[None], x, d["x0"])
@@ -87,10 +98,13 @@ def test_pcg_fp64(kind, W, H, variant):
     prob.linearize(xt)
     A = (lin.JT @ lin.J).tocsr()
     for precond in (True, False):
-        for L in (1, 9, 30):
+        # without the preconditioner the 9 x 7 grids lose orthogonality past
+        # about 15 iterations (iterates then depend on rounding order)
+        Ls = (1, 9, 30) if (precond or W * H > 100) else (1, 9, 12)
+        for L in Ls:
             ref, _ = o.pcg(lin.apply, lin.jtf(), lin.minv(precond), L)
             ref2, _ = o.pcg(lambda v: A @ v, lin.jtf(), lin.minv(precond), L)
-            tol = max(1e-9, 100 * relmax(ref2, ref))
+            tol = pcg_tol(ref, ref2)
             got = to_np(prob.pcg(L, use_precond=precond, variant=variant))
             assert relmax(got, ref) < tol, (precond, L, tol)
 
@@ -112,28 +126,39 @@ def test_gn_fp64(kind, variant):
 def test_gn_mixed(kind):
     K = 4
     if kind == "sfs":
-        # The smoothness residuals of shape from shading are switched on and off
-        # by a threshold (0.01) on neighbouring depth differences (Fig. 26).  On
-        # this workload the first GN step already brings some differences within
-        # about 2e-5 of it, and a later FP32 iterate may then select other
-        # residuals than the FP64 one.  The comparison is made over one outer
-        # iteration, with its premise (no difference within 1e-6 of the
-        # threshold at the points where the mask is evaluated) checked below.
-        d = w.shape_from_shading(130, 70, seed=2)
-        K = 1
+        d = _sfs_general(130, 70)
     else:
         d, _ = MAKERS[kind](130, 70)
     e = o.make_energy(d)
     xo, costs = o.gauss_newton(e, d["x0"], K, 20)
     if kind == "sfs":
-        for xv in (d["x0"], xo):
-            X = np.asarray(xv, float).reshape(d["H"], d["W"])
-            dd = np.concatenate([np.abs(np.diff(X, axis=0)).ravel(), np.abs(np.diff(X, axis=1)).ravel()])
-            assert np.min(np.abs(dd - 0.01)) > 1e-6
+        # The smoothness residuals of shape from shading are switched on and off
+        # by a threshold (0.01) on neighbouring depth differences (Fig. 26),
+        # evaluated at each linearisation point.  FP32 and FP64 iterates select
+        # the same residuals only if no difference that enters the test lies
+        # near the threshold: checked at every outer iteration of the oracle.
+        assert sfs_mask_margin(e, d["x0"], K, 20) > 1e-4
     prob = make_problem(d, "mixed")
     xt = to_dev(prob, d["x0"])
     rep = prob.solve(xt, method="gn", outer_iters=K, pcg_iters=20)
     assert abs(rep["cost_final"] - costs[-1]) <= 1e-4 * costs[-1]
+
+
+def sfs_mask_margin(e, x0, K, L):
+    """Smallest distance to the 0.01 threshold of a neighbouring depth
+    difference that enters the smoothness test, over the K linearisation points
+    of the oracle's GN K x L from x0."""
+    x = np.asarray(x0, float).ravel().copy()
+    worst = np.inf
+    for _ in range(K):
+        X = x.reshape(e.H, e.W)
+        c = X[1:-1, 1:-1]
+        for nb in (X[1:-1, 2:], X[1:-1, :-2], X[2:, 1:-1], X[:-2, 1:-1]):
+            worst = min(worst, float(np.min(np.abs(np.abs(c - nb) - 0.01))))
+        lin = o.Linearization(e, x)
+        delta, _ = o.pcg(lin.apply, lin.jtf(), lin.minv(True), L)
+        x = x + delta
+    return worst
 
 
 # FP32 operator tolerances (relative to the largest entry): a product sums a few
@@ -213,6 +238,6 @@ def test_sfs_fused_launch_shapes(tuning):
         ref, _ = o.pcg(lambda v: lin.apply(v, lam, D) if lam else lin.apply(v), lin.jtf(), Mi, 14)
         # the oracle's own spread between two evaluation orders bounds what can agree
         ref2, _ = o.pcg(lambda v: JTJ @ v + lam * D * v, lin.jtf(), Mi, 14)
-        tol = max(1e-9, 100 * relmax(ref2, ref))
+        tol = pcg_tol(ref, ref2)
         got = to_np(prob.pcg(14, lam=lam, variant="fused"))
         assert relmax(got, ref) < tol, (tuning, lam, tol)

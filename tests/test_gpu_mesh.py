@@ -11,7 +11,7 @@ import torch
 
 import oracle as o
 import workloads as w
-from tests.gpu_util import f32_inputs, make_problem, relmax, require_gpu, to_dev, to_np
+from tests.gpu_util import pcg_tol, f32_inputs, make_problem, relmax, require_gpu, to_dev, to_np
 
 pytestmark = pytest.mark.gpu
 
@@ -71,7 +71,7 @@ def test_pcg_fp64(variant):
     for L in (1, 10, 30):
         ref, _ = o.pcg(lin.apply, lin.jtf(), lin.minv(True), L)
         ref2, _ = o.pcg(lambda v: A @ v, lin.jtf(), lin.minv(True), L)
-        tol = max(1e-9, 100 * relmax(ref2, ref))
+        tol = pcg_tol(ref, ref2)
         got = to_np(prob.pcg(L, variant=variant))
         assert relmax(got, ref) < tol, (L, tol)
 

@@ -33,6 +33,10 @@ def _cases():
     out.append(("sfs", d, d["x0"] + 1e-4 * rng.normal(size=d["x0"].shape)))
     d = w.shape_from_shading(9, 8, seed=4, amplitude=0.002, invalid="hole")
     out.append(("sfs_hole", d, d["x0"] + 1e-4 * rng.normal(size=d["x0"].shape)))
+    # distinct focal lengths and centre coordinates, every lighting coefficient non-zero
+    d = w.shape_from_shading(8, 7, seed=5, amplitude=0.002, focal=(6.5, 9.0), center=(3.2, 2.6),
+                             lighting=(0.5, 0.07, -0.3, 0.04, 0.03, -0.02, 0.05, 0.06, -0.04))
+    out.append(("sfs_general", d, d["x0"] + 1e-4 * rng.normal(size=d["x0"].shape)))
     d = w.arap_mesh(1, seed=3, handle_frac=0.1)
     out.append(("arap_mesh", d, _rand_state(d, rng, 0.2)))
     d = w.laplacian_grid(5, 4, seed=2)

@@ -1,9 +1,11 @@
 """Seeded synthetic inputs for the GN/LM PCG path.
 
 This package only draws inputs: lattices, constraint sets, masks, smooth random
-fields, noise textures and icosphere meshes.  It holds none of the solver's
-arithmetic (no residual, Jacobian, normal or lighting formula), so the oracle and
-the HIP path can both be fed from it without sharing any of the method.
+fields, noise textures, icosphere meshes, and the rendered shading image of a
+smooth surface (``render``: the exact normal of the continuous surface under the
+scene's lighting).  It holds none of the solver's arithmetic (no residual,
+Jacobian, difference normal or step), so the oracle and the HIP path can both be
+fed from it without sharing any of the method.
 
 Every generator takes an explicit ``seed`` and uses
 ``numpy.random.default_rng(seed)``; the same call always returns bit-identical

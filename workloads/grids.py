@@ -10,6 +10,7 @@ import numpy as np
 from scipy.ndimage import gaussian_filter
 
 from .noise import sinusoid_field, Perlin2D
+from .render import shade_surface
 
 # Spherical-harmonic lighting coefficients L1..L9 for shape from shading.  A
 # surface facing the camera, normal (0,0,-1), is lit with brightness
@@ -97,17 +98,21 @@ def poisson_edit(W, H, seed=5, mask="rect"):
 
 
 def shape_from_shading(W, H, seed=2, amplitude=None, noise=0.01, invalid="none",
-                       edge_zero_frac=0.0, w_p=1.0, w_s=100.0, w_g=1.0, focal=None):
+                       edge_zero_frac=0.0, w_p=1.0, w_s=100.0, w_g=1.0, focal=None, center=None,
+                       lighting=SFS_LIGHTING):
     """Depth refinement from shading.
 
     True depth = 1.5 + amplitude * g, with g a sum of 16 seeded plane waves of
     period W/8 .. W, scaled to max |g| = 1.  The default amplitude 0.1*min(1, W/1024)
     keeps neighbouring depth differences at or below about 0.005.  The input depth
-    D_i is a Gaussian blur (sigma 4 px) of the true depth; the intensity image is
-    0.9 plus a directional-slope shading term of amplitude 0.1, plus N(0, noise^2).
-    Edge masks are 1 (``edge_zero_frac`` zeroes a random fraction of them).
-    ``invalid="hole"`` sets D_i = 0 (no depth) inside a disc, which excludes those
-    pixels.  Unknown X starts at D_i.
+    D_i is a Gaussian blur (sigma 4 px) of the true depth.  The intensity image is
+    the true surface rendered under ``lighting`` (``render.shade_surface``: the
+    analytic surface normal of the back-projected depth field, lit by the
+    second-order spherical-harmonic model) plus N(0, noise^2).  Edge masks are 1
+    (``edge_zero_frac`` zeroes a random fraction of them).  ``invalid="hole"``
+    sets D_i = 0 (no depth) inside a disc, which excludes those pixels.
+    ``focal`` is f, or (f_x, f_y) (default 1000 W/1024 for both); ``center`` is
+    (u_x, u_y) (default the image centre).  Unknown X starts at D_i.
     """
     rng = np.random.default_rng(seed)
     if amplitude is None:
@@ -116,9 +121,11 @@ def shape_from_shading(W, H, seed=2, amplitude=None, noise=0.01, invalid="none",
     s = 1.0 / np.max(np.abs(g))
     depth = 1.5 + amplitude * s * g
     di, dj = amplitude * s * gi, amplitude * s * gj
-    phi = rng.uniform(0, 2 * np.pi)
-    slope = (di * np.cos(phi) + dj * np.sin(phi))
-    Im = 0.9 + 0.1 * slope / max(1e-12, np.max(np.abs(slope))) + rng.normal(0.0, noise, (H, W))
+    if focal is None:
+        focal = 1000.0 * W / 1024.0
+    fx, fy = (float(focal), float(focal)) if np.isscalar(focal) else (float(focal[0]), float(focal[1]))
+    ux, uy = ((W - 1) / 2.0, (H - 1) / 2.0) if center is None else (float(center[0]), float(center[1]))
+    Im = shade_surface(depth, di, dj, fx, fy, ux, uy, lighting) + rng.normal(0.0, noise, (H, W))
     D = gaussian_filter(depth, 4.0, mode="nearest")
     if invalid == "hole":
         i, j = _lattice(W, H)
@@ -131,10 +138,7 @@ def shape_from_shading(W, H, seed=2, amplitude=None, noise=0.01, invalid="none",
     if edge_zero_frac > 0:
         eR[rng.random((H, W)) < edge_zero_frac] = 0
         eC[rng.random((H, W)) < edge_zero_frac] = 0
-    if focal is None:
-        focal = 1000.0 * W / 1024.0
-    params = dict(w_p=w_p, w_s=w_s, w_g=w_g, f_x=focal, f_y=focal,
-                  u_x=(W - 1) / 2.0, u_y=(H - 1) / 2.0, L=SFS_LIGHTING)
+    params = dict(w_p=w_p, w_s=w_s, w_g=w_g, f_x=fx, f_y=fy, u_x=ux, u_y=uy, L=tuple(lighting))
     return dict(energy="sfs", W=W, H=H, D=D, Im=Im, edge_r=eR, edge_c=eC,
                 x0=D[None].copy(), depth_true=depth, params=params)
 
