@@ -255,6 +255,21 @@ typedef struct {
 int opt_problem_set_tuning(opt_problem* prob, const opt_tuning* tuning);
 int opt_problem_get_tuning(opt_problem* prob, opt_tuning* tuning);
 
+/*
+ * Graph replay of repeated solves (on by default).  The kernels a solve
+ * enqueues depend only on the unknowns pointer, the solve parameters and the
+ * tuning (every decision of Sec. 4's loop, LM's included, is taken on the
+ * device).  When opt_solve is called again with the same three as the call
+ * before it, the library records that launch sequence once as a HIP graph (on a
+ * private stream of its own) and from then on launches the whole solve as one
+ * graph on the problem's stream while they stay the same.  Results are the same
+ * bits as without it; only the host's launch cost changes (one graph launch
+ * instead of one launch per kernel, which bounds small problems).  Solves with
+ * profiling on (opt_profile_enable) are never replayed.  enable = 0 turns it off
+ * and frees the recorded graph.  Destroying the problem frees it too.
+ */
+int opt_problem_set_graph_replay(opt_problem* prob, int enable);
+
 /* Number of unknown channels per site for an energy (0 if unknown). */
 int opt_energy_channels(int32_t energy);
 

@@ -106,15 +106,20 @@ def pcg(apply_A, b, minv, L):
     return d, info
 
 
-def gauss_newton(energy, x0, outer, inner, use_precond=True):
-    """Returns (x, costs) with costs[k] = E(x_k), k = 0..outer."""
+def gauss_newton(energy, x0, outer, inner, use_precond=True, callback=None):
+    """Returns (x, costs) with costs[k] = E(x_k), k = 0..outer.  If ``callback``
+    is given it is called after every outer iteration as callback(k, x), k the
+    iterations done and x the new iterate (to follow a long solve; it must not
+    modify x)."""
     x = np.asarray(x0, float).ravel().copy()
     costs = []
-    for _ in range(outer):
+    for k in range(outer):
         lin = Linearization(energy, x)
         costs.append(lin.E)
         delta, _ = pcg(lin.apply, lin.jtf(), lin.minv(use_precond), inner)
         x = x + delta
+        if callback is not None:
+            callback(k + 1, x)
     costs.append(cost(energy, x))
     return x, costs
 
@@ -129,12 +134,15 @@ class LMParams:
     min_rel_decrease: float = 1e-3
 
 
-def levenberg_marquardt(energy, x0, outer, inner, prm=LMParams(), use_precond=True, history=None):
+def levenberg_marquardt(energy, x0, outer, inner, prm=LMParams(), use_precond=True, history=None,
+                        callback=None):
     """Returns (x, costs, accepted): costs[k] = E at the start of iteration k, plus
     the final cost; accepted[k] tells whether iteration k took its step.  If
     ``history`` is a list, one dict per iteration is appended to it: the radius
     the iteration used, its gain ratio rho and model decrease m, whether it
-    accepted, and the radius and nu it left."""
+    accepted, and the radius and nu it left.  ``callback``, if given, is called
+    after every iteration as callback(k, x) (k iterations done, x the current
+    iterate; it must not modify x)."""
     x = np.asarray(x0, float).ravel().copy()
     radius, nu = prm.radius0, 2.0
     costs, accepted = [], []
@@ -166,5 +174,7 @@ def levenberg_marquardt(energy, x0, outer, inner, prm=LMParams(), use_precond=Tr
         if history is not None:
             history.append(dict(radius_used=1.0 / lam, lam=lam, rho=rho, m=m, accepted=accepted[-1],
                                 radius=radius, nu=nu))
+        if callback is not None:
+            callback(len(accepted), x)
     costs.append(cost(energy, x))
     return x, costs, accepted

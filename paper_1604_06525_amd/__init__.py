@@ -69,6 +69,7 @@ _proto = {
     "opt_profile_read": (ctypes.c_int, [_P, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64)]),
     "opt_problem_set_tuning": (ctypes.c_int, [_P, ctypes.POINTER(opt_tuning)]),
     "opt_problem_get_tuning": (ctypes.c_int, [_P, ctypes.POINTER(opt_tuning)]),
+    "opt_problem_set_graph_replay": (ctypes.c_int, [_P, ctypes.c_int]),
     "opt_server_reserved_bytes": (ctypes.c_int, [ctypes.c_int32, ctypes.POINTER(ctypes.c_size_t)]),
     "opt_server_create": (ctypes.c_int, [_P, ctypes.c_size_t, ctypes.c_int32, _P, ctypes.POINTER(_P)]),
     "opt_server_destroy": (ctypes.c_int, [_P]),
@@ -290,6 +291,10 @@ class Problem:
         if t.large_grid_form:
             out["large_grid_form"] = 1
         return out
+
+    def set_graph_replay(self, on=True):
+        """opt_problem_set_graph_replay: replay repeated solves as one HIP graph."""
+        _check(lib().opt_problem_set_graph_replay(self.handle, int(on)), "opt_problem_set_graph_replay")
 
     def profile_enable(self, on=True):
         _check(lib().opt_profile_enable(self.handle, int(on)), "opt_profile_enable")

@@ -181,8 +181,35 @@ struct opt_problem {
   std::vector<hipEvent_t> ev_pool;   // created on demand, reused
   size_t ev_used = 0;                // events recorded since the last read
   int64_t prof_iters = 0;
+  // Graph replay of repeated solves (opt_problem_set_graph_replay): the launch
+  // sequence of a solve is determined by the unknowns pointer, the parameters and
+  // the tuning; when a solve repeats the previous one's, that sequence is
+  // recorded once as a HIP graph (on a private stream) and replayed.
+  struct SolveKey {
+    const void* x = nullptr;
+    opt_solve_params sp{};
+    opt_tuning tune{};
+    bool valid = false;
+  };
+  bool graphs = true;
+  hipStream_t cap_stream = nullptr;
+  hipGraphExec_t gexec = nullptr;
+  SolveKey gkey, last_eager;
+  // argument rows as the graph leaves them (restored into row_cache after a replay)
+  std::vector<std::vector<unsigned char>> rows_after_graph;
+
+  void drop_graph() {
+    if (gexec) {
+      (void)hipStreamSynchronize(stream);
+      (void)hipGraphExecDestroy(gexec);
+    }
+    gexec = nullptr;
+    gkey.valid = false;
+  }
 
   ~opt_problem() {
+    drop_graph();
+    if (cap_stream) (void)hipStreamDestroy(cap_stream);
     for (hipEvent_t e : ev_pool) (void)hipEventDestroy(e);
   }
 

@@ -865,6 +865,128 @@ int run_pcg(opt_problem* p, PrecondArgs pa, int lm, int L, int variant) {
   return OPT_OK;
 }
 
+
+// Enqueue the whole solve of Sec. 4 on a created problem: setup, K outer
+// iterations (linearise, init, L PCG iterations, LM decision, update), final
+// cost.  Every decision inside is taken on the device.
+int enqueue_solve(opt_problem* p, void* x, const opt_solve_params* sp) {
+  const int K = sp->outer_iters, Lp = sp->pcg_iters;
+  const int lm = sp->method == OPT_LM;
+  double* trace = p->trace();
+  TRY(launch_row(p, ROW_SETUP, setup_args(p->S(), 0.0, sp->lm_radius0, lm, sp->lm_radius_min), 1, 0, "setup"));
+  PrecondArgs pa{0.0, sp->lm_diag_min, sp->lm_diag_max, sp->use_precond, lm != 0};
+  for (int k = 0; k < K; ++k) {
+    TRY(p->impl->linearize(x, lm));
+    TRY(p->impl->init(x, trace, pa, lm, uses_fused(p, sp->pcg_variant)));
+    if (p->profile) TRY(record_event(p));
+    TRY(run_pcg(p, pa, lm, Lp, sp->pcg_variant));
+    if (p->profile) {
+      TRY(record_event(p));
+      p->prof_iters += Lp;
+    }
+    if (lm) {
+      TRY(p->impl->model(x));
+      TRY(p->impl->cost(x, p->at(p->L.delta), 1));
+      TRY(launch_row(p, ROW_DECIDE, decide_args(p->S(), p->part(P_M), p->part(P_COST), p->nblk, *sp), 1, 0,
+                      "decide"));
+    }
+    TRY(p->impl->apply_step(x, lm));
+  }
+  TRY(p->impl->cost(x, nullptr, 0));
+  TRY(launch_row(p, ROW_FINISH, finish_args(p->S(), p->part(P_COST), p->nblk), 1, 0, "finish"));
+  return OPT_OK;
+}
+
+bool same_params(const opt_solve_params& a, const opt_solve_params& b) {
+  return a.method == b.method && a.outer_iters == b.outer_iters && a.pcg_iters == b.pcg_iters &&
+         a.use_precond == b.use_precond && a.lm_radius0 == b.lm_radius0 && a.lm_radius_min == b.lm_radius_min &&
+         a.lm_radius_max == b.lm_radius_max && a.lm_diag_min == b.lm_diag_min && a.lm_diag_max == b.lm_diag_max &&
+         a.lm_min_rel_decrease == b.lm_min_rel_decrease && a.pcg_variant == b.pcg_variant;
+}
+
+bool same_key(const opt_problem::SolveKey& a, const opt_problem::SolveKey& b) {
+  return a.valid && b.valid && a.x == b.x && same_params(a.sp, b.sp) && a.tune.strip_rows == b.tune.strip_rows &&
+         a.tune.waves_per_simd == b.tune.waves_per_simd && a.tune.large_grid_form == b.tune.large_grid_form;
+}
+
+// Record the solve's launch sequence as a graph on the problem's private
+// stream, instantiate it and launch it on the problem's stream.  Every argument
+// row is stored inside the graph (the row cache is emptied first), so a replay
+// does not depend on what other calls left in the rows.
+int capture_solve(opt_problem* p, void* x, const opt_solve_params* sp, const opt_problem::SolveKey& key) {
+  p->drop_graph();
+  if (!p->cap_stream) HIP_TRY(hipStreamCreateWithFlags(&p->cap_stream, hipStreamNonBlocking));
+  // launch-shape queries (occupancy) are answered before recording starts
+  (void)p->impl->gpu_fill(true, false);
+  (void)p->impl->gpu_fill(true, true);
+  for (auto& c : p->row_cache) c.clear();
+  hipStream_t user = p->stream;
+  HIP_TRY(hipStreamBeginCapture(p->cap_stream, hipStreamCaptureModeThreadLocal));
+  p->stream = p->cap_stream;
+  const int rc = enqueue_solve(p, x, sp);
+  p->stream = user;
+  hipGraph_t g = nullptr;
+  const hipError_t ec = hipStreamEndCapture(p->cap_stream, &g);
+  hipGraphExec_t ex = nullptr;
+  hipError_t ei = hipSuccess;
+  if (rc == OPT_OK && ec == hipSuccess) ei = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+  if (g) (void)hipGraphDestroy(g);
+  if (rc != OPT_OK || ec != hipSuccess || ei != hipSuccess) {
+    // nothing recorded was executed: no row is known to be stored
+    for (auto& c : p->row_cache) c.clear();
+    if (rc != OPT_OK) return rc;
+    return fail(OPT_EHIP, "recording the solve as a graph failed: %s",
+                hipGetErrorString(ec != hipSuccess ? ec : ei));
+  }
+  p->gexec = ex;
+  p->gkey = key;
+  p->rows_after_graph = p->row_cache;
+  HIP_TRY(hipGraphLaunch(p->gexec, p->stream));
+  return OPT_OK;
+}
+
+// The whole solve (opt_solve): enqueue it (or replay its graph) and, if a
+// report is asked for, read the scalars and the cost trace back.
+int solve_problem(opt_problem* p, void* x, const opt_solve_params* sp, opt_solve_report* rep) {
+  TRY(check_params(sp));
+  const int K = sp->outer_iters;
+  const int lm = sp->method == OPT_LM;
+  opt_problem::SolveKey key;
+  key.x = x;
+  key.sp = *sp;
+  key.tune = p->tune;
+  key.valid = true;
+  const bool graphs = p->graphs && !p->profile;
+  if (graphs && p->gexec && same_key(p->gkey, key)) {
+    HIP_TRY(hipGraphLaunch(p->gexec, p->stream));
+    p->row_cache = p->rows_after_graph;
+  } else if (graphs && same_key(p->last_eager, key)) {
+    TRY(capture_solve(p, x, sp, key));
+  } else {
+    TRY(enqueue_solve(p, x, sp));
+    p->last_eager = key;
+  }
+  p->last_x = nullptr;
+  if (!rep) return OPT_OK;
+  // the scalars and the cost trace come back in one synchronisation of the
+  // problem's stream
+  DevScalars hs;
+  std::vector<double> tr((size_t)K + 1, 0.0);
+  HIP_TRY(hipMemcpyAsync(&hs, p->S(), sizeof(DevScalars), hipMemcpyDeviceToHost, p->stream));
+  if (K > 0)
+    HIP_TRY(hipMemcpyAsync(tr.data(), p->trace(), sizeof(double) * (size_t)K, hipMemcpyDeviceToHost, p->stream));
+  HIP_TRY(hipStreamSynchronize(p->stream));
+  const int done = lm ? hs.outer_done : K;
+  for (int k = done; k <= K; ++k) tr[(size_t)k] = hs.E_final;
+  rep->cost_initial = K > 0 ? tr[0] : hs.E_final;
+  rep->cost_final = hs.E_final;
+  rep->outer_done = done;
+  rep->steps_accepted = lm ? hs.n_accepted : K;
+  if (rep->cost_trace) memcpy(rep->cost_trace, tr.data(), sizeof(double) * ((size_t)K + 1));
+  if (hs.nonfinite) return fail(OPT_ENUMERIC, "a cost was NaN or infinite");
+  return OPT_OK;
+}
+
 }  // namespace
 }  // namespace host
 }  // namespace optmi
@@ -983,6 +1105,14 @@ int opt_problem_set_tuning(opt_problem* p, const opt_tuning* t) {
   return OPT_OK;
 }
 
+int opt_problem_set_graph_replay(opt_problem* p, int enable) {
+  if (!p) return fail(OPT_EINVAL, "problem is NULL");
+  p->graphs = enable != 0;
+  if (!p->graphs) p->drop_graph();
+  p->last_eager.valid = false;
+  return OPT_OK;
+}
+
 int opt_problem_get_tuning(opt_problem* p, opt_tuning* t) {
   if (!p || !t) return fail(OPT_EINVAL, "problem or tuning is NULL");
   *t = p->tune;
@@ -1029,48 +1159,7 @@ int opt_cost(opt_problem* p, const void* x, double* cost) {
 
 int opt_solve(opt_problem* p, void* x, const opt_solve_params* sp, opt_solve_report* rep) {
   if (!p || !x) return fail(OPT_EINVAL, "problem or unknowns is NULL");
-  TRY(check_params(sp));
-  const int K = sp->outer_iters, Lp = sp->pcg_iters;
-  const int lm = sp->method == OPT_LM;
-  double* trace = p->trace();
-  TRY(launch_row(p, ROW_SETUP, setup_args(p->S(), 0.0, sp->lm_radius0, lm, sp->lm_radius_min), 1, 0, "setup"));
-  PrecondArgs pa{0.0, sp->lm_diag_min, sp->lm_diag_max, sp->use_precond, lm != 0};
-  for (int k = 0; k < K; ++k) {
-    TRY(p->impl->linearize(x, lm));
-    TRY(p->impl->init(x, trace, pa, lm, uses_fused(p, sp->pcg_variant)));
-    if (p->profile) TRY(record_event(p));
-    TRY(run_pcg(p, pa, lm, Lp, sp->pcg_variant));
-    if (p->profile) {
-      TRY(record_event(p));
-      p->prof_iters += Lp;
-    }
-    if (lm) {
-      TRY(p->impl->model(x));
-      TRY(p->impl->cost(x, p->at(p->L.delta), 1));
-      TRY(launch_row(p, ROW_DECIDE, decide_args(p->S(), p->part(P_M), p->part(P_COST), p->nblk, *sp), 1, 0,
-                      "decide"));
-    }
-    TRY(p->impl->apply_step(x, lm));
-  }
-  TRY(p->impl->cost(x, nullptr, 0));
-  TRY(launch_row(p, ROW_FINISH, finish_args(p->S(), p->part(P_COST), p->nblk), 1, 0, "finish"));
-  p->last_x = nullptr;
-  if (!rep) return OPT_OK;
-  DevScalars hs;
-  TRY(sync_scalars(p, &hs));
-  const int done = lm ? hs.outer_done : K;
-  std::vector<double> tr((size_t)K + 1, hs.E_final);
-  if (done > 0)
-    HIP_TRY(hipMemcpy(tr.data(), trace, sizeof(double) * (size_t)done, hipMemcpyDeviceToHost));
-  tr[(size_t)done] = hs.E_final;
-  for (int k = done + 1; k <= K; ++k) tr[(size_t)k] = hs.E_final;
-  rep->cost_initial = K > 0 ? tr[0] : hs.E_final;
-  rep->cost_final = hs.E_final;
-  rep->outer_done = done;
-  rep->steps_accepted = lm ? hs.n_accepted : K;
-  if (rep->cost_trace) memcpy(rep->cost_trace, tr.data(), sizeof(double) * ((size_t)K + 1));
-  if (hs.nonfinite) return fail(OPT_ENUMERIC, "a cost was NaN or infinite");
-  return OPT_OK;
+  return solve_problem(p, x, sp, rep);
 }
 
 }  // extern "C"
