@@ -185,6 +185,29 @@ void opt_default_params(opt_solve_params* p);
 int opt_solve(opt_problem* prob, void* unknowns, const opt_solve_params* params,
               opt_solve_report* report);
 
+/*
+ * opt_solve for callers that cannot allocate device memory (code under HIP
+ * graph capture, tight serving loops, hosts that forbid hipMalloc): create the
+ * problem of `desc` and solve it as opt_problem_create + opt_solve would, with
+ * the same kernels, launch shape (the automatic one; no tuning) and results,
+ * but with the problem's workspace in the library's static scratch: one
+ * OPT_SCRATCH_BYTES device array per GPU, held from the library's first use on
+ * that GPU until the process ends.  The call allocates no device memory.
+ * `unknowns` (device, channels x sites, in/out) and `report` (may be NULL:
+ * enqueue only) are as for opt_solve; `hip_stream` is a hipStream_t (NULL = the
+ * null stream) on the current device.  A graph's edges are read as by
+ * opt_problem_create (this synchronises the stream).
+ * Errors: those of opt_problem_create and opt_solve, and OPT_ENOMEM when the
+ * problem's workspace (opt_workspace_size) exceeds OPT_SCRATCH_BYTES.
+ * Every call on one GPU uses that GPU's one scratch array and leaves its
+ * contents behind: calls whose work may overlap on one GPU (from several host
+ * threads, or on different streams while an earlier call's work is still in
+ * flight) race and must be serialised by the caller.
+ */
+#define OPT_SCRATCH_BYTES ((size_t)128 << 20)
+int opt_solve_scratch(const opt_problem_desc* desc, void* unknowns, const opt_solve_params* params,
+                      opt_solve_report* report, void* hip_stream);
+
 /* E(x) = sum_r f_r(x)^2 in float64 at `unknowns` (device); synchronises. */
 int opt_cost(opt_problem* prob, const void* unknowns, double* cost);
 

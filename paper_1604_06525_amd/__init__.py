@@ -59,6 +59,8 @@ _proto = {
     "opt_problem_destroy": (ctypes.c_int, [_P]),
     "opt_default_params": (None, [ctypes.POINTER(opt_solve_params)]),
     "opt_solve": (ctypes.c_int, [_P, _P, ctypes.POINTER(opt_solve_params), ctypes.POINTER(opt_solve_report)]),
+    "opt_solve_scratch": (ctypes.c_int, [ctypes.POINTER(opt_problem_desc), _P, ctypes.POINTER(opt_solve_params),
+                                         ctypes.POINTER(opt_solve_report), _P]),
     "opt_cost": (ctypes.c_int, [_P, _P, ctypes.POINTER(ctypes.c_double)]),
     "opt_linearize": (ctypes.c_int, [_P, _P, ctypes.POINTER(ctypes.c_double)]),
     "opt_eval_jtf": (ctypes.c_int, [_P, _P, _P]),
@@ -312,6 +314,38 @@ class Problem:
         d = self.new_vector()
         _check(lib().opt_pcg(self.handle, ctypes.byref(prm), float(lam), _ptr(d)), "opt_pcg")
         return d
+
+
+SCRATCH_BYTES = 128 << 20  # OPT_SCRATCH_BYTES
+
+
+def solve_scratch(energy, arrays, x, params=(), precision="mixed", width=0, height=0, n_vertices=0,
+                  edges=None, solve_params=None, stream=None, report=True, **kw):
+    """opt_solve_scratch: create and solve a problem in the library's static
+    scratch (no device allocation), x in place.  Returns the report dict (as
+    Problem.solve), or None with report=False (work only enqueued)."""
+    d, arrays, edges = make_desc(energy, arrays, params, precision, width, height, n_vertices, edges)
+    dtype = torch.float64 if precision == "fp64" else torch.float32
+    n = n_vertices if n_vertices else width * height
+    if x.dtype != dtype or not x.is_contiguous() or x.numel() != energy_channels(energy) * n or \
+            x.device != arrays[0].device:
+        raise ValueError(f"x must be a contiguous {dtype} tensor of {energy_channels(energy)}x{n} "
+                         f"on {arrays[0].device}")
+    p = solve_params if solve_params is not None else default_params(**kw)
+    st = stream if stream is not None else torch.cuda.current_stream(x.device)
+    sp = ctypes.c_void_p(st.cuda_stream)
+    if not report:
+        _check(lib().opt_solve_scratch(ctypes.byref(d), _ptr(x), ctypes.byref(p), None, sp), "opt_solve_scratch")
+        return None
+    trace = (ctypes.c_double * (p.outer_iters + 1))()
+    rep = opt_solve_report()
+    rep.cost_trace = ctypes.cast(trace, ctypes.POINTER(ctypes.c_double))
+    code = lib().opt_solve_scratch(ctypes.byref(d), _ptr(x), ctypes.byref(p), ctypes.byref(rep), sp)
+    out = dict(cost_initial=rep.cost_initial, cost_final=rep.cost_final,
+               outer_done=rep.outer_done, steps_accepted=rep.steps_accepted,
+               cost_trace=list(trace), code=code)
+    _check(code, "opt_solve_scratch")
+    return out
 
 
 def workspace_size(energy, arrays, params=(), precision="mixed", width=0, height=0, n_vertices=0,

@@ -9,6 +9,7 @@
 #include <cstdio>
 #include <cstring>
 #include <memory>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -987,6 +988,32 @@ int solve_problem(opt_problem* p, void* x, const opt_solve_params* sp, opt_solve
   return OPT_OK;
 }
 
+// ---------------------------------------------------------------- static scratch
+// The workspace of opt_solve_scratch: one file-scope device array, which every
+// GPU the library runs on holds (its own copy) until the process ends.  Host
+// code never uses the array's name as an address: the device address of each
+// GPU's copy is looked up once per device and kept.
+constexpr size_t kScratchBytes = OPT_SCRATCH_BYTES;
+static_assert(kScratchBytes % kAlign == 0, "scratch is a whole number of aligned blocks");
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+std::mutex g_scratch_mu;
+std::vector<void*> g_scratch_ptr;  // by device ordinal; nullptr until looked up
+
+int scratch_of_current_device(void** out) {
+  int dev = 0;
+  HIP_TRY(hipGetDevice(&dev));
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if ((size_t)dev >= g_scratch_ptr.size()) g_scratch_ptr.resize((size_t)dev + 1, nullptr);
+  if (!g_scratch_ptr[(size_t)dev]) {
+    void* ptr = nullptr;
+    HIP_TRY(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)));
+    if (!ptr || ((uintptr_t)ptr) % kAlign) return fail(OPT_EHIP, "static scratch has no usable address");
+    g_scratch_ptr[(size_t)dev] = ptr;
+  }
+  *out = g_scratch_ptr[(size_t)dev];
+  return OPT_OK;
+}
 }  // namespace
 }  // namespace host
 }  // namespace optmi
@@ -1160,6 +1187,23 @@ int opt_cost(opt_problem* p, const void* x, double* cost) {
 int opt_solve(opt_problem* p, void* x, const opt_solve_params* sp, opt_solve_report* rep) {
   if (!p || !x) return fail(OPT_EINVAL, "problem or unknowns is NULL");
   return solve_problem(p, x, sp, rep);
+}
+
+int opt_solve_scratch(const opt_problem_desc* desc, void* unknowns, const opt_solve_params* params,
+                      opt_solve_report* report, void* hip_stream) {
+  if (!unknowns) return fail(OPT_EINVAL, "unknowns is NULL");
+  Shape sh;
+  TRY(check_desc(desc, &sh));
+  TRY(check_params(params));
+  const Layout L = make_layout(sh);
+  if (L.total > kScratchBytes)
+    return fail(OPT_ENOMEM, "the problem needs %zu bytes of workspace; the static scratch holds %zu",
+                L.total, kScratchBytes);
+  void* ws = nullptr;
+  TRY(scratch_of_current_device(&ws));
+  opt_problem p;
+  TRY(problem_init(&p, desc, sh, ws, (hipStream_t)hip_stream));
+  return solve_problem(&p, unknowns, params, report);
 }
 
 }  // extern "C"
