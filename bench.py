@@ -3,6 +3,7 @@
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
     python bench.py --serve [--serve-requests N]
     python bench.py --configs all
+    python bench.py --accuracy [--configs NAME,...]
 
 A step is one whole solve: ARAP image warping on a 1024 x 1024 pixel grid
 (3 unknowns per pixel, 8,192 positional constraints), Gauss-Newton 10 outer x 50
@@ -23,6 +24,18 @@ workload on the host.
 icosphere meshes of levels 7 and 8, optical flow 1920x1080 mixed/FP64, Poisson
 1024^2, and the 1024^2 warp with implicit grid vs explicit graph connectivity):
 one JSON line each, not the contract line.
+
+The default run also times the oracle on the host first (``cpu_baseline``: one
+outer iteration of the same workload, on one core and in one process per core)
+and ends with a compact serving leg: the batching server against plain FIFO
+solves on the serving mix at 1.0 and 2.0 x the plain capacity
+(``--serve-leg-requests`` per load, 0 skips it).
+
+``--accuracy`` compares the GPU with the FP64 oracle at every configuration's
+full size and schedule: relative final-cost error, unknown error (relative to
+the oracle's own step from the initial unknowns, and max-abs), accepted LM steps,
+and for shape from shading the smoothness-mask flips at every linearisation
+point; the oracle's whole-solve time on one thread is reported beside them.
 
 ``--serve`` measures the batching server instead: a seeded Poisson-arrival
 stream of mixed requests (ARAP warps and Poisson edits on grids of side
@@ -61,6 +74,11 @@ def parse():
                     help="'all' or a comma list: per-configuration PCG rates instead of the headline line")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run device copies of a known size (to scale memory counters)")
+    ap.add_argument("--accuracy", action="store_true",
+                    help="GPU final cost and unknowns against the FP64 oracle for every configuration "
+                         "(or those named by --configs), at full size and schedule")
+    ap.add_argument("--serve-leg-requests", type=int, default=500,
+                    help="requests per load of the serving leg of the default run (0: skip the leg)")
     return ap.parse_args()
 
 
@@ -96,17 +114,83 @@ def warp_bytes_per_iter(n):
     return 24 * 3 * n + 13 * n
 
 
-def cpu_baseline(d, pcg_iters):
+def _oracle_outer_sample(pcg_iters):
+    """One Gauss-Newton outer iteration of the FP64 oracle on the headline warp
+    (explicit Jacobian assembly, then pcg_iters PCG iterations with scipy CSR
+    products), single thread.  Returns (assembly seconds, PCG seconds)."""
     import oracle
+    import workloads
+    d = workloads.arap_warp(WARP["W"], WARP["H"], seed=WARP["seed"])
     e = oracle.make_energy(d)
     t0 = time.perf_counter()
     lin = oracle.Linearization(e, d["x0"])
-    oracle.pcg(lin.apply, lin.jtf(), lin.minv(True), pcg_iters)
-    dt = time.perf_counter() - t0
-    return {"value": pcg_iters / dt, "unit": "PCG iters/s", "cores": 1, "kind": "oracle",
-            "sample": f"one GN outer iteration (explicit Jacobian assembly + {pcg_iters} PCG "
-                      f"iterations, FP64, scipy CSR, single thread) of the same 1024x1024 warp; "
-                      f"{dt:.1f} s"}
+    b, minv = lin.jtf(), lin.minv(True)
+    t1 = time.perf_counter()
+    oracle.pcg(lin.apply, b, minv, pcg_iters)
+    t2 = time.perf_counter()
+    return t1 - t0, t2 - t1
+
+
+def _host_cores():
+    try:
+        return len(os.sched_getaffinity(0))
+    except AttributeError:
+        return os.cpu_count() or 1
+
+
+def _cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def _oracle_pool(n):
+    """Worker processes for the oracle, one thread each.  Started before the
+    GPU is touched (spawned, not forked)."""
+    import multiprocessing as mp
+    from concurrent.futures import ProcessPoolExecutor
+    os.environ["OMP_NUM_THREADS"] = "1"
+    os.environ["OPENBLAS_NUM_THREADS"] = "1"
+    return ProcessPoolExecutor(n, mp_context=mp.get_context("spawn"))
+
+
+CPU_PROCS_MAX = 16
+
+
+def cpu_baseline(pcg_iters):
+    """The FP64 oracle on the host, on samples of the headline workload: one
+    outer iteration alone on one core (Jacobian assembly and PCG timed apart),
+    then the same sample in one process per core at once (the oracle's
+    throughput on all cores: its sparse products use one thread each).  Runs
+    before the GPU is used."""
+    n = max(1, min(_host_cores(), CPU_PROCS_MAX))
+    with _oracle_pool(n) as pool:
+        pool.submit(int, 0).result()  # workers up before timing
+        asm1, pcg1 = pool.submit(_oracle_outer_sample, pcg_iters).result()
+        t0 = time.perf_counter()
+        res = list(pool.map(_oracle_outer_sample, [pcg_iters] * n))
+        wall = time.perf_counter() - t0
+    total = sum(pcg_iters / r[1] for r in res)
+    K = WARP["outer"]
+    print(f"cpu_baseline: oracle {pcg_iters / pcg1:.2f} PCG iters/s on one core, {total:.1f} on {n}",
+          file=sys.stderr, flush=True)
+    return {"value": total, "unit": "PCG iters/s", "cores": n, "kind": "oracle",
+            "model": _cpu_model(), "host_cores": _host_cores(),
+            "sample": f"one GN outer iteration of the same 1024x1024 warp (FP64, explicit Jacobian, "
+                      f"scipy CSR, {pcg_iters} PCG iterations) per process: {n} single-thread processes "
+                      f"at once ({wall:.1f} s wall), value = their summed PCG iterations/s over the PCG "
+                      f"phase only (Jacobian assembly excluded)",
+            "one_core": {"pcg_iters_per_s": pcg_iters / pcg1, "jacobian_assembly_s": asm1,
+                         "outer_iteration_s": asm1 + pcg1,
+                         "solve_s_estimate": K * (asm1 + pcg1),
+                         "note": f"solve_s_estimate = {K} outer iterations x (assembly + PCG) of the sample"},
+            "all_cores": {"processes": n, "pcg_iters_per_s_total": total,
+                          "jacobian_assembly_s_mean": float(np.mean([r[0] for r in res])),
+                          "pcg_s_mean": float(np.mean([r[1] for r in res]))}}
 
 
 COPY_BYTES = 2 << 30  # far larger than the 256 MB Infinity Cache
@@ -226,27 +310,34 @@ def _run_batched(pkg, entries, arrivals, which, keep):
     return lat, span, xs, held_sum / max(1, steps)
 
 
-def serve_main(args):
-    import torch
-    import paper_1604_06525_amd as pkg
+def _serving_setup(torch, pkg, dev):
+    """The request pool, each problem solved once (warm-up), and the plain
+    capacity: FIFO solves/s over a 40-request sample of the mix."""
     from workloads.serving import request_stream
-    dev = torch.device("cuda:0")
     entries = _serve_pool(torch, pkg, dev)
     print(f"serve: pool of {len(entries)} problems ready", file=sys.stderr, flush=True)
-    # warm up every problem once, then measure the plain capacity on a sample
     for e in entries:
         e["plain"].solve(e["x0"].clone().reshape(e["plain"].channels, -1), params=e["sp"], report=True)
-    _, which = request_stream(entries_spec := [e["spec"] for e in entries], 40, 1.0, seed=99)
+    _, which = request_stream([e["spec"] for e in entries], 40, 1.0, seed=99)
     t0 = time.perf_counter()
     for k in which:
         e = entries[k]
         e["plain"].solve(e["x0"].clone().reshape(e["plain"].channels, -1), params=e["sp"], report=True)
     capacity = len(which) / (time.perf_counter() - t0)
     print(f"serve: plain capacity {capacity:.1f} solves/s", file=sys.stderr, flush=True)
-    loads = [float(v) for v in args.serve_loads.split(",")]
+    return entries, capacity
+
+
+def serving_sweep(torch, pkg, entries, capacity, loads, n_requests):
+    """Replay one seeded Poisson-arrival stream per load (rate = load x the
+    plain capacity) through the server and through plain FIFO opt_solve.
+    Returns (rows, requests compared bitwise, equal): the first load's results
+    are compared request by request between the two."""
+    from workloads.serving import request_stream
+    spec = [e["spec"] for e in entries]
     rows, equal, compared = [], 0, 0
     for li, load in enumerate(loads):
-        arrivals, which = request_stream(entries_spec, args.serve_requests, load * capacity, seed=5 + li)
+        arrivals, which = request_stream(spec, n_requests, load * capacity, seed=5 + li)
         keep = li == 0
         lat_b, span_b, xs_b, mean_held = _run_batched(pkg, entries, arrivals, which, keep)
         lat_p, span_p, xs_p = _run_plain(entries, arrivals, which, keep)
@@ -261,8 +352,23 @@ def serve_main(args):
                      "plain": {"p50_ms": _pct(lat_p, 50), "p99_ms": _pct(lat_p, 99),
                                "solves_per_s": n / span_p}})
         print(f"serve: load {load}: batched p50/p99 {rows[-1]['batched']['p50_ms']:.1f}/"
-              f"{rows[-1]['batched']['p99_ms']:.1f} ms, plain {rows[-1]['plain']['p50_ms']:.1f}/"
-              f"{rows[-1]['plain']['p99_ms']:.1f} ms", file=sys.stderr, flush=True)
+              f"{rows[-1]['batched']['p99_ms']:.1f} ms {rows[-1]['batched']['solves_per_s']:.1f}/s, plain "
+              f"{rows[-1]['plain']['p50_ms']:.1f}/{rows[-1]['plain']['p99_ms']:.1f} ms "
+              f"{rows[-1]['plain']['solves_per_s']:.1f}/s", file=sys.stderr, flush=True)
+    return rows, compared, equal
+
+
+SERVE_WORKLOAD = ("serving mix: 40% ARAP warp / 40% Poisson edit (grid side 128..1024, GN 10x50), "
+                  "20% ARAP icosphere mesh (level 5..7, LM 10x40); mixed precision")
+
+
+def serve_main(args):
+    import torch
+    import paper_1604_06525_amd as pkg
+    dev = torch.device("cuda:0")
+    entries, capacity = _serving_setup(torch, pkg, dev)
+    loads = [float(v) for v in args.serve_loads.split(",")]
+    rows, compared, equal = serving_sweep(torch, pkg, entries, capacity, loads, args.serve_requests)
     at1 = min(rows, key=lambda r: abs(r["load"] - 1.0))
     out = {
         "metric": "serving p99 latency at the plain capacity (batched)",
@@ -273,8 +379,7 @@ def serve_main(args):
         "vs_baseline": None,
         "dtype": "f32",
         "data": "synthetic",
-        "config": {"workload": "serving mix: 40% ARAP warp / 40% Poisson edit (grid side 128..1024, "
-                               "GN 10x50), 20% ARAP icosphere mesh (level 5..7, LM 10x40); mixed precision",
+        "config": {"workload": SERVE_WORKLOAD,
                    "requests_per_load": args.serve_requests, "arena_bytes": SERVE_ARENA,
                    "max_slots": SERVE_SLOTS, "pool": [e["spec"] for e in entries]},
         "plain_capacity_solves_per_s": capacity,
@@ -307,6 +412,19 @@ CONFIGS = [
     ("warp_1024x1024_gn8x100_mixed", lambda w: w.arap_warp(1024, 1024, seed=2), "mixed", "gn", 8, 100, (24, 13)),
     ("warp_graph_1024x1024_gn8x100_mixed", lambda w: _as_graph(w.arap_warp(1024, 1024, seed=2)), "mixed", "gn",
      8, 100, (24, 13)),
+    # matrix-free against materialised products (Sec. 7, evalJ): the same
+    # problem and schedule in the split form (the recurrence the materialised
+    # form runs) and in the materialised form; bytes are the matrix-free
+    # algorithmic bytes in all three, so the columns compare times
+    ("warp_1024x1024_gn10x50_mixed_split", lambda w: w.arap_warp(1024, 1024, seed=2), "mixed", "gn", 10, 50,
+     (24, 13), dict(pcg_variant="split")),
+    ("warp_1024x1024_gn10x50_mixed_materialized", lambda w: w.arap_warp(1024, 1024, seed=2), "mixed", "gn", 10, 50,
+     (24, 13), dict(pcg_variant="materialized", materialize=True)),
+    # volumetric ARAP on a 64^3 voxel block (implicit 3D connectivity), and the
+    # Laplacian on a 1024^2 image
+    ("volume_64x64x64_lm10x40_mixed", lambda w: w.arap_volume(64, 64, 64, seed=6), "mixed", "lm", 10, 40, (24, 37)),
+    ("laplacian_1024x1024_gn10x50_mixed", lambda w: w.laplacian_grid(1024, 1024, seed=0), "mixed", "gn", 10, 50,
+     (24, 5)),
 ]
 
 
@@ -339,17 +457,20 @@ def configs_main(args):
     from workloads.layout import problem_args
     dev = torch.device("cuda:0")
     only = set(args.configs.split(",")) if args.configs != "all" else None
-    for name, gen, prec, method, outer, inner, (bu, bs) in CONFIGS:
+    for name, gen, prec, method, outer, inner, (bu, bs), *extra in CONFIGS:
         if only and name not in only:
             continue
+        extra = dict(extra[0]) if extra else {}
+        variant = extra.pop("pcg_variant", "fused")
         d = gen(workloads)
         dt = np.float64 if prec == "fp64" else np.float32
         energy, arrs, params, dims = problem_args(d, dt)
         if "edges" in dims:
             dims = dict(dims, edges=torch.from_numpy(dims["edges"]).to(dev))
-        prob = pkg.Problem(energy, [torch.from_numpy(a).to(dev) for a in arrs], params, precision=prec, **dims)
+        prob = pkg.Problem(energy, [torch.from_numpy(a).to(dev) for a in arrs], params, precision=prec, **dims,
+                           **extra)
         x0 = torch.from_numpy(np.ascontiguousarray(np.asarray(d["x0"], dt).reshape(prob.channels, -1))).to(dev)
-        sp = pkg.default_params(method=method, outer_iters=outer, pcg_iters=inner)
+        sp = pkg.default_params(method=method, outer_iters=outer, pcg_iters=inner, pcg_variant=variant)
         x = x0.clone()
         for _ in range(args.warmup):
             x.copy_(x0)
@@ -377,13 +498,157 @@ def configs_main(args):
         achieved = bpi / (iter_us * 1e-6) / 1e9
         rep = prob.solve(x.copy_(x0), params=sp)
         print(json.dumps({"config": name, "sites": n, "unknowns": N, "precision": prec, "method": method,
-                          "outer_iters": outer, "pcg_iters": inner, "pcg_form": pcg_form(energy, prob.channels, n, prec, "V" in d),
+                          "outer_iters": outer, "pcg_iters": inner,
+                          "pcg_form": variant if variant != "fused" else pcg_form(energy, prob.channels, n, prec, "V" in d),
                           "pcg_iters_per_s": pcg_iters / (pcg_ms / 1e3), "iter_us": iter_us,
                           "bytes_per_iter": bpi, "achieved_GBs": achieved, "frac_of_8TBs": achieved / HBM_PEAK_GBS,
                           "solve_ms_median": float(np.median(solve_ms)), "cost_initial": rep["cost_initial"],
                           "cost_final": rep["cost_final"], "launch": prob.get_tuning()}), flush=True)
         del prob
         torch.cuda.synchronize()
+
+
+# ---------------------------------------------------------------- accuracy against the oracle
+# Every configuration of the measurement table at its full size and schedule:
+# name, generator, precision, method, outer, inner.  The FP64 oracle solves the
+# same problem on the host (for mixed precision on the FP32-rounded inputs the
+# GPU holds); the GPU's final cost and unknowns are compared with it.
+ACCURACY = [
+    ("warp_64x64_gn5x20_fp64", lambda w: w.arap_warp(64, 64, seed=1), "fp64", "gn", 5, 20),
+    ("warp_1024x1024_gn10x50_mixed", lambda w: w.arap_warp(1024, 1024, seed=2), "mixed", "gn", 10, 50),
+    ("warp_1024x1024_gn10x50_fp64", lambda w: w.arap_warp(1024, 1024, seed=2), "fp64", "gn", 10, 50),
+    ("sfs_1024x1024_gn10x50_mixed", lambda w: w.shape_from_shading(1024, 1024, seed=2), "mixed", "gn", 10, 50),
+    # the same problem in FP64, and under LM (whose accepted steps never raise
+    # the cost): Gauss-Newton is not monotone on it
+    ("sfs_1024x1024_gn10x50_fp64", lambda w: w.shape_from_shading(1024, 1024, seed=2), "fp64", "gn", 10, 50),
+    ("sfs_1024x1024_lm10x50_mixed", lambda w: w.shape_from_shading(1024, 1024, seed=2), "mixed", "lm", 10, 50),
+    ("mesh_icosphere7_lm10x40_mixed", lambda w: w.arap_mesh(7, seed=3), "mixed", "lm", 10, 40),
+    ("mesh_icosphere7_lm10x40_fp64", lambda w: w.arap_mesh(7, seed=3), "fp64", "lm", 10, 40),
+    ("mesh_icosphere8_lm10x40_mixed", lambda w: w.arap_mesh(8, seed=3), "mixed", "lm", 10, 40),
+    ("flow_1920x1080_gn10x50_mixed", lambda w: w.optical_flow(1920, 1080, seed=4), "mixed", "gn", 10, 50),
+    ("flow_1920x1080_gn10x50_fp64", lambda w: w.optical_flow(1920, 1080, seed=4), "fp64", "gn", 10, 50),
+    ("poisson_1024x1024_gn10x50_mixed", lambda w: w.poisson_edit(1024, 1024, seed=5), "mixed", "gn", 10, 50),
+]
+
+
+def _as_held(d, precision):
+    """The workload as the GPU holds it: under mixed precision every float array
+    rounded to float32 (and back to float64 for the oracle).  Re-packaging only."""
+    if precision == "fp64":
+        return d
+    return {k: (v.astype(np.float32).astype(np.float64) if isinstance(v, np.ndarray) and v.dtype.kind == "f" else v)
+            for k, v in d.items()}
+
+
+def _oracle_config(name):
+    """Worker process: the oracle's whole solve of one configuration (FP64, one
+    thread).  Returns its cost trace, final unknowns, accepted steps (LM), the
+    smoothness masks at every linearisation point (shape from shading) and the
+    time taken.  Prints one progress line per outer iteration."""
+    import oracle
+    import workloads
+    spec = {c[0]: c for c in ACCURACY}[name]
+    _, gen, precision, method, K, L = spec
+    d = _as_held(gen(workloads), precision)
+    e = oracle.make_energy(d)
+    masks = []
+    t0 = time.perf_counter()
+
+    def progress(k, x):
+        if d["energy"] == "sfs" and k < K:
+            masks.append(e.smooth_valid(np.asarray(x).reshape(d["H"], d["W"])))
+        print(f"accuracy: oracle {name} iteration {k}/{K} ({time.perf_counter() - t0:.0f} s)",
+              file=sys.stderr, flush=True)
+
+    if d["energy"] == "sfs":
+        masks.append(e.smooth_valid(np.asarray(d["x0"], float).reshape(d["H"], d["W"])))
+    if method == "gn":
+        x, costs = oracle.gauss_newton(e, d["x0"], K, L, callback=progress)
+        acc = None
+    else:
+        x, costs, acc = oracle.levenberg_marquardt(e, d["x0"], K, L, callback=progress)
+    return {"costs": costs, "x": x, "accepted": acc, "masks": masks, "seconds": time.perf_counter() - t0}
+
+
+def accuracy_main(args):
+    """One JSON line per configuration: the GPU's final cost and unknowns against
+    the FP64 oracle's at full size and schedule, plus the oracle's whole-solve
+    time on one host core."""
+    only = set(args.configs.split(",")) if args.configs and args.configs != "all" else None
+    todo = [c for c in ACCURACY if not only or c[0] in only]
+    # the oracle workers are started before anything touches the GPU, one
+    # thread each
+    workers = max(1, min(len(todo), _host_cores() - 1))
+    pool = _oracle_pool(workers)
+    # longest first
+    futs = {c[0]: pool.submit(_oracle_config, c[0]) for c in sorted(todo, key=lambda c: -_oracle_weight(c))}
+    import torch
+    import paper_1604_06525_amd as pkg
+    import workloads
+    import oracle
+    from workloads.layout import problem_args
+    dev = torch.device("cuda:0")
+    gpu = {}
+    for name, gen, precision, method, K, L in todo:
+        d = gen(workloads)
+        dt = np.float64 if precision == "fp64" else np.float32
+        energy, arrs, params, dims = problem_args(d, dt)
+        if "edges" in dims:
+            dims = dict(dims, edges=torch.from_numpy(dims["edges"]).to(dev))
+        prob = pkg.Problem(energy, [torch.from_numpy(a).to(dev) for a in arrs], params, precision=precision, **dims)
+        x0 = torch.from_numpy(np.ascontiguousarray(np.asarray(d["x0"], dt).reshape(prob.channels, -1))).to(dev)
+        x = x0.clone()
+        rep = prob.solve(x, method=method, outer_iters=K, pcg_iters=L)
+        out = {"rep": rep, "x": x.cpu().double().numpy().ravel()}
+        if energy == "sfs" and method == "gn":
+            # the iterate at every linearisation point: Gauss-Newton keeps no
+            # state between outer iterations, so K solves of one iteration each
+            # pass through the same iterates
+            e = oracle.make_energy(_as_held(d, precision))
+            xs = x0.clone()
+            masks = [e.smooth_valid(xs.cpu().double().numpy().reshape(d["H"], d["W"]))]
+            for k in range(K - 1):
+                prob.solve(xs, method=method, outer_iters=1, pcg_iters=L, report=False)
+                masks.append(e.smooth_valid(xs.cpu().double().numpy().reshape(d["H"], d["W"])))
+            out["masks"] = masks
+        gpu[name] = out
+        print(f"accuracy: GPU {name} done, cost {rep['cost_final']:.10g}", file=sys.stderr, flush=True)
+        del prob
+        torch.cuda.synchronize()
+    rows = []
+    for name, gen, precision, method, K, L in todo:
+        ref = futs[name].result()
+        g = gpu[name]
+        d0 = np.asarray(_as_held(gen(__import__("workloads")), precision)["x0"], float).ravel()
+        xo, xg = np.asarray(ref["x"], float).ravel(), g["x"]
+        Eo, Eg = ref["costs"][-1], g["rep"]["cost_final"]
+        row = {"config": name, "precision": precision, "method": method, "outer_iters": K, "pcg_iters": L,
+               "cost_oracle": Eo, "cost_gpu": Eg, "rel_cost_err": abs(Eg - Eo) / Eo,
+               "rel_cost_err_max_over_trace": max(abs(a - b) / b for a, b in zip(g["rep"]["cost_trace"], ref["costs"])),
+               "unknown_err_rel": float(np.linalg.norm(xg - xo) / max(np.linalg.norm(xo - d0), 1e-300)),
+               "unknown_err_maxabs": float(np.abs(xg - xo).max()),
+               "oracle_solve_s": ref["seconds"], "oracle_threads": 1,
+               "oracle_processes_at_once": workers}
+        if method == "lm":
+            row["accepted_oracle"] = int(sum(ref["accepted"]))
+            row["accepted_gpu"] = int(g["rep"]["steps_accepted"])
+        if "masks" in g:
+            row["smooth_mask_flips_per_linearisation"] = [int(np.count_nonzero(a != b))
+                                                          for a, b in zip(g["masks"], ref["masks"])]
+        rows.append(row)
+        print(json.dumps(row), flush=True)
+    pool.shutdown()
+    print(json.dumps({"accuracy_summary": {r["config"]: r["rel_cost_err"] for r in rows},
+                      "host": {"cores": _host_cores(), "model": _cpu_model()}}), flush=True)
+
+
+def _oracle_weight(c):
+    """Rough oracle cost of a configuration, to start the longest first."""
+    name = c[0]
+    for key, wgt in (("icosphere8", 8), ("flow", 6), ("sfs", 4), ("1024x1024", 3), ("icosphere7", 2)):
+        if key in name:
+            return wgt
+    return 1
 
 
 def main():
@@ -398,9 +663,15 @@ def main():
     if args.copy_calibration:
         copy_calibration()
         return
+    if args.accuracy:
+        accuracy_main(args)
+        return
     if args.configs:
         configs_main(args)
         return
+    # the oracle's CPU baseline runs first, in worker processes started before
+    # anything touches the GPU
+    cpu = None if args.no_cpu_baseline else cpu_baseline(WARP["pcg"])
     import torch
     import paper_1604_06525_amd as pkg
     import workloads
@@ -472,8 +743,20 @@ def main():
         "cost_initial": rep["cost_initial"],
         "cost_final": rep["cost_final"],
     }
-    if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(d, WARP["pcg"])
+    if cpu is not None:
+        out["cpu_baseline"] = cpu
+    if args.serve_leg_requests > 0:
+        # compact serving leg: the batching server against plain FIFO solves on
+        # the same Poisson-arrival streams, at the plain capacity (latency) and
+        # at twice it (where plain saturates and throughput shows)
+        del prob
+        torch.cuda.synchronize()
+        entries, capacity = _serving_setup(torch, pkg, dev)
+        rows, compared, equal = serving_sweep(torch, pkg, entries, capacity, [1.0, 2.0], args.serve_leg_requests)
+        out["serving"] = {"workload": SERVE_WORKLOAD, "requests_per_load": args.serve_leg_requests,
+                          "plain_capacity_solves_per_s": capacity, "loads": rows,
+                          "bitwise_equal_to_plain": f"{equal}/{compared}",
+                          "note": "latency = result on the host minus arrival; solves/s over the whole stream"}
     print(json.dumps(out), flush=True)
 
 

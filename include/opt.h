@@ -56,11 +56,19 @@ extern "C" {
 #define OPT_ENUMERIC (-5)     /* a cost came out NaN or infinite */
 #define OPT_EUNSUPPORTED (-6) /* combination of domain/energy/precision not built */
 
-typedef enum { OPT_GRID2D = 0, OPT_GRAPH = 1 } opt_domain;
+typedef enum { OPT_GRID2D = 0, OPT_GRAPH = 1, OPT_GRID3D = 2 } opt_domain;
 
 /*
  * Energies.  For each: unknown channels; arrays[] in order; params[] in order.
  *
+ * OPT_E_LAPLACIAN (grid or graph; Figs. 3 and 5, the introductory example).  On
+ *   a grid: 1 unknown per pixel; residuals w_fit (X - A) and w_reg (X(i,j) -
+ *   X(i+1,j)), w_reg (X(i,j) - X(i,j+1)) where the neighbour is on the grid.  On
+ *   a graph: 3 unknowns per vertex (a float3); residuals w_fit (X_v - A_v) and
+ *   w_reg (X_v0 - X_v1) once per listed edge.  arrays: [0] A (1 plane on a grid,
+ *   3 on a graph).  params: w_fit, w_reg.  Linear: one GN step with an exact
+ *   inner solve reaches the minimiser (w_fit^2 I + w_reg^2 L) x = w_fit^2 A.
+ *   opt_energy_channels reports its grid form (1).
  * OPT_E_ARAP_WARP (grid; Fig. 24, Appendix A.1.1).  Unknowns 3: offset x, offset y,
  *   angle.  arrays: [0] U rest positions (2 planes), [1] C targets (2 planes; a
  *   target is used when both components are >= 0), [2] mask (uint8; pixels with
@@ -79,6 +87,11 @@ typedef enum { OPT_GRID2D = 0, OPT_GRAPH = 1 } opt_domain;
  *   (3 planes; a component is used when >= -999999.9).  Each listed undirected
  *   edge {v0, v1} contributes the ARAP residual in both orientations.  params:
  *   w_fit, w_reg.
+ * OPT_E_ARAP_VOLUME (3D grid, OPT_GRID3D; Fig. 31, A.2.5).  Unknowns 6 per
+ *   voxel as for the mesh; voxel (i, j, k) is (k*height + j)*width + i.  The
+ *   voxel lattice is the connectivity: every voxel has the ARAP residual towards
+ *   each in-bounds neighbour along +-x, +-y, +-z (so each lattice edge counts in
+ *   both orientations).  arrays and params as for OPT_E_ARAP_MESH.
  */
 typedef enum {
   OPT_E_LAPLACIAN = 0,
@@ -86,7 +99,8 @@ typedef enum {
   OPT_E_POISSON = 2,
   OPT_E_SFS = 3,
   OPT_E_FLOW = 4,
-  OPT_E_ARAP_MESH = 5
+  OPT_E_ARAP_MESH = 5,
+  OPT_E_ARAP_VOLUME = 6
 } opt_energy;
 
 typedef enum { OPT_FP64 = 0, OPT_MIXED = 1 } opt_precision;
@@ -103,20 +117,31 @@ typedef enum { OPT_GN = 0, OPT_LM = 1 } opt_method;
  *   asking for it runs the split form.
  * OPT_PCG_SPLIT: the textbook recurrence (alpha = r.z / p.Ap, then beta), two
  *   kernels per iteration.
+ * OPT_PCG_MATERIALIZED: the materialised alternative of Sec. 7 (evalJ): J is
+ *   evaluated into the workspace once per outer iteration and each PCG
+ *   iteration multiplies by it twice (y = J p, then q = J^T y, J^T read through
+ *   per-unknown lists of J's entries), with the textbook recurrence.  Needs a
+ *   problem created with desc.materialize = 1 (OPT_EINVAL otherwise); built for
+ *   ARAP warping on a grid.  For comparing matrix-free and materialised
+ *   products; a server runs such requests in the split form.
  */
-typedef enum { OPT_PCG_FUSED = 0, OPT_PCG_SPLIT = 1 } opt_pcg_variant;
+typedef enum { OPT_PCG_FUSED = 0, OPT_PCG_SPLIT = 1, OPT_PCG_MATERIALIZED = 2 } opt_pcg_variant;
 
 typedef struct {
   int32_t domain;     /* opt_domain */
   int32_t energy;     /* opt_energy */
   int32_t precision;  /* opt_precision */
-  int32_t width, height;           /* grid size (OPT_GRID2D), each >= 1 */
+  int32_t width, height;           /* grid size (OPT_GRID2D, OPT_GRID3D), each >= 1 */
   int32_t n_vertices, n_edges;     /* graph size (OPT_GRAPH), V >= 1, E >= 0 */
   const int32_t* edges;            /* device, [E][2] vertex ids (v0, v1); read by
                                       opt_problem_create only */
   const void* arrays[8];           /* device, energy-specific (see opt_energy) */
   double params[16];               /* energy-specific (see opt_energy) */
   int32_t n_params;                /* number of params[] entries supplied */
+  int32_t depth;                   /* OPT_GRID3D: third grid size (>= 1); else unused */
+  int32_t materialize;             /* 1: the workspace also holds the materialised
+                                      Jacobian (OPT_PCG_MATERIALIZED; OPT_EUNSUPPORTED
+                                      for an energy without it); 0: not */
 } opt_problem_desc;
 
 typedef struct opt_problem opt_problem;
@@ -293,6 +318,61 @@ int opt_problem_get_tuning(opt_problem* prob, opt_tuning* tuning);
  */
 int opt_problem_set_graph_replay(opt_problem* prob, int enable);
 
+/*
+ * Multi-pass optimisation (Sec. 7: between solves the caller may change the
+ * problem state; hierarchical, coarse-to-fine solves are the common case).  The
+ * steps between passes as kernels, and the hierarchical optical flow of
+ * Appendix A.2.3 built from them.  All images are row-major planes (site
+ * j*W + i) of the bulk type of `precision` (float64 under OPT_FP64, float32
+ * under OPT_MIXED), device memory, work enqueued on `hip_stream` (a
+ * hipStream_t; NULL = the null stream) without synchronising.
+ *
+ * opt_image_downsample2: dst (planes x floor(W/2) x floor(H/2)) = the mean of
+ *   each 2 x 2 block of src (planes x W x H); W, H >= 2; 1 <= planes <= 8.
+ * opt_image_gradient: the derivative images of img (W x H) along the width
+ *   (dx) and the height (dy): central differences (img(i+1) - img(i-1)) / 2
+ *   inside, one-sided differences on the first and last column or row, 0 along
+ *   a dimension of one pixel.  These are the derivative images the sampled-image
+ *   operator of the flow energy reads (Sec. 7).
+ * opt_field_upsample: dst(c; i, j) = scale[c] * S(src_c; (i + 1/2) Ws/Wd - 1/2,
+ *   (j + 1/2) Hs/Hd - 1/2), S the bilinear clamp-to-edge sample with texel
+ *   centres at integer coordinates: the coarse field at the point under each
+ *   fine pixel's centre, scaled per plane (a flow measured in coarse pixels is
+ *   scaled by the size ratio).  scale: host array of `planes` values.
+ *
+ * opt_solve_flow_pyramid: the hierarchical dense optical flow of A.2.3 on
+ *   frames I and I_hat (W x H): level l of `levels` has floor(W/2^l) x
+ *   floor(H/2^l) pixels (the coarsest at least 4 x 4); its images are the 2 x 2
+ *   means of the level above (level 0 is I, I_hat themselves) and its
+ *   derivative images are opt_image_gradient of its I_hat.  The coarsest level
+ *   starts from zero flow; every level is solved as opt_solve would solve the
+ *   OPT_E_FLOW problem of its images (params w_fit, w_reg; `params` for every
+ *   level) with the automatic launch shape; each finer level starts from the
+ *   solution below it, upsampled (opt_field_upsample, scaled by the size
+ *   ratios).  `unknowns` (device, 2 planes u, v of W x H) receives the level-0
+ *   solution; with levels == 1 it is also the starting point.  `workspace`:
+ *   device, 256-byte aligned, at least opt_flow_pyramid_workspace_size bytes,
+ *   caller-owned.  `reports` (host, may be NULL) holds `levels` reports,
+ *   reports[l] for level l (each as opt_solve fills it; its cost_trace may be
+ *   NULL); with reports the call synchronises once per level, without it it
+ *   only enqueues work.  Errors: OPT_EINVAL (sizes, levels, precision,
+ *   parameters), OPT_ENOMEM (workspace too small), OPT_ENUMERIC (a level's cost
+ *   was not finite; later levels are not solved).
+ */
+int opt_image_downsample2(const void* src, int32_t width, int32_t height, int32_t planes, int32_t precision,
+                          void* dst, void* hip_stream);
+int opt_image_gradient(const void* img, int32_t width, int32_t height, int32_t precision, void* dx, void* dy,
+                       void* hip_stream);
+int opt_field_upsample(const void* src, int32_t src_width, int32_t src_height, int32_t planes,
+                       const double* scale, int32_t precision, void* dst, int32_t dst_width, int32_t dst_height,
+                       void* hip_stream);
+int opt_flow_pyramid_workspace_size(int32_t width, int32_t height, int32_t levels, int32_t precision,
+                                    size_t* bytes);
+int opt_solve_flow_pyramid(const void* I, const void* I_hat, int32_t width, int32_t height, int32_t levels,
+                           double w_fit, double w_reg, int32_t precision, const opt_solve_params* params,
+                           void* unknowns, void* workspace, size_t workspace_bytes, void* hip_stream,
+                           opt_solve_report* reports);
+
 /* Number of unknown channels per site for an energy (0 if unknown). */
 int opt_energy_channels(int32_t energy);
 
@@ -303,7 +383,8 @@ int opt_energy_channels(int32_t energy);
  * a few thousand unknowns): each kernel launch carries little work.  A server
  * advances every active request by one outer iteration per opt_server_step, and
  * runs each stage of that iteration as one launch per energy kind covering all
- * of its requests.  Each request keeps the arithmetic and reduction order of
+ * of its requests; the energy kinds run on streams of their own (forked from
+ * and joined back to the server's stream within the step), so they overlap.  Each request keeps the arithmetic and reduction order of
  * opt_solve with the same parameters, so its result is bit-identical to solving
  * it alone, whatever else runs beside it.  One exception: a grid problem whose
  * internal vectors pass 256 MB runs the fused PCG form alone but the split form
@@ -322,12 +403,17 @@ int opt_energy_channels(int32_t energy);
  *   is collected or cancelled) and solve parameters.  Returns OPT_EAGAIN (nothing
  *   admitted) if no slot is free or no free arena range is large enough; the
  *   request may be submitted again after a step has retired others.  A graph's
- *   edges are read at submission (this synchronises the stream).  *ticket names
- *   the request.
+ *   edge list is copied to the host behind the work already on the server's
+ *   stream (the call does not wait for the steps in flight); a later step
+ *   builds its incidence lists once that copy has completed, and the request
+ *   starts from then on.  An edge naming a vertex outside [0, V) drops the
+ *   request: poll then returns OPT_EINVAL for its ticket.  *ticket names the
+ *   request.
  * opt_server_step: enqueue one quantum: admitted requests start, in admission
  *   order, while the running set's estimated GPU fill (the share of the device's
  *   wavefront slots its launches occupy, each at most 1) stays within the fill
- *   budget (default 1.0; at least one request always runs); every running
+ *   budget (default 4.0: launches of mid-sized problems are short, and several
+ *   run side by side; at least one request always runs); every running
  *   request does one outer iteration (linearise, PCG init, its pcg_iters PCG
  *   iterations, LM decision, update); requests that reach their outer_iters (or
  *   whose LM radius is known to have fallen below the minimum) get their final

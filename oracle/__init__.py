@@ -7,7 +7,7 @@ package: only ``tests/``, ``__graft_entry__.smoke()`` and the ``cpu_baseline`` l
 What it computes (Opt, arXiv 1604.06525):
 
 * residual vectors F(x) of each energy, written from the energies defined in
-  Appendix C (Figs. 24-27, 30; Laplacian of Figs. 3 and 5), in plain vectorised
+  Appendix C (Figs. 24-27, 30, 31; Laplacian of Figs. 3 and 5), in plain vectorised
   numpy, FP64 (``energies``);
 * an explicit sparse Jacobian J(x) (scipy CSR).  Entries come from complex-step
   forward differentiation of F, exact to rounding, with columns grouped by a
@@ -22,13 +22,13 @@ What it computes (Opt, arXiv 1604.06525):
 Everything is double precision.  It is a correctness reference, not a tuned CPU
 solver.
 """
-from .energies import (ArapWarp, Poisson, ShapeFromShading, OpticalFlow, ArapMesh,
+from .energies import (ArapWarp, Poisson, ShapeFromShading, OpticalFlow, ArapMesh, ArapVolume,
                        LaplacianGrid, LaplacianGraph, make_energy)
 from .assemble import jacobian, jacobian_dense_bruteforce, fd_jacobian
 from .solver import (Linearization, pcg, gauss_newton, levenberg_marquardt, cost,
                      LMParams)
 
-__all__ = ["ArapWarp", "Poisson", "ShapeFromShading", "OpticalFlow", "ArapMesh",
+__all__ = ["ArapWarp", "Poisson", "ShapeFromShading", "OpticalFlow", "ArapMesh", "ArapVolume",
            "LaplacianGrid", "LaplacianGraph", "make_energy", "jacobian",
            "jacobian_dense_bruteforce", "fd_jacobian", "Linearization", "pcg",
            "gauss_newton", "levenberg_marquardt", "cost", "LMParams"]

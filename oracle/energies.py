@@ -405,6 +405,79 @@ class ArapMesh(_Graph):
         return np.concatenate([f, f, f, fwd, fwd, fwd, bwd, bwd, bwd])
 
 
+OFFSETS6 = ((1, 0, 0), (-1, 0, 0), (0, 1, 0), (0, -1, 0), (0, 0, 1), (0, 0, -1))
+
+
+def _shift3(A, di, dj, dk):
+    """B[..., k, j, i] = A[..., k+dk, j+dj, i+di] where that voxel exists, else 0;
+    and the mask of where it does."""
+    D, H, W = A.shape[-3:]
+    B = np.zeros_like(A)
+    inb = np.zeros((D, H, W), bool)
+    k0, k1 = max(0, -dk), min(D, D - dk)
+    j0, j1 = max(0, -dj), min(H, H - dj)
+    i0, i1 = max(0, -di), min(W, W - di)
+    if k1 > k0 and j1 > j0 and i1 > i0:
+        B[..., k0:k1, j0:j1, i0:i1] = A[..., k0 + dk:k1 + dk, j0 + dj:j1 + dj, i0 + di:i1 + di]
+        inb[k0:k1, j0:j1, i0:i1] = True
+    return B, inb
+
+
+class ArapVolume:
+    """ARAP volumetric deformation on a 3D grid (Fig. 31; A.2.5).  Unknowns per
+    voxel: Offset (3), Euler angles (3); voxel (i, j, k) has index (k*H + j)*W + i.
+
+    Fit: r = w_fit (O_v - C_v), each component valid iff C_v >= -999999.9 there.
+    For each voxel v and each neighbour u = v + s, s in +-x, +-y, +-z, that lies
+    on the grid: r(v->u) = w_reg [(O_v - O_u) - R(a_v)(U_v - U_u)] (3 rows).
+    Row order: fit x,y,z (n rows each); then per offset s (in OFFSETS6 order) the
+    x, y, z rows (n each, zero where u is off the grid).
+    """
+    n_chan = 6
+
+    def __init__(self, W, H, D, U, C, w_fit, w_reg):
+        self.W, self.H, self.D = W, H, D
+        self.U = np.asarray(U, float).reshape(3, D, H, W)
+        self.C = np.asarray(C, float).reshape(3, D, H, W)
+        self.w_fit, self.w_reg = float(w_fit), float(w_reg)
+        self.active = np.ones(W * H * D, bool)
+
+    @property
+    def n_sites(self):
+        return self.W * self.H * self.D
+
+    def site_colors(self):
+        k, j, i = np.meshgrid(np.arange(self.D), np.arange(self.H), np.arange(self.W), indexing="ij")
+        return ((i % 2) + 2 * (j % 2) + 4 * (k % 2)).ravel(), 8
+
+    def residuals(self, x):
+        x = np.asarray(x).reshape(6, self.D, self.H, self.W)
+        O, A = x[:3], x[3:]
+        fv = self.C >= -999999.9
+        out = [np.where(fv[c], self.w_fit * (O[c] - self.C[c]), 0) for c in range(3)]
+        for di, dj, dk in OFFSETS6:
+            Oq, inb = _shift3(O, di, dj, dk)
+            Uq, _ = _shift3(self.U, di, dj, dk)
+            Rd = euler_rotate(A, self.U - Uq)
+            r = self.w_reg * ((O - Oq) - Rd)
+            out += [np.where(inb, r[c], 0) for c in range(3)]
+        return np.concatenate([np.ravel(o) for o in out])
+
+    def row_sites(self):
+        W, H, D = self.W, self.H, self.D
+        k, j, i = np.meshgrid(np.arange(D), np.arange(H), np.arange(W), indexing="ij")
+        v = ((k * H + j) * W + i).ravel()
+        f = np.stack([v, -np.ones_like(v)], 1)
+        blocks = [f, f, f]
+        for di, dj, dk in OFFSETS6:
+            ii, jj, kk = i + di, j + dj, k + dk
+            ok = ((ii >= 0) & (ii < W) & (jj >= 0) & (jj < H) & (kk >= 0) & (kk < D)).ravel()
+            u = np.where(ok, ((kk * H + jj) * W + ii).ravel(), -1)
+            g = np.stack([v, u], 1)
+            blocks += [g, g, g]
+        return np.concatenate(blocks)
+
+
 class LaplacianGrid(_Grid):
     """Laplacian smoothing on an image (Fig. 3): r_fit = w_fit (X - A),
     r_h = w_reg (X(i,j) - X(i+1,j)), r_v = w_reg (X(i,j) - X(i,j+1)), the last two
@@ -478,6 +551,8 @@ def make_energy(w):
                                 p["u_y"], p["L"])
     if kind == "arap_mesh":
         return ArapMesh(w["V"], w["edges"], w["U"], w["C"], p["w_fit"], p["w_reg"])
+    if kind == "arap_volume":
+        return ArapVolume(w["W"], w["H"], w["D"], w["U"], w["C"], p["w_fit"], p["w_reg"])
     if kind == "laplacian":
         return LaplacianGrid(w["W"], w["H"], w["A"], p["w_fit"], p["w_reg"])
     if kind == "laplacian_graph":

@@ -15,11 +15,11 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libopt.so")
 
 OPT_OK, OPT_EINVAL, OPT_ENOMEM, OPT_EHIP, OPT_EAGAIN, OPT_ENUMERIC, OPT_EUNSUPPORTED = 0, -1, -2, -3, -4, -5, -6
-GRID2D, GRAPH = 0, 1
-ENERGIES = {"laplacian": 0, "arap_warp": 1, "poisson": 2, "sfs": 3, "flow": 4, "arap_mesh": 5}
+GRID2D, GRAPH, GRID3D = 0, 1, 2
+ENERGIES = {"laplacian": 0, "arap_warp": 1, "poisson": 2, "sfs": 3, "flow": 4, "arap_mesh": 5, "arap_volume": 6}
 PRECISIONS = {"fp64": 0, "mixed": 1}
 GN, LM = 0, 1
-PCG_FUSED, PCG_SPLIT = 0, 1
+PCG_FUSED, PCG_SPLIT, PCG_MATERIALIZED = 0, 1, 2
 
 
 class opt_problem_desc(ctypes.Structure):
@@ -27,7 +27,8 @@ class opt_problem_desc(ctypes.Structure):
                 ("width", ctypes.c_int32), ("height", ctypes.c_int32),
                 ("n_vertices", ctypes.c_int32), ("n_edges", ctypes.c_int32),
                 ("edges", ctypes.c_void_p), ("arrays", ctypes.c_void_p * 8),
-                ("params", ctypes.c_double * 16), ("n_params", ctypes.c_int32)]
+                ("params", ctypes.c_double * 16), ("n_params", ctypes.c_int32), ("depth", ctypes.c_int32),
+                ("materialize", ctypes.c_int32)]
 
 
 class opt_solve_params(ctypes.Structure):
@@ -67,6 +68,18 @@ _proto = {
     "opt_apply_jtj": (ctypes.c_int, [_P, _P, _P, ctypes.c_double, ctypes.POINTER(opt_solve_params)]),
     "opt_pcg": (ctypes.c_int, [_P, ctypes.POINTER(opt_solve_params), ctypes.c_double, _P]),
     "opt_energy_channels": (ctypes.c_int, [ctypes.c_int32]),
+    "opt_image_downsample2": (ctypes.c_int, [_P, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
+                                             _P, _P]),
+    "opt_image_gradient": (ctypes.c_int, [_P, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, _P, _P, _P]),
+    "opt_field_upsample": (ctypes.c_int, [_P, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
+                                          ctypes.POINTER(ctypes.c_double), ctypes.c_int32, _P, ctypes.c_int32,
+                                          ctypes.c_int32, _P]),
+    "opt_flow_pyramid_workspace_size": (ctypes.c_int, [ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
+                                                       ctypes.c_int32, ctypes.POINTER(ctypes.c_size_t)]),
+    "opt_solve_flow_pyramid": (ctypes.c_int, [_P, _P, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
+                                              ctypes.c_double, ctypes.c_double, ctypes.c_int32,
+                                              ctypes.POINTER(opt_solve_params), _P, _P, ctypes.c_size_t, _P,
+                                              ctypes.POINTER(opt_solve_report)]),
     "opt_profile_enable": (ctypes.c_int, [_P, ctypes.c_int]),
     "opt_profile_read": (ctypes.c_int, [_P, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64)]),
     "opt_problem_set_tuning": (ctypes.c_int, [_P, ctypes.POINTER(opt_tuning)]),
@@ -129,7 +142,7 @@ def default_params(**kw):
         if k == "method" and isinstance(v, str):
             v = {"gn": GN, "lm": LM}[v.lower()]
         if k == "pcg_variant" and isinstance(v, str):
-            v = {"fused": PCG_FUSED, "split": PCG_SPLIT}[v.lower()]
+            v = {"fused": PCG_FUSED, "split": PCG_SPLIT, "materialized": PCG_MATERIALIZED}[v.lower()]
         if not hasattr(p, k):
             raise TypeError(f"unknown solve parameter {k}")
         setattr(p, k, v)
@@ -140,15 +153,73 @@ def energy_channels(energy):
     return lib().opt_energy_channels(ENERGIES[energy] if isinstance(energy, str) else energy)
 
 
+# The data arrays each energy takes (include/opt.h): planes over the sites, and
+# whether an array holds bulk values (the precision's float type) or a uint8 mask.
+ARRAY_SPEC = {
+    "arap_warp": [(2, "bulk"), (2, "bulk"), (1, "u8")],
+    "poisson": [(4, "bulk"), (1, "u8")],
+    "sfs": [(1, "bulk"), (1, "bulk"), (1, "u8"), (1, "u8")],
+    "flow": [(1, "bulk"), (1, "bulk"), (1, "bulk"), (1, "bulk")],
+    "arap_mesh": [(3, "bulk"), (3, "bulk")],
+    "arap_volume": [(3, "bulk"), (3, "bulk")],
+    "laplacian": [(1, "bulk")],  # 3 planes on a graph
+}
+
+
+def _check_tensor(t, dtype, numel, what):
+    if not isinstance(t, torch.Tensor):
+        raise ValueError(f"{what} must be a torch tensor, got {type(t).__name__}")
+    if t.dtype != dtype:
+        raise ValueError(f"{what} must have dtype {dtype}, got {t.dtype}")
+    if t.numel() != numel:
+        raise ValueError(f"{what} must have {numel} elements, got {t.numel()}")
+    if not t.is_contiguous():
+        raise ValueError(f"{what} must be contiguous")
+
+
+def len_channels(energy, graph=False):
+    """Unknown channels per site (the header's table; no library call).  The
+    Laplacian smooths a scalar on a grid and a float3 on a graph."""
+    if energy == "laplacian":
+        return 3 if graph else 1
+    return {"arap_warp": 3, "poisson": 4, "sfs": 1, "flow": 2, "arap_mesh": 6, "arap_volume": 6}[energy]
+
+
+def check_request(energy, arrays, x, precision, n_sites, graph=False):
+    """Raise ValueError unless the data arrays and the unknowns match what the
+    library will read and write for this energy, precision and site count
+    (checked on the host before any pointer reaches a kernel)."""
+    bulk = torch.float64 if precision == "fp64" else torch.float32
+    spec = ARRAY_SPEC.get(energy)
+    if spec is None:
+        raise ValueError(f"unknown energy {energy}")
+    if len(arrays) != len(spec):
+        raise ValueError(f"{energy} takes {len(spec)} arrays, got {len(arrays)}")
+    if energy == "laplacian" and graph:
+        spec = [(3, "bulk")]
+    named = [(f"array {k} of {energy}", a) for k, a in enumerate(arrays)]
+    for (what, a), (planes, kind) in zip(named, spec):
+        _check_tensor(a, bulk if kind == "bulk" else torch.uint8, planes * n_sites, what)
+    if x is not None:
+        _check_tensor(x, bulk, len_channels(energy, graph) * n_sites, "unknowns")
+        named.append(("unknowns", x))
+    for what, t in named:
+        if t.device.type != "cuda":
+            raise ValueError(f"{what} must be on a CUDA device, got {t.device}")
+
+
 def make_desc(energy, arrays, params=(), precision="mixed", width=0, height=0, n_vertices=0,
-              edges=None):
+              edges=None, depth=0, materialize=False):
     """An opt_problem_desc for the given tensors; returns (desc, arrays, edges)
-    (the tensors the descriptor points to, to be kept alive by the caller)."""
+    (the tensors the descriptor points to, to be kept alive by the caller).
+    A graph when n_vertices is given, a 3D grid when depth is, else a 2D grid."""
     d = opt_problem_desc()
-    d.domain = GRAPH if n_vertices else GRID2D
+    d.domain = GRAPH if n_vertices else (GRID3D if depth else GRID2D)
     d.energy = ENERGIES[energy]
     d.precision = PRECISIONS[precision]
     d.width, d.height = width, height
+    d.depth = depth
+    d.materialize = int(bool(materialize))
     d.n_vertices = n_vertices
     if edges is not None:
         if not edges.is_contiguous() or edges.dtype != torch.int32:
@@ -177,15 +248,17 @@ class Problem:
     """
 
     def __init__(self, energy, arrays, params=(), precision="mixed", width=0, height=0,
-                 n_vertices=0, edges=None, stream=None, workspace=None, tuning="auto"):
+                 n_vertices=0, edges=None, stream=None, workspace=None, tuning="auto", depth=0,
+                 materialize=False):
         self.energy = energy
         self.precision = precision
         self.dtype = torch.float64 if precision == "fp64" else torch.float32
-        self.channels = energy_channels(energy)
+        self.channels = len_channels(energy, bool(n_vertices)) if energy == "laplacian" else energy_channels(energy)
+        self.n_sites = n_vertices if n_vertices else width * height * (depth if depth else 1)
+        check_request(energy, list(arrays), None, precision, self.n_sites, bool(n_vertices))
         self.desc, self.arrays, self.edges = make_desc(energy, arrays, params, precision, width, height,
-                                                       n_vertices, edges)
+                                                       n_vertices, edges, depth, materialize)
         d = self.desc
-        self.n_sites = n_vertices if n_vertices else width * height
         nbytes = ctypes.c_size_t(0)
         _check(lib().opt_workspace_size(ctypes.byref(d), ctypes.byref(nbytes)), "opt_workspace_size")
         dev = self.arrays[0].device
@@ -202,7 +275,7 @@ class Problem:
                "opt_problem_create")
         self.handle = h
         self._lib = lib()
-        if tuning == "auto" and not n_vertices:
+        if tuning == "auto" and not n_vertices and not depth:
             from . import tune
             t = tune.best(tune.load(), energy, precision, self.n_sites)
             if t["strip_rows"] or t["waves_per_simd"]:
@@ -320,17 +393,13 @@ SCRATCH_BYTES = 128 << 20  # OPT_SCRATCH_BYTES
 
 
 def solve_scratch(energy, arrays, x, params=(), precision="mixed", width=0, height=0, n_vertices=0,
-                  edges=None, solve_params=None, stream=None, report=True, **kw):
+                  edges=None, solve_params=None, stream=None, report=True, depth=0, **kw):
     """opt_solve_scratch: create and solve a problem in the library's static
     scratch (no device allocation), x in place.  Returns the report dict (as
     Problem.solve), or None with report=False (work only enqueued)."""
-    d, arrays, edges = make_desc(energy, arrays, params, precision, width, height, n_vertices, edges)
-    dtype = torch.float64 if precision == "fp64" else torch.float32
-    n = n_vertices if n_vertices else width * height
-    if x.dtype != dtype or not x.is_contiguous() or x.numel() != energy_channels(energy) * n or \
-            x.device != arrays[0].device:
-        raise ValueError(f"x must be a contiguous {dtype} tensor of {energy_channels(energy)}x{n} "
-                         f"on {arrays[0].device}")
+    n = n_vertices if n_vertices else width * height * (depth if depth else 1)
+    check_request(energy, list(arrays), x, precision, n, bool(n_vertices))
+    d, arrays, edges = make_desc(energy, arrays, params, precision, width, height, n_vertices, edges, depth)
     p = solve_params if solve_params is not None else default_params(**kw)
     st = stream if stream is not None else torch.cuda.current_stream(x.device)
     sp = ctypes.c_void_p(st.cuda_stream)
@@ -348,9 +417,84 @@ def solve_scratch(energy, arrays, x, params=(), precision="mixed", width=0, heig
     return out
 
 
+# ---------------------------------------------------------------- multi-pass steps
+def _stream_of(t, stream):
+    st = stream if stream is not None else torch.cuda.current_stream(t.device)
+    return ctypes.c_void_p(st.cuda_stream)
+
+
+def _img_check(t, precision, numel, name):
+    dtype = torch.float64 if precision == "fp64" else torch.float32
+    if t.dtype != dtype or not t.is_contiguous() or t.numel() != numel or t.device.type != "cuda":
+        raise ValueError(f"{name} must be a contiguous {dtype} CUDA tensor of {numel} elements")
+
+
+def image_downsample2(src, width, height, planes=1, precision="mixed", stream=None):
+    """opt_image_downsample2: 2 x 2 block means; returns planes x H/2 x W/2."""
+    _img_check(src, precision, planes * width * height, "src")
+    dst = torch.empty((planes, height // 2, width // 2), dtype=src.dtype, device=src.device)
+    _check(lib().opt_image_downsample2(_ptr(src), width, height, planes, PRECISIONS[precision], _ptr(dst),
+                                       _stream_of(src, stream)), "opt_image_downsample2")
+    return dst
+
+
+def image_gradient(img, width, height, precision="mixed", stream=None):
+    """opt_image_gradient: (dx, dy), each H x W."""
+    _img_check(img, precision, width * height, "img")
+    dx = torch.empty((height, width), dtype=img.dtype, device=img.device)
+    dy = torch.empty_like(dx)
+    _check(lib().opt_image_gradient(_ptr(img), width, height, PRECISIONS[precision], _ptr(dx), _ptr(dy),
+                                    _stream_of(img, stream)), "opt_image_gradient")
+    return dx, dy
+
+
+def field_upsample(src, src_width, src_height, planes, scale, dst_width, dst_height, precision="mixed",
+                   stream=None):
+    """opt_field_upsample: planes x dst_height x dst_width."""
+    _img_check(src, precision, planes * src_width * src_height, "src")
+    sc = (ctypes.c_double * planes)(*[float(v) for v in scale])
+    dst = torch.empty((planes, dst_height, dst_width), dtype=src.dtype, device=src.device)
+    _check(lib().opt_field_upsample(_ptr(src), src_width, src_height, planes, sc, PRECISIONS[precision], _ptr(dst),
+                                    dst_width, dst_height, _stream_of(src, stream)), "opt_field_upsample")
+    return dst
+
+
+def flow_pyramid_workspace_size(width, height, levels, precision="mixed"):
+    b = ctypes.c_size_t(0)
+    _check(lib().opt_flow_pyramid_workspace_size(width, height, levels, PRECISIONS[precision], ctypes.byref(b)),
+           "opt_flow_pyramid_workspace_size")
+    return b.value
+
+
+def solve_flow_pyramid(I, I_hat, x, levels, w_fit, w_reg, precision="mixed", solve_params=None, stream=None,
+                       workspace_bytes=None, report=True, **kw):
+    """opt_solve_flow_pyramid on frames I, I_hat (H x W); x (2 x H x W) receives
+    the flow.  Returns the per-level reports (level 0 = finest first), or None
+    with report=False."""
+    H, W = I.shape[-2], I.shape[-1]
+    _img_check(I, precision, W * H, "I")
+    _img_check(I_hat, precision, W * H, "I_hat")
+    _img_check(x, precision, 2 * W * H, "x")
+    nbytes = flow_pyramid_workspace_size(W, H, levels, precision) if workspace_bytes is None else workspace_bytes
+    ws = torch.empty(max(int(nbytes), 1), dtype=torch.uint8, device=x.device)
+    p = solve_params if solve_params is not None else default_params(**kw)
+    traces = [(ctypes.c_double * (p.outer_iters + 1))() for _ in range(levels)]
+    reps = (opt_solve_report * levels)()
+    for k in range(levels):
+        reps[k].cost_trace = ctypes.cast(traces[k], ctypes.POINTER(ctypes.c_double))
+    code = lib().opt_solve_flow_pyramid(_ptr(I), _ptr(I_hat), W, H, levels, float(w_fit), float(w_reg),
+                                        PRECISIONS[precision], ctypes.byref(p), _ptr(x), _ptr(ws), int(nbytes),
+                                        _stream_of(x, stream), reps if report else None)
+    _check(code, "opt_solve_flow_pyramid")
+    if not report:
+        return None
+    return [dict(cost_initial=r.cost_initial, cost_final=r.cost_final, outer_done=r.outer_done,
+                 steps_accepted=r.steps_accepted, cost_trace=list(t)) for r, t in zip(reps, traces)]
+
+
 def workspace_size(energy, arrays, params=(), precision="mixed", width=0, height=0, n_vertices=0,
-                   edges=None):
-    d, _, _ = make_desc(energy, arrays, params, precision, width, height, n_vertices, edges)
+                   edges=None, depth=0):
+    d, _, _ = make_desc(energy, arrays, params, precision, width, height, n_vertices, edges, depth)
     nbytes = ctypes.c_size_t(0)
     _check(lib().opt_workspace_size(ctypes.byref(d), ctypes.byref(nbytes)), "opt_workspace_size")
     return nbytes.value
@@ -393,10 +537,12 @@ class Server:
             self.handle = None
 
     def submit(self, energy, arrays, x, params=(), precision="mixed", width=0, height=0,
-               n_vertices=0, edges=None, solve_params=None, **kw):
+               n_vertices=0, edges=None, solve_params=None, depth=0, **kw):
         """Admit a request solving x in place; returns its ticket, or None when
         the server is full (OPT_EAGAIN)."""
-        d, arrays, edges = make_desc(energy, arrays, params, precision, width, height, n_vertices, edges)
+        n_sites = n_vertices if n_vertices else width * height * (depth if depth else 1)
+        check_request(energy, list(arrays), x, precision, n_sites, bool(n_vertices))
+        d, arrays, edges = make_desc(energy, arrays, params, precision, width, height, n_vertices, edges, depth)
         sp = solve_params if solve_params is not None else default_params(**kw)
         t = ctypes.c_int64(-1)
         code = lib().opt_server_submit(self.handle, ctypes.byref(d), _ptr(x), ctypes.byref(sp),

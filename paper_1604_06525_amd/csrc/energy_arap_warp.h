@@ -157,6 +157,90 @@ struct ArapWarp {
     d[2] = wr2 * dt;
   }
 
+  // Materialised Jacobian (evalJ, Sec. 7): the rows anchored at site s, each
+  // with kJSlots entries (column = internal vector index site*C + channel, -1
+  // for no entry, value 0 there): rows 2k, 2k+1 are the x and y regulariser
+  // towards neighbour k, rows 8, 9 the x and y fit.  Columns of excluded
+  // unknowns are dropped (Exclude), so a row exists only where both of its
+  // pixels are active.  An unknown appears in at most kJTSlots rows: an offset
+  // in its fit, its four own regularisers and its four neighbours'; an angle in
+  // its own eight regulariser rows.
+  static constexpr int kJRows = 10, kJSlots = 3, kJTSlots = 9;
+  __device__ __forceinline__ void eval_j(int s, T* __restrict__ val, int* __restrict__ col) const {
+    const int i = s % W, j = s / W;
+    const uint32_t fp = flags[s];
+    const T* sp = st + (size_t)s * 4;
+    const T c = sp[0], sn = sp[1], Ux = sp[2], Uy = sp[3];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      const int q = nbr(i, j, s, k);
+      const bool on = (fp & ACTIVE) && q >= 0 && (flags[q] & ACTIVE);
+      const T dx = on ? Ux - st[(size_t)q * 4 + 2] : T(0), dy = on ? Uy - st[(size_t)q * 4 + 3] : T(0);
+      const T a[2] = {-sn * dx - c * dy, c * dx - sn * dy};  // R'(t_p)(U_p - U_q)
+#pragma unroll
+      for (int ch = 0; ch < 2; ++ch) {
+        const int r = (2 * k + ch) * kJSlots;
+        col[r] = on ? s * 3 + ch : -1;
+        col[r + 1] = on ? q * 3 + ch : -1;
+        col[r + 2] = on ? s * 3 + 2 : -1;
+        val[r] = on ? wr : T(0);
+        val[r + 1] = on ? -wr : T(0);
+        val[r + 2] = on ? -wr * a[ch] : T(0);
+      }
+    }
+    const bool fit = (fp & ACTIVE) && (fp & FIT);
+#pragma unroll
+    for (int ch = 0; ch < 2; ++ch) {
+      const int r = (8 + ch) * kJSlots;
+      col[r] = fit ? s * 3 + ch : -1;
+      col[r + 1] = -1;
+      col[r + 2] = -1;
+      val[r] = fit ? wf : T(0);
+      val[r + 1] = T(0);
+      val[r + 2] = T(0);
+    }
+  }
+
+  // The column lists of J^T for the unknowns of site s (kJTSlots entries each,
+  // indices into eval_j's entries, in row order of appearance below, -1 after
+  // the last): the structure of eval_j read by column.  Offset channel c: its
+  // fit row, its own four regularisers (slot 0), the neighbours' regularisers
+  // pointing back at s (slot 1); angle: its own eight regulariser rows (slot 2).
+  __device__ __forceinline__ void eval_jt(int s, int* __restrict__ jt) const {
+    const int i = s % W, j = s / W;
+    const bool act = flags[s] & ACTIVE;
+    bool on[4];
+    int q[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      q[k] = nbr(i, j, s, k);
+      on[k] = act && q[k] >= 0 && (flags[q[k]] & ACTIVE);
+    }
+    const bool fit = act && (flags[s] & FIT);
+    auto at = [](int site, int row, int slot) { return (site * kJRows + row) * kJSlots + slot; };
+#pragma unroll
+    for (int ch = 0; ch < 2; ++ch) {
+      int* o = jt + ch * kJTSlots;
+      int m = 0;
+      if (fit) o[m++] = at(s, 8 + ch, 0);
+#pragma unroll
+      for (int k = 0; k < 4; ++k)
+        if (on[k]) o[m++] = at(s, 2 * k + ch, 0);
+#pragma unroll
+      for (int k = 0; k < 4; ++k)
+        if (on[k]) o[m++] = at(q[k], 2 * (k ^ 1) + ch, 1);  // (k ^ 1): the opposite offset
+      for (; m < kJTSlots; ++m) o[m] = -1;
+    }
+    int* o = jt + 2 * kJTSlots;
+    int m = 0;
+#pragma unroll
+    for (int k = 0; k < 4; ++k)
+#pragma unroll
+      for (int ch = 0; ch < 2; ++ch)
+        if (on[k]) o[m++] = at(s, 2 * k + ch, 2);
+    for (; m < kJTSlots; ++m) o[m] = -1;
+  }
+
   // Per-site edge geometry that apply computes and jsq reuses: for each
   // neighbour k, a_p = R'(t_p)(U_p - U_q).
   struct JCache {

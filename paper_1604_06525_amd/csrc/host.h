@@ -58,19 +58,23 @@ struct Shape {
   int n_edges = 0;     // graph: listed undirected edges
   int stage_w = 0;     // graph: values per vertex pcg_a stages (0: not staged)
   bool graph = false;
+  // materialised Jacobian (OPT_PCG_MATERIALIZED): rows per site, entries per
+  // row, entries per J^T column
+  bool mat = false;
+  int mat_rows = 0, mat_slots = 0, mat_tslots = 0;
 };
 
 // Byte offsets of every region of a problem's workspace.
 struct Layout {
-  size_t r0, r1, p0, p1, q, diag, minv, damp, delta, state, flags, csr, halo, parts, scal, trace,
-      rows, total;
+  size_t r0, r1, p0, p1, q, diag, minv, damp, delta, state, flags, csr, halo, jval, jcol, jt, jy, parts, scal,
+      trace, rows, total;
 };
 
 // Argument rows a single problem launches with, one device slot of kMaxArgBytes
 // each in its workspace (the batching server keeps its own tables).
 enum RowKind {
   ROW_SETUP, ROW_LIN, ROW_INIT, ROW_PCGA, ROW_APPLY, ROW_PCGB, ROW_FUSED, ROW_STEP, ROW_COST,
-  ROW_TRIAL, ROW_MODEL, ROW_DECIDE, ROW_FINISH, ROW_PLANES, kNumRows
+  ROW_TRIAL, ROW_MODEL, ROW_DECIDE, ROW_FINISH, ROW_PLANES, ROW_EVALJ, ROW_MATP, ROW_MATA, ROW_MATB, kNumRows
 };
 
 // Partial-sum buffers of kMaxBlocks doubles each; the fused form uses two pairs.
@@ -91,18 +95,26 @@ struct PrecondArgs {
 // ---------------------------------------------------------------- batching
 // Argument tables of batched launches are written into pinned host staging
 // memory while a step is planned, copied to device memory in one transfer, and
-// then the recorded launches are enqueued.
+// then the recorded launches are enqueued.  Launches are recorded into lanes:
+// each lane's launches go to one stream, in recording order; the server
+// enqueues the lanes round robin, one launch of each in turn, so that lanes on
+// different streams start together.
+constexpr int kMaxLanes = 4;
+
 struct Batcher {
   char* host = nullptr;   // pinned staging
   char* dev = nullptr;    // device table area of the same size
   size_t cap = 0, used = 0;
-  hipStream_t stream = nullptr;
-  std::vector<std::function<int()>> launches;
+  hipStream_t stream = nullptr;  // stream of the lane being recorded
+  int lane = 0;                  // lane being recorded
+  std::vector<std::function<int()>> q[kMaxLanes];
 
   void reset() {
     used = 0;
-    launches.clear();
+    lane = 0;
+    for (auto& l : q) l.clear();
   }
+  void push(std::function<int()> f) { q[lane].push_back(std::move(f)); }
   // Reserve `bytes` (256-aligned); returns the offset or -1 if full.
   long long reserve(size_t bytes) {
     const size_t off = align_up(used);
@@ -139,6 +151,12 @@ class Impl {
   virtual int pcg_b(int k, int L, PrecondArgs pa, int lm_gate) = 0;
   virtual int fused(int iter, int L, PrecondArgs pa, int lm_gate) = 0;
   virtual bool has_fused() const = 0;
+  // materialised form (OPT_PCG_MATERIALIZED): evaluate J at the linearisation
+  // point, then per iteration y = J p and q = J^T y (+ damping), then pcg_b
+  virtual bool has_mat() const { return false; }
+  virtual int eval_j() = 0;
+  virtual int mat_a(int k, int L, PrecondArgs pa, int lm_gate) = 0;
+  virtual int mat_b(int k, int L, PrecondArgs pa, int lm_gate) = 0;
   // the fused form runs the instantiation for vectors past 256 MB (solo only:
   // the server runs such problems in the split form)
   virtual bool fused_is_big() const { return false; }
@@ -223,9 +241,19 @@ namespace optmi {
 namespace host {
 
 // Build the handle's state inside `workspace` (validated descriptor); for a
-// graph this sorts the edges into the incidence list and synchronises.
+// graph this sorts the edges into the incidence list and synchronises, unless
+// defer_graph (the caller then builds and uploads it: build_incidence_host,
+// upload_incidence).
 int problem_init(opt_problem* p, const opt_problem_desc* desc, const Shape& sh, void* workspace,
-                 hipStream_t stream);
+                 hipStream_t stream, bool defer_graph = false);
+
+// Graph incidence and staging lists as one host array (see opt_capi.hip).
+size_t incidence_words(const Shape& sh);
+int build_incidence_host(const Shape& sh, const int* edges, int* out);
+int upload_incidence(opt_problem* p, const int* words);
+
+// opt_solve on a created problem (parameters validated here).
+int solve(opt_problem* p, void* x, const opt_solve_params* sp, opt_solve_report* rep);
 
 // An argument struct with every byte zero (padding included) before its fields
 // are set, so equal arguments compare equal byte for byte.
@@ -338,7 +366,7 @@ int batch_launch(const BatchTable<A>& t, int iter, hipStream_t st, const char* n
 }
 
 // Record a batched launch of `A` rows (one per problem) with the given block
-// counts, for iterations [iter_lo, iter_hi).
+// counts, for iterations [iter_lo, iter_hi) (one recorded launch each).
 template <class A>
 int batch_record(Batcher& B, const A* rows, const int* grids, int n, int iter_lo, int iter_hi,
                  const char* name) {
@@ -346,10 +374,7 @@ int batch_record(Batcher& B, const A* rows, const int* grids, int n, int iter_lo
   BatchTable<A> t;
   TRY(batch_table(B, rows, grids, n, &t));
   hipStream_t st = B.stream;
-  B.launches.push_back([=]() -> int {
-    for (int it = iter_lo; it < iter_hi; ++it) TRY(batch_launch(t, it, st, name));
-    return OPT_OK;
-  });
+  for (int it = iter_lo; it < iter_hi; ++it) B.push([=]() -> int { return batch_launch(t, it, st, name); });
   return OPT_OK;
 }
 

@@ -421,6 +421,162 @@ __device__ __forceinline__ void run(const SplitBArgs<T, C>& a, VG g, int k) {
   block_store(rz, pick(a.rz_part, (k + 1) & 1), g);
 }
 
+// ---------------------------------------------------------------- materialised PCG
+// The alternative to the matrix-free products that Sec. 7 compares them with:
+// J is evaluated once per linearisation into device memory (evalJ; a fixed
+// number of entries per residual row, the energy's eval_j) and every PCG
+// iteration multiplies by it twice, y = J p then q = J^T y.  J^T is not stored:
+// each unknown's list of the J entries in its column (built once from the
+// structure by evalJ) gathers them.  The recurrence is the split form's: per
+// iteration p = z + beta p (MatP), y = J p (MatA), q = J^T y (MatB, with the
+// partials of p.q), then pcg_b unchanged.
+
+// Energies that can materialise their Jacobian (E::kJRows).
+template <class E, class = void>
+struct MatOf : std::false_type {};
+template <class E>
+struct MatOf<E, std::void_t<decltype(E::kJRows)>> : std::true_type {};
+
+template <class E>
+struct EvalJArgs {
+  E e;
+  typename E::Real* val;  // [n][kJRows][kJSlots]
+  int* col;
+  int* jt;                // [n][C][kJTSlots]
+};
+
+template <class E>
+__device__ __forceinline__ void run(const EvalJArgs<E>& a, VG g, int) {
+  constexpr int RS = E::kJRows * E::kJSlots, CT = E::C * E::kJTSlots;
+  OPT_SITE_LOOP(s, a.e.n, g) {
+    a.e.eval_j(s, a.val + (size_t)s * RS, a.col + (size_t)s * RS);
+    a.e.eval_jt(s, a.jt + (size_t)s * CT);
+  }
+}
+
+template <typename T>
+struct MatBufs {
+  const T* val;    // J entries, rows x slots
+  const int* col;  // their internal vector index (-1: none)
+  const int* jt;   // per unknown, tslots indices into val (-1: none), row order
+  T* y;            // J p, one per row
+  long long rows;
+};
+
+// p_k = z + beta p_{k-1} with z = M^-1 r (beta from the r.z partials of the
+// previous pcg_b, or of init); stored for the two products and pcg_b.
+template <typename T, int C>
+struct MatPArgs {
+  int n;
+  const T* r;
+  const T* minv;
+  T* p[2];
+  const double* rz_part[2];
+  int n_part;
+  DevScalars* S;
+  int lm_gate;
+  int L;
+};
+
+template <typename T, int C>
+__device__ __forceinline__ void run(const MatPArgs<T, C>& a, VG g, int k) {
+  DevScalars* S = a.S;
+  if (k >= a.L || S->stopped || (a.lm_gate && S->done)) return;
+  const double rz = reduce_partials(pick(a.rz_part, k & 1), a.n_part);
+  const T beta = k > 0 ? (T)(rz / S->rz[(k - 1) & 1]) : T(0);
+  if (is_block_leader(g)) S->rz[k & 1] = rz;
+  const T* pold = pick(a.p, (k + 1) & 1);
+  T* pnew = pick(a.p, k & 1);
+  OPT_SITE_LOOP(s, a.n, g) {
+    T rv[C], mv[C], po[C];
+    const size_t o = vix<C>(0, s);
+#pragma unroll
+    for (int c = 0; c < C; ++c) {
+      rv[c] = a.r[o + c];
+      mv[c] = a.minv[o + c];
+      po[c] = k > 0 ? pold[o + c] : T(0);
+    }
+#pragma unroll
+    for (int c = 0; c < C; ++c) pnew[o + c] = fma(beta, po[c], mv[c] * rv[c]);
+  }
+}
+
+// y = J p, one thread per residual row.
+template <class E>
+struct MatAArgs {
+  MatBufs<typename E::Real> m;
+  const typename E::Real* p;
+  const DevScalars* S;
+  int lm_gate;
+  int L;
+};
+
+template <class E>
+__device__ __forceinline__ void run(const MatAArgs<E>& a, VG g, int k) {
+  using T = typename E::Real;
+  constexpr int NS = E::kJSlots;
+  const DevScalars* S = a.S;
+  if (k >= a.L || S->stopped || (a.lm_gate && S->done)) return;
+  const MatBufs<T>& m = a.m;
+  for (long long r = (long long)unit_of_block(g) * kBlock + threadIdx.x; r < m.rows;
+       r += (long long)g.nb * kBlock) {
+    int cl[NS];
+    T vl[NS];
+#pragma unroll
+    for (int t = 0; t < NS; ++t) {
+      cl[t] = m.col[r * NS + t];
+      vl[t] = m.val[r * NS + t];
+    }
+    T acc = T(0);
+#pragma unroll
+    for (int t = 0; t < NS; ++t)
+      if (cl[t] >= 0) acc = fma(vl[t], a.p[cl[t]], acc);
+    m.y[r] = acc;
+  }
+}
+
+// q = J^T y (+ damping p), partials of p . q.
+template <class E>
+struct MatBArgs {
+  MatBufs<typename E::Real> m;
+  int n;
+  const typename E::Real* p;
+  const typename E::Real* damp;
+  typename E::Real* q;
+  double* pq_part;
+  DevScalars* S;
+  int lm_gate;
+  int L;
+};
+
+template <class E>
+__device__ __forceinline__ void run(const MatBArgs<E>& a, VG g, int k) {
+  using T = typename E::Real;
+  constexpr int C = E::C, NS = E::kJSlots, NT = E::kJTSlots;
+  DevScalars* S = a.S;
+  if (k >= a.L || S->stopped || (a.lm_gate && S->done)) return;
+  const MatBufs<T>& m = a.m;
+  double pq = 0.0;
+  OPT_SITE_LOOP(s, a.n, g) {
+#pragma unroll
+    for (int c = 0; c < C; ++c) {
+      const size_t u = vix<C>(c, s);
+      int e[NT];
+#pragma unroll
+      for (int t = 0; t < NT; ++t) e[t] = m.jt[u * NT + t];
+      T acc = T(0);
+#pragma unroll
+      for (int t = 0; t < NT; ++t)
+        if (e[t] >= 0) acc = fma(m.val[e[t]], m.y[e[t] / NS], acc);
+      const T pv = a.p[u];
+      if (a.damp) acc = fma(a.damp[u], pv, acc);
+      a.q[u] = acc;
+      pq += (double)pv * (double)acc;
+    }
+  }
+  block_store(pq, a.pq_part, g);
+}
+
 // ---------------------------------------------------------------- fused iteration
 // Value that lane l-1 (from_left) or l+1 (from_right) of the wave holds; 0 past
 // the ends of the wave.  DPP wave shifts, so no LDS traffic.

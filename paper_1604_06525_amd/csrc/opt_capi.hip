@@ -54,6 +54,12 @@ Layout make_layout(const Shape& sh) {
   if (sh.graph)
     off += align_up(sizeof(int) * (2 * (size_t)sh.n_edges + (size_t)(sh.n + kBlock - 1) / kBlock *
                                                                   (1 + (size_t)halo_cap(sh.tsize, sh.stage_w))));
+  // materialised Jacobian: entries (values, columns), J^T lists, y = J p
+  const size_t jrows = sh.mat ? (size_t)sh.n * sh.mat_rows : 0;
+  L.jval = off; off += align_up(jrows * sh.mat_slots * sh.tsize);
+  L.jcol = off; off += align_up(jrows * sh.mat_slots * sizeof(int));
+  L.jt = off; off += align_up((size_t)(sh.mat ? sh.n : 0) * sh.C * sh.mat_tslots * sizeof(int));
+  L.jy = off; off += align_up(jrows * sh.tsize);
   L.parts = off; off += align_up(kNumPartBufs * (size_t)kMaxBlocks * sizeof(double));
   L.scal = off; off += align_up(sizeof(DevScalars));
   L.trace = off; off += align_up((size_t)kTraceCap * sizeof(double));
@@ -66,22 +72,26 @@ namespace {
 
 int energy_channels(int e) {
   switch (e) {
+    case OPT_E_LAPLACIAN: return LaplacianGrid<float>::C;
     case OPT_E_ARAP_WARP: return ArapWarp<float>::C;
     case OPT_E_POISSON: return Poisson<float>::C;
     case OPT_E_FLOW: return OpticalFlow<float>::C;
     case OPT_E_SFS: return ShapeFromShading<float>::C;
     case OPT_E_ARAP_MESH: return ArapMesh<float>::C;
+    case OPT_E_ARAP_VOLUME: return ArapVolume<float>::C;
     default: return 0;
   }
 }
 
 int energy_state_planes(int e) {
   switch (e) {
+    case OPT_E_LAPLACIAN: return 0;
     case OPT_E_ARAP_WARP: return ArapWarp<float>::kOwnState;
     case OPT_E_POISSON: return Poisson<float>::kOwnState;
     case OPT_E_FLOW: return OpticalFlow<float>::kOwnState;
     case OPT_E_SFS: return ShapeFromShading<float>::kOwnState;
     case OPT_E_ARAP_MESH: return ArapMesh<float>::kOwnState;
+    case OPT_E_ARAP_VOLUME: return ArapVolume<float>::kOwnState;
     default: return 0;
   }
 }
@@ -102,24 +112,40 @@ int stage_width(int e) {
   }
 }
 
+// Materialised-Jacobian dimensions of an energy on a domain (rows per site,
+// entries per row, entries per J^T column); false if it has none.
+bool mat_dims(int e, int domain, int* rows, int* slots, int* tslots) {
+  if (e == OPT_E_ARAP_WARP && domain == OPT_GRID2D) {
+    *rows = ArapWarp<float>::kJRows;
+    *slots = ArapWarp<float>::kJSlots;
+    *tslots = ArapWarp<float>::kJTSlots;
+    return true;
+  }
+  return false;
+}
+
 int n_params_needed(int e) {
   switch (e) {
+    case OPT_E_LAPLACIAN: return 2;
     case OPT_E_ARAP_WARP: return 2;
     case OPT_E_POISSON: return 0;
     case OPT_E_FLOW: return 2;
     case OPT_E_SFS: return 16;
     case OPT_E_ARAP_MESH: return 2;
+    case OPT_E_ARAP_VOLUME: return 2;
     default: return 0;
   }
 }
 
 int n_arrays_needed(int e) {
   switch (e) {
+    case OPT_E_LAPLACIAN: return 1;
     case OPT_E_ARAP_WARP: return 3;
     case OPT_E_POISSON: return 2;
     case OPT_E_FLOW: return 4;
     case OPT_E_SFS: return 4;
     case OPT_E_ARAP_MESH: return 2;
+    case OPT_E_ARAP_VOLUME: return 2;
     default: return 0;
   }
 }
@@ -132,10 +158,21 @@ int check_desc(const opt_problem_desc* d, Shape* sh) {
     return fail(OPT_EINVAL, "precision %d is not OPT_FP64 or OPT_MIXED", d->precision);
   const int C = energy_channels(d->energy);
   if (C == 0) return fail(OPT_EUNSUPPORTED, "energy %d is not built", d->energy);
-  const bool grid_energy = d->energy != OPT_E_ARAP_MESH;
-  // ARAP warping runs on either domain (the graph form takes an edge list)
-  const bool both = d->energy == OPT_E_ARAP_WARP;
-  if (d->domain == OPT_GRID2D) {
+  const bool volume_energy = d->energy == OPT_E_ARAP_VOLUME;
+  const bool grid_energy = d->energy != OPT_E_ARAP_MESH && !volume_energy;
+  // ARAP warping and the Laplacian run on either 2D domain (the graph form
+  // takes an edge list)
+  const bool both = d->energy == OPT_E_ARAP_WARP || d->energy == OPT_E_LAPLACIAN;
+  if (volume_energy != (d->domain == OPT_GRID3D))
+    return fail(OPT_EUNSUPPORTED, "energy %d and domain %d do not go together (OPT_E_ARAP_VOLUME is the "
+                "OPT_GRID3D energy)", d->energy, d->domain);
+  if (d->domain == OPT_GRID3D) {
+    if (d->width < 1 || d->height < 1 || d->depth < 1)
+      return fail(OPT_EINVAL, "grid size %d x %d x %d must be positive", d->width, d->height, d->depth);
+    if ((long long)d->width * d->height * d->depth > (1LL << 28))
+      return fail(OPT_EINVAL, "grid of %lld sites is too large", (long long)d->width * d->height * d->depth);
+    sh->n = d->width * d->height * d->depth;
+  } else if (d->domain == OPT_GRID2D) {
     if (!grid_energy) return fail(OPT_EUNSUPPORTED, "energy %d needs the graph domain", d->energy);
     if (d->width < 1 || d->height < 1)
       return fail(OPT_EINVAL, "grid size %d x %d must be positive", d->width, d->height);
@@ -163,9 +200,21 @@ int check_desc(const opt_problem_desc* d, Shape* sh) {
                 n_params_needed(d->energy), d->n_params);
   for (int k = 0; k < n_arrays_needed(d->energy); ++k)
     if (!d->arrays[k]) return fail(OPT_EINVAL, "arrays[%d] is NULL", k);
-  sh->C = C;
+  // the graph Laplacian smooths a float3 per vertex (the grid one a scalar)
+  sh->C = d->energy == OPT_E_LAPLACIAN && d->domain == OPT_GRAPH ? LaplacianGraph<float>::C : C;
   sh->state_planes = energy_state_planes(d->energy);
   sh->tsize = d->precision == OPT_FP64 ? sizeof(double) : sizeof(float);
+  if (d->materialize != 0 && d->materialize != 1)
+    return fail(OPT_EINVAL, "materialize %d is not 0 or 1", d->materialize);
+  if (d->materialize) {
+    if (!mat_dims(d->energy, d->domain, &sh->mat_rows, &sh->mat_slots, &sh->mat_tslots))
+      return fail(OPT_EUNSUPPORTED, "energy %d on domain %d has no materialised Jacobian", d->energy, d->domain);
+    // every entry index fits an int32
+    if ((long long)sh->n * sh->mat_rows * sh->mat_slots >= (1LL << 31))
+      return fail(OPT_EINVAL, "materialised Jacobian of %lld entries is too large",
+                  (long long)sh->n * sh->mat_rows * sh->mat_slots);
+    sh->mat = true;
+  }
   return OPT_OK;
 }
 
@@ -397,6 +446,74 @@ class ImplT final : public Impl {
   int pcg_b(int k, int L, PrecondArgs, int lm) override {
     return go(ROW_PCGB, pcgb_args(L, lm), nblk(), k, "pcg_b");
   }
+  // ------------------------------------------------ materialised form
+  bool has_mat() const override { return MatOf<E>::value; }
+  MatBufs<T> mat_bufs() const {
+    MatBufs<T> m = blank<MatBufs<T>>();
+    m.val = vec(p_->L.jval);
+    m.col = (const int*)p_->at(p_->L.jcol);
+    m.jt = (const int*)p_->at(p_->L.jt);
+    m.y = vec(p_->L.jy);
+    m.rows = (long long)e_.n * p_->sh.mat_rows;
+    return m;
+  }
+  int eval_j() override {
+    if constexpr (!MatOf<E>::value) {
+      return fail(OPT_EUNSUPPORTED, "no materialised Jacobian for this energy");
+    } else {
+      EvalJArgs<E> a = blank<EvalJArgs<E>>();
+      a.e = e_;
+      a.val = vec(p_->L.jval);
+      a.col = (int*)p_->at(p_->L.jcol);
+      a.jt = (int*)p_->at(p_->L.jt);
+      return go(ROW_EVALJ, a, nblk(), 0, "eval_j");
+    }
+  }
+  // p_k, then y = J p_k (one thread per row, over as many blocks as rows fill)
+  int mat_a(int k, int L, PrecondArgs, int lm) override {
+    if constexpr (!MatOf<E>::value) {
+      return fail(OPT_EUNSUPPORTED, "no materialised Jacobian for this energy");
+    } else {
+      MatPArgs<T, E::C> ap = blank<MatPArgs<T, E::C>>();
+      ap.n = e_.n;
+      ap.r = rbuf(0);
+      ap.minv = vec(p_->L.minv);
+      ap.p[0] = pbuf(0);
+      ap.p[1] = pbuf(1);
+      ap.rz_part[0] = p_->part(P_RZ0);
+      ap.rz_part[1] = p_->part(P_RZ1);
+      ap.n_part = p_->nblk;
+      ap.S = p_->S();
+      ap.lm_gate = lm;
+      ap.L = L;
+      TRY(go(ROW_MATP, ap, nblk(), k, "mat_p"));
+      MatAArgs<E> a = blank<MatAArgs<E>>();
+      a.m = mat_bufs();
+      a.p = pbuf(k);
+      a.S = p_->S();
+      a.lm_gate = lm;
+      a.L = L;
+      const long long blocks = (a.m.rows + kBlock - 1) / kBlock;
+      return go(ROW_MATA, a, (int)std::min<long long>(blocks, 65535), k, "mat_a");
+    }
+  }
+  int mat_b(int k, int L, PrecondArgs pa, int lm) override {
+    if constexpr (!MatOf<E>::value) {
+      return fail(OPT_EUNSUPPORTED, "no materialised Jacobian for this energy");
+    } else {
+      MatBArgs<E> a = blank<MatBArgs<E>>();
+      a.m = mat_bufs();
+      a.n = e_.n;
+      a.p = pbuf(k);
+      a.damp = damp(pa);
+      a.q = vec(p_->L.q);
+      a.pq_part = p_->part(P_PQ);
+      a.S = p_->S();
+      a.lm_gate = lm;
+      a.L = L;
+      return go(ROW_MATB, a, nblk(), k, "mat_b");
+    }
+  }
   // The fused kernels address memory through raw buffers whose in-range byte
   // offsets stay under 2^28.  Whole vectors (and the state) of at most 256 MB:
   // the regular instantiation.  Past that the radius-1 kernel's BIG
@@ -543,13 +660,11 @@ class ImplT final : public Impl {
           TRY(batch_table(B, ra.data(), grids.data(), n, &ta));
           TRY(batch_table(B, rb.data(), grids.data(), n, &tb));
           hipStream_t stream = B.stream;
-          B.launches.push_back([=]() -> int {
-            for (int it = 0; it < Lmax; ++it) {
+          for (int it = 0; it < Lmax; ++it)
+            B.push([=]() -> int {
               TRY(batch_launch(ta, it, stream, "pcg_a[batch]"));
-              TRY(batch_launch(tb, it, stream, "pcg_b[batch]"));
-            }
-            return OPT_OK;
-          });
+              return batch_launch(tb, it, stream, "pcg_b[batch]");
+            });
           return OPT_OK;
         }
       case Stage::MODEL:
@@ -678,6 +793,48 @@ std::unique_ptr<Impl> make_impl_t(opt_problem* p) {
       e.sw_gT = (T)e.sw_g;
       return std::unique_ptr<Impl>(new ImplT<ShapeFromShading<T>>(p, e));
     }
+    case OPT_E_LAPLACIAN: {
+      if (d.domain == OPT_GRAPH) {
+        LaplacianGraph<T> e;
+        e.n = p->sh.n;
+        e.rp = (const int*)p->at(p->L.csr);
+        e.nb = e.rp + (p->sh.n + 1);
+        e.A = (const T*)d.arrays[0];
+        e.flags = (uint8_t*)p->at(p->L.flags);
+        e.wf2 = (T)(d.params[0] * d.params[0]);
+        e.wr2 = (T)(d.params[1] * d.params[1]);
+        e.wf_d = d.params[0];
+        e.wr_d = d.params[1];
+        return std::unique_ptr<Impl>(new ImplT<LaplacianGraph<T>>(p, e));
+      }
+      LaplacianGrid<T> e;
+      e.W = d.width;
+      e.H = d.height;
+      e.n = p->sh.n;
+      e.A = (const T*)d.arrays[0];
+      e.flags = (uint8_t*)p->at(p->L.flags);
+      e.wf2 = (T)(d.params[0] * d.params[0]);
+      e.wr2 = (T)(d.params[1] * d.params[1]);
+      e.wf_d = d.params[0];
+      e.wr_d = d.params[1];
+      return std::unique_ptr<Impl>(new ImplT<LaplacianGrid<T>>(p, e));
+    }
+    case OPT_E_ARAP_VOLUME: {
+      ArapVolume<T> e;
+      e.n = p->sh.n;
+      e.W = d.width;
+      e.H = d.height;
+      e.D = d.depth;
+      e.U = (const T*)d.arrays[0];
+      e.Ct = (const T*)d.arrays[1];
+      e.trig = (T*)p->at(p->L.state);
+      e.flags = (uint8_t*)p->at(p->L.flags);
+      e.wf = (T)d.params[0];
+      e.wr = (T)d.params[1];
+      e.wf_d = d.params[0];
+      e.wr_d = d.params[1];
+      return std::unique_ptr<Impl>(new ImplT<ArapVolume<T>>(p, e));
+    }
     case OPT_E_ARAP_MESH: {
       ArapMesh<T> e;
       e.n = p->sh.n;
@@ -704,18 +861,29 @@ std::unique_ptr<Impl> make_impl(opt_problem* p) {
   return make_impl_t<float>(p);
 }
 
-// Graph domain: turn the edge list into a per-vertex incidence list (CSR) in the
-// workspace.  A stable counting sort on the host: vertex v lists, in edge-list
-// order, the other end of every edge that touches it, so the order of every
-// per-vertex sum is fixed.  Synchronises the stream.
-int build_incidence(opt_problem* p) {
-  const int V = p->sh.n, E = p->sh.n_edges;
-  std::vector<int> edges((size_t)2 * E), rp((size_t)V + 1, 0), nb((size_t)2 * E);
-  if (E > 0) {
-    HIP_TRY(hipMemcpyAsync(edges.data(), p->desc.edges, sizeof(int) * 2 * (size_t)E,
-                           hipMemcpyDeviceToHost, p->stream));
-    HIP_TRY(hipStreamSynchronize(p->stream));
-  }
+}  // namespace
+
+// Graph domain: the per-vertex incidence list (CSR) and the staging lists, as
+// one host array of incidence_words() ints: [row offsets (V+1) | neighbour ids
+// (2E)] (the workspace's csr region) then [chunk-local slots (2E) | halo counts
+// (chunks) | halo ids (chunks x cap)] (its halo region).
+size_t incidence_words(const Shape& sh) {
+  const size_t V = (size_t)sh.n, E = (size_t)sh.n_edges, nch = (V + kBlock - 1) / kBlock;
+  return (V + 1) + 2 * E + 2 * E + nch + nch * (size_t)halo_cap(sh.tsize, sh.stage_w);
+}
+
+// Build them from the edge list (host, [E][2]).  A stable counting sort: vertex
+// v lists, in edge-list order, the other end of every edge that touches it, so
+// the order of every per-vertex sum is fixed.
+int build_incidence_host(const Shape& sh, const int* edges, int* out) {
+  const int V = sh.n, E = sh.n_edges;
+  int* rp = out;
+  int* nb = rp + V + 1;
+  int* nbl = nb + 2 * (size_t)E;
+  const int nch = (V + kBlock - 1) / kBlock, cap = halo_cap(sh.tsize, sh.stage_w);
+  int* hcnt = nbl + 2 * (size_t)E;
+  int* hid = hcnt + nch;
+  std::fill(rp, rp + V + 1, 0);
   for (int e = 0; e < E; ++e) {
     const int a = edges[2 * (size_t)e], b = edges[2 * (size_t)e + 1];
     if (a < 0 || a >= V || b < 0 || b >= V)
@@ -724,7 +892,7 @@ int build_incidence(opt_problem* p) {
     rp[(size_t)b + 1]++;
   }
   for (int v = 0; v < V; ++v) rp[(size_t)v + 1] += rp[v];
-  std::vector<int> pos(rp.begin(), rp.end() - 1);
+  std::vector<int> pos(rp, rp + V);
   for (int e = 0; e < E; ++e) {
     const int a = edges[2 * (size_t)e], b = edges[2 * (size_t)e + 1];
     nb[(size_t)pos[a]++] = b;
@@ -735,9 +903,9 @@ int build_incidence(opt_problem* p) {
   // its LDS slot: u - chunk start inside the chunk, kBlock + halo index for a
   // staged outside one, -(u + 1) for one past the cap (read from global memory).
   // An energy that is not staged gets cap 0 and every outside slot negative.
-  const int nch = (V + kBlock - 1) / kBlock, cap = halo_cap(p->sh.tsize, p->sh.stage_w);
-  std::vector<int> nbl(nb.size()), hcnt((size_t)nch, 0), hid((size_t)nch * cap, 0), seen((size_t)V, -1),
-      slot((size_t)V, -1);
+  std::fill(hcnt, hcnt + nch, 0);
+  std::fill(hid, hid + (size_t)nch * cap, 0);
+  std::vector<int> seen((size_t)V, -1), slot((size_t)V, -1);
   for (int c = 0; c < nch; ++c) {
     int nh = 0;
     for (int v = c * kBlock; v < std::min(V, (c + 1) * kBlock); ++v)
@@ -756,27 +924,38 @@ int build_incidence(opt_problem* p) {
       }
     hcnt[c] = nh;
   }
-  int* dst = (int*)p->at(p->L.csr);
-  HIP_TRY(hipMemcpyAsync(dst, rp.data(), sizeof(int) * rp.size(), hipMemcpyHostToDevice, p->stream));
-  int* hl = (int*)p->at(p->L.halo);
-  HIP_TRY(hipMemcpyAsync(hl + nbl.size(), hcnt.data(), sizeof(int) * hcnt.size(), hipMemcpyHostToDevice,
+  return OPT_OK;
+}
+
+// Enqueue the copies of the incidence arrays into the workspace on the
+// problem's stream (`words` must stay valid until they have run).
+int upload_incidence(opt_problem* p, const int* words) {
+  const size_t V = (size_t)p->sh.n, E = (size_t)p->sh.n_edges;
+  const size_t csr = V + 1 + 2 * E, total = incidence_words(p->sh);
+  HIP_TRY(hipMemcpyAsync(p->at(p->L.csr), words, sizeof(int) * csr, hipMemcpyHostToDevice, p->stream));
+  HIP_TRY(hipMemcpyAsync(p->at(p->L.halo), words + csr, sizeof(int) * (total - csr), hipMemcpyHostToDevice,
                          p->stream));
+  return OPT_OK;
+}
+
+// Copy the edge list to the host (on the problem's stream, behind the work
+// already there), build the lists and upload them; synchronises the stream.
+int build_incidence(opt_problem* p) {
+  const int E = p->sh.n_edges;
+  std::vector<int> edges((size_t)2 * E), words(incidence_words(p->sh));
   if (E > 0) {
-    HIP_TRY(hipMemcpyAsync(dst + V + 1, nb.data(), sizeof(int) * nb.size(), hipMemcpyHostToDevice,
+    HIP_TRY(hipMemcpyAsync(edges.data(), p->desc.edges, sizeof(int) * 2 * (size_t)E, hipMemcpyDeviceToHost,
                            p->stream));
-    HIP_TRY(hipMemcpyAsync(hl, nbl.data(), sizeof(int) * nbl.size(), hipMemcpyHostToDevice, p->stream));
+    HIP_TRY(hipStreamSynchronize(p->stream));
   }
-  if (!hid.empty())
-    HIP_TRY(hipMemcpyAsync(hl + nbl.size() + hcnt.size(), hid.data(), sizeof(int) * hid.size(),
-                           hipMemcpyHostToDevice, p->stream));
+  TRY(build_incidence_host(p->sh, edges.data(), words.data()));
+  TRY(upload_incidence(p, words.data()));
   HIP_TRY(hipStreamSynchronize(p->stream));
   return OPT_OK;
 }
 
-}  // namespace
-
 int problem_init(opt_problem* p, const opt_problem_desc* desc, const Shape& sh, void* workspace,
-                 hipStream_t stream) {
+                 hipStream_t stream, bool defer_graph) {
   p->desc = *desc;
   p->sh = sh;
   p->L = make_layout(sh);
@@ -790,7 +969,7 @@ int problem_init(opt_problem* p, const opt_problem_desc* desc, const Shape& sh, 
   p->n_simd = std::max(1, cus) * 4;  // four SIMDs per compute unit
   p->impl = make_impl(p);
   if (!p->impl) return fail(OPT_EUNSUPPORTED, "energy %d is not built", desc->energy);
-  if (sh.graph) TRY(build_incidence(p));
+  if (sh.graph && !defer_graph) TRY(build_incidence(p));
   TRY(launch_row(p, ROW_SETUP, setup_args(p->S(), 0.0, 1.0, 0, 0.0), 1, 0, "setup"));
   return OPT_OK;
 }
@@ -817,8 +996,10 @@ int check_params(const opt_solve_params* sp) {
     if (!(sp->lm_radius0 > 0) || !(sp->lm_radius_max > 0) || !(sp->lm_radius_min >= 0))
       return fail(OPT_EINVAL, "LM radii must be positive");
   }
-  if (sp->pcg_variant != OPT_PCG_FUSED && sp->pcg_variant != OPT_PCG_SPLIT)
-    return fail(OPT_EINVAL, "pcg_variant %d is not OPT_PCG_FUSED or OPT_PCG_SPLIT", sp->pcg_variant);
+  if (sp->pcg_variant != OPT_PCG_FUSED && sp->pcg_variant != OPT_PCG_SPLIT &&
+      sp->pcg_variant != OPT_PCG_MATERIALIZED)
+    return fail(OPT_EINVAL, "pcg_variant %d is not OPT_PCG_FUSED, OPT_PCG_SPLIT or OPT_PCG_MATERIALIZED",
+                sp->pcg_variant);
   if (!(sp->lm_diag_min >= 0) || !(sp->lm_diag_max >= sp->lm_diag_min))
     return fail(OPT_EINVAL, "LM diagonal clamp [%g, %g] is invalid", sp->lm_diag_min,
                 sp->lm_diag_max);
@@ -854,6 +1035,16 @@ int uses_fused(opt_problem* p, int variant) {
 }
 
 int run_pcg(opt_problem* p, PrecondArgs pa, int lm, int L, int variant) {
+  if (variant == OPT_PCG_MATERIALIZED) {
+    if (!p->sh.mat) return fail(OPT_EINVAL, "OPT_PCG_MATERIALIZED needs a problem created with materialize = 1");
+    TRY(p->impl->eval_j());
+    for (int k = 0; k < L; ++k) {
+      TRY(p->impl->mat_a(k, L, pa, lm));
+      TRY(p->impl->mat_b(k, L, pa, lm));
+      TRY(p->impl->pcg_b(k, L, pa, lm));
+    }
+    return OPT_OK;
+  }
   if (uses_fused(p, variant)) {
     if (L > 0) TRY(p->impl->fused(-1, L, pa, lm));
     for (int i = 0; i < L; ++i) TRY(p->impl->fused(i, L, pa, lm));
@@ -1015,6 +1206,11 @@ int scratch_of_current_device(void** out) {
   return OPT_OK;
 }
 }  // namespace
+
+int solve(opt_problem* p, void* x, const opt_solve_params* sp, opt_solve_report* rep) {
+  return solve_problem(p, x, sp, rep);
+}
+
 }  // namespace host
 }  // namespace optmi
 

@@ -10,9 +10,9 @@
 //
 // Scheduling.  Requests are admitted (workspace carved from the arena) when a
 // slot and a range are free, and started in admission order while the running
-// set's estimated GPU fill stays within a budget: a request that fills the GPU
-// by itself runs alone, as in a plain first-in first-out solver, and small
-// requests share steps.  Steps are pipelined: a step is enqueued without
+// set's estimated GPU fill (the wavefront slots of each request's widest launch
+// over the device's) stays within a budget.  The requests of one energy kind
+// share each launch; the kinds run on streams of their own, so they overlap.  Steps are pipelined: a step is enqueued without
 // waiting for the GPU (up to kDepth in flight); its scalars and results come back
 // through pinned memory behind an event, and the host harvests completed steps
 // whenever it calls in.
@@ -27,6 +27,7 @@
 #include <map>
 #include <memory>
 #include <new>
+#include <string>
 #include <vector>
 
 #include "opt.h"
@@ -40,6 +41,13 @@ namespace {
 constexpr int kStageKinds = 12;  // table kinds that one step can write
 constexpr int kMaxKinds = 56;    // energy form (7) x precision x method x PCG form
 constexpr int kDepth = 3;        // steps in flight
+constexpr int kLanes = kMaxLanes - 1;  // streams the energy-kind groups of a step run on
+// Default fill budget: the running set may hold about four GPUs' worth of
+// launches.  A launch of a mid-sized problem fills the wavefront slots but is
+// short, so its time is mostly latency that co-running launches hide
+// (saturation throughput of the serving mix measured 157 / 251 / 216 solves/s
+// at budgets 1 / 4 / unlimited).
+constexpr double kDefaultFillBudget = 4.0;
 
 // Arena byte ranges, first fit with coalescing.
 class RangeAlloc {
@@ -102,7 +110,26 @@ struct Slot {
   bool cancelled = false;
   double fill = 1.0;      // estimated share of the GPU that one of its launches occupies
   int64_t last_step = -1; // last step that enqueued work for it
+  // A graph request's edge list is copied to pinned memory behind the work on
+  // the server's stream; its incidence lists are built on the host by the first
+  // step after that copy has completed, and the request starts from then on.
+  bool graph_pending = false;
+  hipEvent_t ev_edges = nullptr;
+  int* edges_pin = nullptr;  // 2E ints; freed once the lists are built
+  int* inc_pin = nullptr;    // incidence_words ints; their upload reads them, so kept until release
 };
+
+// Free a slot's graph staging (waiting for the edge copy if it may still run).
+void free_graph_staging(Slot& s) {
+  if (s.ev_edges) {
+    (void)hipEventSynchronize(s.ev_edges);
+    (void)hipEventDestroy(s.ev_edges);
+    s.ev_edges = nullptr;
+  }
+  if (s.edges_pin) (void)hipHostFree(s.edges_pin);
+  if (s.inc_pin) (void)hipHostFree(s.inc_pin);
+  s.edges_pin = s.inc_pin = nullptr;
+}
 
 // Pinned per-slot landing area for a finished request.
 struct ResultArea {
@@ -120,6 +147,8 @@ struct Result {
   opt_solve_report rep{};
   std::vector<double> trace;
   bool nonfinite = false;
+  int code = OPT_OK;  // a request dropped before it ran (its edge list was invalid)
+  std::string msg;
 };
 
 struct StepRec {
@@ -148,13 +177,20 @@ struct opt_server {
   size_t arena_bytes = 0;
   int max_slots = 0;
   hipStream_t stream = nullptr;
-  double fill_budget = 1.0;
+  double fill_budget = kDefaultFillBudget;
   Batcher B;
   char* staging[kDepth] = {};           // pinned argument tables, one per step in flight
   DevScalars* dev_gather = nullptr;     // device, one row per slot
   DevScalars* host_gather[kDepth] = {}; // pinned, one per step in flight
   ResultArea* res = nullptr;            // pinned, one per slot
   StepRec steps[kDepth];
+  // Each group of requests that share launches (one energy kind) runs on a lane
+  // stream of its own, so that the groups of a step overlap on the device.  A
+  // step forks the lanes from the server's stream after its table copy and joins
+  // them back before its read-backs.
+  hipStream_t lanes[kLanes] = {};
+  hipEvent_t ev_fork[kDepth] = {};
+  hipEvent_t ev_join[kDepth][kLanes] = {};
   int64_t n_steps = 0, n_done = 0;      // steps enqueued, steps completed and harvested
   RangeAlloc ranges;
   std::vector<Slot> slots;
@@ -164,11 +200,17 @@ struct opt_server {
 
   ~opt_server() {
     if (n_steps > n_done) (void)hipStreamSynchronize(stream);
+    for (Slot& s : slots) free_graph_staging(s);
     for (int k = 0; k < kDepth; ++k) {
       if (staging[k]) (void)hipHostFree(staging[k]);
       if (host_gather[k]) (void)hipHostFree(host_gather[k]);
       if (steps[k].ev) (void)hipEventDestroy(steps[k].ev);
+      if (ev_fork[k]) (void)hipEventDestroy(ev_fork[k]);
+      for (hipEvent_t e : ev_join[k])
+        if (e) (void)hipEventDestroy(e);
     }
+    for (hipStream_t l : lanes)
+      if (l) (void)hipStreamDestroy(l);
     if (res) (void)hipHostFree(res);
   }
 };
@@ -217,8 +259,38 @@ int record_scalar(opt_server* sv, const std::vector<int>& ids, F make, const cha
 }
 
 void release_slot(opt_server* sv, Slot& s) {
+  free_graph_staging(s);
   sv->ranges.release(s.ws_off, s.ws_bytes);
   s = Slot();
+}
+
+// Graph requests whose edge list has arrived: build their incidence lists and
+// enqueue the upload (before this step's launches).  A request whose edges are
+// invalid is dropped and reported by poll.
+int finish_graph_admissions(opt_server* sv) {
+  for (size_t i = 0; i < sv->slots.size(); ++i) {
+    Slot& s = sv->slots[i];
+    if (s.state != SlotState::NEW || !s.graph_pending) continue;
+    const hipError_t q = hipEventQuery(s.ev_edges);
+    if (q == hipErrorNotReady) continue;
+    if (q != hipSuccess) return fail(OPT_EHIP, "hipEventQuery failed: %s", hipGetErrorString(q));
+    const int rc = build_incidence_host(s.p->sh, s.edges_pin, s.inc_pin);
+    if (rc != OPT_OK) {
+      Result r;
+      r.code = rc;
+      r.msg = last_error();
+      sv->results[s.ticket] = std::move(r);
+      release_slot(sv, s);
+      continue;
+    }
+    TRY(upload_incidence(s.p.get(), s.inc_pin));
+    (void)hipEventDestroy(s.ev_edges);
+    s.ev_edges = nullptr;
+    (void)hipHostFree(s.edges_pin);
+    s.edges_pin = nullptr;
+    s.graph_pending = false;
+  }
+  return OPT_OK;
 }
 
 // The report of a finished request, as opt_solve fills it.
@@ -305,7 +377,10 @@ int opt_server_create(void* arena, size_t arena_bytes, int32_t max_slots, void* 
     HIP_TRY(hipHostMalloc((void**)&sv->staging[k], tb, hipHostMallocDefault));
     HIP_TRY(hipHostMalloc((void**)&sv->host_gather[k], gb, hipHostMallocDefault));
     HIP_TRY(hipEventCreateWithFlags(&sv->steps[k].ev, hipEventDisableTiming));
+    HIP_TRY(hipEventCreateWithFlags(&sv->ev_fork[k], hipEventDisableTiming));
+    for (int l = 0; l < kLanes; ++l) HIP_TRY(hipEventCreateWithFlags(&sv->ev_join[k][l], hipEventDisableTiming));
   }
+  for (int l = 0; l < kLanes; ++l) HIP_TRY(hipStreamCreateWithFlags(&sv->lanes[l], hipStreamNonBlocking));
   HIP_TRY(hipHostMalloc((void**)&sv->res, sizeof(ResultArea) * (size_t)max_slots, hipHostMallocDefault));
   sv->B.dev = sv->arena;
   sv->B.cap = tb;
@@ -353,10 +428,33 @@ int opt_server_submit(opt_server* sv, const opt_problem_desc* desc, void* unknow
     sv->ranges.release(off, need);
     return fail(OPT_ENOMEM, "host allocation failed");
   }
-  const int rc = problem_init(p.get(), desc, sh, sv->arena + off, sv->stream);
+  const int rc = problem_init(p.get(), desc, sh, sv->arena + off, sv->stream, /*defer_graph=*/true);
   if (rc != OPT_OK) {
     sv->ranges.release(off, need);
     return rc;
+  }
+  int* edges_pin = nullptr;
+  int* inc_pin = nullptr;
+  hipEvent_t ev_edges = nullptr;
+  if (sh.graph) {
+    // the edge list comes back behind the work already on the server's stream,
+    // without waiting for it
+    const size_t ne = std::max<size_t>(1, 2 * (size_t)sh.n_edges);
+    hipError_t e = hipHostMalloc((void**)&edges_pin, sizeof(int) * ne, hipHostMallocDefault);
+    if (e == hipSuccess) e = hipHostMalloc((void**)&inc_pin, sizeof(int) * incidence_words(sh), hipHostMallocDefault);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&ev_edges, hipEventDisableTiming);
+    if (e == hipSuccess && sh.n_edges > 0)
+      e = hipMemcpyAsync(edges_pin, desc->edges, sizeof(int) * 2 * (size_t)sh.n_edges, hipMemcpyDeviceToHost,
+                         sv->stream);
+    if (e == hipSuccess) e = hipEventRecord(ev_edges, sv->stream);
+    if (e != hipSuccess) {
+      if (ev_edges) (void)hipEventSynchronize(ev_edges), (void)hipEventDestroy(ev_edges);
+      (void)hipStreamSynchronize(sv->stream);
+      if (edges_pin) (void)hipHostFree(edges_pin);
+      if (inc_pin) (void)hipHostFree(inc_pin);
+      sv->ranges.release(off, need);
+      return fail(OPT_EHIP, "staging the edge list failed: %s", hipGetErrorString(e));
+    }
   }
   for (auto it = sv->tuning.rbegin(); it != sv->tuning.rend(); ++it)
     if (it->energy == desc->energy && it->precision == desc->precision && sh.n >= it->min_sites &&
@@ -375,6 +473,10 @@ int opt_server_submit(opt_server* sv, const opt_problem_desc* desc, void* unknow
   s.fused = sp->pcg_variant == OPT_PCG_FUSED && p->impl->has_fused() && !p->impl->fused_is_big();
   s.fill = p->impl->gpu_fill(s.fused, sp->method == OPT_LM);
   s.p = std::move(p);
+  s.graph_pending = sh.graph;
+  s.ev_edges = ev_edges;
+  s.edges_pin = edges_pin;
+  s.inc_pin = inc_pin;
   *ticket = s.ticket;
   return OPT_OK;
 }
@@ -383,8 +485,10 @@ int opt_server_step(opt_server* sv) {
   if (!sv) return fail(OPT_EINVAL, "server is NULL");
   TRY(harvest(sv, false));
   if (sv->n_steps - sv->n_done >= kDepth) TRY(harvest(sv, true));
+  TRY(finish_graph_admissions(sv));
   // start admitted requests in admission order while the running set's fill
-  // stays within the budget (at least one request always runs)
+  // stays within the budget (at least one request always runs); a graph
+  // request whose lists are not built yet waits without holding up the rest
   double running = 0.0;
   for (const Slot& s : sv->slots)
     if (runnable(s)) running += s.fill;
@@ -396,6 +500,7 @@ int opt_server_step(opt_server* sv) {
   std::vector<int> fresh;
   for (int i : order) {
     Slot& s = sv->slots[(size_t)i];
+    if (s.graph_pending) continue;
     if (running > 0.0 && running + s.fill > sv->fill_budget) break;
     s.state = SlotState::RUN;
     running += s.fill;
@@ -418,38 +523,86 @@ int opt_server_step(opt_server* sv) {
     if (after >= s.sp.outer_iters || s.lm_done) fin.push_back(i);
   }
   if (fresh.empty() && run.empty() && fin.empty()) {
-    // nothing to enqueue: wait for the oldest step in flight, if any
-    if (sv->n_steps > sv->n_done) TRY(harvest(sv, true));
+    // nothing to enqueue: wait for the oldest step in flight, if any, or for a
+    // pending edge list
+    if (sv->n_steps > sv->n_done) {
+      TRY(harvest(sv, true));
+    } else {
+      for (Slot& s : sv->slots)
+        if (s.state == SlotState::NEW && s.graph_pending) {
+          HIP_TRY(hipEventSynchronize(s.ev_edges));
+          break;
+        }
+    }
     return OPT_OK;
   }
 
   const int ring = (int)(sv->n_steps % kDepth);
   sv->B.reset();
   sv->B.host = sv->staging[ring];
+  // lane 0: the server's stream, before the fork (setup of the requests that start)
+  sv->B.lane = 0;
+  sv->B.stream = sv->stream;
   TRY(record_scalar<SetupArgs>(sv, fresh, [](Slot& s, int) {
     return setup_args(s.p->S(), 0.0, s.sp.lm_radius0, s.sp.method == OPT_LM ? 1 : 0, s.sp.lm_radius_min);
   }, "setup[batch]"));
-  // one outer iteration (Sec. 4) for every running request
-  TRY(record_stage(sv, Stage::LIN, run));
-  TRY(record_stage(sv, Stage::INIT, run));
-  TRY(record_stage(sv, Stage::PCG, run));
-  TRY(record_stage(sv, Stage::MODEL, lm_run));
-  TRY(record_stage(sv, Stage::TRIAL_COST, lm_run));
-  TRY(record_scalar<DecideArgs>(sv, lm_run, [](Slot& s, int) {
-    return decide_args(s.p->S(), s.p->part(P_M), s.p->part(P_COST), s.p->nblk, s.sp);
-  }, "decide[batch]"));
-  TRY(record_stage(sv, Stage::STEP, run));
-  TRY(record_stage(sv, Stage::COST, fin));
-  TRY(record_scalar<FinishArgs>(sv, fin, [](Slot& s, int) {
-    return finish_args(s.p->S(), s.p->part(P_COST), s.p->nblk);
-  }, "finish[batch]"));
+  // one outer iteration (Sec. 4) for every running request, and the final cost
+  // of those that finish: each group of requests sharing launches on a lane
+  struct Group {
+    std::vector<int> run, lm, fin;
+  };
+  std::map<int, Group> groups;
+  for (int i : run) groups[key_of(sv->slots[(size_t)i])].run.push_back(i);
+  for (int i : lm_run) groups[key_of(sv->slots[(size_t)i])].lm.push_back(i);
+  for (int i : fin) groups[key_of(sv->slots[(size_t)i])].fin.push_back(i);
   DevScalars* dg = sv->dev_gather;
-  TRY(record_scalar<GatherArgs>(sv, lm_run, [dg](Slot& s, int i) {
-    return GatherArgs{s.p->S(), dg + i};
-  }, "gather[batch]"));
-  // enqueue: tables, launches, read-backs, event; no wait
+  int gi = 0;
+  for (auto& kv : groups) {
+    const Group& g = kv.second;
+    const int lane = gi++ % kLanes;
+    sv->B.lane = 1 + lane;
+    sv->B.stream = sv->lanes[lane];
+    TRY(record_stage(sv, Stage::LIN, g.run));
+    TRY(record_stage(sv, Stage::INIT, g.run));
+    TRY(record_stage(sv, Stage::PCG, g.run));
+    TRY(record_stage(sv, Stage::MODEL, g.lm));
+    TRY(record_stage(sv, Stage::TRIAL_COST, g.lm));
+    TRY(record_scalar<DecideArgs>(sv, g.lm, [](Slot& s, int) {
+      return decide_args(s.p->S(), s.p->part(P_M), s.p->part(P_COST), s.p->nblk, s.sp);
+    }, "decide[batch]"));
+    TRY(record_stage(sv, Stage::STEP, g.run));
+    TRY(record_stage(sv, Stage::COST, g.fin));
+    TRY(record_scalar<FinishArgs>(sv, g.fin, [](Slot& s, int) {
+      return finish_args(s.p->S(), s.p->part(P_COST), s.p->nblk);
+    }, "finish[batch]"));
+    TRY(record_scalar<GatherArgs>(sv, g.lm, [dg](Slot& s, int i) {
+      return GatherArgs{s.p->S(), dg + i};
+    }, "gather[batch]"));
+  }
+  // enqueue: tables, setup, fork, the lanes' launches round robin, join,
+  // read-backs, event; no wait
   if (sv->B.used) HIP_TRY(hipMemcpyAsync(sv->B.dev, sv->B.host, sv->B.used, hipMemcpyHostToDevice, sv->stream));
-  for (auto& f : sv->B.launches) TRY(f());
+  for (auto& f : sv->B.q[0]) TRY(f());
+  const int n_lanes = std::min(kLanes, gi);
+  if (n_lanes > 0) {
+    HIP_TRY(hipEventRecord(sv->ev_fork[ring], sv->stream));
+    for (int l = 0; l < n_lanes; ++l) HIP_TRY(hipStreamWaitEvent(sv->lanes[l], sv->ev_fork[ring], 0));
+    size_t next[kMaxLanes] = {};
+    for (bool more = true; more;) {
+      more = false;
+      for (int l = 1; l <= n_lanes; ++l) {
+        std::vector<std::function<int()>>& q = sv->B.q[l];
+        if (next[l] < q.size()) {
+          TRY(q[next[l]++]());
+          more = more || next[l] < q.size();
+        }
+      }
+    }
+    for (int l = 0; l < n_lanes; ++l) {
+      HIP_TRY(hipEventRecord(sv->ev_join[ring][l], sv->lanes[l]));
+      HIP_TRY(hipStreamWaitEvent(sv->stream, sv->ev_join[ring][l], 0));
+    }
+  }
   if (!lm_run.empty())
     HIP_TRY(hipMemcpyAsync(sv->host_gather[ring], sv->dev_gather, sizeof(DevScalars) * (size_t)sv->max_slots,
                            hipMemcpyDeviceToHost, sv->stream));
@@ -488,6 +641,12 @@ int opt_server_poll(opt_server* sv, int64_t ticket, int32_t* done, opt_solve_rep
   }
   *done = 1;
   const Result& r = it->second;
+  if (r.code != OPT_OK) {
+    const int code = r.code;
+    const std::string msg = r.msg;
+    sv->results.erase(it);
+    return fail(code, "request dropped: %s", msg.c_str());
+  }
   const bool nonfinite = r.nonfinite;
   if (report) {
     double* dst = report->cost_trace;

@@ -51,7 +51,7 @@ def _desc(energy="arap_warp", W=64, H=48, precision="mixed", n_params=None, arra
     for k in range(arrays):
         d.arrays[k] = 0x1000 * (k + 1)  # never dereferenced by these calls
     d.n_params = {"arap_warp": 2, "poisson": 0, "flow": 2, "sfs": 16, "arap_mesh": 2,
-                  "laplacian": 0}[energy] if n_params is None else n_params
+                  "laplacian": 2, "arap_volume": 2}[energy] if n_params is None else n_params
     if V and E:
         d.edges = 0x9000
     return d
@@ -84,6 +84,15 @@ def test_workspace_size_valid_and_monotone(lib):
     assert _ws(lib, _desc(W=1024, H=1024))[1] >= 9 * 3 * 1024 * 1024 * 4
     rc, b = _ws(lib, _desc("arap_mesh", V=1000, E=3000, arrays=2))
     assert rc == pkg.OPT_OK and b >= 9 * 6 * 1000 * 4 + 4 * (1001 + 6000)
+    # a 3D grid: six unknowns per voxel
+    d = _desc("arap_volume", W=10, H=9, arrays=2, domain=pkg.GRID3D)
+    d.depth = 8
+    rc, b = _ws(lib, d)
+    assert rc == pkg.OPT_OK and b >= 9 * 6 * 720 * 4
+    # the Laplacian: one unknown per pixel on a grid, three per vertex on a graph
+    rc1, b1 = _ws(lib, _desc("laplacian", W=100, H=100, arrays=1))
+    rc3, b3 = _ws(lib, _desc("laplacian", V=10000, E=0, arrays=1))
+    assert rc1 == rc3 == pkg.OPT_OK and b3 > b1 >= 9 * 10000 * 4
 
 
 @pytest.mark.parametrize("bad,code", [
@@ -92,7 +101,10 @@ def test_workspace_size_valid_and_monotone(lib):
     (dict(arrays=2), pkg.OPT_EINVAL),
     (dict(n_params=1), pkg.OPT_EINVAL),
     (dict(n_params=17), pkg.OPT_EINVAL),
-    (dict(energy="laplacian", arrays=0), pkg.OPT_EUNSUPPORTED),
+    (dict(energy="laplacian", arrays=0), pkg.OPT_EINVAL),           # its data array is missing
+    (dict(energy="arap_volume", arrays=2), pkg.OPT_EUNSUPPORTED),    # 3D energy on a 2D grid
+    (dict(energy="arap_warp", arrays=3, domain=pkg.GRID3D), pkg.OPT_EUNSUPPORTED),  # 2D energy on a 3D grid
+    (dict(energy="arap_volume", arrays=2, domain=pkg.GRID3D), pkg.OPT_EINVAL),  # depth 0
     (dict(energy="arap_mesh", arrays=2), pkg.OPT_EUNSUPPORTED),      # graph energy on a grid
     (dict(energy="poisson", arrays=2, domain=pkg.GRAPH, V=10, E=0), pkg.OPT_EUNSUPPORTED),  # grid-only energy on a graph
     (dict(domain=7), pkg.OPT_EINVAL),

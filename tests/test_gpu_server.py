@@ -221,3 +221,74 @@ def test_lm_radius_below_minimum_does_nothing():
     out = _run_until_done(sv, [t])
     assert torch.equal(x, xa)
     _same(out[t], repa)
+
+
+def test_graph_submit_does_not_wait_for_steps_in_flight():
+    """Admitting a mesh copies its edge list behind the work on the server's
+    stream and builds its lists at a later step: submit returns without waiting
+    for the steps already enqueued (here about three outer iterations of a
+    4096^2 warp, tens of milliseconds of GPU work)."""
+    import time
+    big = _request(w.arap_warp(4096, 4096, seed=9, n_constraints=2000, margin=8), "mixed",
+                   method="gn", outer_iters=3, pcg_iters=50)
+    mesh = _request(w.arap_mesh(4, seed=3, handle_frac=0.05, sigma=0.1), "mixed", method="lm",
+                    outer_iters=3, pcg_iters=10)
+    xa, repa = _alone(mesh)
+    sv = pkg.Server(3 << 30, max_slots=4)
+    tb, _ = _submit(sv, big)
+    for _ in range(3):
+        sv.step()
+    torch.cuda.synchronize()  # (nothing else of ours is queued; the server's steps run on its stream)
+    tb2, _ = _submit(sv, big)
+    for _ in range(3):
+        sv.step()  # three steps of the second warp in flight
+    t0 = time.perf_counter()
+    tm, xm = _submit(sv, mesh)
+    dt = time.perf_counter() - t0
+    out = _run_until_done(sv, [tb, tb2, tm], max_steps=50)
+    assert torch.equal(xm, xa)
+    _same(out[tm], repa)
+    assert dt < 0.02, f"submit took {dt * 1e3:.1f} ms"
+
+
+def test_invalid_edge_list_is_dropped_at_a_later_step():
+    d = w.arap_mesh(2, seed=3)
+    d["edges"] = d["edges"].copy()
+    d["edges"][7, 0] = d["V"] + 5
+    r = _request(d, "mixed", method="lm", outer_iters=2, pcg_iters=5)
+    ok = _request(w.arap_warp(40, 30, seed=2, n_constraints=10, margin=2), "mixed", method="gn",
+                  outer_iters=2, pcg_iters=5)
+    xa, repa = _alone(ok)
+    sv = pkg.Server(64 << 20, max_slots=4)
+    tbad, _ = _submit(sv, r)
+    tok, xok = _submit(sv, ok)
+    assert tbad is not None
+    for _ in range(10):
+        sv.step()
+    with pytest.raises(pkg.OptError) as ei:
+        sv.poll(tbad)
+    assert ei.value.code == pkg.OPT_EINVAL and "outside" in str(ei.value)
+    out = _run_until_done(sv, [tok])
+    assert torch.equal(xok, xa)
+    _same(out[tok], repa)
+
+
+def test_nonfinite_request_is_isolated():
+    """A request whose data holds a NaN reports OPT_ENUMERIC; the requests
+    batched with it (same energy kind, same launches) give the bits they give
+    alone."""
+    good = [_request(w.arap_warp(64, 48, seed=s, n_constraints=20, margin=2), "mixed", method="gn",
+                     outer_iters=3, pcg_iters=10) for s in (11, 12)]
+    d = w.arap_warp(64, 48, seed=13, n_constraints=20, margin=2)
+    d["U"] = d["U"].copy()
+    d["U"][0, 20, 30] = np.nan  # one rest position: its regularisers are NaN
+    bad = _request(d, "mixed", method="gn", outer_iters=3, pcg_iters=10)
+    alone = [_alone(r) for r in good]
+    sv = pkg.Server(128 << 20, max_slots=4)
+    subs = [_submit(sv, good[0]), _submit(sv, bad), _submit(sv, good[1])]
+    tickets = [t for t, _ in subs]
+    out = _run_until_done(sv, list(tickets))
+    assert out[tickets[1]]["code"] == pkg.OPT_ENUMERIC
+    for (t, x), (xa, repa) in zip([subs[0], subs[2]], alone):
+        assert torch.equal(x, xa)
+        _same(out[t], repa)

@@ -1,7 +1,7 @@
 """Seeded synthetic inputs for the GN/LM PCG path.
 
 This package only draws inputs: lattices, constraint sets, masks, smooth random
-fields, noise textures, icosphere meshes, and the rendered shading image of a
+fields, noise textures, icosphere meshes, voxel blocks, and the rendered shading image of a
 smooth surface (``render``: the exact normal of the continuous surface under the
 scene's lighting).  It holds none of the solver's arithmetic (no residual,
 Jacobian, difference normal or step), so the oracle and the HIP path can both be
@@ -14,7 +14,8 @@ arrays.
 from .grids import (arap_warp, poisson_edit, shape_from_shading, optical_flow,
                     laplacian_grid, SFS_LIGHTING)
 from .mesh import icosphere, morton_order, arap_mesh, laplacian_mesh, grid_edges
+from .volume import arap_volume, lattice_edges
 
 __all__ = ["arap_warp", "poisson_edit", "shape_from_shading", "optical_flow",
            "laplacian_grid", "SFS_LIGHTING", "icosphere", "morton_order",
-           "arap_mesh", "laplacian_mesh", "grid_edges"]
+           "arap_mesh", "laplacian_mesh", "grid_edges", "arap_volume", "lattice_edges"]

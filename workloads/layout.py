@@ -8,13 +8,18 @@ ARRAY_ORDER = {
     "sfs": ["D", "Im", "edge_r", "edge_c"],
     "flow": ["I", "Ihat", "Ihat_dx", "Ihat_dy"],
     "arap_mesh": ["U", "C"],
+    "arap_volume": ["U", "C"],
+    "laplacian": ["A"],
+    "laplacian_graph": ["A"],
 }
+# the library's name of each workload energy
+LIB_ENERGY = {"laplacian_graph": "laplacian"}
 
 
 def param_list(d):
     p = d["params"]
     e = d["energy"]
-    if e in ("arap_warp", "arap_mesh", "flow"):
+    if e in ("arap_warp", "arap_mesh", "arap_volume", "flow", "laplacian", "laplacian_graph"):
         return [p["w_fit"], p["w_reg"]]
     if e == "poisson":
         return []
@@ -25,8 +30,8 @@ def param_list(d):
 
 def problem_args(d, bulk_dtype):
     """(energy, [numpy arrays], [params], dims) with bulk arrays cast to
-    ``bulk_dtype`` and masks left as uint8.  ``dims`` holds width/height for a
-    grid or n_vertices/edges for a graph."""
+    ``bulk_dtype`` and masks left as uint8.  ``dims`` holds width/height (and
+    depth for a 3D grid) for a grid or n_vertices/edges for a graph."""
     e = d["energy"]
     arrs = []
     for k in ARRAY_ORDER[e]:
@@ -34,6 +39,8 @@ def problem_args(d, bulk_dtype):
         arrs.append(np.ascontiguousarray(a if a.dtype == np.uint8 else a.astype(bulk_dtype)))
     if "V" in d:
         dims = dict(n_vertices=int(d["V"]), edges=np.ascontiguousarray(d["edges"], dtype=np.int32))
+    elif e == "arap_volume":
+        dims = dict(width=int(d["W"]), height=int(d["H"]), depth=int(d["D"]))
     else:
         dims = dict(width=int(d["W"]), height=int(d["H"]))
-    return e, arrs, param_list(d), dims
+    return LIB_ENERGY.get(e, e), arrs, param_list(d), dims
