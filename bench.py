@@ -440,7 +440,7 @@ def pcg_form(energy, channels, n, prec, graph=False):
     its vectors and state under 256 MB; the radius-1 kernel has an
     instantiation for larger grids (buffers based at each strip's first row)."""
     tsize = 8 if prec == "fp64" else 4
-    if graph or energy not in ("arap_warp", "poisson", "flow", "sfs"):
+    if graph or energy not in ("arap_warp", "poisson", "flow", "sfs", "laplacian"):
         return "split"
     if energy == "sfs" and 4 * n * tsize > (1 << 28):
         return "split"
