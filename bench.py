@@ -434,19 +434,6 @@ def _as_graph(d):
     return dict(d, V=d["W"] * d["H"], edges=grid_edges(d["W"], d["H"]))
 
 
-def pcg_form(energy, channels, n, prec, graph=False):
-    """Which PCG form the library runs by default: a fused kernel for grid
-    energies, the split form for graphs.  The shape-from-shading kernel needs
-    its vectors and state under 256 MB; the radius-1 kernel has an
-    instantiation for larger grids (buffers based at each strip's first row)."""
-    tsize = 8 if prec == "fp64" else 4
-    if graph or energy not in ("arap_warp", "poisson", "flow", "sfs", "laplacian"):
-        return "split"
-    if energy == "sfs" and 4 * n * tsize > (1 << 28):
-        return "split"
-    return "fused"
-
-
 def configs_main(args):
     """One JSON line per configuration: PCG iterations/s over the PCG phases,
     the per-iteration time against the algorithmic bytes, and the whole-solve
@@ -499,7 +486,7 @@ def configs_main(args):
         rep = prob.solve(x.copy_(x0), params=sp)
         print(json.dumps({"config": name, "sites": n, "unknowns": N, "precision": prec, "method": method,
                           "outer_iters": outer, "pcg_iters": inner,
-                          "pcg_form": variant if variant != "fused" else pcg_form(energy, prob.channels, n, prec, "V" in d),
+                          "pcg_form": prob.pcg_form(variant),
                           "pcg_iters_per_s": pcg_iters / (pcg_ms / 1e3), "iter_us": iter_us,
                           "bytes_per_iter": bpi, "achieved_GBs": achieved, "frac_of_8TBs": achieved / HBM_PEAK_GBS,
                           "solve_ms_median": float(np.median(solve_ms)), "cost_initial": rep["cost_initial"],

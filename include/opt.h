@@ -112,9 +112,14 @@ typedef enum { OPT_GN = 0, OPT_LM = 1 } opt_method;
  * OPT_PCG_FUSED: one kernel per iteration, the single-reduction recurrence of
  *   Chronopoulos and Gear (alpha and beta from r.z and (A z).z of the previous
  *   iteration), with A p evaluated exactly; r, p and d each cross HBM once.
- *   Available for the grid energies (ARAP warp, Poisson, flow; shape
- *   from shading with its own residual-streaming kernel); a graph problem
- *   asking for it runs the split form.
+ *   Available for the grid energies (ARAP warp, Poisson, flow, the Laplacian;
+ *   shape from shading with its own residual-streaming kernel) and, on a
+ *   graph, for the ARAP mesh and the Laplacian: there a block stages a chunk
+ *   of 256 vertices with its one- and two-ring neighbourhoods, whose lists are
+ *   built with the incidence list; a graph whose chunks pass the lists' caps
+ *   (one-ring 256, two-ring 320 vertices, 2048 incidence entries of the chunk
+ *   and of its one-ring), and every other graph energy, runs the split form
+ *   (opt_problem_pcg_form tells which).
  * OPT_PCG_SPLIT: the textbook recurrence (alpha = r.z / p.Ap, then beta), two
  *   kernels per iteration.
  * OPT_PCG_MATERIALIZED: the materialised alternative of Sec. 7 (evalJ): J is
@@ -317,6 +322,15 @@ int opt_problem_get_tuning(opt_problem* prob, opt_tuning* tuning);
  * and frees the recorded graph.  Destroying the problem frees it too.
  */
 int opt_problem_set_graph_replay(opt_problem* prob, int enable);
+
+/*
+ * The PCG form a solve of this problem runs when it asks for `variant`
+ * (opt_pcg_variant): *form = OPT_PCG_FUSED where the fused kernel serves it
+ * (the grid energies; on a graph, the ARAP mesh and the Laplacian when every
+ * chunk's lists fit their caps), else OPT_PCG_SPLIT; OPT_PCG_MATERIALIZED
+ * answers itself.  OPT_EINVAL for a NULL argument or an unknown variant.
+ */
+int opt_problem_pcg_form(opt_problem* prob, int variant, int* form);
 
 /*
  * Multi-pass optimisation (Sec. 7: between solves the caller may change the

@@ -85,6 +85,7 @@ _proto = {
     "opt_problem_set_tuning": (ctypes.c_int, [_P, ctypes.POINTER(opt_tuning)]),
     "opt_problem_get_tuning": (ctypes.c_int, [_P, ctypes.POINTER(opt_tuning)]),
     "opt_problem_set_graph_replay": (ctypes.c_int, [_P, ctypes.c_int]),
+    "opt_problem_pcg_form": (ctypes.c_int, [_P, ctypes.c_int, ctypes.POINTER(ctypes.c_int)]),
     "opt_server_reserved_bytes": (ctypes.c_int, [ctypes.c_int32, ctypes.POINTER(ctypes.c_size_t)]),
     "opt_server_create": (ctypes.c_int, [_P, ctypes.c_size_t, ctypes.c_int32, _P, ctypes.POINTER(_P)]),
     "opt_server_destroy": (ctypes.c_int, [_P]),
@@ -370,6 +371,14 @@ class Problem:
     def set_graph_replay(self, on=True):
         """opt_problem_set_graph_replay: replay repeated solves as one HIP graph."""
         _check(lib().opt_problem_set_graph_replay(self.handle, int(on)), "opt_problem_set_graph_replay")
+
+    def pcg_form(self, variant="fused"):
+        """opt_problem_pcg_form: the form ("fused", "split" or "materialized")
+        a solve asking for `variant` runs."""
+        v = {"fused": PCG_FUSED, "split": PCG_SPLIT, "materialized": PCG_MATERIALIZED}[variant.lower()]
+        out = ctypes.c_int(-1)
+        _check(lib().opt_problem_pcg_form(self.handle, v, ctypes.byref(out)), "opt_problem_pcg_form")
+        return {PCG_FUSED: "fused", PCG_SPLIT: "split", PCG_MATERIALIZED: "materialized"}[out.value]
 
     def profile_enable(self, on=True):
         _check(lib().opt_profile_enable(self.handle, int(on)), "opt_profile_enable")

@@ -25,6 +25,25 @@ constexpr int halo_cap(size_t tsize, int width) {
 // ... and up to this many of the chunk's neighbour slots are staged as well.
 constexpr int nbl_cap(size_t tsize) { return tsize > 4 ? 1024 : 1536; }
 
+// The fused graph PCG kernel stages, per chunk C of kBlock vertices, the chunk,
+// its one-ring R1 (outside vertices adjacent to C) and its two-ring R2 (vertices
+// adjacent to R1 outside C and R1), and needs the incidence lists of C and R1 in
+// chunk-local slots: caps on |R1|, |R2|, C's incidence entries and R1's.  A
+// graph with any chunk past a cap runs the split form.  A chunk's row of lists
+// holds kGfRow ints: [|R1|, |R2|, R1 entries, 0], the R1 then R2 vertex ids
+// (kGfR1 + kGfR2 ints), then three blocks of 16-bit slots, each 16-byte aligned
+// and read whole: C's incidence entries (kGfCs), R1's (kGfRs) and R1's list
+// offsets (kGfR1 + 2, padded).  Slots: 0..kBlock-1 for C, kBlock + i for R1
+// vertex i, kBlock + |R1| + i for R2 vertex i.
+constexpr int kGfR1 = 256, kGfR2 = 320, kGfCs = 2048, kGfRs = 2048;
+constexpr int kGfIds = 4;                                          // ints before the ids
+constexpr int kGfCsI = (kGfIds + kGfR1 + kGfR2 + 3) / 4 * 4;       // int offset of C's slots
+constexpr int kGfRsI = kGfCsI + kGfCs / 2;                         // ... of R1's slots
+constexpr int kGfRoI = kGfRsI + kGfRs / 2;                         // ... of R1's offsets
+constexpr int kGfRoN = ((kGfR1 + 2) / 2 + 3) / 4;                  // 16-byte blocks of the offsets
+constexpr int kGfRow = kGfRoI + 4 * kGfRoN;
+static_assert(kGfCs / 8 == 256 && kGfRs / 8 == 256, "one 16-byte block of each slot list per thread");
+
 // Chunk-local neighbour slots and halo lists of a graph problem: nbl[k] names the
 // neighbour of incidence-list entry k by its LDS slot (u - chunk start inside the
 // chunk, kBlock + halo index for a staged outside vertex, -(u + 1) for one past
@@ -157,6 +176,15 @@ __device__ __forceinline__ void reduce_partials2(const double* __restrict__ pa, 
   __syncthreads();
   *ta = total[0];
   *tb = total[1];
+}
+
+// p as a pointer to global memory.  Pointers read from an argument row in
+// device memory are generic; accesses through them compile to flat
+// instructions, which also count against the LDS/scalar counter, so every wait
+// for an LDS read would wait for outstanding HBM loads and stores as well.
+template <typename T>
+__device__ __forceinline__ __attribute__((address_space(1))) T* gmem(T* p) {
+  return (__attribute__((address_space(1))) T*)p;
 }
 
 __device__ __forceinline__ bool is_block_leader(VG g) { return g.bid == 0 && threadIdx.x == 0; }

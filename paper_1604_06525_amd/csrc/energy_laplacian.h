@@ -207,6 +207,58 @@ struct LaplacianGraph {
     for (int c = 0; c < 3; ++c) g[c] = wf2 * P(c, v) + wr2 * acc[c];
   }
 
+  // Fused graph PCG hooks: the staged record of a vertex is its p, and a
+  // neighbour's share of delta reads all three components of u.  A loop
+  // {v, v} adds nothing to the product and is not counted in the diagonal.
+  static constexpr bool kGraphFused = true;
+  static constexpr int kRec = 3;
+  static constexpr int kHalo = 3;
+  struct GOwn {};
+  using GRaw = Vals<T, 1>;
+  __device__ __forceinline__ GRaw graw(int) const { return GRaw{}; }
+  __device__ __forceinline__ GOwn gown_of(const GRaw&) const { return GOwn{}; }
+  __device__ __forceinline__ void grec(const GOwn&, const T* p, T* r) const {
+#pragma unroll
+    for (int c = 0; c < 3; ++c) r[c] = p[c];
+  }
+  template <class RA, class NA>
+  __device__ __forceinline__ void gapply_h(int sv, RA R, NA NB, int k0, int k1, uint32_t, T* g, T* dg) const {
+    T acc[3] = {}, cnt = T(0);
+    for (int k = k0; k < k1; ++k) {
+      const int s = NB(k);
+#pragma unroll
+      for (int c = 0; c < 3; ++c) acc[c] += R(sv, c) - R(s, c);
+      cnt += s != sv ? T(1) : T(0);
+    }
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      g[c] = fma(wr2, acc[c], wf2 * R(sv, c));
+      dg[c] = wf2 + wr2 * cnt;
+    }
+  }
+  template <class RA, class NA>
+  __device__ __forceinline__ void gapply(const GOwn&, const T*, const T*, int sv, RA R, NA NB, int k0, int k1,
+                                         uint32_t fl, T* g) const {
+    T dg[3];
+    gapply_h(sv, R, NB, k0, k1, fl, g, dg);
+  }
+  // w_fit^2 |u_v|^2 + half of w_reg^2 |u_v - u_s|^2 for each listed edge at v
+  // (each edge's residual is shared by its two ends).
+  template <class RA, class UA, class NA>
+  __device__ __forceinline__ T gjsq(const GOwn&, const T* u, RA, UA UH, NA NB, int k0, int k1, uint32_t) const {
+    T acc = T(0);
+    for (int k = k0; k < k1; ++k) {
+      const int s = NB(k);
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        const T e = u[c] - UH(s, c);
+        acc = fma(e, e, acc);
+      }
+    }
+    const T uu = fma(u[2], u[2], fma(u[1], u[1], u[0] * u[0]));
+    return fma(T(0.5) * wr2, acc, wf2 * uu);
+  }
+
   template <class XA, class DA>
   __device__ __forceinline__ double model(XA X, DA Dl, int v) const {
     double acc = 0.0;

@@ -58,6 +58,7 @@ struct Shape {
   int n_edges = 0;     // graph: listed undirected edges
   int stage_w = 0;     // graph: values per vertex pcg_a stages (0: not staged)
   bool graph = false;
+  bool gfz = false;    // graph: the fused PCG form's per-chunk lists are built
   // materialised Jacobian (OPT_PCG_MATERIALIZED): rows per site, entries per
   // row, entries per J^T column
   bool mat = false;
@@ -66,8 +67,8 @@ struct Shape {
 
 // Byte offsets of every region of a problem's workspace.
 struct Layout {
-  size_t r0, r1, p0, p1, q, diag, minv, damp, delta, state, flags, csr, halo, jval, jcol, jt, jy, parts, scal,
-      trace, rows, total;
+  size_t r0, r1, p0, p1, q, diag, minv, damp, delta, state, flags, csr, halo, gfz, jval, jcol, jt, jy, parts,
+      scal, trace, rows, total;
 };
 
 // Argument rows a single problem launches with, one device slot of kMaxArgBytes
@@ -188,6 +189,7 @@ struct opt_problem {
   int nblk = 1;
   int n_simd = 1024;  // SIMDs of the device (fused kernel launch shape)
   const void* last_x = nullptr;
+  bool gfused = false;  // graph: the fused PCG form's lists are built and fit
   // last bytes stored in each device argument row (a row is stored again only
   // when it changes)
   std::vector<std::vector<unsigned char>> row_cache =
@@ -247,9 +249,10 @@ namespace host {
 int problem_init(opt_problem* p, const opt_problem_desc* desc, const Shape& sh, void* workspace,
                  hipStream_t stream, bool defer_graph = false);
 
-// Graph incidence and staging lists as one host array (see opt_capi.hip).
+// Graph incidence and staging lists as one host array (see opt_capi.hip);
+// *gfused tells whether the fused PCG form's lists fit their caps.
 size_t incidence_words(const Shape& sh);
-int build_incidence_host(const Shape& sh, const int* edges, int* out);
+int build_incidence_host(const Shape& sh, const int* edges, int* out, bool* gfused);
 int upload_incidence(opt_problem* p, const int* words);
 
 // opt_solve on a created problem (parameters validated here).

@@ -18,6 +18,7 @@
 #include "host.h"
 #include "energies.h"
 #include "fused_sfs.h"
+#include "fused_graph.h"
 
 namespace optmi {
 namespace host {
@@ -38,6 +39,12 @@ int fail(int code, const char* fmt, ...) {
 
 const char* last_error() { return g_err.c_str(); }
 
+// Ints of the fused graph form's lists: a row per chunk.
+size_t gfz_words(const Shape& sh) {
+  const size_t nch = ((size_t)sh.n + kBlock - 1) / kBlock;
+  return nch * kGfRow;
+}
+
 Layout make_layout(const Shape& sh) {
   Layout L{};
   size_t off = 0;
@@ -54,6 +61,8 @@ Layout make_layout(const Shape& sh) {
   if (sh.graph)
     off += align_up(sizeof(int) * (2 * (size_t)sh.n_edges + (size_t)(sh.n + kBlock - 1) / kBlock *
                                                                   (1 + (size_t)halo_cap(sh.tsize, sh.stage_w))));
+  L.gfz = off;  // graph, fused form: per-chunk lists [chunks][kGfRow]
+  if (sh.gfz) off += align_up(sizeof(int) * gfz_words(sh));
   // materialised Jacobian: entries (values, columns), J^T lists, y = J p
   const size_t jrows = sh.mat ? (size_t)sh.n * sh.mat_rows : 0;
   L.jval = off; off += align_up(jrows * sh.mat_slots * sh.tsize);
@@ -192,6 +201,7 @@ int check_desc(const opt_problem_desc* d, Shape* sh) {
     sh->n_edges = d->n_edges;
     sh->graph = true;
     sh->stage_w = stage_width(d->energy);
+    sh->gfz = d->energy == OPT_E_ARAP_MESH || d->energy == OPT_E_LAPLACIAN;
   } else {
     return fail(OPT_EINVAL, "domain %d is not OPT_GRID2D or OPT_GRAPH", d->domain);
   }
@@ -261,6 +271,8 @@ class ImplT final : public Impl {
   // residual-streaming one for shape from shading (radius 2)
   static constexpr bool kSfs = std::is_same_v<E, ShapeFromShading<T>>;
   static constexpr bool kFusedOk = !E::kGraph && (E::kRadius == 1 || kSfs);
+  // graph energies with the fused graph kernel's hooks
+  static constexpr bool kGFused = E::kGraph && GraphFusedOf<E>::value;
   static constexpr int kCols = kSfs ? kSfsCols : kStripCols;
   ImplT(opt_problem* p, const E& e) : p_(p), e_(e) {}
 
@@ -399,6 +411,46 @@ class ImplT final : public Impl {
     *grid = g.grid;
     return a;
   }
+  // Blocks per CU the fused graph kernel holds (its LDS decides).
+  template <bool DAMP>
+  static int gfused_blocks_per_cu() {
+    static const int occ = [] {
+      int blocks = 0;
+      if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, k_batch<GraphFusedArgs<E, DAMP>>, kBlock, 0) !=
+          hipSuccess)
+        return 1;
+      return std::max(1, blocks);
+    }();
+    return occ;
+  }
+  // One block per chunk, at most as many as are resident at once (each then
+  // walks its chunks with a fixed stride) and at most kMaxBlocks.
+  int gfused_grid(bool damped) const {
+    const int nch = (e_.n + kBlock - 1) / kBlock;
+    const int per_cu = damped ? gfused_blocks_per_cu<true>() : gfused_blocks_per_cu<false>();
+    return std::max(1, std::min({nch, kMaxBlocks, per_cu * std::max(1, p_->n_simd / 4)}));
+  }
+  template <bool DAMP>
+  GraphFusedArgs<E, DAMP> gfused_args(int L, PrecondArgs pa, int lm, int* grid) const {
+    GraphFusedArgs<E, DAMP> a = blank<GraphFusedArgs<E, DAMP>>();
+    a.e = e_;
+    a.b.u[0] = rbuf(0);
+    a.b.u[1] = rbuf(1);
+    a.b.p[0] = pbuf(0);
+    a.b.p[1] = pbuf(1);
+    a.b.x = vec(p_->L.delta);
+    a.b.part[0] = p_->part(P_F0);
+    a.b.part[1] = p_->part(P_F1);
+    a.b.diag = vec(p_->L.diag);
+    a.gl.rows = (const int*)p_->at(p_->L.gfz);
+    a.pc = pc(pa);
+    a.S = p_->S();
+    a.lm_gate = lm;
+    a.L = L;
+    *grid = gfused_grid(DAMP);
+    a.n_part = *grid;
+    return a;
+  }
   StepArgs<E> step_args(void* x, int lm) const {
     StepArgs<E> a = blank<StepArgs<E>>();
     a.e = e_;
@@ -534,7 +586,9 @@ class ImplT final : public Impl {
     return true;
   }
   bool has_fused() const override {
-    if constexpr (!kFusedOk) {
+    if constexpr (kGFused) {
+      return p_->gfused;
+    } else if constexpr (!kFusedOk) {
       return false;
     } else if constexpr (kSfs) {
       return whole_fits();
@@ -551,7 +605,12 @@ class ImplT final : public Impl {
   }
   // iter = -1 is the priming launch (it writes only partials).
   int fused(int iter, int L, PrecondArgs pa, int lm) override {
-    if constexpr (!kFusedOk) {
+    if constexpr (kGFused) {
+      if (!p_->gfused) return fail(OPT_EUNSUPPORTED, "the graph's lists do not fit the fused form");
+      int grid = 0;
+      if (pa.damped) return go(ROW_FUSED, gfused_args<true>(L, pa, lm, &grid), grid, iter, "fused");
+      return go(ROW_FUSED, gfused_args<false>(L, pa, lm, &grid), grid, iter, "fused");
+    } else if constexpr (!kFusedOk) {
       return fail(OPT_EUNSUPPORTED, "no fused PCG kernel for this energy");
     } else {
       int grid = 0;
@@ -583,6 +642,12 @@ class ImplT final : public Impl {
   double gpu_fill(bool use_fused, bool damped) const override {
     double waves = (double)nblk() * kWaves;
     int occ = 2;
+    if constexpr (kGFused) {
+      if (use_fused && has_fused()) {
+        waves = (double)gfused_grid(damped) * kWaves;
+        occ = std::max(1, (damped ? gfused_blocks_per_cu<true>() : gfused_blocks_per_cu<false>()) * kWaves / 4);
+      }
+    }
     if constexpr (kFusedOk) {
       if (use_fused && has_fused()) {
         const StripGeom g = geom(damped);
@@ -631,7 +696,15 @@ class ImplT final : public Impl {
         }, 0, 1, "init[batch]");
       case Stage::PCG:
         if (use_fused) {
-          if constexpr (!kFusedOk) {
+          if constexpr (kGFused) {
+            if (s[0].pa.damped)
+              return rec<GraphFusedArgs<E, true>>(B, s, n, [](const ImplT& m, const SlotRef& r, int* g) {
+                return m.template gfused_args<true>(r.L, r.pa, r.lm, g);
+              }, -1, Lmax, "fused[batch]");
+            return rec<GraphFusedArgs<E, false>>(B, s, n, [](const ImplT& m, const SlotRef& r, int* g) {
+              return m.template gfused_args<false>(r.L, r.pa, r.lm, g);
+            }, -1, Lmax, "fused[batch]");
+          } else if constexpr (!kFusedOk) {
             return fail(OPT_EUNSUPPORTED, "no fused PCG kernel for this energy");
           } else {
             // one group holds problems of one method (the server keys groups by
@@ -869,13 +942,79 @@ std::unique_ptr<Impl> make_impl(opt_problem* p) {
 // (chunks) | halo ids (chunks x cap)] (its halo region).
 size_t incidence_words(const Shape& sh) {
   const size_t V = (size_t)sh.n, E = (size_t)sh.n_edges, nch = (V + kBlock - 1) / kBlock;
-  return (V + 1) + 2 * E + 2 * E + nch + nch * (size_t)halo_cap(sh.tsize, sh.stage_w);
+  return (V + 1) + 2 * E + 2 * E + nch + nch * (size_t)halo_cap(sh.tsize, sh.stage_w) +
+         (sh.gfz ? gfz_words(sh) : 0);
 }
+
+namespace {
+
+// The fused form's lists of every chunk (layout: common.h, kGfRow).  R1 lists
+// the chunk's outside
+// neighbours in order of first reference (its vertices in id order, each
+// vertex's incidence in order), R2 the neighbours of R1 outside the chunk and
+// R1 in the same way; an R1 vertex's list keeps its incidence order, so its
+// terms are summed as its own chunk sums them.  False if a chunk passes a cap.
+bool build_gfz(const Shape& sh, const int* rp, const int* nb, int* out) {
+  const int V = sh.n, nch = (V + kBlock - 1) / kBlock;
+  int* rows = out;
+  std::vector<int> mark((size_t)V, -1), slot((size_t)V, 0), ring;
+  for (int c = 0; c < nch; ++c) {
+    const int v0 = c * kBlock, v1 = std::min(V, v0 + kBlock);
+    int* row = rows + (size_t)c * kGfRow;
+    std::fill(row, row + kGfRow, 0);
+    if (rp[v1] - rp[v0] > kGfCs) return false;
+    ring.clear();
+    auto local = [&](int u) { return u >= v0 && u < v1; };
+    for (int v = v0; v < v1; ++v)
+      for (int k = rp[v]; k < rp[v + 1]; ++k) {
+        const int u = nb[k];
+        if (local(u) || mark[u] == c) continue;
+        mark[u] = c;
+        slot[u] = kBlock + (int)ring.size();
+        ring.push_back(u);
+      }
+    const int n1 = (int)ring.size();
+    if (n1 > kGfR1) return false;
+    for (int j = 0; j < n1; ++j) {
+      const int w = ring[(size_t)j];
+      for (int k = rp[w]; k < rp[w + 1]; ++k) {
+        const int u = nb[k];
+        if (local(u) || mark[u] == c) continue;
+        mark[u] = c;
+        slot[u] = kBlock + (int)ring.size();
+        ring.push_back(u);
+      }
+    }
+    const int n2 = (int)ring.size() - n1;
+    if (n2 > kGfR2) return false;
+    auto slot_of = [&](int u) { return local(u) ? u - v0 : slot[u]; };
+    uint16_t* cs = (uint16_t*)(row + kGfCsI);
+    uint16_t* r1s = (uint16_t*)(row + kGfRsI);
+    uint16_t* r1o = (uint16_t*)(row + kGfRoI);
+    for (int k = rp[v0]; k < rp[v1]; ++k) cs[k - rp[v0]] = (uint16_t)slot_of(nb[k]);
+    int ne1 = 0;
+    r1o[0] = 0;
+    for (int j = 0; j < n1; ++j) {
+      const int w = ring[(size_t)j];
+      if (ne1 + (rp[w + 1] - rp[w]) > kGfRs) return false;
+      for (int k = rp[w]; k < rp[w + 1]; ++k) r1s[ne1++] = (uint16_t)slot_of(nb[k]);
+      r1o[j + 1] = (uint16_t)ne1;
+    }
+    row[0] = n1;
+    row[1] = n2;
+    row[2] = ne1;
+    for (int j = 0; j < n1 + n2; ++j) row[kGfIds + j] = ring[(size_t)j];
+  }
+  return true;
+}
+
+}  // namespace
 
 // Build them from the edge list (host, [E][2]).  A stable counting sort: vertex
 // v lists, in edge-list order, the other end of every edge that touches it, so
 // the order of every per-vertex sum is fixed.
-int build_incidence_host(const Shape& sh, const int* edges, int* out) {
+int build_incidence_host(const Shape& sh, const int* edges, int* out, bool* gfused) {
+  *gfused = false;
   const int V = sh.n, E = sh.n_edges;
   int* rp = out;
   int* nb = rp + V + 1;
@@ -924,6 +1063,7 @@ int build_incidence_host(const Shape& sh, const int* edges, int* out) {
       }
     hcnt[c] = nh;
   }
+  if (sh.gfz) *gfused = build_gfz(sh, rp, nb, hid + (size_t)nch * cap);
   return OPT_OK;
 }
 
@@ -932,9 +1072,12 @@ int build_incidence_host(const Shape& sh, const int* edges, int* out) {
 int upload_incidence(opt_problem* p, const int* words) {
   const size_t V = (size_t)p->sh.n, E = (size_t)p->sh.n_edges;
   const size_t csr = V + 1 + 2 * E, total = incidence_words(p->sh);
+  const size_t gfz = p->sh.gfz ? gfz_words(p->sh) : 0, halo = total - csr - gfz;
   HIP_TRY(hipMemcpyAsync(p->at(p->L.csr), words, sizeof(int) * csr, hipMemcpyHostToDevice, p->stream));
-  HIP_TRY(hipMemcpyAsync(p->at(p->L.halo), words + csr, sizeof(int) * (total - csr), hipMemcpyHostToDevice,
-                         p->stream));
+  HIP_TRY(hipMemcpyAsync(p->at(p->L.halo), words + csr, sizeof(int) * halo, hipMemcpyHostToDevice, p->stream));
+  if (gfz)
+    HIP_TRY(hipMemcpyAsync(p->at(p->L.gfz), words + csr + halo, sizeof(int) * gfz, hipMemcpyHostToDevice,
+                           p->stream));
   return OPT_OK;
 }
 
@@ -948,8 +1091,10 @@ int build_incidence(opt_problem* p) {
                            p->stream));
     HIP_TRY(hipStreamSynchronize(p->stream));
   }
-  TRY(build_incidence_host(p->sh, edges.data(), words.data()));
+  bool gfused = false;
+  TRY(build_incidence_host(p->sh, edges.data(), words.data(), &gfused));
   TRY(upload_incidence(p, words.data()));
+  p->gfused = gfused;
   HIP_TRY(hipStreamSynchronize(p->stream));
   return OPT_OK;
 }
@@ -1333,6 +1478,15 @@ int opt_problem_set_graph_replay(opt_problem* p, int enable) {
   p->graphs = enable != 0;
   if (!p->graphs) p->drop_graph();
   p->last_eager.valid = false;
+  return OPT_OK;
+}
+
+int opt_problem_pcg_form(opt_problem* p, int variant, int* form) {
+  if (!p || !form) return fail(OPT_EINVAL, "problem or form is NULL");
+  if (variant != OPT_PCG_FUSED && variant != OPT_PCG_SPLIT && variant != OPT_PCG_MATERIALIZED)
+    return fail(OPT_EINVAL, "pcg_variant %d is not OPT_PCG_FUSED, OPT_PCG_SPLIT or OPT_PCG_MATERIALIZED", variant);
+  *form = variant == OPT_PCG_MATERIALIZED ? OPT_PCG_MATERIALIZED
+                                          : (uses_fused(p, variant) ? OPT_PCG_FUSED : OPT_PCG_SPLIT);
   return OPT_OK;
 }
 

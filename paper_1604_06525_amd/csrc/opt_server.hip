@@ -274,7 +274,8 @@ int finish_graph_admissions(opt_server* sv) {
     const hipError_t q = hipEventQuery(s.ev_edges);
     if (q == hipErrorNotReady) continue;
     if (q != hipSuccess) return fail(OPT_EHIP, "hipEventQuery failed: %s", hipGetErrorString(q));
-    const int rc = build_incidence_host(s.p->sh, s.edges_pin, s.inc_pin);
+    bool gfused = false;
+    const int rc = build_incidence_host(s.p->sh, s.edges_pin, s.inc_pin, &gfused);
     if (rc != OPT_OK) {
       Result r;
       r.code = rc;
@@ -284,6 +285,10 @@ int finish_graph_admissions(opt_server* sv) {
       continue;
     }
     TRY(upload_incidence(s.p.get(), s.inc_pin));
+    // the form is known now: the fused one if the lists fit their caps
+    s.p->gfused = gfused;
+    s.fused = s.sp.pcg_variant == OPT_PCG_FUSED && s.p->impl->has_fused() && !s.p->impl->fused_is_big();
+    s.fill = s.p->impl->gpu_fill(s.fused, s.sp.method == OPT_LM);
     (void)hipEventDestroy(s.ev_edges);
     s.ev_edges = nullptr;
     (void)hipHostFree(s.edges_pin);
