@@ -107,57 +107,7 @@ __device__ __forceinline__ void run(const GraphFusedArgs<E, DAMP>& a, VG g, int 
   const double alpha_old = iter > 0 ? S->alpha[(iter - 1) & 1] : 1.0;
   const double lam_now = a.lm_gate ? S->lambda : 0.0;
   if ((stopped_at != 0 && stopped_at != iter + 1) || lm_done) return;
-  const double* part_in = pick(a.b.part, (iter + 1) & 1);
-  double* part_out = pick(a.b.part, iter & 1);
-  double alpha = 0.0, beta = 0.0;
-  const double alpha_prev = (iter & 1) ? alpha_old : 0.0;
-  if (iter >= 0) {
-    double gam, del;
-    reduce_partials2(part_in, part_in + kMaxBlocks, a.n_part, &gam, &del);
-    double den = del;
-    if (iter > 0) {
-      beta = gam / gam_old;
-      den = del - beta * gam / alpha_old;
-    }
-    if (!(den > 0.0)) {
-      if (is_block_leader(g)) S->stopped = iter + 1;
-      if (iter & 1) {
-        // the update alpha_{i-1} p_{i-1} deferred from the previous iteration
-        const T ap = (T)alpha_prev;
-        for (int chunk = unit_of_block(g); chunk < nch; chunk += g.nb) {
-          const int v = chunk * kBlock + (int)threadIdx.x;
-          if (v >= n || !(flags[v] & E::ACTIVE)) continue;
-#pragma unroll
-          for (int c = 0; c < C; ++c) {
-            const size_t o = vix<C>(c, v);
-            x[o] = fma(ap, pin[o], x[o]);
-          }
-        }
-      }
-      return;
-    }
-    alpha = gam / den;
-    if (is_block_leader(g)) {
-      S->gam[iter & 1] = gam;
-      S->alpha[iter & 1] = alpha;
-    }
-  }
-  const T aT = (T)alpha, bT = (T)beta, apT = (T)alpha_prev;
-  Precond<T> pc = a.pc;
-  if (a.lm_gate) pc.lam = (T)lam_now;
-  // the preconditioner entry M and its inverse, and the damping, of an
-  // unknown with diagonal dg (as Precond gives them; lambda is 0 for GN)
-  auto precond = [&](T dg, T* m, T* mi, T* dmp) {
-    *dmp = (DAMP && pc.lam != T(0)) ? pc.damp(dg) : T(0);
-    *m = DAMP ? pc.den(dg) : (pc.use ? dg : T(1));
-    const T rm = recip(*m);
-    *mi = pc.use ? (*m > T(0) ? rm : T(0)) : T(1);
-  };
-  auto R = [&](int s, int k) -> T { return sm.rec[k][s]; };
-  auto UH = [&](int s, int c) -> T { return sm.uh[c][s]; };
-  double g_acc = 0.0, d_acc = 0.0;
   const int t = threadIdx.x;
-
   // What a thread loads for one chunk, issued while the chunk before it is
   // computed: its vertex of C and the chunk's lists (stage A) and the data of
   // its outside slot t (stage B), whose id was loaded one chunk earlier still,
@@ -213,6 +163,67 @@ __device__ __forceinline__ void run(const GraphFusedArgs<E, DAMP>& a, VG g, int 
     }
     P.raw0 = e.graw(id);
   };
+  // The first chunk's loads do not depend on alpha and beta: they go out
+  // before the previous launch's partial sums are reduced.
+  const int first = unit_of_block(g);
+  Pre P;
+  int id_next = 0;  // outside slot t of the chunk after P's
+  if (first < nch) {
+    P.id0 = id_of(first, t);
+    load_a(first, P);
+    load_b(P);
+    if (first + g.nb < nch) id_next = id_of(first + g.nb, t);
+  }
+  const double* part_in = pick(a.b.part, (iter + 1) & 1);
+  double* part_out = pick(a.b.part, iter & 1);
+  double alpha = 0.0, beta = 0.0;
+  const double alpha_prev = (iter & 1) ? alpha_old : 0.0;
+  if (iter >= 0) {
+    double gam, del;
+    reduce_partials2(part_in, part_in + kMaxBlocks, a.n_part, &gam, &del);
+    double den = del;
+    if (iter > 0) {
+      beta = gam / gam_old;
+      den = del - beta * gam / alpha_old;
+    }
+    if (!(den > 0.0)) {
+      if (is_block_leader(g)) S->stopped = iter + 1;
+      if (iter & 1) {
+        // the update alpha_{i-1} p_{i-1} deferred from the previous iteration
+        const T ap = (T)alpha_prev;
+        for (int chunk = unit_of_block(g); chunk < nch; chunk += g.nb) {
+          const int v = chunk * kBlock + (int)threadIdx.x;
+          if (v >= n || !(flags[v] & E::ACTIVE)) continue;
+#pragma unroll
+          for (int c = 0; c < C; ++c) {
+            const size_t o = vix<C>(c, v);
+            x[o] = fma(ap, pin[o], x[o]);
+          }
+        }
+      }
+      return;
+    }
+    alpha = gam / den;
+    if (is_block_leader(g)) {
+      S->gam[iter & 1] = gam;
+      S->alpha[iter & 1] = alpha;
+    }
+  }
+  const T aT = (T)alpha, bT = (T)beta, apT = (T)alpha_prev;
+  Precond<T> pc = a.pc;
+  if (a.lm_gate) pc.lam = (T)lam_now;
+  // the preconditioner entry M and its inverse, and the damping, of an
+  // unknown with diagonal dg (as Precond gives them; lambda is 0 for GN)
+  auto precond = [&](T dg, T* m, T* mi, T* dmp) {
+    *dmp = (DAMP && pc.lam != T(0)) ? pc.damp(dg) : T(0);
+    *m = DAMP ? pc.den(dg) : (pc.use ? dg : T(1));
+    const T rm = recip(*m);
+    *mi = pc.use ? (*m > T(0) ? rm : T(0)) : T(1);
+  };
+  auto R = [&](int s, int k) -> T { return sm.rec[k][s]; };
+  auto UH = [&](int s, int c) -> T { return sm.uh[c][s]; };
+  double g_acc = 0.0, d_acc = 0.0;
+
   // p and the record of an outside vertex into slot kBlock + j
   auto stage_out = [&](int j, uint32_t f, const T* u, const T* pold, const typename E::GRaw& raw) {
     T pj[C], r[NR];
@@ -223,15 +234,7 @@ __device__ __forceinline__ void run(const GraphFusedArgs<E, DAMP>& a, VG g, int 
     for (int k = 0; k < NR; ++k) sm.rec[k][kBlock + j] = r[k];
   };
 
-  int chunk = unit_of_block(g);
-  Pre P;
-  int id_next = 0;  // outside slot t of the chunk after P's
-  if (chunk < nch) {
-    P.id0 = id_of(chunk, t);
-    load_a(chunk, P);
-    load_b(P);
-    if (chunk + g.nb < nch) id_next = id_of(chunk + g.nb, t);
-  }
+  int chunk = first;
   for (; chunk < nch; chunk += g.nb) {
     const int v0 = chunk * kBlock, v = v0 + t;
     const bool in = v < n;
