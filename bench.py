@@ -425,6 +425,10 @@ CONFIGS = [
     ("volume_64x64x64_lm10x40_mixed", lambda w: w.arap_volume(64, 64, 64, seed=6), "mixed", "lm", 10, 40, (24, 37)),
     ("laplacian_1024x1024_gn10x50_mixed", lambda w: w.laplacian_grid(1024, 1024, seed=0), "mixed", "gn", 10, 50,
      (24, 5)),
+    # the level-8 mesh in the split form (two kernels per iteration), beside
+    # its fused graph form above
+    ("mesh_icosphere8_lm10x40_mixed_split", lambda w: w.arap_mesh(8, seed=3), "mixed", "lm", 10, 40, (24, 52),
+     dict(pcg_variant="split")),
 ]
 
 
