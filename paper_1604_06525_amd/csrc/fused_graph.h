@@ -41,7 +41,7 @@ struct GraphFusedOf : std::false_type {};
 template <class E>
 struct GraphFusedOf<E, std::void_t<decltype(E::kGraphFused)>> : std::bool_constant<E::kGraphFused> {};
 
-// The graph's per-chunk lists (layout: common.h, kGfRow).
+// The graph's per-chunk lists (layout: opt_limits.h, kGfRow).
 struct GraphLists {
   const int* __restrict__ rows;  // [chunks][kGfRow]
 };

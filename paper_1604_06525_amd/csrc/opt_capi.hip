@@ -19,6 +19,7 @@
 #include "energies.h"
 #include "fused_sfs.h"
 #include "fused_graph.h"
+#include "graph_lists.h"
 
 namespace optmi {
 namespace host {
@@ -40,10 +41,7 @@ int fail(int code, const char* fmt, ...) {
 const char* last_error() { return g_err.c_str(); }
 
 // Ints of the fused graph form's lists: a row per chunk.
-size_t gfz_words(const Shape& sh) {
-  const size_t nch = ((size_t)sh.n + kBlock - 1) / kBlock;
-  return nch * kGfRow;
-}
+size_t gfz_words(const Shape& sh) { return lists::gfz_words(sh.n); }
 
 Layout make_layout(const Shape& sh) {
   Layout L{};
@@ -937,133 +935,18 @@ std::unique_ptr<Impl> make_impl(opt_problem* p) {
 }  // namespace
 
 // Graph domain: the per-vertex incidence list (CSR) and the staging lists, as
-// one host array of incidence_words() ints: [row offsets (V+1) | neighbour ids
-// (2E)] (the workspace's csr region) then [chunk-local slots (2E) | halo counts
-// (chunks) | halo ids (chunks x cap)] (its halo region).
-size_t incidence_words(const Shape& sh) {
-  const size_t V = (size_t)sh.n, E = (size_t)sh.n_edges, nch = (V + kBlock - 1) / kBlock;
-  return (V + 1) + 2 * E + 2 * E + nch + nch * (size_t)halo_cap(sh.tsize, sh.stage_w) +
-         (sh.gfz ? gfz_words(sh) : 0);
+// one host array (graph_lists.h has the layout and the builders).
+lists::GraphShape graph_shape(const Shape& sh) {
+  return lists::GraphShape{sh.n, sh.n_edges, halo_cap(sh.tsize, sh.stage_w), sh.gfz};
 }
 
-namespace {
+size_t incidence_words(const Shape& sh) { return lists::words(graph_shape(sh)); }
 
-// The fused form's lists of every chunk (layout: common.h, kGfRow).  R1 lists
-// the chunk's outside
-// neighbours in order of first reference (its vertices in id order, each
-// vertex's incidence in order), R2 the neighbours of R1 outside the chunk and
-// R1 in the same way; an R1 vertex's list keeps its incidence order, so its
-// terms are summed as its own chunk sums them.  False if a chunk passes a cap.
-bool build_gfz(const Shape& sh, const int* rp, const int* nb, int* out) {
-  const int V = sh.n, nch = (V + kBlock - 1) / kBlock;
-  int* rows = out;
-  std::vector<int> mark((size_t)V, -1), slot((size_t)V, 0), ring;
-  for (int c = 0; c < nch; ++c) {
-    const int v0 = c * kBlock, v1 = std::min(V, v0 + kBlock);
-    int* row = rows + (size_t)c * kGfRow;
-    std::fill(row, row + kGfRow, 0);
-    if (rp[v1] - rp[v0] > kGfCs) return false;
-    ring.clear();
-    auto local = [&](int u) { return u >= v0 && u < v1; };
-    for (int v = v0; v < v1; ++v)
-      for (int k = rp[v]; k < rp[v + 1]; ++k) {
-        const int u = nb[k];
-        if (local(u) || mark[u] == c) continue;
-        mark[u] = c;
-        slot[u] = kBlock + (int)ring.size();
-        ring.push_back(u);
-      }
-    const int n1 = (int)ring.size();
-    if (n1 > kGfR1) return false;
-    for (int j = 0; j < n1; ++j) {
-      const int w = ring[(size_t)j];
-      for (int k = rp[w]; k < rp[w + 1]; ++k) {
-        const int u = nb[k];
-        if (local(u) || mark[u] == c) continue;
-        mark[u] = c;
-        slot[u] = kBlock + (int)ring.size();
-        ring.push_back(u);
-      }
-    }
-    const int n2 = (int)ring.size() - n1;
-    if (n2 > kGfR2) return false;
-    auto slot_of = [&](int u) { return local(u) ? u - v0 : slot[u]; };
-    uint16_t* cs = (uint16_t*)(row + kGfCsI);
-    uint16_t* r1s = (uint16_t*)(row + kGfRsI);
-    uint16_t* r1o = (uint16_t*)(row + kGfRoI);
-    for (int k = rp[v0]; k < rp[v1]; ++k) cs[k - rp[v0]] = (uint16_t)slot_of(nb[k]);
-    int ne1 = 0;
-    r1o[0] = 0;
-    for (int j = 0; j < n1; ++j) {
-      const int w = ring[(size_t)j];
-      if (ne1 + (rp[w + 1] - rp[w]) > kGfRs) return false;
-      for (int k = rp[w]; k < rp[w + 1]; ++k) r1s[ne1++] = (uint16_t)slot_of(nb[k]);
-      r1o[j + 1] = (uint16_t)ne1;
-    }
-    row[0] = n1;
-    row[1] = n2;
-    row[2] = ne1;
-    for (int j = 0; j < n1 + n2; ++j) row[kGfIds + j] = ring[(size_t)j];
-  }
-  return true;
-}
-
-}  // namespace
-
-// Build them from the edge list (host, [E][2]).  A stable counting sort: vertex
-// v lists, in edge-list order, the other end of every edge that touches it, so
-// the order of every per-vertex sum is fixed.
 int build_incidence_host(const Shape& sh, const int* edges, int* out, bool* gfused) {
-  *gfused = false;
-  const int V = sh.n, E = sh.n_edges;
-  int* rp = out;
-  int* nb = rp + V + 1;
-  int* nbl = nb + 2 * (size_t)E;
-  const int nch = (V + kBlock - 1) / kBlock, cap = halo_cap(sh.tsize, sh.stage_w);
-  int* hcnt = nbl + 2 * (size_t)E;
-  int* hid = hcnt + nch;
-  std::fill(rp, rp + V + 1, 0);
-  for (int e = 0; e < E; ++e) {
-    const int a = edges[2 * (size_t)e], b = edges[2 * (size_t)e + 1];
-    if (a < 0 || a >= V || b < 0 || b >= V)
-      return fail(OPT_EINVAL, "edge %d = (%d, %d) names a vertex outside [0, %d)", e, a, b, V);
-    rp[(size_t)a + 1]++;
-    rp[(size_t)b + 1]++;
-  }
-  for (int v = 0; v < V; ++v) rp[(size_t)v + 1] += rp[v];
-  std::vector<int> pos(rp, rp + V);
-  for (int e = 0; e < E; ++e) {
-    const int a = edges[2 * (size_t)e], b = edges[2 * (size_t)e + 1];
-    nb[(size_t)pos[a]++] = b;
-    nb[(size_t)pos[b]++] = a;
-  }
-  // Per chunk of kBlock consecutive vertices: its outside neighbours in order of
-  // first reference, the first halo_cap of them staged.  nbl names a neighbour by
-  // its LDS slot: u - chunk start inside the chunk, kBlock + halo index for a
-  // staged outside one, -(u + 1) for one past the cap (read from global memory).
-  // An energy that is not staged gets cap 0 and every outside slot negative.
-  std::fill(hcnt, hcnt + nch, 0);
-  std::fill(hid, hid + (size_t)nch * cap, 0);
-  std::vector<int> seen((size_t)V, -1), slot((size_t)V, -1);
-  for (int c = 0; c < nch; ++c) {
-    int nh = 0;
-    for (int v = c * kBlock; v < std::min(V, (c + 1) * kBlock); ++v)
-      for (int k = rp[v]; k < rp[(size_t)v + 1]; ++k) {
-        const int u = nb[k];
-        if (u / kBlock == c) {
-          nbl[k] = u - c * kBlock;
-          continue;
-        }
-        if (seen[u] != c) {
-          seen[u] = c;
-          slot[u] = nh < cap ? nh : -1;
-          if (nh < cap) hid[(size_t)c * cap + nh++] = u;
-        }
-        nbl[k] = slot[u] >= 0 ? kBlock + slot[u] : -(u + 1);
-      }
-    hcnt[c] = nh;
-  }
-  if (sh.gfz) *gfused = build_gfz(sh, rp, nb, hid + (size_t)nch * cap);
+  const long long bad = lists::build(graph_shape(sh), edges, out, gfused);
+  if (bad >= 0)
+    return fail(OPT_EINVAL, "edge %lld = (%d, %d) names a vertex outside [0, %d)", bad, edges[2 * bad],
+                edges[2 * bad + 1], sh.n);
   return OPT_OK;
 }
 

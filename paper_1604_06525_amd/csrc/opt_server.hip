@@ -32,9 +32,11 @@
 
 #include "opt.h"
 #include "host.h"
+#include "serve_sched.h"
 
 using namespace optmi;
 using namespace optmi::host;
+using optmi::sched::SlotState;
 
 namespace {
 
@@ -49,71 +51,17 @@ constexpr int kLanes = kMaxLanes - 1;  // streams the energy-kind groups of a st
 // at budgets 1 / 4 / unlimited).
 constexpr double kDefaultFillBudget = 4.0;
 
-// Arena byte ranges, first fit with coalescing.
-class RangeAlloc {
- public:
-  void reset(size_t off, size_t bytes) {
-    free_.clear();
-    if (bytes) free_[off] = bytes;
-  }
-  bool alloc(size_t bytes, size_t* off) {
-    for (auto it = free_.begin(); it != free_.end(); ++it) {
-      if (it->second < bytes) continue;
-      *off = it->first;
-      const size_t rest = it->second - bytes, at = it->first + bytes;
-      free_.erase(it);
-      if (rest) free_[at] = rest;
-      return true;
-    }
-    return false;
-  }
-  void release(size_t off, size_t bytes) {
-    auto it = free_.emplace(off, bytes).first;
-    auto nx = std::next(it);
-    if (nx != free_.end() && it->first + it->second == nx->first) {
-      it->second += nx->second;
-      free_.erase(nx);
-    }
-    if (it != free_.begin()) {
-      auto pv = std::prev(it);
-      if (pv->first + pv->second == it->first) {
-        pv->second += it->second;
-        free_.erase(it);
-      }
-    }
-  }
-  size_t free_bytes() const {
-    size_t t = 0;
-    for (auto& kv : free_) t += kv.second;
-    return t;
-  }
-
- private:
-  std::map<size_t, size_t> free_;
-};
-
-// NEW: admitted, not started.  RUN: in the running set.  DRAIN: its last work
-// is enqueued (final cost, or it was cancelled); the slot is released once the
-// step that carries that work has completed.
-enum class SlotState { EMPTY, NEW, RUN, DRAIN };
-
-struct Slot {
-  SlotState state = SlotState::EMPTY;
-  int64_t ticket = -1;
+// A request: its scheduling state (serve_sched.h: the life cycle NEW, RUN, DRAIN and
+// the start policy) and what its launches need.
+struct Slot : sched::SlotCore {
   std::unique_ptr<opt_problem> p;
-  size_t ws_off = 0, ws_bytes = 0;
   void* x = nullptr;
   opt_solve_params sp{};
-  int it = 0;             // outer iterations enqueued
-  bool lm_done = false;   // LM radius fell below its minimum (seen in a completed step)
   bool fused = false;     // PCG form used
-  bool cancelled = false;
-  double fill = 1.0;      // estimated share of the GPU that one of its launches occupies
-  int64_t last_step = -1; // last step that enqueued work for it
   // A graph request's edge list is copied to pinned memory behind the work on
   // the server's stream; its incidence lists are built on the host by the first
-  // step after that copy has completed, and the request starts from then on.
-  bool graph_pending = false;
+  // step after that copy has completed (graph_pending until then), and the
+  // request starts from then on.
   hipEvent_t ev_edges = nullptr;
   int* edges_pin = nullptr;  // 2E ints; freed once the lists are built
   int* inc_pin = nullptr;    // incidence_words ints; their upload reads them, so kept until release
@@ -192,7 +140,7 @@ struct opt_server {
   hipEvent_t ev_fork[kDepth] = {};
   hipEvent_t ev_join[kDepth][kLanes] = {};
   int64_t n_steps = 0, n_done = 0;      // steps enqueued, steps completed and harvested
-  RangeAlloc ranges;
+  sched::RangeAlloc ranges;
   std::vector<Slot> slots;
   std::map<int64_t, Result> results;
   std::vector<TuneEntry> tuning;  // later entries take precedence
@@ -331,21 +279,14 @@ int harvest(opt_server* sv, bool block) {
       if (q != hipSuccess) return fail(OPT_EHIP, "hipEventQuery failed: %s", hipGetErrorString(q));
     }
     first = false;
-    for (int i : r.gathered) {
-      Slot& s = sv->slots[(size_t)i];
-      if (s.state == SlotState::RUN && sv->host_gather[ring][i].done) s.lm_done = true;
-    }
     for (int i : r.retiring)
       if (!sv->slots[(size_t)i].cancelled) finish_result(sv, i);
     sv->n_done++;
-    for (Slot& s : sv->slots)
-      if (s.state == SlotState::DRAIN && s.last_step < sv->n_done) release_slot(sv, s);
+    const DevScalars* g = sv->host_gather[ring];
+    sched::complete_step(sv->slots, r.gathered, sv->n_done, [g](int i) { return g[i].done != 0; },
+                         [sv](int i) { release_slot(sv, sv->slots[(size_t)i]); });
   }
   return OPT_OK;
-}
-
-bool runnable(const Slot& s) {
-  return s.state == SlotState::RUN && !s.cancelled && s.it < s.sp.outer_iters && !s.lm_done;
 }
 
 }  // namespace
@@ -475,6 +416,8 @@ int opt_server_submit(opt_server* sv, const opt_problem_desc* desc, void* unknow
   s.ws_bytes = need;
   s.x = unknowns;
   s.sp = *sp;
+  s.outer = sp->outer_iters;
+  s.lm = sp->method == OPT_LM;
   s.fused = sp->pcg_variant == OPT_PCG_FUSED && p->impl->has_fused() && !p->impl->fused_is_big();
   s.fill = p->impl->gpu_fill(s.fused, sp->method == OPT_LM);
   s.p = std::move(p);
@@ -491,43 +434,13 @@ int opt_server_step(opt_server* sv) {
   TRY(harvest(sv, false));
   if (sv->n_steps - sv->n_done >= kDepth) TRY(harvest(sv, true));
   TRY(finish_graph_admissions(sv));
-  // start admitted requests in admission order while the running set's fill
-  // stays within the budget (at least one request always runs); a graph
-  // request whose lists are not built yet waits without holding up the rest
-  double running = 0.0;
-  for (const Slot& s : sv->slots)
-    if (runnable(s)) running += s.fill;
-  std::vector<int> order;
-  for (int i = 0; i < sv->max_slots; ++i)
-    if (sv->slots[(size_t)i].state == SlotState::NEW) order.push_back(i);
-  std::sort(order.begin(), order.end(),
-            [&](int a, int b) { return sv->slots[(size_t)a].ticket < sv->slots[(size_t)b].ticket; });
-  std::vector<int> fresh;
-  for (int i : order) {
-    Slot& s = sv->slots[(size_t)i];
-    if (s.graph_pending) continue;
-    if (running > 0.0 && running + s.fill > sv->fill_budget) break;
-    s.state = SlotState::RUN;
-    running += s.fill;
-    fresh.push_back(i);
-  }
-  // this step: one outer iteration for every runnable request; the final cost
-  // for requests whose iterations are then all enqueued (or whose LM solve has
-  // stopped)
-  std::vector<int> run, lm_run, fin;
-  for (int i = 0; i < sv->max_slots; ++i) {
-    const Slot& s = sv->slots[(size_t)i];
-    if (!runnable(s)) continue;
-    run.push_back(i);
-    if (s.sp.method == OPT_LM) lm_run.push_back(i);
-  }
-  for (int i = 0; i < sv->max_slots; ++i) {
-    const Slot& s = sv->slots[(size_t)i];
-    if (s.state != SlotState::RUN || s.cancelled) continue;
-    const int after = s.it + (runnable(s) ? 1 : 0);
-    if (after >= s.sp.outer_iters || s.lm_done) fin.push_back(i);
-  }
-  if (fresh.empty() && run.empty() && fin.empty()) {
+  // start admitted requests (serve_sched.h: admission order, fill budget), then plan
+  // the step: one outer iteration for every runnable request, the final cost
+  // for those whose iterations are then all enqueued (or whose LM solve stopped)
+  const std::vector<int> fresh = sched::start_requests(sv->slots, sv->fill_budget);
+  const sched::StepPlan plan = sched::plan_step(sv->slots);
+  const std::vector<int>&run = plan.run, &lm_run = plan.lm, &fin = plan.fin;
+  if (fresh.empty() && plan.empty()) {
     // nothing to enqueue: wait for the oldest step in flight, if any, or for a
     // pending edge list
     if (sv->n_steps > sv->n_done) {
@@ -622,15 +535,7 @@ int opt_server_step(opt_server* sv) {
   rec.gathered = lm_run;
   rec.retiring = fin;
   HIP_TRY(hipEventRecord(rec.ev, sv->stream));
-  const int64_t idx = sv->n_steps++;
-  for (int i : run) sv->slots[(size_t)i].it += 1;
-  for (int i : fresh) sv->slots[(size_t)i].last_step = idx;
-  for (int i : run) sv->slots[(size_t)i].last_step = idx;
-  for (int i : fin) {
-    Slot& s = sv->slots[(size_t)i];
-    s.last_step = idx;
-    s.state = SlotState::DRAIN;
-  }
+  sched::commit_step(sv->slots, fresh, plan, sv->n_steps++);
   return OPT_OK;
 }
 
@@ -667,17 +572,9 @@ int opt_server_poll(opt_server* sv, int64_t ticket, int32_t* done, opt_solve_rep
 int opt_server_cancel(opt_server* sv, int64_t ticket) {
   if (!sv) return fail(OPT_EINVAL, "server is NULL");
   if (sv->results.erase(ticket)) return OPT_OK;
-  for (Slot& s : sv->slots)
-    if (s.state != SlotState::EMPTY && s.ticket == ticket && !s.cancelled) {
-      // work already enqueued for it must complete before its range is reused
-      s.cancelled = true;
-      if (s.last_step < sv->n_done) {
-        release_slot(sv, s);
-      } else {
-        s.state = SlotState::DRAIN;
-      }
-      return OPT_OK;
-    }
+  // work already enqueued for it must complete before its range is reused
+  if (sched::cancel(sv->slots, ticket, sv->n_done, [sv](int i) { release_slot(sv, sv->slots[(size_t)i]); }))
+    return OPT_OK;
   return fail(OPT_EINVAL, "ticket %lld is not known", (long long)ticket);
 }
 
