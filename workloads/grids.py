@@ -188,3 +188,19 @@ def laplacian_grid(W, H, seed=0, w_fit=0.1, w_reg=0.9):
     A = v + 0.1 * rng.normal(size=(H, W))
     return dict(energy="laplacian", W=W, H=H, A=A[None], x0=np.zeros((1, H, W)),
                 params=dict(w_fit=w_fit, w_reg=w_reg))
+
+
+def lp_smooth(W, H, seed=0, p=1.0, eps=1e-2, w_fit=1.0, w_reg=0.5, noise=0.1, blocks=12):
+    """Edge-preserving smoothing input: a piecewise-constant image (random
+    axis-aligned blocks of random grey levels over a background) plus Gaussian
+    noise; the solve starts from the noisy image."""
+    rng = np.random.default_rng(seed)
+    A = np.full((H, W), 0.5)
+    for _ in range(blocks):
+        x0, y0 = rng.integers(0, W), rng.integers(0, H)
+        w, h = rng.integers(max(1, W // 8), max(2, W // 2)), rng.integers(max(1, H // 8), max(2, H // 2))
+        A[y0:y0 + h, x0:x0 + w] = rng.uniform(0.0, 1.0)
+    A = A + noise * rng.normal(size=(H, W))
+    return dict(energy="lp_smooth", W=W, H=H, A=A[None], x0=A[None].copy(),
+                params=dict(w_fit=w_fit, w_reg=w_reg, p=p, eps=eps))
+

@@ -11,6 +11,7 @@ ARRAY_ORDER = {
     "arap_volume": ["U", "C"],
     "laplacian": ["A"],
     "laplacian_graph": ["A"],
+    "lp_smooth": ["A"],
 }
 # the library's name of each workload energy
 LIB_ENERGY = {"laplacian_graph": "laplacian"}
@@ -21,6 +22,8 @@ def param_list(d):
     e = d["energy"]
     if e in ("arap_warp", "arap_mesh", "arap_volume", "flow", "laplacian", "laplacian_graph"):
         return [p["w_fit"], p["w_reg"]]
+    if e == "lp_smooth":
+        return [p["w_fit"], p["w_reg"], p["p"], p["eps"]]
     if e == "poisson":
         return []
     if e == "sfs":
