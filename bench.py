@@ -425,6 +425,10 @@ CONFIGS = [
     ("volume_64x64x64_lm10x40_mixed", lambda w: w.arap_volume(64, 64, 64, seed=6), "mixed", "lm", 10, 40, (24, 37)),
     ("laplacian_1024x1024_gn10x50_mixed", lambda w: w.laplacian_grid(1024, 1024, seed=0), "mixed", "gn", 10, 50,
      (24, 5)),
+    # l_p edge-preserving smoothing (p = 1) by IRLS: the Laplacian stencil with
+    # two frozen edge weights per pixel as state
+    ("lp_smooth_1024x1024_gn10x50_mixed", lambda w: w.lp_smooth(1024, 1024, seed=0), "mixed", "gn", 10, 50,
+     (24, 9)),
     # the level-8 mesh in the split form (two kernels per iteration), beside
     # its fused graph form above
     ("mesh_icosphere8_lm10x40_mixed_split", lambda w: w.arap_mesh(8, seed=3), "mixed", "lm", 10, 40, (24, 52),
@@ -519,6 +523,7 @@ ACCURACY = [
     ("flow_1920x1080_gn10x50_mixed", lambda w: w.optical_flow(1920, 1080, seed=4), "mixed", "gn", 10, 50),
     ("flow_1920x1080_gn10x50_fp64", lambda w: w.optical_flow(1920, 1080, seed=4), "fp64", "gn", 10, 50),
     ("poisson_1024x1024_gn10x50_mixed", lambda w: w.poisson_edit(1024, 1024, seed=5), "mixed", "gn", 10, 50),
+    ("lp_smooth_1024x1024_gn10x50_mixed", lambda w: w.lp_smooth(1024, 1024, seed=0), "mixed", "gn", 10, 50),
 ]
 
 
@@ -553,7 +558,11 @@ def _oracle_config(name):
 
     if d["energy"] == "sfs":
         masks.append(e.smooth_valid(np.asarray(d["x0"], float).reshape(d["H"], d["W"])))
-    if method == "gn":
+    if d["energy"] == "lp_smooth":
+        # IRLS: Gauss-Newton steps with the weights frozen at each linearisation
+        x, costs = oracle.irls(e, d["x0"], K, L, callback=progress)
+        acc = None
+    elif method == "gn":
         x, costs = oracle.gauss_newton(e, d["x0"], K, L, callback=progress)
         acc = None
     else:

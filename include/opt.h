@@ -92,6 +92,15 @@ typedef enum { OPT_GRID2D = 0, OPT_GRAPH = 1, OPT_GRID3D = 2 } opt_domain;
  *   voxel lattice is the connectivity: every voxel has the ARAP residual towards
  *   each in-bounds neighbour along +-x, +-y, +-z (so each lattice edge counts in
  *   both orientations).  arrays and params as for OPT_E_ARAP_MESH.
+ * OPT_E_LP_SMOOTH (grid; Sec. 7, the IRLS variant of Gauss-Newton).  1 unknown
+ *   per pixel.  Data term w_fit (X - A), squared; edge terms f = w_reg (X(i,j) -
+ *   X(i+1,j)), w_reg (X(i,j) - X(i,j+1)) where the neighbour is on the grid,
+ *   entering as (f^2 + eps^2)^(p/2).  The reported cost is that objective.  Each
+ *   outer iteration freezes w = (p/2) (f^2 + eps^2)^((p-2)/2) per edge at the
+ *   current unknowns and takes a Gauss-Newton step on the reweighted least
+ *   squares sum (w_fit (X - A))^2 + sum w f^2 (iteratively reweighted least
+ *   squares).  arrays: [0] A.  params: w_fit, w_reg, p in (0, 2], eps > 0
+ *   (OPT_EINVAL otherwise).  OPT_LM is refused (OPT_EUNSUPPORTED).
  */
 typedef enum {
   OPT_E_LAPLACIAN = 0,
@@ -100,7 +109,8 @@ typedef enum {
   OPT_E_SFS = 3,
   OPT_E_FLOW = 4,
   OPT_E_ARAP_MESH = 5,
-  OPT_E_ARAP_VOLUME = 6
+  OPT_E_ARAP_VOLUME = 6,
+  OPT_E_LP_SMOOTH = 7
 } opt_energy;
 
 typedef enum { OPT_FP64 = 0, OPT_MIXED = 1 } opt_precision;

@@ -124,12 +124,13 @@ def gauss_newton(energy, x0, outer, inner, use_precond=True, callback=None):
     return x, costs
 
 
-def irls(energy, x0, outer, inner, use_precond=True):
+def irls(energy, x0, outer, inner, use_precond=True, callback=None):
     """Iteratively reweighted least squares (Sec. 7, variants of GN/LM): each
     outer iteration fixes the energy's weights at the current x
     (energy.freeze), then takes one Gauss-Newton step, inner PCG iterations, on
     the fixed-weight least-squares problem.  Returns (x, objectives) with
-    objectives[k] = energy.objective(x_k), k = 0..outer."""
+    objectives[k] = energy.objective(x_k), k = 0..outer.  ``callback`` as for
+    gauss_newton."""
     x = np.asarray(x0, float).ravel().copy()
     objs = []
     for _ in range(outer):
@@ -138,6 +139,8 @@ def irls(energy, x0, outer, inner, use_precond=True):
         lin = Linearization(energy, x)
         delta, _ = pcg(lin.apply, lin.jtf(), lin.minv(use_precond), inner)
         x = x + delta
+        if callback is not None:
+            callback(len(objs), x)
     objs.append(energy.objective(x))
     return x, objs
 

@@ -6,5 +6,6 @@
 #include "energy_arap_warp_graph.h"
 #include "energy_flow.h"
 #include "energy_laplacian.h"
+#include "energy_lp_smooth.h"
 #include "energy_poisson.h"
 #include "energy_sfs.h"

@@ -85,6 +85,7 @@ constexpr int kNumPartBufs = 10;
 Layout make_layout(const Shape& sh);
 int check_desc(const opt_problem_desc* d, Shape* sh);
 int check_params(const opt_solve_params* sp);
+int check_method(const opt_problem_desc* d, const opt_solve_params* sp);
 int check_tuning(const opt_tuning* t);
 
 struct PrecondArgs {

@@ -653,11 +653,13 @@ struct StreamRow {
 // Stencil views centred on row R (rows U before and D after it in the walk); V
 // selects the vector.  Horizontal neighbours come from the adjacent lanes
 // (DPP), vertical ones from the row ring.  Views: P (vector), S (state), F
-// (flags), A (active weight).  Lane exchanges whose values the body does not
-// read are dropped by the compiler.
+// (flags), A (active weight).  With flip (a walk up the grid) a view at dj < 0
+// reads D and one at dj > 0 reads U, so the body sees the grid's orientation.
+// Lane exchanges whose values the body does not read are dropped by the
+// compiler.
 template <class E, bool DAMP, class VSel, class Body>
 __device__ __forceinline__ auto with_views(const StreamRow<E, DAMP>& U, const StreamRow<E, DAMP>& R,
-                                           const StreamRow<E, DAMP>& D, VSel V, Body body) {
+                                           const StreamRow<E, DAMP>& D, VSel V, Body body, bool flip = false) {
   using T = typename E::Real;
   constexpr int C = E::C, NS = StreamRow<E, DAMP>::NS;
   T vl[C], vr[C], sl[NS], sr[NS];
@@ -673,17 +675,22 @@ __device__ __forceinline__ auto with_views(const StreamRow<E, DAMP>& U, const St
   }
   const uint32_t fl = from_left(R.f), fr = from_right(R.f);
   const T al = from_left(R.aw), ar = from_right(R.aw);
+  // dj is a constant at every call, so a view off the row is one select of
+  // the two rows' values on the uniform flag.  Both values are read first: a
+  // choice between two places in the row ring, read once, would send the ring
+  // to scratch memory.
+  auto pick_ud = [](bool down, auto u, auto d) { return down ? d : u; };
   auto Pv = [&](int c, int di, int dj) -> T {
-    return dj < 0 ? V(U, c) : dj > 0 ? V(D, c) : di < 0 ? vl[c] : di > 0 ? vr[c] : V(R, c);
+    return dj != 0 ? pick_ud((dj > 0) != flip, V(U, c), V(D, c)) : di < 0 ? vl[c] : di > 0 ? vr[c] : V(R, c);
   };
   auto Sv = [&](int q, int di, int dj) -> T {
-    return dj < 0 ? U.st[q] : dj > 0 ? D.st[q] : di < 0 ? sl[q] : di > 0 ? sr[q] : R.st[q];
+    return dj != 0 ? pick_ud((dj > 0) != flip, U.st[q], D.st[q]) : di < 0 ? sl[q] : di > 0 ? sr[q] : R.st[q];
   };
   auto Fv = [&](int di, int dj) -> uint32_t {
-    return dj < 0 ? U.f : dj > 0 ? D.f : di < 0 ? fl : di > 0 ? fr : R.f;
+    return dj != 0 ? pick_ud((dj > 0) != flip, U.f, D.f) : di < 0 ? fl : di > 0 ? fr : R.f;
   };
   auto Av = [&](int di, int dj) -> T {
-    return dj < 0 ? U.aw : dj > 0 ? D.aw : di < 0 ? al : di > 0 ? ar : R.aw;
+    return dj != 0 ? pick_ud((dj > 0) != flip, U.aw, D.aw) : di < 0 ? al : di > 0 ? ar : R.aw;
   };
   return body(Pv, Sv, Fv, Av);
 }
@@ -759,9 +766,9 @@ __device__ __forceinline__ void run(const FusedArgs<E, DAMP, BIG>& a, VG g, int 
   // Strips are numbered along grid rows, so horizontally adjacent strips run
   // side by side (and mostly on one XCD).  Vertically adjacent strips walk in
   // opposite directions, so both reach the halo rows they share at about the
-  // same time and the second read is served by the L2.  The operators treat
-  // the rows above and below a site alike, so a strip walking up only sees the
-  // four neighbour terms in another order.
+  // same time and the second read is served by the L2.  A site's operator sees
+  // its rows in grid orientation either way (the streaming energy's, symmetric
+  // in the two, in walk order).
   const int sy = strip / a.n_sx, sx = strip % a.n_sx;
   const int col = sx * sw - 2 + lane;
   const int y0 = sy * a.rq + min(sy, a.rr), y1 = min(y0 + a.rq + (sy < a.rr ? 1 : 0), H);
@@ -904,20 +911,26 @@ __device__ __forceinline__ void run(const FusedArgs<E, DAMP, BIG>& a, VG g, int 
         // d of that row is fetched now, to be updated in the next step
         const int y1r = y - dir;
         T gv[C], dg[C];
-        with_views(R2, R1, R0, selp, [&](auto Pv, auto Sv, auto Fv, auto Av) {
-          if constexpr (SA::kOn) {
+        if constexpr (SA::kOn) {
+          with_views(R2, R1, R0, selp, [&](auto Pv, auto Sv, auto Fv, auto Av) {
             e.apply_stream(Pv, Sv, Fv, Av, shift, cprev, cnext, gv, R1.jc);
             e.diag_stream(Sv, Fv, Av, dg);
-          } else {
+            return 0;
+          });
+        } else {
+          // the views in grid orientation (row above, row below), whichever way
+          // the strip walks: an energy may keep a value per edge at one of its
+          // ends (a weight of the edge below a site)
+          with_views(R2, R1, R0, selp, [&](auto Pv, auto Sv, auto Fv, auto) {
             if constexpr (JCacheOf<E>::kOn) {
               e.apply_c(Pv, Sv, Fv, col, y1r, gv, R1.jc);
             } else {
               e.apply(Pv, Sv, Fv, col, y1r, gv);
             }
             e.diag(Sv, Fv, dg);
-          }
-          return 0;
-        });
+            return 0;
+          }, dir < 0);
+        }
         const bool act = R1.f & E::ACTIVE;
         const bool prod = y1r >= y0 && y1r < y1;  // uniform
         const unsigned ox = act ? lane_o + ((prod && xupd) ? (unsigned)((y1r - yb) * W) * VB : kBufOutOfRange)
@@ -950,13 +963,15 @@ __device__ __forceinline__ void run(const FusedArgs<E, DAMP, BIG>& a, VG g, int 
         // row y - 2 dir is final: partial of delta = |J u|^2 (+ u.(lambda D) u),
         // and the stores of d, u, p
         const int yo = y - 2 * dir;
+        // grid orientation as for the product (the streaming energy's rows are
+        // symmetric and stay in walk order)
         const T jq = with_views(R3, R2, R1, selu, [&](auto Pv, auto Sv, auto Fv, auto Av) {
           if constexpr (JCacheOf<E>::kOn) {
             return e.jsq_c(Pv, Fv, Av, R2.jc);
           } else {
             return e.jsq(Pv, Sv, Fv, col, yo);
           }
-        });
+        }, !SA::kOn && dir < 0);
         const bool act = R2.f & E::ACTIVE;
         d_acc += (double)((out_lane && (R2.f & E::INGRID)) ? jq : T(0));
         const unsigned o = lane_o + (unsigned)((yo - yb) * W) * VB;

@@ -86,6 +86,7 @@ int energy_channels(int e) {
     case OPT_E_SFS: return ShapeFromShading<float>::C;
     case OPT_E_ARAP_MESH: return ArapMesh<float>::C;
     case OPT_E_ARAP_VOLUME: return ArapVolume<float>::C;
+    case OPT_E_LP_SMOOTH: return LpSmoothGrid<float>::C;
     default: return 0;
   }
 }
@@ -99,6 +100,7 @@ int energy_state_planes(int e) {
     case OPT_E_SFS: return ShapeFromShading<float>::kOwnState;
     case OPT_E_ARAP_MESH: return ArapMesh<float>::kOwnState;
     case OPT_E_ARAP_VOLUME: return ArapVolume<float>::kOwnState;
+    case OPT_E_LP_SMOOTH: return LpSmoothGrid<float>::kOwnState;
     default: return 0;
   }
 }
@@ -140,6 +142,7 @@ int n_params_needed(int e) {
     case OPT_E_SFS: return 16;
     case OPT_E_ARAP_MESH: return 2;
     case OPT_E_ARAP_VOLUME: return 2;
+    case OPT_E_LP_SMOOTH: return 4;
     default: return 0;
   }
 }
@@ -153,6 +156,7 @@ int n_arrays_needed(int e) {
     case OPT_E_SFS: return 4;
     case OPT_E_ARAP_MESH: return 2;
     case OPT_E_ARAP_VOLUME: return 2;
+    case OPT_E_LP_SMOOTH: return 1;
     default: return 0;
   }
 }
@@ -208,6 +212,11 @@ int check_desc(const opt_problem_desc* d, Shape* sh) {
                 n_params_needed(d->energy), d->n_params);
   for (int k = 0; k < n_arrays_needed(d->energy); ++k)
     if (!d->arrays[k]) return fail(OPT_EINVAL, "arrays[%d] is NULL", k);
+  if (d->energy == OPT_E_LP_SMOOTH) {
+    const double p = d->params[2], eps = d->params[3];
+    if (!(p > 0.0 && p <= 2.0)) return fail(OPT_EINVAL, "p = %g is outside (0, 2]", p);
+    if (!(eps > 0.0) || !std::isfinite(eps)) return fail(OPT_EINVAL, "eps = %g must be positive", eps);
+  }
   // the graph Laplacian smooths a float3 per vertex (the grid one a scalar)
   sh->C = d->energy == OPT_E_LAPLACIAN && d->domain == OPT_GRAPH ? LaplacianGraph<float>::C : C;
   sh->state_planes = energy_state_planes(d->energy);
@@ -890,6 +899,22 @@ std::unique_ptr<Impl> make_impl_t(opt_problem* p) {
       e.wr_d = d.params[1];
       return std::unique_ptr<Impl>(new ImplT<LaplacianGrid<T>>(p, e));
     }
+    case OPT_E_LP_SMOOTH: {
+      LpSmoothGrid<T> e;
+      e.W = d.width;
+      e.H = d.height;
+      e.n = p->sh.n;
+      e.A = (const T*)d.arrays[0];
+      e.st = (T*)p->at(p->L.state);
+      e.flags = (uint8_t*)p->at(p->L.flags);
+      e.wf2 = (T)(d.params[0] * d.params[0]);
+      e.wr2 = (T)(d.params[1] * d.params[1]);
+      e.wf_d = d.params[0];
+      e.wr_d = d.params[1];
+      e.p_d = d.params[2];
+      e.eps2_d = d.params[3] * d.params[3];
+      return std::unique_ptr<Impl>(new ImplT<LpSmoothGrid<T>>(p, e));
+    }
     case OPT_E_ARAP_VOLUME: {
       ArapVolume<T> e;
       e.n = p->sh.n;
@@ -1009,6 +1034,13 @@ int check_tuning(const opt_tuning* t) {
     return fail(OPT_EINVAL, "waves_per_simd %d outside [0, 64]", t->waves_per_simd);
   if (t->large_grid_form != 0 && t->large_grid_form != 1)
     return fail(OPT_EINVAL, "large_grid_form %d is not 0 or 1", t->large_grid_form);
+  return OPT_OK;
+}
+
+// A method the energy offers: the IRLS energy takes Gauss-Newton steps only.
+int check_method(const opt_problem_desc* d, const opt_solve_params* sp) {
+  if (d->energy == OPT_E_LP_SMOOTH && sp->method == OPT_LM)
+    return fail(OPT_EUNSUPPORTED, "the l_p smoothing energy is solved by IRLS, which takes Gauss-Newton steps");
   return OPT_OK;
 }
 
@@ -1169,6 +1201,7 @@ int capture_solve(opt_problem* p, void* x, const opt_solve_params* sp, const opt
 // report is asked for, read the scalars and the cost trace back.
 int solve_problem(opt_problem* p, void* x, const opt_solve_params* sp, opt_solve_report* rep) {
   TRY(check_params(sp));
+  TRY(check_method(&p->desc, sp));
   const int K = sp->outer_iters;
   const int lm = sp->method == OPT_LM;
   opt_problem::SolveKey key;
@@ -1428,6 +1461,7 @@ int opt_solve_scratch(const opt_problem_desc* desc, void* unknowns, const opt_so
   Shape sh;
   TRY(check_desc(desc, &sh));
   TRY(check_params(params));
+  TRY(check_method(desc, params));
   const Layout L = make_layout(sh);
   if (L.total > kScratchBytes)
     return fail(OPT_ENOMEM, "the problem needs %zu bytes of workspace; the static scratch holds %zu",

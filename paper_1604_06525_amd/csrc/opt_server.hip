@@ -356,6 +356,7 @@ int opt_server_submit(opt_server* sv, const opt_problem_desc* desc, void* unknow
   Shape sh;
   TRY(check_desc(desc, &sh));
   TRY(check_params(sp));
+  TRY(check_method(desc, sp));
   TRY(harvest(sv, false));
   const size_t need = align_up(make_layout(sh).total);
   size_t slot = (size_t)sv->max_slots;

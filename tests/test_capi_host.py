@@ -51,7 +51,7 @@ def _desc(energy="arap_warp", W=64, H=48, precision="mixed", n_params=None, arra
     for k in range(arrays):
         d.arrays[k] = 0x1000 * (k + 1)  # never dereferenced by these calls
     d.n_params = {"arap_warp": 2, "poisson": 0, "flow": 2, "sfs": 16, "arap_mesh": 2,
-                  "laplacian": 2, "arap_volume": 2}[energy] if n_params is None else n_params
+                  "laplacian": 2, "arap_volume": 2, "lp_smooth": 4}[energy] if n_params is None else n_params
     if V and E:
         d.edges = 0x9000
     return d
@@ -156,9 +156,27 @@ def test_default_params(lib):
         pkg.default_params(no_such=1)
 
 
+@pytest.mark.parametrize("p,eps,code", [
+    (1.0, 0.01, pkg.OPT_OK), (2.0, 1e-3, pkg.OPT_OK), (0.3, 1.0, pkg.OPT_OK),
+    (0.0, 0.01, pkg.OPT_EINVAL), (2.5, 0.01, pkg.OPT_EINVAL), (-1.0, 0.01, pkg.OPT_EINVAL),
+    (1.0, 0.0, pkg.OPT_EINVAL), (1.0, -1.0, pkg.OPT_EINVAL), (float("nan"), 0.01, pkg.OPT_EINVAL),
+])
+def test_lp_smooth_parameters(lib, p, eps, code):
+    """The IRLS energy takes p in (0, 2] and eps > 0 (params 3 and 4)."""
+    d = _desc("lp_smooth", W=40, H=30, arrays=1)
+    d.params[0], d.params[1], d.params[2], d.params[3] = 1.0, 0.5, p, eps
+    rc, b = _ws(lib, d)
+    assert rc == code
+    if code == pkg.OPT_OK:
+        assert b >= 9 * 1200 * 4 + 2 * 1200 * 4  # nine vectors and two weights per pixel
+    d2 = _desc("lp_smooth", V=100, E=0, arrays=1)
+    d2.params[2], d2.params[3] = 1.0, 0.01
+    assert _ws(lib, d2)[0] == pkg.OPT_EUNSUPPORTED  # grid only
+
+
 def test_energy_channels(lib):
-    assert [pkg.energy_channels(e) for e in ("arap_warp", "poisson", "sfs", "flow", "arap_mesh")] == \
-        [3, 4, 1, 2, 6]
+    assert [pkg.energy_channels(e) for e in ("arap_warp", "poisson", "sfs", "flow", "arap_mesh", "lp_smooth")] == \
+        [3, 4, 1, 2, 6, 1]
     assert pkg.energy_channels(99) == 0
 
 

@@ -45,7 +45,8 @@ def _alone(r):
 
 
 def _mix():
-    """Requests of every energy, both precisions, GN and LM, both PCG forms."""
+    """Requests of every energy, both precisions, GN and LM, both PCG forms (the
+    IRLS energy with both)."""
     return [
         _request(w.arap_warp(33, 17, seed=1, n_constraints=12, margin=2), "fp64",
                  method="gn", outer_iters=3, pcg_iters=10),
@@ -62,6 +63,10 @@ def _mix():
                  outer_iters=5, pcg_iters=8),
         _request(w.arap_warp(64, 64, seed=7, n_constraints=40, margin=2), "mixed",
                  method="gn", outer_iters=0, pcg_iters=5),
+        _request(w.lp_smooth(90, 70, seed=8, p=1.0, eps=0.02), "mixed", method="gn", outer_iters=4,
+                 pcg_iters=12),
+        _request(w.lp_smooth(40, 33, seed=9, p=0.8, eps=0.05), "fp64", method="gn", outer_iters=3,
+                 pcg_iters=10, pcg_variant="split"),
     ]
 
 
