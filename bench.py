@@ -524,6 +524,9 @@ ACCURACY = [
     ("flow_1920x1080_gn10x50_fp64", lambda w: w.optical_flow(1920, 1080, seed=4), "fp64", "gn", 10, 50),
     ("poisson_1024x1024_gn10x50_mixed", lambda w: w.poisson_edit(1024, 1024, seed=5), "mixed", "gn", 10, 50),
     ("lp_smooth_1024x1024_gn10x50_mixed", lambda w: w.lp_smooth(1024, 1024, seed=0), "mixed", "gn", 10, 50),
+    ("lp_smooth_1024x1024_gn10x50_fp64", lambda w: w.lp_smooth(1024, 1024, seed=0), "fp64", "gn", 10, 50),
+    ("laplacian_1024x1024_gn10x50_mixed", lambda w: w.laplacian_grid(1024, 1024, seed=0), "mixed", "gn", 10, 50),
+    ("volume_64x64x64_lm10x40_mixed", lambda w: w.arap_volume(64, 64, 64, seed=6), "mixed", "lm", 10, 40),
 ]
 
 
