@@ -40,6 +40,9 @@ struct OpticalFlow {
   static constexpr int kStatePlanes = 2;  // J_fit along u and along v
   static constexpr int kOwnState = 2;
   static constexpr int kRadius = 1;
+  // fused strip walk in FP32: d loaded with its row, start-up peeled (in FP64
+  // the registers they take cost more than the waits they save)
+  static constexpr int kFusedWalk = sizeof(T) == 4 ? 3 : 0;
   enum : uint32_t { ACTIVE = 1, INGRID = 2 };
 
   int W, H, n;

@@ -31,6 +31,7 @@ struct LaplacianGrid {
   static constexpr int kStatePlanes = 0;
   static constexpr int kOwnState = 0;
   static constexpr int kRadius = 1;
+  static constexpr int kFusedWalk = sizeof(T) == 4 ? 1 : 0;  // fused strip walk in FP32: d loaded with its row
   enum : uint32_t { ACTIVE = 1, INGRID = 2 };
 
   int W, H, n;

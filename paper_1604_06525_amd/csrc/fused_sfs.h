@@ -21,7 +21,10 @@
 // and walks it downwards: step k starts row y = y0 - 3 + k, forms p and JB
 // there, the vertical shading terms, G and the smoothness J p one row up, q, the
 // u update and the partial of gamma two rows up (where d, u, p are stored), and
-// the partial of delta three rows up.  Loads cover rows y0-3 .. y1+2.
+// the partial of delta three rows up.  Loads cover rows y0-3 .. y1+2; d comes
+// with its row, and the start-up steps are peeled off the loop (walk_steps).
+// k_y of the walk's rows is formed once per 64 rows, lane i holding that of
+// step i, and read back with a lane read per step.
 #pragma once
 #include "energy_sfs.h"
 #include "kernels.h"
@@ -38,7 +41,7 @@ struct SfsRow {
   T JB, gh, gv, G;    // shading terms along p
   T s0, s1, s2;       // smoothness J p (0 where that residual is not valid)
   T JBu;              // shading derivative along u_{i+1}
-  T ky;               // k_y of this row (one FP64 division per row)
+  T ky;               // k_y of this row
 };
 
 template <typename T, bool DAMP>
@@ -101,6 +104,9 @@ __device__ __forceinline__ void run(const FusedArgs<ShapeFromShading<T>, DAMP>& 
     R.u = Buin.load(ov, 0);
     R.p = Bpin.load(ov, 0);
     R.dg = Bdg.load(ov, 0);
+    // d of a produced row, when this launch updates it
+    const bool prod = y >= y0 && y < y1;
+    R.x = Bx.load(lane_o + ((prod && xupd) ? rs * VB : kBufOutOfRange), 0);
   };
 #pragma unroll
   for (int k = 0; k < kPrefetch; ++k) issue(ring[k], y0 - 3 + k);
@@ -153,8 +159,11 @@ __device__ __forceinline__ void run(const FusedArgs<ShapeFromShading<T>, DAMP>& 
   double g_acc = 0.0, d_acc = 0.0;
 
   if (has_strip) {
-    auto step = [&](auto PH, int k) {
+    // k_y of step k's row is lane k % 64 of kyv (refreshed every 64 steps)
+    T kyv = kyT(y0 - 3 + lane);
+    auto step = [&](auto PH, int k, auto steady) {
       constexpr int ph = decltype(PH)::value;
+      constexpr bool st = decltype(steady)::value;
       Row& R0 = ring[ph];                // row y = y0 - 3 + k
       Row& R1 = ring[(ph + N - 1) % N];  // y - 1
       Row& R2 = ring[(ph + N - 2) % N];  // y - 2
@@ -167,14 +176,15 @@ __device__ __forceinline__ void run(const FusedArgs<ShapeFromShading<T>, DAMP>& 
       // iteration 0), JB and gh (rows y0-2 .. y1+2)
       R0.po = R0.p;
       R0.p = fma(bT, R0.p, R0.u);
-      R0.ky = kyT(y);
-      if (k >= 1) {
+      if (k > 0 && (k & 63) == 0) kyv = kyT(y + lane);  // uniform
+      R0.ky = lane_value(kyv, k & 63);
+      if (st || k >= 1) {
         R0.JB = fma(R0.dB0, R0.p, fma(R0.dBl, from_left(R0.p), R0.dBu * R1.p));
         const uint32_t f = R0.f;
         const T eh = ((f & E::IBE) && (f & E::ER)) ? T(1) : T(0);
         R0.gh = eh * (R0.JB - from_right(R0.JB));
       }
-      if (k >= 2) {
+      if (st || k >= 2) {
         // row y - 1: gv, G, smoothness J p
         const uint32_t f = R1.f;
         const T ev = ((f & E::IBE) && (f & E::EC)) ? T(1) : T(0);
@@ -186,14 +196,8 @@ __device__ __forceinline__ void run(const FusedArgs<ShapeFromShading<T>, DAMP>& 
         R1.s0 = vs ? T(4) * kxc * p0 - kxl * pl - kxc * pu - kxr * pr - kxc * pd : T(0);
         R1.s1 = vs ? T(4) * kyb * p0 - kyb * pl - kyu * pu - kyb * pr - kyd * pd : T(0);
         R1.s2 = vs ? T(4) * p0 - pl - pu - pr - pd : T(0);
-        // d of row y - 1 is fetched now, to be updated in the next step
-        const bool act1 = f & E::ACTIVE;
-        const bool prod1 = y - 1 >= y0 && y - 1 < y1;
-        const unsigned ox = act1 ? lane_o + ((prod1 && xupd) ? (unsigned)((y - 1) * W) * VB : kBufOutOfRange)
-                                 : kBufOutOfRange;
-        R1.x = Bx.load(ox, 0);
       }
-      if (k >= 4) {
+      if (st || k >= 4) {
         // row y - 2 (rows y0-1 .. y1): q = J^T J p (+ lambda D p), u_{i+1},
         // gamma, stores
         const int y2 = y - 2;
@@ -229,7 +233,7 @@ __device__ __forceinline__ void run(const FusedArgs<ShapeFromShading<T>, DAMP>& 
         buf_storev<1, kFusedStoreAux<T>>(Buout, o, 0, &R2.u);
         buf_storev<1, kFusedStoreAux<T>>(Bpout, o, 0, &pv);
       }
-      if (k >= 6) {
+      if (st || k >= 6) {
         // row y - 3 (a produced row) is final: partial of delta = |J u|^2 over
         // its residuals
         const int y3 = y - 3;
@@ -250,11 +254,7 @@ __device__ __forceinline__ void run(const FusedArgs<ShapeFromShading<T>, DAMP>& 
         d_acc += (double)((out_lane && prod) ? ds : T(0));
       }
     };
-    for (int k = 0; k < K; k += N) {
-      unroll_seq(std::make_integer_sequence<int, N>{}, [&](auto PH) {
-        if (k + decltype(PH)::value < K) step(PH, k + decltype(PH)::value);
-      });
-    }
+    walk_steps<N, 6, true>(K, step);
   }
   double gs, ds;
   block_sum2(g_acc, d_acc, &gs, &ds);

@@ -605,6 +605,17 @@ __device__ __forceinline__ double from_right(double v) {
 __device__ __forceinline__ uint32_t from_left(uint32_t v) { return dpp_from_left(v); }
 __device__ __forceinline__ uint32_t from_right(uint32_t v) { return dpp_from_right(v); }
 
+// The value lane i (uniform, below 64) holds, in every lane.
+__device__ __forceinline__ float lane_value(float v, int i) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, v), i));
+}
+__device__ __forceinline__ double lane_value(double v, int i) {
+  const uint64_t b = __builtin_bit_cast(uint64_t, v);
+  const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)b, i);
+  const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(b >> 32), i);
+  return __builtin_bit_cast(double, ((uint64_t)hi << 32) | lo);
+}
+
 // One wave per strip of 64 columns: 60 produced, 2 halo columns on each side.
 constexpr int kStripCols = 60;
 
@@ -741,6 +752,61 @@ __device__ __forceinline__ void unroll_seq(std::integer_sequence<int, I...>, F f
 template <typename T>
 constexpr int kPrefetchOf = sizeof(T) > 4 ? 2 : 4;
 
+// How an energy's strip walk is laid out (chosen per energy from measurement:
+// both choices cost registers, and with them waves per SIMD).
+//  * kPrefetchD: d of a produced row is loaded with the row's other data, so
+//    the update of d waits on no load issued later (else it is loaded one step
+//    before it is updated, and the wait for it also drains the rows in flight).
+//  * kPeel: the steps before the pipeline is full run apart from the loop (see
+//    walk_steps).
+// An energy sets them with `static constexpr int kFusedWalk` (bit 0: kPrefetchD,
+// bit 1: kPeel).
+template <class E, class = void>
+struct FusedWalkOf {
+  static constexpr bool kPrefetchD = false, kPeel = false;
+};
+template <class E>
+struct FusedWalkOf<E, std::void_t<decltype(E::kFusedWalk)>> {
+  static constexpr bool kPrefetchD = (E::kFusedWalk & 1) != 0, kPeel = (E::kFusedWalk & 2) != 0;
+};
+
+// The K steps of a strip walk; step(PH, k, steady) gets the ring slot k % N as
+// a constant.  Plain form: groups of N steps, each step tested against K.
+// Peeled form: steps 0 .. P-1 one at a time (their tests for a pipeline not yet
+// full fold away), then groups of N steps with no test at all, then the rest.
+// In the plain form a loop iteration has branches whose paths carry different
+// numbers of loads in flight; the wait after such a merge drains every load,
+// prefetched rows included.  steady is true from step P on in the peeled form
+// and always false in the plain one.
+template <int N, int P, bool PEEL, class Step>
+__device__ __forceinline__ void walk_steps(int K, Step step) {
+  static_assert(P < N, "the start-up steps fit one turn of the ring");
+  if constexpr (PEEL) {
+    unroll_seq(std::make_integer_sequence<int, P>{}, [&](auto J) {
+      constexpr int j = decltype(J)::value;
+      if (j < K) step(std::integral_constant<int, j % N>{}, j, std::false_type{});
+    });
+    int k = P;
+    for (; k + N <= K; k += N) {
+      unroll_seq(std::make_integer_sequence<int, N>{}, [&](auto J) {
+        constexpr int j = decltype(J)::value;
+        step(std::integral_constant<int, (P + j) % N>{}, k + j, std::true_type{});
+      });
+    }
+    unroll_seq(std::make_integer_sequence<int, N - 1>{}, [&](auto J) {
+      constexpr int j = decltype(J)::value;
+      if (k + j < K) step(std::integral_constant<int, (P + j) % N>{}, k + j, std::true_type{});
+    });
+  } else {
+    for (int k = 0; k < K; k += N) {
+      unroll_seq(std::make_integer_sequence<int, N>{}, [&](auto J) {
+        constexpr int j = decltype(J)::value;
+        if (k + j < K) step(std::integral_constant<int, j>{}, k + j, std::false_type{});
+      });
+    }
+  }
+}
+
 template <class E, bool DAMP, bool BIG>
 __device__ __forceinline__ void run(const FusedArgs<E, DAMP, BIG>& a, VG g, int iter) {
   using T = typename E::Real;
@@ -807,6 +873,7 @@ __device__ __forceinline__ void run(const FusedArgs<E, DAMP, BIG>& a, VG g, int 
   const unsigned lane_o = out_lane ? (unsigned)col * VB : kBufOutOfRange;
   // The row of step k lives in ring slot k % N; its loads are issued
   // kPrefetch steps before it is started.
+  using FW = FusedWalkOf<E>;
   Row ring[N];
   auto issue = [&](Row& R, int y) {
     const bool in = y >= ylo && y <= yhi;
@@ -820,6 +887,11 @@ __device__ __forceinline__ void run(const FusedArgs<E, DAMP, BIG>& a, VG g, int 
     const unsigned o = lane_v + (in ? rs * VB : kBufOutOfRange);
     buf_loadv<C>(Buin, o, 0, R.u);
     buf_loadv<C>(Bpin, o, 0, R.p);
+    if constexpr (FW::kPrefetchD) {
+      // d of a produced row, when this launch updates it
+      const bool prod = y >= y0 && y < y1;
+      buf_loadv<C>(Bx, lane_o + ((prod && xupd) ? rs * VB : kBufOutOfRange), 0, R.x);
+    }
   };
   // The first rows do not depend on alpha and beta: fetch them while the
   // previous launch's partial sums are reduced.
@@ -884,8 +956,9 @@ __device__ __forceinline__ void run(const FusedArgs<E, DAMP, BIG>& a, VG g, int 
     using SA = StreamApplyOf<E>;
     typename SA::Carry cprev{};  // residuals of the edge (y - 2 dir, y - dir)
     auto shift = [](T v, int di) { return di > 0 ? from_right(v) : from_left(v); };
-    auto step = [&](auto PH, int k) {
+    auto step = [&](auto PH, int k, auto steady) {
       constexpr int ph = decltype(PH)::value;
+      constexpr bool st = decltype(steady)::value;
       Row& R0 = ring[ph];                // row y = ybeg + dir k
       Row& R1 = ring[(ph + N - 1) % N];  // y - dir
       Row& R2 = ring[(ph + N - 2) % N];  // y - 2 dir
@@ -903,12 +976,13 @@ __device__ __forceinline__ void run(const FusedArgs<E, DAMP, BIG>& a, VG g, int 
       R0.aw = (R0.f & E::ACTIVE) ? T(1) : T(0);
       typename SA::Carry cnext{};  // residuals of the edge (y - dir, y)
       if constexpr (SA::kOn) {
-        if (k >= 1) cnext = e.edge_next(R1, R0);
+        if (st || k >= 1) cnext = e.edge_next(R1, R0);
       }
-      if (k >= 2) {
+      if (st || k >= 2) {
         // on row y - dir: s = A p (with the LM damping), the diagonal M from the
         // state, u_{i+1} = u_i - alpha M^-1 s and the partial of gamma = sum M u^2;
-        // d of that row is fetched now, to be updated in the next step
+        // d of that row is fetched now (unless it came with the row), to be
+        // updated in the next step
         const int y1r = y - dir;
         T gv[C], dg[C];
         if constexpr (SA::kOn) {
@@ -933,9 +1007,11 @@ __device__ __forceinline__ void run(const FusedArgs<E, DAMP, BIG>& a, VG g, int 
         }
         const bool act = R1.f & E::ACTIVE;
         const bool prod = y1r >= y0 && y1r < y1;  // uniform
-        const unsigned ox = act ? lane_o + ((prod && xupd) ? (unsigned)((y1r - yb) * W) * VB : kBufOutOfRange)
-                                : kBufOutOfRange;
-        buf_loadv<C>(Bx, ox, 0, R1.x);
+        if constexpr (!FW::kPrefetchD) {
+          const unsigned ox = act ? lane_o + ((prod && xupd) ? (unsigned)((y1r - yb) * W) * VB : kBufOutOfRange)
+                                  : kBufOutOfRange;
+          buf_loadv<C>(Bx, ox, 0, R1.x);
+        }
         T gs = 0, dd = 0;
 #pragma unroll
         for (int c = 0; c < C; ++c) {
@@ -959,7 +1035,7 @@ __device__ __forceinline__ void run(const FusedArgs<E, DAMP, BIG>& a, VG g, int 
         if constexpr (DAMP) d_acc += (double)((out_lane && prod && (R1.f & E::INGRID)) ? dd : T(0));
       }
       if constexpr (SA::kOn) cprev = cnext;
-      if (k >= 4) {
+      if (st || k >= 4) {
         // row y - 2 dir is final: partial of delta = |J u|^2 (+ u.(lambda D) u),
         // and the stores of d, u, p
         const int yo = y - 2 * dir;
@@ -988,11 +1064,7 @@ __device__ __forceinline__ void run(const FusedArgs<E, DAMP, BIG>& a, VG g, int 
         buf_storev<C, kFusedStoreAux<T>>(Bpout, o, 0, pv);
       }
     };
-    for (int k = 0; k < K; k += N) {
-      unroll_seq(std::make_integer_sequence<int, N>{}, [&](auto PH) {
-        if (k + decltype(PH)::value < K) step(PH, k + decltype(PH)::value);
-      });
-    }
+    walk_steps<N, 4, FW::kPeel>(K, step);
   }
   double gs, ds;
   block_sum2(g_acc, d_acc, &gs, &ds);

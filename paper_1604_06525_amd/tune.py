@@ -126,9 +126,16 @@ def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--out", default=DEFAULT_PATH)
     ap.add_argument("--quick", action="store_true", help="mixed precision, ARAP warp only")
+    ap.add_argument("--energies", default="", help="comma list: retune these energies only, keeping the "
+                    "other energies' entries of --base")
+    ap.add_argument("--base", default=DEFAULT_PATH)
     a = ap.parse_args()
     if a.quick:
         entries = autotune(energies=("arap_warp",), precisions=("mixed",))
+    elif a.energies:
+        names = tuple(a.energies.split(","))
+        kept = [e for e in load(a.base) if e["energy"] not in names]
+        entries = kept + autotune(energies=names)
     else:
         entries = autotune()
     save(entries, a.out)
