@@ -116,8 +116,9 @@ __device__ __forceinline__ void run(const GraphFusedArgs<E, DAMP>& a, VG g, int 
   // with stage A.  A row's unused id entries are 0, so a stage-B load past the
   // rings reads vertex 0 and is not used.
   struct Pre {
-    int k0, k1;
-    uint32_t fl;
+    int n1, n2;     // ring sizes of the chunk
+    int kb, r0, r1; // CSR offsets: the chunk's first vertex, this vertex and the next
+    uint8_t fl;
     T u[C], po[C], xv[C], dg[C];
     typename E::GRaw raw;
     int id0, id1;
@@ -127,30 +128,35 @@ __device__ __forceinline__ void run(const GraphFusedArgs<E, DAMP>& a, VG g, int 
     GfInt4 cs, r1s, r1o;  // 16-byte blocks t of the row's slot lists
   };
   auto id_of = [&](int chunk, int j) { return rows[(size_t)chunk * kGfRow + kGfIds + j]; };
+  // Both stages are free of branches and of arithmetic on what they load: a
+  // value used (or a path merged) while loads are in flight waits for all of
+  // them.  A thread past the graph's end reads the chunk's first vertex (its
+  // values are not used), p_{i-1} and d are read whether or not they are
+  // needed (selected where they are used), and the raw CSR offsets are kept.
   auto load_a = [&](int chunk, Pre& P) {
     const int v0 = chunk * kBlock, v = v0 + t;
-    const bool in = v < n;
+    const int vl = v < n ? v : v0;
     const auto* __restrict__ row = rows + (size_t)chunk * kGfRow;
     P.id1 = row[kGfIds + kBlock + t];
-    const int kb = rp[v0];
-    P.k0 = in ? rp[v] - kb : 0;
-    P.k1 = in ? rp[v + 1] - kb : 0;
-    P.fl = in ? (uint32_t)flags[v] : 0u;
-    if (in) {
+    P.n1 = row[0];
+    P.n2 = row[1];
+    P.kb = rp[v0];
+    P.r0 = rp[vl];
+    P.r1 = rp[vl + 1];
+    P.fl = flags[vl];
 #pragma unroll
-      for (int c = 0; c < C; ++c) {
-        const size_t o = vix<C>(c, v);
-        P.u[c] = uin[o];
-        P.po[c] = read_pold ? pin[o] : T(0);
-        P.xv[c] = xupd ? x[o] : T(0);
-        P.dg[c] = diag[o];
-      }
-      P.raw = e.graw(v);
+    for (int c = 0; c < C; ++c) {
+      const size_t o = vix<C>(c, vl);
+      P.u[c] = uin[o];
+      P.po[c] = pin[o];
+      P.xv[c] = x[o];
+      P.dg[c] = diag[o];
     }
+    P.raw = e.graw(vl);
     using G4 = const __attribute__((address_space(1))) GfInt4;
     P.cs = ((G4*)(row + kGfCsI))[t];
     P.r1s = ((G4*)(row + kGfRsI))[t];
-    if (t < kGfRoN) P.r1o = ((G4*)(row + kGfRoI))[t];
+    P.r1o = ((G4*)(row + kGfRoI))[t < kGfRoN ? t : kGfRoN - 1];
   };
   auto load_b = [&](Pre& P) {
     const int id = P.id0;
@@ -159,21 +165,21 @@ __device__ __forceinline__ void run(const GraphFusedArgs<E, DAMP>& a, VG g, int 
     for (int c = 0; c < C; ++c) {
       const size_t o = vix<C>(c, id);
       P.u0[c] = uin[o];
-      P.p0[c] = read_pold ? pin[o] : T(0);
+      P.p0[c] = pin[o];
     }
     P.raw0 = e.graw(id);
   };
   // The first chunk's loads do not depend on alpha and beta: they go out
   // before the previous launch's partial sums are reduced.
+  // (Chunk numbers past the last are read as the last chunk, whose loads are
+  // then not used: a graph has at least one vertex, so nch >= 1.)
   const int first = unit_of_block(g);
+  const int last = nch - 1;
   Pre P;
-  int id_next = 0;  // outside slot t of the chunk after P's
-  if (first < nch) {
-    P.id0 = id_of(first, t);
-    load_a(first, P);
-    load_b(P);
-    if (first + g.nb < nch) id_next = id_of(first + g.nb, t);
-  }
+  P.id0 = id_of(min(first, last), t);
+  load_a(min(first, last), P);
+  load_b(P);
+  int id_next = id_of(min(first + g.nb, last), t);  // outside slot t of the chunk after P's
   const double* part_in = pick(a.b.part, (iter + 1) & 1);
   double* part_out = pick(a.b.part, iter & 1);
   double alpha = 0.0, beta = 0.0;
@@ -239,12 +245,15 @@ __device__ __forceinline__ void run(const GraphFusedArgs<E, DAMP>& a, VG g, int 
     const int v0 = chunk * kBlock, v = v0 + t;
     const bool in = v < n;
     const auto* __restrict__ row = rows + (size_t)chunk * kGfRow;
-    const int n1 = row[0], n2 = row[1];
+    const int n1 = P.n1, n2 = P.n2;
     // ---- phase 1: records and lists into LDS
     T uw[NH];  // u_i of R1 vertex t
     uint32_t flw = 0;
     if (t < n1 + n2) {
-      stage_out(t, P.f0, P.u0, P.p0, P.raw0);
+      T p0[C];
+#pragma unroll
+      for (int c = 0; c < C; ++c) p0[c] = read_pold ? P.p0[c] : T(0);
+      stage_out(t, P.f0, P.u0, p0, P.raw0);
       if (t < n1) {
         flw = P.f0;
 #pragma unroll
@@ -267,15 +276,15 @@ __device__ __forceinline__ void run(const GraphFusedArgs<E, DAMP>& a, VG g, int 
     sm.r1s[t] = P.r1s;
     if (t < kGfRoN) sm.r1o[t] = P.r1o;
     // the chunk's own vertex, out of the prefetch registers
-    const int k0 = P.k0, k1 = P.k1;
-    const uint32_t fl = P.fl;
+    const int k0 = in ? P.r0 - P.kb : 0, k1 = in ? P.r1 - P.kb : 0;
+    const uint32_t fl = in ? (uint32_t)P.fl : 0u;
     const bool act = in && (fl & E::ACTIVE);
     T uv[C], po[C], xv[C], dgv[C];
 #pragma unroll
     for (int c = 0; c < C; ++c) {
       uv[c] = P.u[c];
-      po[c] = P.po[c];
-      xv[c] = P.xv[c];
+      po[c] = read_pold ? P.po[c] : T(0);
+      xv[c] = xupd ? P.xv[c] : T(0);
       dgv[c] = P.dg[c];
     }
     typename E::GOwn own{};
@@ -295,7 +304,7 @@ __device__ __forceinline__ void run(const GraphFusedArgs<E, DAMP>& a, VG g, int 
       P.id0 = id_next;
       load_a(next, P);
       load_b(P);
-      if (next + g.nb < nch) id_next = id_of(next + g.nb, t);
+      id_next = id_of(min(next + g.nb, last), t);
     }
     // ---- phase 2: s, M, u_{i+1} on C (all components) and on R1 (halo)
     // (vector types may alias any other type, so reading the blocks as 16-bit
