@@ -365,6 +365,37 @@ struct ArapMesh {
 #pragma unroll
     for (int c = 0; c < 3; ++c) g[c] = (fl & (FIT0 << c)) ? fma(wf2, p[c], gO[c]) : gO[c];
   }
+  // gapply and the vertex's diagonal, formed from the same edges (d d^T summed
+  // in incidence order and diag_from: init's arithmetic, so the same bits
+  // init stored, without reading them).
+  template <class RA, class NA>
+  __device__ __forceinline__ void gapply_d(const GOwn& o, const T* p, const T* rv, int, RA R, NA NB, int k0,
+                                           int k1, uint32_t fl, T* g, T* dg) const {
+    const T wr2 = wr * wr, wf2 = wf * wf;
+    T gO[3] = {}, Mv[9] = {}, Sdd[6] = {};
+#pragma unroll 2
+    for (int k = k0; k < k1; ++k) {
+      T d[3], j1[3];
+      edge_o(p, rv + 3, o.U, R, NB(k), wr2, gO, d, j1);
+#pragma unroll
+      for (int i = 0; i < 3; ++i)
+#pragma unroll
+        for (int j = 0; j < 3; ++j) Mv[3 * i + j] = fma(j1[i], d[j], Mv[3 * i + j]);
+      add_ddt(Sdd, d);
+    }
+#pragma unroll
+    for (int q = 0; q < 3; ++q) {
+      T acc = T(0);
+#pragma unroll
+      for (int i = 0; i < 3; ++i)
+#pragma unroll
+        for (int j = 0; j < 3; ++j) acc = fma(o.G[j][q][i], Mv[3 * i + j], acc);
+      g[3 + q] = -wr2 * acc;
+    }
+#pragma unroll
+    for (int c = 0; c < 3; ++c) g[c] = (fl & (FIT0 << c)) ? fma(wf2, p[c], gO[c]) : gO[c];
+    diag_from(o.G, Sdd, k1 - k0, fl, dg);
+  }
   // The offset part of gapply at the staged vertex in slot sv (R1 of a chunk),
   // and of the diagonal (as init's diag_from gives it).
   template <class RA, class NA>

@@ -243,6 +243,12 @@ struct LaplacianGraph {
     T dg[3];
     gapply_h(sv, R, NB, k0, k1, fl, g, dg);
   }
+  // the product and the diagonal (init's value, formed the same way)
+  template <class RA, class NA>
+  __device__ __forceinline__ void gapply_d(const GOwn&, const T*, const T*, int sv, RA R, NA NB, int k0, int k1,
+                                           uint32_t fl, T* g, T* dg) const {
+    gapply_h(sv, R, NB, k0, k1, fl, g, dg);
+  }
   // w_fit^2 |u_v|^2 + half of w_reg^2 |u_v - u_s|^2 for each listed edge at v
   // (each edge's residual is shared by its two ends).
   template <class RA, class UA, class NA>

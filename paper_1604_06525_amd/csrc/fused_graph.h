@@ -19,18 +19,19 @@
 // gapply_h), so delta is the one of the stored u_{i+1}, bit for bit.
 //
 // Per chunk, three phases separated by barriers:
-//   1. each thread loads its vertex of C (u_i, p_{i-1}, flags, state, d and
-//      the diagonal init stored) and the outside vertices t, t + kBlock, ...
-//      of R1 and R2, forms p_i and the energy's record (kRec values) of each
-//      into LDS;
+//   1. each thread loads its vertex of C (u_i, p_{i-1}, flags, state and d)
+//      and the outside vertices t, t + kBlock, ... of R1 and R2, forms p_i and
+//      the energy's record (kRec values) of each into LDS;
 //   2. s, the diagonal M and u_{i+1} on its vertex of C (all components) and on
 //      R1 vertex t (the kHalo components delta reads); the C vertex's p_i,
-//      u_{i+1} and d are final and stored here;
+//      u_{i+1} and d are final and stored here.  The diagonal is formed from
+//      the staged records with init's arithmetic (the bits init stored, which
+//      are not read);
 //   3. its vertex's share of |J u_{i+1}|^2 (energy gjsq).
 // The energy provides: kGraphFused, kRec, kHalo (a record starts with p's first
-// kHalo components), GOwn gown(v), grec(own, p, rec), gapply (the full
-// product), gapply_h (the first kHalo components of the product and of the
-// diagonal, the latter with the bits init stores) and gjsq.
+// kHalo components), GOwn gown(v), grec(own, p, rec), gapply_d (the full
+// product and the diagonal), gapply_h (the first kHalo components of both) and
+// gjsq; the diagonals have the bits init stores.
 #pragma once
 #include "kernels.h"
 
@@ -95,7 +96,6 @@ __device__ __forceinline__ void run(const GraphFusedArgs<E, DAMP>& a, VG g, int 
   auto* __restrict__ uout = gmem(pick(a.b.u, (iter + 1) & 1));
   auto* __restrict__ pout = gmem(pick(a.b.p, iter & 1));
   auto* __restrict__ x = gmem(a.b.x);
-  const auto* __restrict__ diag = gmem(a.b.diag);
   const auto* __restrict__ flags = gmem(e.flags);
   const auto* __restrict__ rp = gmem(e.rp);
   const auto* __restrict__ rows = gmem(a.gl.rows);
@@ -119,7 +119,7 @@ __device__ __forceinline__ void run(const GraphFusedArgs<E, DAMP>& a, VG g, int 
     int n1, n2;     // ring sizes of the chunk
     int kb, r0, r1; // CSR offsets: the chunk's first vertex, this vertex and the next
     uint8_t fl;
-    T u[C], po[C], xv[C], dg[C];
+    T u[C], po[C], xv[C];
     typename E::GRaw raw;
     int id0, id1;
     uint32_t f0;
@@ -128,6 +128,10 @@ __device__ __forceinline__ void run(const GraphFusedArgs<E, DAMP>& a, VG g, int 
     GfInt4 cs, r1s, r1o;  // 16-byte blocks t of the row's slot lists
   };
   auto id_of = [&](int chunk, int j) { return rows[(size_t)chunk * kGfRow + kGfIds + j]; };
+  // p_{i-1} and d are read from u_i's addresses when they are not needed (no
+  // extra HBM traffic; the values are not used).
+  const auto* __restrict__ pin_l = read_pold ? pin : uin;
+  const auto* __restrict__ x_l = xupd ? x : uin;
   // Both stages are free of branches and of arithmetic on what they load: a
   // value used (or a path merged) while loads are in flight waits for all of
   // them.  A thread past the graph's end reads the chunk's first vertex (its
@@ -148,9 +152,8 @@ __device__ __forceinline__ void run(const GraphFusedArgs<E, DAMP>& a, VG g, int 
     for (int c = 0; c < C; ++c) {
       const size_t o = vix<C>(c, vl);
       P.u[c] = uin[o];
-      P.po[c] = pin[o];
-      P.xv[c] = x[o];
-      P.dg[c] = diag[o];
+      P.po[c] = pin_l[o];
+      P.xv[c] = x_l[o];
     }
     P.raw = e.graw(vl);
     using G4 = const __attribute__((address_space(1))) GfInt4;
@@ -165,7 +168,7 @@ __device__ __forceinline__ void run(const GraphFusedArgs<E, DAMP>& a, VG g, int 
     for (int c = 0; c < C; ++c) {
       const size_t o = vix<C>(c, id);
       P.u0[c] = uin[o];
-      P.p0[c] = pin[o];
+      P.p0[c] = pin_l[o];
     }
     P.raw0 = e.graw(id);
   };
@@ -279,13 +282,12 @@ __device__ __forceinline__ void run(const GraphFusedArgs<E, DAMP>& a, VG g, int 
     const int k0 = in ? P.r0 - P.kb : 0, k1 = in ? P.r1 - P.kb : 0;
     const uint32_t fl = in ? (uint32_t)P.fl : 0u;
     const bool act = in && (fl & E::ACTIVE);
-    T uv[C], po[C], xv[C], dgv[C];
+    T uv[C], po[C], xv[C];
 #pragma unroll
     for (int c = 0; c < C; ++c) {
       uv[c] = P.u[c];
       po[c] = read_pold ? P.po[c] : T(0);
       xv[c] = xupd ? P.xv[c] : T(0);
-      dgv[c] = P.dg[c];
     }
     typename E::GOwn own{};
     if (in) own = e.gown_of(P.raw);
@@ -315,12 +317,9 @@ __device__ __forceinline__ void run(const GraphFusedArgs<E, DAMP>& a, VG g, int 
     auto NBc = [&](int k) -> int { return cs16[k]; };
     T un[C];
     {
-      // the diagonal init stored (the same bits diag_from gives on R1 below)
       T sv[C], dg[C];
       if (act) {
-        e.gapply(own, p, rv, t, R, NBc, k0, k1, fl, sv);
-#pragma unroll
-        for (int c = 0; c < C; ++c) dg[c] = dgv[c];
+        e.gapply_d(own, p, rv, t, R, NBc, k0, k1, fl, sv, dg);
       } else {
 #pragma unroll
         for (int c = 0; c < C; ++c) sv[c] = dg[c] = T(0);
