@@ -137,8 +137,10 @@ typedef enum { OPT_GN = 0, OPT_LM = 1 } opt_method;
  *   iteration multiplies by it twice (y = J p, then q = J^T y, J^T read through
  *   per-unknown lists of J's entries), with the textbook recurrence.  Needs a
  *   problem created with desc.materialize = 1 (OPT_EINVAL otherwise); built for
- *   ARAP warping on a grid.  For comparing matrix-free and materialised
- *   products; a server runs such requests in the split form.
+ *   ARAP warping and shape from shading on a grid (for the latter, the fully
+ *   materialised strategy of Sec. 8.3: J's rows come from the stored lighting
+ *   partials).  For comparing matrix-free and materialised products; a server
+ *   runs such requests in the split form.
  */
 typedef enum { OPT_PCG_FUSED = 0, OPT_PCG_SPLIT = 1, OPT_PCG_MATERIALIZED = 2 } opt_pcg_variant;
 

@@ -325,6 +325,95 @@ struct ShapeFromShading {
     g[0] = acc;
   }
 
+  // Materialised Jacobian (evalJ, Sec. 7 and the fully materialised strategy
+  // of Sec. 8.3): the rows anchored at pixel s, kJSlots entries each (column =
+  // pixel, -1 for none, value 0 there): row 0 the depth prior, 1 and 2 the
+  // shading differences gh and gv, 3..5 the three smoothness components.  Each
+  // entry is d r / d X from the stored lighting partials, summed where a row
+  // reads a pixel twice; columns of excluded pixels are dropped.  A row that
+  // exists has all its pixels on the grid (IBE keeps them one pixel inside).
+  static constexpr int kJRows = 6, kJSlots = 5, kJTSlots = 26;
+  __device__ __forceinline__ void eval_j(int s, T* __restrict__ val, int* __restrict__ col) const {
+    const int i = s % W, j = s / W;
+    const uint32_t f = flags[s];
+    auto B = [&](int site, int k) -> T { return st[(size_t)site * 4 + k]; };
+    auto put = [&](int row, int slot, int site, bool on, T v) {
+      const bool keep = on && (flags[site] & ACTIVE);
+      col[row * kJSlots + slot] = keep ? site : -1;
+      val[row * kJSlots + slot] = keep ? v : T(0);
+    };
+    for (int k = 0; k < kJRows * kJSlots; ++k) {
+      col[k] = -1;
+      val[k] = T(0);
+    }
+    put(0, 0, s, (f & ACTIVE) != 0, sw_pT);
+    const bool rh = (f & IBE) && (f & ER), rv = (f & IBE) && (f & EC);
+    if (rh) {
+      put(1, 0, s, true, sw_gT * (B(s, 1) - B(s + 1, 2)));
+      put(1, 1, s - 1, true, sw_gT * B(s, 2));
+      put(1, 2, s - W, true, sw_gT * B(s, 3));
+      put(1, 3, s + 1, true, -sw_gT * B(s + 1, 1));
+      put(1, 4, s + 1 - W, true, -sw_gT * B(s + 1, 3));
+    }
+    if (rv) {
+      put(2, 0, s, true, sw_gT * (B(s, 1) - B(s + W, 3)));
+      put(2, 1, s - 1, true, sw_gT * B(s, 2));
+      put(2, 2, s - W, true, sw_gT * B(s, 3));
+      put(2, 3, s + W, true, -sw_gT * B(s + W, 1));
+      put(2, 4, s + W - 1, true, -sw_gT * B(s + W, 2));
+    }
+    if (f & VS) {
+      const T kxa = T((i - ux) / fx), kxl = T((i - 1 - ux) / fx), kxr = T((i + 1 - ux) / fx);
+      const T kyb = T((j - uy) / fy), kyu = T((j - 1 - uy) / fy), kyd = T((j + 1 - uy) / fy);
+      const T c0[5] = {T(4) * kxa, -kxl, -kxa, -kxr, -kxa};  // s, s-1, s-W, s+1, s+W
+      const T c1[5] = {T(4) * kyb, -kyb, -kyu, -kyb, -kyd};
+      const T c2[5] = {T(4), T(-1), T(-1), T(-1), T(-1)};
+      const int at[5] = {s, s - 1, s - W, s + 1, s + W};
+#pragma unroll
+      for (int t = 0; t < 5; ++t) {
+        put(3, t, at[t], true, sw_sT * c0[t]);
+        put(4, t, at[t], true, sw_sT * c1[t]);
+        put(5, t, at[t], true, sw_sT * c2[t]);
+      }
+    }
+  }
+
+  // The entries of J's column s (kJTSlots indices into eval_j's entries, -1
+  // for none): for each row type, the anchor pixels whose row reads s and the
+  // slot s takes there (the slot tables of eval_j read backwards).  Anchors off
+  // the grid are skipped; an anchor whose row is absent holds a 0 entry there.
+  __device__ __forceinline__ void eval_jt(int s, int* __restrict__ jt) const {
+    const int i = s % W, j = s / W;
+    auto at = [](int site, int row, int slot) { return (site * kJRows + row) * kJSlots + slot; };
+    int m = 0;
+    auto add = [&](int di, int dj, int row, int slot) {
+      const int a = i + di, b = j + dj;
+      jt[m++] = (a >= 0 && a < W && b >= 0 && b < H) ? at(s + dj * W + di, row, slot) : -1;
+    };
+    add(0, 0, 0, 0);
+    // gh anchored at s, s+1, s+W, s-1, s-1+W (slots 0..4)
+    add(0, 0, 1, 0);
+    add(1, 0, 1, 1);
+    add(0, 1, 1, 2);
+    add(-1, 0, 1, 3);
+    add(-1, 1, 1, 4);
+    // gv anchored at s, s+1, s+W, s-W, s+1-W
+    add(0, 0, 2, 0);
+    add(1, 0, 2, 1);
+    add(0, 1, 2, 2);
+    add(0, -1, 2, 3);
+    add(1, -1, 2, 4);
+    // smoothness anchored at s, s+1, s+W, s-1, s-W
+#pragma unroll
+    for (int row = 3; row < 6; ++row) {
+      add(0, 0, row, 0);
+      add(1, 0, row, 1);
+      add(0, 1, row, 2);
+      add(-1, 0, row, 3);
+      add(0, -1, row, 4);
+    }
+  }
+
   template <class XA, class DA>
   __device__ __forceinline__ double model(XA X, DA Dl, int s) const {
     const int i = s % W, j = s / W;

@@ -130,6 +130,12 @@ bool mat_dims(int e, int domain, int* rows, int* slots, int* tslots) {
     *tslots = ArapWarp<float>::kJTSlots;
     return true;
   }
+  if (e == OPT_E_SFS && domain == OPT_GRID2D) {
+    *rows = ShapeFromShading<float>::kJRows;
+    *slots = ShapeFromShading<float>::kJSlots;
+    *tslots = ShapeFromShading<float>::kJTSlots;
+    return true;
+  }
   return false;
 }
 

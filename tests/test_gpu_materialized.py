@@ -1,6 +1,8 @@
 """The materialised PCG form (OPT_PCG_MATERIALIZED; the evalJ alternative of
 Sec. 7): J evaluated into the workspace once per linearisation, each PCG
-iteration y = J p then q = J^T y, with the textbook recurrence.
+iteration y = J p then q = J^T y, with the textbook recurrence.  ARAP warping,
+and shape from shading (the fully materialised end of Sec. 8.3's strategies:
+its J rows are built from the stored lighting partials).
 
 Parity: its PCG iterates and whole GN/LM solves against the FP64 oracle (the
 oracle-spread rule for PCG, 1e-9 relative cost for solves) and against the
@@ -98,6 +100,63 @@ def test_graph_replay_of_a_materialized_solve():
     assert all(torch.equal(out[0], t) for t in out[1:])
 
 
+SFS_LIGHT = (0.5, 0.07, -0.3, 0.04, 0.03, -0.02, 0.05, 0.06, -0.04)
+
+
+def _sfs(W=41, H=33, seed=2):
+    """Shape from shading with distinct lighting coefficients, f_x != f_y, an
+    off-centre principal point, a hole of excluded pixels and zeroed edge masks."""
+    d = w.shape_from_shading(W, H, seed=seed, focal=(0.95 * W, 1.1 * W),
+                             center=((W - 1) / 2 + 1.3, (H - 1) / 2 - 0.7), lighting=SFS_LIGHT,
+                             invalid="hole", edge_zero_frac=0.1)
+    rng = np.random.default_rng(seed)
+    x = d["x0"] + 1e-4 * rng.normal(size=d["x0"].shape)
+    return d, np.where((d["D"] > 0)[None], x, d["x0"])
+
+
+@pytest.mark.parametrize("lam", [0.0, 0.3])
+def test_sfs_pcg_fp64_against_oracle_and_split(lam):
+    d, x = _sfs()
+    lin = o.Linearization(o.make_energy(d), x)
+    D = lin.damping()
+    prob = _problem(d, "fp64")
+    prob.linearize(to_dev(prob, x))
+    A = ((lin.JT @ lin.J) + lam * sp.diags(D)).tocsr()
+    for L in (1, 10, 25):
+        ref, _ = o.pcg(lambda v: lin.apply(v, lam, D), lin.jtf(), lin.minv(True, lam, D), L)
+        ref2, _ = o.pcg(lambda v: A @ v, lin.jtf(), lin.minv(True, lam, D), L)
+        got = to_np(prob.pcg(L, lam=lam, variant="materialized"))
+        assert relmax(got, ref) < pcg_tol(ref, ref2), L
+        split = to_np(prob.pcg(L, lam=lam, variant="split"))
+        assert relmax(got, split) < 1e-11, L
+
+
+def test_sfs_product_equals_the_oracle_jacobian():
+    """One materialised PCG iteration from r = J^T F reproduces the oracle's first
+    step exactly up to rounding: p_0 = M^-1 r and alpha from p.(J^T J p)."""
+    d, x = _sfs(30, 24, seed=5)
+    lin = o.Linearization(o.make_energy(d), x)
+    prob = _problem(d, "fp64")
+    prob.linearize(to_dev(prob, x))
+    ref, _ = o.pcg(lambda v: lin.JT @ (lin.J @ v), lin.jtf(), lin.minv(True), 1)
+    assert relmax(to_np(prob.pcg(1, variant="materialized")), ref) < 1e-12
+
+
+def test_sfs_gn_fp64_and_mixed():
+    d, _ = _sfs(48, 40, seed=3)
+    e = o.make_energy(d)
+    xo, costs = o.gauss_newton(e, d["x0"], 2, 20)
+    prob = _problem(d, "fp64")
+    rep = prob.solve(to_dev(prob, d["x0"]), method="gn", outer_iters=2, pcg_iters=20, pcg_variant="materialized")
+    assert np.allclose(rep["cost_trace"], costs, rtol=1e-9, atol=0)
+    d32 = f32_inputs(d)
+    xo, costs = o.gauss_newton(o.make_energy(d32), d32["x0"], 1, 20)
+    prob = _problem(d, "mixed")
+    rep = prob.solve(to_dev(prob, d32["x0"]), method="gn", outer_iters=1, pcg_iters=20,
+                     pcg_variant="materialized")
+    assert abs(rep["cost_final"] - costs[-1]) <= 1e-4 * costs[-1]
+
+
 def test_requires_a_materialized_problem():
     d, x = _warp()
     prob = _problem(d, "fp64", materialize=False)
@@ -105,7 +164,7 @@ def test_requires_a_materialized_problem():
     with pytest.raises(pkg.OptError) as ei:
         prob.pcg(3, variant="materialized")
     assert ei.value.code == pkg.OPT_EINVAL
-    ds = w.shape_from_shading(40, 30, seed=2)
+    dp = w.poisson_edit(40, 30, seed=2)
     with pytest.raises(pkg.OptError) as ei:
-        _problem(ds, "fp64")
+        _problem(dp, "fp64")
     assert ei.value.code == pkg.OPT_EUNSUPPORTED
