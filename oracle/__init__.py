@@ -23,12 +23,12 @@ Everything is double precision.  It is a correctness reference, not a tuned CPU
 solver.
 """
 from .energies import (ArapWarp, Poisson, ShapeFromShading, OpticalFlow, ArapMesh, ArapVolume,
-                       LaplacianGrid, LaplacianGraph, LpSmoothGrid, make_energy)
+                       LaplacianGrid, LaplacianGraph, LpSmoothGrid, IntrinsicImage, make_energy)
 from .assemble import jacobian, jacobian_dense_bruteforce, fd_jacobian
 from .solver import (Linearization, pcg, gauss_newton, levenberg_marquardt, irls, cost,
                      LMParams)
 
 __all__ = ["ArapWarp", "Poisson", "ShapeFromShading", "OpticalFlow", "ArapMesh", "ArapVolume",
-           "LaplacianGrid", "LaplacianGraph", "LpSmoothGrid", "make_energy", "jacobian",
+           "LaplacianGrid", "LaplacianGraph", "LpSmoothGrid", "IntrinsicImage", "make_energy", "jacobian",
            "jacobian_dense_bruteforce", "fd_jacobian", "Linearization", "pcg",
            "gauss_newton", "levenberg_marquardt", "irls", "cost", "LMParams"]

@@ -568,6 +568,95 @@ class LpSmoothGrid(_Grid):
                                _grid_sites(W, H, [(0, 0), (0, 1)])])
 
 
+class IntrinsicImage(_Grid):
+    """Intrinsic image decomposition (A.2.4, Fig. 33), solved by IRLS (Sec. 7):
+    per pixel a reflectance r (3 channels) and a shading s, channel order
+    (r0, r1, r2, s).  For each pixel and each of its four stencil neighbours q
+    on the grid (+x, -x, +y, -y), a reflectance term f = w_a (r - r_q) (a
+    3-vector) entering as (|f|^2 + eps^2)^(p/2) and a shading term w_s (s - s_q)
+    (squared); a fit w_fit (r_c + s - I_c) per channel (squared):
+
+        Phi(x) = sum fit^2 + sum_(pixel, q) [(|f|^2 + eps^2)^(p/2) + (w_s (s - s_q))^2].
+
+    Each edge appears once from each end.  IRLS freezes, per edge, the weight
+    w = (p/2) (|f|^2 + eps^2)^((p-2)/2) at the current x (both ends share it)
+    and takes a least-squares step on the frozen problem; ``residuals`` are
+    those of the frozen problem: the fits, then per direction the three
+    components of sqrt(w) f, then per direction the shading term.  The weight
+    reads as for LpSmoothGrid (eps, and the factor p/2 beside the l_2 fit).
+    Row order: fit (3 channels), reflectance (4 directions x 3 components),
+    shading (4 directions)."""
+    n_chan = 4
+    DIRS = ((1, 0), (-1, 0), (0, 1), (0, -1))
+
+    def __init__(self, W, H, I, w_fit, w_a, w_s, p, eps):
+        self.W, self.H = W, H
+        self.I = np.asarray(I, float).reshape(3, H, W)
+        self.w_fit, self.w_a, self.w_s = float(w_fit), float(w_a), float(w_s)
+        self.p, self.eps = float(p), float(eps)
+        self.active = np.ones(W * H, bool)
+        self.wh = np.ones((H, W))  # weight of the edge to the right of a pixel (0 past the grid)
+        self.wv = np.ones((H, W))  # of the edge below
+
+    def weight(self, f2):
+        """w for |f|^2 = f2."""
+        return 0.5 * self.p * (f2 + self.eps ** 2) ** (0.5 * (self.p - 2.0))
+
+    def dir_weights(self):
+        """The frozen weight of each direction's edge at every pixel (0 off the grid)."""
+        wl, _ = _shift(self.wh, -1, 0)
+        wu, _ = _shift(self.wv, 0, -1)
+        return (self.wh, wl, self.wv, wu)
+
+    def freeze(self, x):
+        X = np.asarray(x, float).reshape(4, self.H, self.W)
+        R = X[:3]
+        for k, (di, dj) in ((0, (1, 0)), (2, (0, 1))):
+            Rq, inb = _shift(R, di, dj)
+            f2 = (self.w_a ** 2) * ((R - Rq) ** 2).sum(0)
+            w = np.where(inb, self.weight(f2), 0.0)
+            if k == 0:
+                self.wh = w
+            else:
+                self.wv = w
+
+    def objective(self, x):
+        X = np.asarray(x, float).reshape(4, self.H, self.W)
+        R, S = X[:3], X[3]
+        fit = self.w_fit * (R + S[None] - self.I)
+        e = float((fit * fit).sum())
+        for di, dj in self.DIRS:
+            Rq, inb = _shift(R, di, dj)
+            Sq, _ = _shift(S, di, dj)
+            f2 = (self.w_a ** 2) * ((R - Rq) ** 2).sum(0)
+            e += float(np.where(inb, (f2 + self.eps ** 2) ** (0.5 * self.p), 0.0).sum())
+            e += float(np.where(inb, (self.w_s * (S - Sq)) ** 2, 0.0).sum())
+        return e
+
+    def residuals(self, x):
+        X = self._x(x)
+        R, S = X[:3], X[3]
+        out = [(self.w_fit * (R[c] + S - self.I[c])).ravel() for c in range(3)]
+        for (di, dj), w in zip(self.DIRS, self.dir_weights()):
+            Rq, inb = _shift(R, di, dj)
+            for c in range(3):
+                out.append(np.where(inb, np.sqrt(w) * self.w_a * (R[c] - Rq[c]), 0).ravel())
+        for di, dj in self.DIRS:
+            Sq, inb = _shift(S, di, dj)
+            out.append(np.where(inb, self.w_s * (S - Sq), 0).ravel())
+        return np.concatenate(out)
+
+    def row_sites(self):
+        W, H = self.W, self.H
+        fit = _pad_cols(_grid_sites(W, H, [(0, 0)]), 2)
+        rows = [fit] * 3
+        for di, dj in self.DIRS:
+            rows += [_grid_sites(W, H, [(0, 0), (di, dj)])] * 3
+        for di, dj in self.DIRS:
+            rows.append(_grid_sites(W, H, [(0, 0), (di, dj)]))
+        return np.concatenate(rows)
+
+
 class LaplacianGraph(_Graph):
     """Laplacian smoothing on a graph (Fig. 5), float3 per vertex:
     r_fit = w_fit (X_v - A_v); r_e = w_reg (X_v0 - X_v1) for each listed edge.
@@ -622,4 +711,6 @@ def make_energy(w):
         return LaplacianGraph(w["V"], w["edges"], w["A"], p["w_fit"], p["w_reg"])
     if kind == "lp_smooth":
         return LpSmoothGrid(w["W"], w["H"], w["A"], p["w_fit"], p["w_reg"], p["p"], p["eps"])
+    if kind == "intrinsic":
+        return IntrinsicImage(w["W"], w["H"], w["I"], p["w_fit"], p["w_a"], p["w_s"], p["p"], p["eps"])
     raise ValueError(kind)

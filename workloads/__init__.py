@@ -12,10 +12,10 @@ Every generator takes an explicit ``seed`` and uses
 arrays.
 """
 from .grids import (arap_warp, poisson_edit, shape_from_shading, optical_flow,
-                    laplacian_grid, lp_smooth, SFS_LIGHTING)
+                    laplacian_grid, lp_smooth, intrinsic_image, SFS_LIGHTING)
 from .mesh import icosphere, morton_order, arap_mesh, laplacian_mesh, grid_edges
 from .volume import arap_volume, lattice_edges
 
 __all__ = ["arap_warp", "poisson_edit", "shape_from_shading", "optical_flow",
-           "laplacian_grid", "lp_smooth", "SFS_LIGHTING", "icosphere", "morton_order",
+           "laplacian_grid", "lp_smooth", "intrinsic_image", "SFS_LIGHTING", "icosphere", "morton_order",
            "arap_mesh", "laplacian_mesh", "grid_edges", "arap_volume", "lattice_edges"]

@@ -204,3 +204,22 @@ def lp_smooth(W, H, seed=0, p=1.0, eps=1e-2, w_fit=1.0, w_reg=0.5, noise=0.1, bl
     return dict(energy="lp_smooth", W=W, H=H, A=A[None], x0=A[None].copy(),
                 params=dict(w_fit=w_fit, w_reg=w_reg, p=p, eps=eps))
 
+
+def intrinsic_image(W, H, seed=0, p=0.8, eps=1e-2, w_fit=1.0, w_a=1.0, w_s=3.0, noise=0.02, blocks=12):
+    """Intrinsic decomposition input in the log domain: a reflectance that is
+    piecewise constant per channel (random axis-aligned blocks of random
+    colours over a background), plus a smooth shading field (a seeded sum of
+    plane waves), plus Gaussian noise per channel.  The solve starts with all of
+    the image as reflectance and zero shading."""
+    rng = np.random.default_rng(seed)
+    R = np.empty((3, H, W))
+    R[:] = rng.uniform(-0.5, 0.5, size=(3, 1, 1))
+    for _ in range(blocks):
+        x0, y0 = rng.integers(0, W), rng.integers(0, H)
+        w, h = rng.integers(max(1, W // 8), max(2, W // 2)), rng.integers(max(1, H // 8), max(2, H // 2))
+        R[:, y0:y0 + h, x0:x0 + w] = rng.uniform(-1.0, 0.5, size=(3, 1, 1))
+    S, _, _ = sinusoid_field((H, W), rng, 4, max(2.0, W / 2), float(max(W, 4)))
+    I = R + 0.5 * S[None] + noise * rng.normal(size=(3, H, W))
+    x0 = np.concatenate([I, np.zeros((1, H, W))])
+    return dict(energy="intrinsic", W=W, H=H, I=I, x0=x0,
+                params=dict(w_fit=w_fit, w_a=w_a, w_s=w_s, p=p, eps=eps))

@@ -12,6 +12,7 @@ ARRAY_ORDER = {
     "laplacian": ["A"],
     "laplacian_graph": ["A"],
     "lp_smooth": ["A"],
+    "intrinsic": ["I"],
 }
 # the library's name of each workload energy
 LIB_ENERGY = {"laplacian_graph": "laplacian"}
@@ -24,6 +25,8 @@ def param_list(d):
         return [p["w_fit"], p["w_reg"]]
     if e == "lp_smooth":
         return [p["w_fit"], p["w_reg"], p["p"], p["eps"]]
+    if e == "intrinsic":
+        return [p["w_fit"], p["w_a"], p["w_s"], p["p"], p["eps"]]
     if e == "poisson":
         return []
     if e == "sfs":
