@@ -437,6 +437,10 @@ CONFIGS = [
     # two frozen edge weights per pixel as state
     ("lp_smooth_1024x1024_gn10x50_mixed", lambda w: w.lp_smooth(1024, 1024, seed=0), "mixed", "gn", 10, 50,
      (24, 9)),
+    # the paper's IRLS example: intrinsic image decomposition at its 640 x 360
+    # (reflectance and shading, 4 unknowns per pixel; p = 0.8)
+    ("intrinsic_640x360_gn10x50_mixed", lambda w: w.intrinsic_image(640, 360, seed=0), "mixed", "gn", 10, 50,
+     (24, 9)),
     # the level-8 mesh in the split form (two kernels per iteration), beside
     # its fused graph form above
     ("mesh_icosphere8_lm10x40_mixed_split", lambda w: w.arap_mesh(8, seed=3), "mixed", "lm", 10, 40, (24, 52),
@@ -533,6 +537,8 @@ ACCURACY = [
     ("poisson_1024x1024_gn10x50_mixed", lambda w: w.poisson_edit(1024, 1024, seed=5), "mixed", "gn", 10, 50),
     ("lp_smooth_1024x1024_gn10x50_mixed", lambda w: w.lp_smooth(1024, 1024, seed=0), "mixed", "gn", 10, 50),
     ("lp_smooth_1024x1024_gn10x50_fp64", lambda w: w.lp_smooth(1024, 1024, seed=0), "fp64", "gn", 10, 50),
+    ("intrinsic_640x360_gn10x50_mixed", lambda w: w.intrinsic_image(640, 360, seed=0), "mixed", "gn", 10, 50),
+    ("intrinsic_640x360_gn10x50_fp64", lambda w: w.intrinsic_image(640, 360, seed=0), "fp64", "gn", 10, 50),
     ("laplacian_1024x1024_gn10x50_mixed", lambda w: w.laplacian_grid(1024, 1024, seed=0), "mixed", "gn", 10, 50),
     ("volume_64x64x64_lm10x40_mixed", lambda w: w.arap_volume(64, 64, 64, seed=6), "mixed", "lm", 10, 40),
 ]
@@ -569,7 +575,7 @@ def _oracle_config(name):
 
     if d["energy"] == "sfs":
         masks.append(e.smooth_valid(np.asarray(d["x0"], float).reshape(d["H"], d["W"])))
-    if d["energy"] == "lp_smooth":
+    if d["energy"] in ("lp_smooth", "intrinsic"):
         # IRLS: Gauss-Newton steps with the weights frozen at each linearisation
         x, costs = oracle.irls(e, d["x0"], K, L, callback=progress)
         acc = None

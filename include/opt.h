@@ -101,6 +101,19 @@ typedef enum { OPT_GRID2D = 0, OPT_GRAPH = 1, OPT_GRID3D = 2 } opt_domain;
  *   squares sum (w_fit (X - A))^2 + sum w f^2 (iteratively reweighted least
  *   squares).  arrays: [0] A.  params: w_fit, w_reg, p in (0, 2], eps > 0
  *   (OPT_EINVAL otherwise).  OPT_LM is refused (OPT_EUNSUPPORTED).
+ * OPT_E_INTRINSIC (grid; A.2.4, Fig. 33, solved by IRLS as Sec. 7 describes).
+ *   4 unknowns per pixel: reflectance r (3 channels) and shading s, in the
+ *   channel order r0, r1, r2, s.  Residuals at a pixel: the fits w_fit (r_c + s -
+ *   I_c), and for each of the four stencil neighbours q on the grid the
+ *   reflectance term f = w_a (r - r_q), entering as (|f|^2 + eps^2)^(p/2), and
+ *   the shading term w_s (s - s_q) (each edge thus counts at both ends).  The
+ *   reported cost is that objective.  Each outer iteration freezes w = (p/2)
+ *   (|f|^2 + eps^2)^((p-2)/2) per edge and takes a Gauss-Newton step on the
+ *   reweighted least-squares problem.  A uniform shift of r down and s up leaves
+ *   everything unchanged (the PCG keeps to the normal equations' range).
+ *   arrays: [0] I (3 planes, image in the log domain).  params: w_fit, w_a,
+ *   w_s, p in (0, 2], eps > 0 (OPT_EINVAL otherwise).  OPT_LM is refused
+ *   (OPT_EUNSUPPORTED).
  */
 typedef enum {
   OPT_E_LAPLACIAN = 0,
@@ -110,7 +123,8 @@ typedef enum {
   OPT_E_FLOW = 4,
   OPT_E_ARAP_MESH = 5,
   OPT_E_ARAP_VOLUME = 6,
-  OPT_E_LP_SMOOTH = 7
+  OPT_E_LP_SMOOTH = 7,
+  OPT_E_INTRINSIC = 8
 } opt_energy;
 
 typedef enum { OPT_FP64 = 0, OPT_MIXED = 1 } opt_precision;

@@ -17,7 +17,7 @@ LIB_PATH = os.path.join(_HERE, "libopt.so")
 OPT_OK, OPT_EINVAL, OPT_ENOMEM, OPT_EHIP, OPT_EAGAIN, OPT_ENUMERIC, OPT_EUNSUPPORTED = 0, -1, -2, -3, -4, -5, -6
 GRID2D, GRAPH, GRID3D = 0, 1, 2
 ENERGIES = {"laplacian": 0, "arap_warp": 1, "poisson": 2, "sfs": 3, "flow": 4, "arap_mesh": 5, "arap_volume": 6,
-            "lp_smooth": 7}
+            "lp_smooth": 7, "intrinsic": 8}
 PRECISIONS = {"fp64": 0, "mixed": 1}
 GN, LM = 0, 1
 PCG_FUSED, PCG_SPLIT, PCG_MATERIALIZED = 0, 1, 2
@@ -166,6 +166,7 @@ ARRAY_SPEC = {
     "arap_volume": [(3, "bulk"), (3, "bulk")],
     "laplacian": [(1, "bulk")],  # 3 planes on a graph
     "lp_smooth": [(1, "bulk")],
+    "intrinsic": [(3, "bulk")],
 }
 
 
@@ -186,7 +187,7 @@ def len_channels(energy, graph=False):
     if energy == "laplacian":
         return 3 if graph else 1
     return {"arap_warp": 3, "poisson": 4, "sfs": 1, "flow": 2, "arap_mesh": 6, "arap_volume": 6,
-            "lp_smooth": 1}[energy]
+            "lp_smooth": 1, "intrinsic": 4}[energy]
 
 
 def check_request(energy, arrays, x, precision, n_sites, graph=False):

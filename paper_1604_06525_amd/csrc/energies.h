@@ -7,5 +7,6 @@
 #include "energy_flow.h"
 #include "energy_laplacian.h"
 #include "energy_lp_smooth.h"
+#include "energy_intrinsic.h"
 #include "energy_poisson.h"
 #include "energy_sfs.h"

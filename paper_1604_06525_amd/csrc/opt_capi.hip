@@ -87,6 +87,7 @@ int energy_channels(int e) {
     case OPT_E_ARAP_MESH: return ArapMesh<float>::C;
     case OPT_E_ARAP_VOLUME: return ArapVolume<float>::C;
     case OPT_E_LP_SMOOTH: return LpSmoothGrid<float>::C;
+    case OPT_E_INTRINSIC: return IntrinsicImage<float>::C;
     default: return 0;
   }
 }
@@ -101,6 +102,7 @@ int energy_state_planes(int e) {
     case OPT_E_ARAP_MESH: return ArapMesh<float>::kOwnState;
     case OPT_E_ARAP_VOLUME: return ArapVolume<float>::kOwnState;
     case OPT_E_LP_SMOOTH: return LpSmoothGrid<float>::kOwnState;
+    case OPT_E_INTRINSIC: return IntrinsicImage<float>::kOwnState;
     default: return 0;
   }
 }
@@ -149,6 +151,7 @@ int n_params_needed(int e) {
     case OPT_E_ARAP_MESH: return 2;
     case OPT_E_ARAP_VOLUME: return 2;
     case OPT_E_LP_SMOOTH: return 4;
+    case OPT_E_INTRINSIC: return 5;
     default: return 0;
   }
 }
@@ -163,6 +166,7 @@ int n_arrays_needed(int e) {
     case OPT_E_ARAP_MESH: return 2;
     case OPT_E_ARAP_VOLUME: return 2;
     case OPT_E_LP_SMOOTH: return 1;
+    case OPT_E_INTRINSIC: return 1;
     default: return 0;
   }
 }
@@ -218,8 +222,9 @@ int check_desc(const opt_problem_desc* d, Shape* sh) {
                 n_params_needed(d->energy), d->n_params);
   for (int k = 0; k < n_arrays_needed(d->energy); ++k)
     if (!d->arrays[k]) return fail(OPT_EINVAL, "arrays[%d] is NULL", k);
-  if (d->energy == OPT_E_LP_SMOOTH) {
-    const double p = d->params[2], eps = d->params[3];
+  if (d->energy == OPT_E_LP_SMOOTH || d->energy == OPT_E_INTRINSIC) {
+    const int at = d->energy == OPT_E_LP_SMOOTH ? 2 : 3;  // p, then eps
+    const double p = d->params[at], eps = d->params[at + 1];
     if (!(p > 0.0 && p <= 2.0)) return fail(OPT_EINVAL, "p = %g is outside (0, 2]", p);
     if (!(eps > 0.0) || !std::isfinite(eps)) return fail(OPT_EINVAL, "eps = %g must be positive", eps);
   }
@@ -921,6 +926,24 @@ std::unique_ptr<Impl> make_impl_t(opt_problem* p) {
       e.eps2_d = d.params[3] * d.params[3];
       return std::unique_ptr<Impl>(new ImplT<LpSmoothGrid<T>>(p, e));
     }
+    case OPT_E_INTRINSIC: {
+      IntrinsicImage<T> e;
+      e.W = d.width;
+      e.H = d.height;
+      e.n = p->sh.n;
+      e.I = (const T*)d.arrays[0];
+      e.st = (T*)p->at(p->L.state);
+      e.flags = (uint8_t*)p->at(p->L.flags);
+      e.wf2 = (T)(d.params[0] * d.params[0]);
+      e.wa2 = (T)(d.params[1] * d.params[1]);
+      e.ws2 = (T)(d.params[2] * d.params[2]);
+      e.wf_d = d.params[0];
+      e.wa_d = d.params[1];
+      e.ws_d = d.params[2];
+      e.p_d = d.params[3];
+      e.eps2_d = d.params[4] * d.params[4];
+      return std::unique_ptr<Impl>(new ImplT<IntrinsicImage<T>>(p, e));
+    }
     case OPT_E_ARAP_VOLUME: {
       ArapVolume<T> e;
       e.n = p->sh.n;
@@ -1045,8 +1068,8 @@ int check_tuning(const opt_tuning* t) {
 
 // A method the energy offers: the IRLS energy takes Gauss-Newton steps only.
 int check_method(const opt_problem_desc* d, const opt_solve_params* sp) {
-  if (d->energy == OPT_E_LP_SMOOTH && sp->method == OPT_LM)
-    return fail(OPT_EUNSUPPORTED, "the l_p smoothing energy is solved by IRLS, which takes Gauss-Newton steps");
+  if ((d->energy == OPT_E_LP_SMOOTH || d->energy == OPT_E_INTRINSIC) && sp->method == OPT_LM)
+    return fail(OPT_EUNSUPPORTED, "energy %d is solved by IRLS, which takes Gauss-Newton steps", d->energy);
   return OPT_OK;
 }
 

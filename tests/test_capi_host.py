@@ -51,7 +51,8 @@ def _desc(energy="arap_warp", W=64, H=48, precision="mixed", n_params=None, arra
     for k in range(arrays):
         d.arrays[k] = 0x1000 * (k + 1)  # never dereferenced by these calls
     d.n_params = {"arap_warp": 2, "poisson": 0, "flow": 2, "sfs": 16, "arap_mesh": 2,
-                  "laplacian": 2, "arap_volume": 2, "lp_smooth": 4}[energy] if n_params is None else n_params
+                  "laplacian": 2, "arap_volume": 2, "lp_smooth": 4, "intrinsic": 5}[energy] \
+        if n_params is None else n_params
     if V and E:
         d.edges = 0x9000
     return d
@@ -174,9 +175,27 @@ def test_lp_smooth_parameters(lib, p, eps, code):
     assert _ws(lib, d2)[0] == pkg.OPT_EUNSUPPORTED  # grid only
 
 
+@pytest.mark.parametrize("p,eps,code", [
+    (0.8, 0.01, pkg.OPT_OK), (2.0, 1e-3, pkg.OPT_OK),
+    (0.0, 0.01, pkg.OPT_EINVAL), (2.5, 0.01, pkg.OPT_EINVAL), (1.0, 0.0, pkg.OPT_EINVAL),
+    (float("nan"), 0.01, pkg.OPT_EINVAL), (1.0, float("inf"), pkg.OPT_EINVAL),
+])
+def test_intrinsic_parameters(lib, p, eps, code):
+    """The intrinsic decomposition takes p in (0, 2] and eps > 0 (params 4 and 5)."""
+    d = _desc("intrinsic", W=40, H=30, arrays=1)
+    d.params[0], d.params[1], d.params[2], d.params[3], d.params[4] = 1.0, 1.0, 3.0, p, eps
+    rc, b = _ws(lib, d)
+    assert rc == code
+    if code == pkg.OPT_OK:
+        assert b >= 9 * 1200 * 16 + 2 * 1200 * 4  # nine vectors of 4 channels and two weights per pixel
+    d2 = _desc("intrinsic", V=100, E=0, arrays=1)
+    d2.params[3], d2.params[4] = 1.0, 0.01
+    assert _ws(lib, d2)[0] == pkg.OPT_EUNSUPPORTED  # grid only
+
+
 def test_energy_channels(lib):
-    assert [pkg.energy_channels(e) for e in ("arap_warp", "poisson", "sfs", "flow", "arap_mesh", "lp_smooth")] == \
-        [3, 4, 1, 2, 6, 1]
+    assert [pkg.energy_channels(e) for e in ("arap_warp", "poisson", "sfs", "flow", "arap_mesh", "lp_smooth",
+                                             "intrinsic")] == [3, 4, 1, 2, 6, 1, 4]
     assert pkg.energy_channels(99) == 0
 
 
