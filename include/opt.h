@@ -475,7 +475,7 @@ int opt_energy_channels(int32_t energy);
  *   uncollected result.
  * opt_server_info: requests held (running or admitted) and free arena bytes.
  * opt_server_add_tuning: launch tuning (opt_tuning) applied at admission to
- *   requests of that energy and precision whose site count lies in
+ *   2D-grid requests of that energy and precision whose site count lies in
  *   [min_sites, max_sites]; a later entry overrides an earlier one.
  *
  * A server is not thread-safe: calls on one server must not overlap.  Work the

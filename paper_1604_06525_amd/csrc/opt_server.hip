@@ -403,7 +403,9 @@ int opt_server_submit(opt_server* sv, const opt_problem_desc* desc, void* unknow
       return fail(OPT_EHIP, "staging the edge list failed: %s", hipGetErrorString(e));
     }
   }
-  for (auto it = sv->tuning.rbegin(); it != sv->tuning.rend(); ++it)
+  // (launch shapes are those of the 2D grid kernels: a graph request of the same
+  // energy, the Laplacian's, takes none)
+  for (auto it = sv->tuning.rbegin(); it != sv->tuning.rend() && desc->domain == OPT_GRID2D; ++it)
     if (it->energy == desc->energy && it->precision == desc->precision && sh.n >= it->min_sites &&
         sh.n <= it->max_sites) {
       p->tune = it->t;

@@ -2,8 +2,8 @@
 
     python -m paper_1604_06525_amd.tune [--out tuning.json] [--quick]
 
-For each energy with a fused kernel (ARAP warp, Poisson, optical flow, shape
-from shading), each
+For each grid energy with a fused kernel (ARAP warp, Poisson, optical flow,
+shape from shading, the Laplacian, l_p smoothing, intrinsic decomposition), each
 precision and each size class (grid sides 128, 256, 512, 1024, 2048), it times
 the PCG phase of a short solve on a seeded synthetic problem for every candidate
 launch shape (fixed strip heights, and balanced partitions with 1 to 4 strips
@@ -25,7 +25,7 @@ DEFAULT_PATH = os.path.join(HERE, "tuning.json")
 CANDIDATES = tuple(("rows", r) for r in (4, 6, 8, 12, 16, 24, 32)) + \
     tuple(("waves", w) for w in (1, 2, 3, 4)) + (("auto", 0),)
 SIDES = (128, 256, 512, 1024, 2048)
-ENERGIES = ("arap_warp", "poisson", "flow", "sfs")
+ENERGIES = ("arap_warp", "poisson", "flow", "sfs", "laplacian", "lp_smooth", "intrinsic")
 
 
 def _problem(energy, side, precision):
@@ -39,6 +39,12 @@ def _problem(energy, side, precision):
         d = workloads.poisson_edit(side, side, seed=5)
     elif energy == "sfs":
         d = workloads.shape_from_shading(side, side, seed=2)
+    elif energy == "laplacian":
+        d = workloads.laplacian_grid(side, side, seed=0)
+    elif energy == "lp_smooth":
+        d = workloads.lp_smooth(side, side, seed=0)
+    elif energy == "intrinsic":
+        d = workloads.intrinsic_image(side, side, seed=0)
     else:
         d = workloads.optical_flow(side, side, seed=4)
     dt = np.float64 if precision == "fp64" else np.float32
