@@ -423,11 +423,14 @@ CONFIGS = [
     # shape from shading's materialisation strategies (Sec. 8.3, Fig. 17): the
     # lighting term and its partials stored per linearisation with the rest of
     # J recomputed (the fused line above, and the split form), against the
-    # whole J stored; bytes are the lighting-stored algorithmic bytes throughout
+    # whole J stored and against nothing stored (the lighting recomputed in
+    # every product); bytes are the lighting-stored algorithmic bytes throughout
     ("sfs_1024x1024_gn10x50_mixed_split", lambda w: w.shape_from_shading(1024, 1024, seed=2), "mixed", "gn", 10, 50,
      (24, 13), dict(pcg_variant="split")),
     ("sfs_1024x1024_gn10x50_mixed_materialized", lambda w: w.shape_from_shading(1024, 1024, seed=2), "mixed", "gn",
      10, 50, (24, 13), dict(pcg_variant="materialized", materialize=True)),
+    ("sfs_1024x1024_gn10x50_mixed_recompute", lambda w: w.shape_from_shading(1024, 1024, seed=2), "mixed", "gn",
+     10, 50, (24, 13), dict(pcg_variant="recompute")),
     # volumetric ARAP on a 64^3 voxel block (implicit 3D connectivity), and the
     # Laplacian on a 1024^2 image
     ("volume_64x64x64_lm10x40_mixed", lambda w: w.arap_volume(64, 64, 64, seed=6), "mixed", "lm", 10, 40, (24, 37)),

@@ -155,8 +155,20 @@ typedef enum { OPT_GN = 0, OPT_LM = 1 } opt_method;
  *   materialised strategy of Sec. 8.3: J's rows come from the stored lighting
  *   partials).  For comparing matrix-free and materialised products; a server
  *   runs such requests in the split form.
+ * OPT_PCG_RECOMPUTE: the split form with the per-site state an energy stores at
+ *   each linearisation recomputed inside every product instead of read: for
+ *   shape from shading the lighting term's partials at each pixel the product
+ *   reads, from the linearisation point (the fully matrix-free strategy of
+ *   Sec. 8.3, Fig. 17; the stored values are reproduced, so the iterates are
+ *   the split form's).  Built for shape from shading (OPT_EUNSUPPORTED
+ *   otherwise); a server runs such requests in the split form.
  */
-typedef enum { OPT_PCG_FUSED = 0, OPT_PCG_SPLIT = 1, OPT_PCG_MATERIALIZED = 2 } opt_pcg_variant;
+typedef enum {
+  OPT_PCG_FUSED = 0,
+  OPT_PCG_SPLIT = 1,
+  OPT_PCG_MATERIALIZED = 2,
+  OPT_PCG_RECOMPUTE = 3
+} opt_pcg_variant;
 
 typedef struct {
   int32_t domain;     /* opt_domain */
@@ -354,7 +366,8 @@ int opt_problem_set_graph_replay(opt_problem* prob, int enable);
  * (opt_pcg_variant): *form = OPT_PCG_FUSED where the fused kernel serves it
  * (the grid energies; on a graph, the ARAP mesh and the Laplacian when every
  * chunk's lists fit their caps), else OPT_PCG_SPLIT; OPT_PCG_MATERIALIZED
- * answers itself.  OPT_EINVAL for a NULL argument or an unknown variant.
+ * and OPT_PCG_RECOMPUTE answer themselves (the latter OPT_EUNSUPPORTED for an
+ * energy without it).  OPT_EINVAL for a NULL argument or an unknown variant.
  */
 int opt_problem_pcg_form(opt_problem* prob, int variant, int* form);
 

@@ -20,7 +20,7 @@ ENERGIES = {"laplacian": 0, "arap_warp": 1, "poisson": 2, "sfs": 3, "flow": 4, "
             "lp_smooth": 7, "intrinsic": 8}
 PRECISIONS = {"fp64": 0, "mixed": 1}
 GN, LM = 0, 1
-PCG_FUSED, PCG_SPLIT, PCG_MATERIALIZED = 0, 1, 2
+PCG_FUSED, PCG_SPLIT, PCG_MATERIALIZED, PCG_RECOMPUTE = 0, 1, 2, 3
 
 
 class opt_problem_desc(ctypes.Structure):
@@ -144,7 +144,8 @@ def default_params(**kw):
         if k == "method" and isinstance(v, str):
             v = {"gn": GN, "lm": LM}[v.lower()]
         if k == "pcg_variant" and isinstance(v, str):
-            v = {"fused": PCG_FUSED, "split": PCG_SPLIT, "materialized": PCG_MATERIALIZED}[v.lower()]
+            v = {"fused": PCG_FUSED, "split": PCG_SPLIT, "materialized": PCG_MATERIALIZED,
+                 "recompute": PCG_RECOMPUTE}[v.lower()]
         if not hasattr(p, k):
             raise TypeError(f"unknown solve parameter {k}")
         setattr(p, k, v)
@@ -377,12 +378,14 @@ class Problem:
         _check(lib().opt_problem_set_graph_replay(self.handle, int(on)), "opt_problem_set_graph_replay")
 
     def pcg_form(self, variant="fused"):
-        """opt_problem_pcg_form: the form ("fused", "split" or "materialized")
-        a solve asking for `variant` runs."""
-        v = {"fused": PCG_FUSED, "split": PCG_SPLIT, "materialized": PCG_MATERIALIZED}[variant.lower()]
+        """opt_problem_pcg_form: the form ("fused", "split", "materialized" or
+        "recompute") a solve asking for `variant` runs."""
+        v = {"fused": PCG_FUSED, "split": PCG_SPLIT, "materialized": PCG_MATERIALIZED,
+                 "recompute": PCG_RECOMPUTE}[variant.lower()]
         out = ctypes.c_int(-1)
         _check(lib().opt_problem_pcg_form(self.handle, v, ctypes.byref(out)), "opt_problem_pcg_form")
-        return {PCG_FUSED: "fused", PCG_SPLIT: "split", PCG_MATERIALIZED: "materialized"}[out.value]
+        return {PCG_FUSED: "fused", PCG_SPLIT: "split", PCG_MATERIALIZED: "materialized",
+                PCG_RECOMPUTE: "recompute"}[out.value]
 
     def profile_enable(self, on=True):
         _check(lib().opt_profile_enable(self.handle, int(on)), "opt_profile_enable")

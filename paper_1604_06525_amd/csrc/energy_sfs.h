@@ -451,4 +451,46 @@ struct ShapeFromShading {
   }
 };
 
+// Shape from shading with nothing stored between linearisations but the
+// depth: the fully matrix-free strategy of Sec. 8.3 (Fig. 17).  The product
+// recomputes the lighting term's partials from the linearisation point xlin in
+// every PCG iteration, at each of the eleven pixels whose partials the centre's
+// J^T J p reads (the shading residuals of its two-pixel neighbourhood), with
+// the same arithmetic as linearize, so the stored values are reproduced.  Only
+// the product (the split form's pcg_a) uses it.
+template <typename T>
+struct ShapeFromShadingLit : ShapeFromShading<T> {
+  using Base = ShapeFromShading<T>;
+  const T* __restrict__ xlin;  // the linearisation point (caller-facing plane)
+
+  // table slot of a pixel offset the product reads, -1 for one it does not
+  static constexpr int slot_of(int di, int dj) {
+    return dj == 0 ? (di == 0 ? 0 : di == -1 ? 1 : di == 1 ? 2 : di == 2 ? 3 : -1)
+         : dj == -1 ? (di == 0 ? 4 : di == 1 ? 5 : -1)
+         : dj == 1 ? (di == 0 ? 6 : di == -1 ? 7 : di == 1 ? 8 : -1)
+         : dj == 2 ? (di == 0 ? 9 : -1) : -1;
+  }
+  static constexpr int kPix = 10;
+
+  template <class PV, class SV, class FV>
+  __device__ __forceinline__ void apply(PV P, SV, FV F, int i, int j, T* g) const {
+    const int W = this->W;
+    const int s = j * W + i;
+    T tab[kPix][4];
+    constexpr int off[kPix][2] = {{0, 0}, {-1, 0}, {1, 0}, {2, 0}, {0, -1}, {1, -1}, {0, 1}, {-1, 1}, {1, 1}, {0, 2}};
+#pragma unroll
+    for (int t = 0; t < kPix; ++t) {
+      const int a = i + off[t][0], b = j + off[t][1], q = s + off[t][1] * W + off[t][0];
+      auto Xo = [&](int di, int dj) -> T { return xlin[q + dj * W + di]; };
+      // shading() reads nothing for a pixel not one inside the border
+      this->template shading<T>(a, b, Xo, &tab[t][0], &tab[t][1], &tab[t][2], &tab[t][3]);
+    }
+    auto Sl = [&](int k, int di, int dj) -> T {
+      const int t = slot_of(di, dj);
+      return t >= 0 ? tab[t][k] : T(0);
+    };
+    Base::apply(P, Sl, F, i, j, g);
+  }
+};
+
 }  // namespace optmi

@@ -75,7 +75,8 @@ struct Layout {
 // each in its workspace (the batching server keeps its own tables).
 enum RowKind {
   ROW_SETUP, ROW_LIN, ROW_INIT, ROW_PCGA, ROW_APPLY, ROW_PCGB, ROW_FUSED, ROW_STEP, ROW_COST,
-  ROW_TRIAL, ROW_MODEL, ROW_DECIDE, ROW_FINISH, ROW_PLANES, ROW_EVALJ, ROW_MATP, ROW_MATA, ROW_MATB, kNumRows
+  ROW_TRIAL, ROW_MODEL, ROW_DECIDE, ROW_FINISH, ROW_PLANES, ROW_EVALJ, ROW_MATP, ROW_MATA, ROW_MATB, ROW_PCGA_LIT,
+  kNumRows
 };
 
 // Partial-sum buffers of kMaxBlocks doubles each; the fused form uses two pairs.
@@ -151,6 +152,10 @@ class Impl {
   virtual int init(const void* x, double* trace, PrecondArgs pa, int lm_gate, int u_form) = 0;
   virtual int pcg_a(int k, int L, PrecondArgs pa, int lm_gate) = 0;
   virtual int pcg_b(int k, int L, PrecondArgs pa, int lm_gate) = 0;
+  // pcg_a with the stored per-site state recomputed inside the product
+  // (OPT_PCG_RECOMPUTE; shape from shading only)
+  virtual bool has_recompute() const { return false; }
+  virtual int pcg_a_recompute(int k, int L, PrecondArgs pa, int lm_gate) = 0;
   virtual int fused(int iter, int L, PrecondArgs pa, int lm_gate) = 0;
   virtual bool has_fused() const = 0;
   // materialised form (OPT_PCG_MATERIALIZED): evaluate J at the linearisation

@@ -505,6 +505,7 @@ class ImplT final : public Impl {
   }
 
   int linearize(const void* x, int lm) override {
+    xlin_ = (const T*)x;
     return go(ROW_LIN, lin_args(x, lm), nblk(), 0, "linearize");
   }
   int init(const void* x, double* trace, PrecondArgs pa, int lm, int u_form) override {
@@ -515,6 +516,24 @@ class ImplT final : public Impl {
   }
   int pcg_b(int k, int L, PrecondArgs, int lm) override {
     return go(ROW_PCGB, pcgb_args(L, lm), nblk(), k, "pcg_b");
+  }
+  bool has_recompute() const override { return kSfs; }
+  int pcg_a_recompute(int k, int L, PrecondArgs pa, int lm) override {
+    if constexpr (!kSfs) {
+      return fail(OPT_EUNSUPPORTED, "OPT_PCG_RECOMPUTE is built for shape from shading only");
+    } else {
+      if (!xlin_) return fail(OPT_EINVAL, "OPT_PCG_RECOMPUTE needs a linearisation point");
+      SplitAArgs<ShapeFromShadingLit<T>, 0> a = blank<SplitAArgs<ShapeFromShadingLit<T>, 0>>();
+      static_cast<ShapeFromShading<T>&>(a.e) = e_;
+      a.e.xlin = xlin_;
+      const SplitAArgs<E, 0> b = pcga_args(L, pa, lm);
+      a.b = b.b;
+      a.n_part = b.n_part;
+      a.S = b.S;
+      a.lm_gate = b.lm_gate;
+      a.L = b.L;
+      return go(ROW_PCGA_LIT, a, nblk(), k, "pcg_a_recompute");
+    }
   }
   // ------------------------------------------------ materialised form
   bool has_mat() const override { return MatOf<E>::value; }
@@ -785,6 +804,7 @@ class ImplT final : public Impl {
  private:
   opt_problem* p_;
   E e_;
+  const T* xlin_ = nullptr;  // the last linearisation point (OPT_PCG_RECOMPUTE reads it)
 };
 
 // The staging lists build_incidence writes after the incidence list.
@@ -1085,10 +1105,8 @@ int check_params(const opt_solve_params* sp) {
     if (!(sp->lm_radius0 > 0) || !(sp->lm_radius_max > 0) || !(sp->lm_radius_min >= 0))
       return fail(OPT_EINVAL, "LM radii must be positive");
   }
-  if (sp->pcg_variant != OPT_PCG_FUSED && sp->pcg_variant != OPT_PCG_SPLIT &&
-      sp->pcg_variant != OPT_PCG_MATERIALIZED)
-    return fail(OPT_EINVAL, "pcg_variant %d is not OPT_PCG_FUSED, OPT_PCG_SPLIT or OPT_PCG_MATERIALIZED",
-                sp->pcg_variant);
+  if (sp->pcg_variant < OPT_PCG_FUSED || sp->pcg_variant > OPT_PCG_RECOMPUTE)
+    return fail(OPT_EINVAL, "pcg_variant %d is not an opt_pcg_variant", sp->pcg_variant);
   if (!(sp->lm_diag_min >= 0) || !(sp->lm_diag_max >= sp->lm_diag_min))
     return fail(OPT_EINVAL, "LM diagonal clamp [%g, %g] is invalid", sp->lm_diag_min,
                 sp->lm_diag_max);
@@ -1124,6 +1142,15 @@ int uses_fused(opt_problem* p, int variant) {
 }
 
 int run_pcg(opt_problem* p, PrecondArgs pa, int lm, int L, int variant) {
+  if (variant == OPT_PCG_RECOMPUTE) {
+    if (!p->impl->has_recompute())
+      return fail(OPT_EUNSUPPORTED, "OPT_PCG_RECOMPUTE is built for shape from shading only");
+    for (int k = 0; k < L; ++k) {
+      TRY(p->impl->pcg_a_recompute(k, L, pa, lm));
+      TRY(p->impl->pcg_b(k, L, pa, lm));
+    }
+    return OPT_OK;
+  }
   if (variant == OPT_PCG_MATERIALIZED) {
     if (!p->sh.mat) return fail(OPT_EINVAL, "OPT_PCG_MATERIALIZED needs a problem created with materialize = 1");
     TRY(p->impl->eval_j());
@@ -1428,10 +1455,13 @@ int opt_problem_set_graph_replay(opt_problem* p, int enable) {
 
 int opt_problem_pcg_form(opt_problem* p, int variant, int* form) {
   if (!p || !form) return fail(OPT_EINVAL, "problem or form is NULL");
-  if (variant != OPT_PCG_FUSED && variant != OPT_PCG_SPLIT && variant != OPT_PCG_MATERIALIZED)
-    return fail(OPT_EINVAL, "pcg_variant %d is not OPT_PCG_FUSED, OPT_PCG_SPLIT or OPT_PCG_MATERIALIZED", variant);
-  *form = variant == OPT_PCG_MATERIALIZED ? OPT_PCG_MATERIALIZED
-                                          : (uses_fused(p, variant) ? OPT_PCG_FUSED : OPT_PCG_SPLIT);
+  if (variant < OPT_PCG_FUSED || variant > OPT_PCG_RECOMPUTE)
+    return fail(OPT_EINVAL, "pcg_variant %d is not an opt_pcg_variant", variant);
+  if (variant == OPT_PCG_RECOMPUTE && !p->impl->has_recompute())
+    return fail(OPT_EUNSUPPORTED, "OPT_PCG_RECOMPUTE is built for shape from shading only");
+  *form = variant == OPT_PCG_MATERIALIZED || variant == OPT_PCG_RECOMPUTE
+              ? variant
+              : (uses_fused(p, variant) ? OPT_PCG_FUSED : OPT_PCG_SPLIT);
   return OPT_OK;
 }
 

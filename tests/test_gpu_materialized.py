@@ -157,6 +157,49 @@ def test_sfs_gn_fp64_and_mixed():
     assert abs(rep["cost_final"] - costs[-1]) <= 1e-4 * costs[-1]
 
 
+@pytest.mark.parametrize("lam", [0.0, 0.3])
+def test_sfs_recompute_against_oracle_and_split(lam):
+    """OPT_PCG_RECOMPUTE (the lighting partials recomputed inside every product
+    from the linearisation point): the oracle's iterates, and the split form's
+    up to the order of additions (the stored values are reproduced)."""
+    d, x = _sfs()
+    lin = o.Linearization(o.make_energy(d), x)
+    D = lin.damping()
+    prob = _problem(d, "fp64", materialize=False)
+    prob.linearize(to_dev(prob, x))
+    A = ((lin.JT @ lin.J) + lam * sp.diags(D)).tocsr()
+    assert prob.pcg_form("recompute") == "recompute"
+    for L in (1, 10, 25):
+        ref, _ = o.pcg(lambda v: lin.apply(v, lam, D), lin.jtf(), lin.minv(True, lam, D), L)
+        ref2, _ = o.pcg(lambda v: A @ v, lin.jtf(), lin.minv(True, lam, D), L)
+        got = to_np(prob.pcg(L, lam=lam, variant="recompute"))
+        assert relmax(got, ref) < pcg_tol(ref, ref2), L
+        split = to_np(prob.pcg(L, lam=lam, variant="split"))
+        assert relmax(got, split) < 1e-12, L
+
+
+def test_sfs_recompute_solves():
+    d, _ = _sfs(48, 40, seed=3)
+    e = o.make_energy(d)
+    xo, costs = o.gauss_newton(e, d["x0"], 2, 20)
+    prob = _problem(d, "fp64", materialize=False)
+    rep = prob.solve(to_dev(prob, d["x0"]), method="gn", outer_iters=2, pcg_iters=20, pcg_variant="recompute")
+    assert np.allclose(rep["cost_trace"], costs, rtol=1e-9, atol=0)
+    xo, costs, acc = o.levenberg_marquardt(e, d["x0"], 3, 15)
+    rep = prob.solve(to_dev(prob, d["x0"]), method="lm", outer_iters=3, pcg_iters=15, pcg_variant="recompute")
+    assert rep["steps_accepted"] == sum(acc)
+    assert np.allclose(rep["cost_trace"][:len(costs)], costs, rtol=1e-9, atol=0)
+
+
+def test_recompute_is_shape_from_shading_only():
+    d, x = _warp()
+    prob = _problem(d, "fp64", materialize=False)
+    prob.linearize(to_dev(prob, x))
+    with pytest.raises(pkg.OptError) as ei:
+        prob.pcg(3, variant="recompute")
+    assert ei.value.code == pkg.OPT_EUNSUPPORTED
+
+
 def test_requires_a_materialized_problem():
     d, x = _warp()
     prob = _problem(d, "fp64", materialize=False)
