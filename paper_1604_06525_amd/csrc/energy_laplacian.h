@@ -32,6 +32,7 @@ struct LaplacianGrid {
   static constexpr int kOwnState = 0;
   static constexpr int kRadius = 1;
   static constexpr int kFusedWalk = sizeof(T) == 4 ? 1 : 0;  // fused strip walk in FP32: d loaded with its row
+  static constexpr int kFusedPrefetch = sizeof(T) == 4 ? 3 : 2;  // rows ahead (four measured 7% slower in FP32)
   enum : uint32_t { ACTIVE = 1, INGRID = 2 };
 
   int W, H, n;

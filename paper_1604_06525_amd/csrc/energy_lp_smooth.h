@@ -33,6 +33,7 @@ struct LpSmoothGrid {
   static constexpr int kStatePlanes = 2;
   static constexpr int kOwnState = 2;
   static constexpr int kRadius = 1;
+  static constexpr int kFusedPrefetch = sizeof(T) == 4 ? 3 : 2;  // rows ahead (four measured 4% slower in FP32)
   enum : uint32_t { ACTIVE = 1, INGRID = 2 };
 
   int W, H, n;

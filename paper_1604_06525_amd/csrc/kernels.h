@@ -760,7 +760,8 @@ constexpr int kPrefetchOf = sizeof(T) > 4 ? 2 : 4;
 //  * kPeel: the steps before the pipeline is full run apart from the loop (see
 //    walk_steps).
 // An energy sets them with `static constexpr int kFusedWalk` (bit 0: kPrefetchD,
-// bit 1: kPeel).
+// bit 1: kPeel), and the rows prefetched ahead (kPrefetchOf by default) with
+// `static constexpr int kFusedPrefetch`.
 template <class E, class = void>
 struct FusedWalkOf {
   static constexpr bool kPrefetchD = false, kPeel = false;
@@ -768,6 +769,14 @@ struct FusedWalkOf {
 template <class E>
 struct FusedWalkOf<E, std::void_t<decltype(E::kFusedWalk)>> {
   static constexpr bool kPrefetchD = (E::kFusedWalk & 1) != 0, kPeel = (E::kFusedWalk & 2) != 0;
+};
+template <class E, class = void>
+struct FusedPrefetchOf {
+  static constexpr int value = kPrefetchOf<typename E::Real>;
+};
+template <class E>
+struct FusedPrefetchOf<E, std::void_t<decltype(E::kFusedPrefetch)>> {
+  static constexpr int value = E::kFusedPrefetch;
 };
 
 // The K steps of a strip walk; step(PH, k, steady) gets the ring slot k % N as
@@ -812,7 +821,8 @@ __device__ __forceinline__ void run(const FusedArgs<E, DAMP, BIG>& a, VG g, int 
   using T = typename E::Real;
   using Row = StreamRow<E, DAMP>;
   constexpr int C = E::C, NS = E::kStatePlanes;
-  constexpr int kPrefetch = kPrefetchOf<T>;
+  constexpr int kPrefetch = FusedPrefetchOf<E>::value;
+  static_assert(kPrefetch >= 1, "at least the next row is in flight");
   constexpr int N = kPrefetch + 4;  // ring slots: four rows in use, the rest in flight
   const E& e = a.e;
   DevScalars* S = a.S;
