@@ -36,6 +36,7 @@ struct IntrinsicImage {
   static constexpr int kStatePlanes = 2;
   static constexpr int kOwnState = 2;
   static constexpr int kRadius = 1;
+  static constexpr int kFusedWalk = sizeof(T) == 4 ? 1 : 0;  // FP32: d loaded with its row (the peeled walk was slower)
   enum : uint32_t { ACTIVE = 1, INGRID = 2 };
 
   int W, H, n;

@@ -33,7 +33,10 @@ struct LpSmoothGrid {
   static constexpr int kStatePlanes = 2;
   static constexpr int kOwnState = 2;
   static constexpr int kRadius = 1;
-  static constexpr int kFusedPrefetch = sizeof(T) == 4 ? 3 : 2;  // rows ahead (four measured 4% slower in FP32)
+  // fused strip walk in FP32: three rows ahead and d loaded with its row (four
+  // rows measured 4% slower, d a step ahead 4% slower, the peeled walk 13%)
+  static constexpr int kFusedPrefetch = sizeof(T) == 4 ? 3 : 2;
+  static constexpr int kFusedWalk = sizeof(T) == 4 ? 1 : 0;
   enum : uint32_t { ACTIVE = 1, INGRID = 2 };
 
   int W, H, n;
