@@ -22,7 +22,11 @@
 // Stencil functions read through views: P(c, di, dj) and S(k, di, dj) give
 // unknown-vector channel c and state plane k at offset (di, dj) from the centre,
 // F(di, dj) the flags there (0 off the grid).  State planes: cos t, sin t, U_x, U_y.
+// In FP32 a site stores its angle instead of cos t and sin t (12 bytes instead
+// of 16, read every PCG iteration); the two are formed where the record is read,
+// by the branch-free sin and cos of angle_trig.h.  FP64 stores them.
 #pragma once
+#include "angle_trig.h"
 #include "common.h"
 
 namespace optmi {
@@ -32,8 +36,11 @@ struct ArapWarp {
   using Real = T;
   static constexpr bool kGraph = false;
   static constexpr int C = 3;             // unknown channels
-  static constexpr int kStatePlanes = 4;  // per site: cos t, sin t, U_x, U_y
-  static constexpr int kOwnState = 4;     // all four are stored (U copied beside the angle)
+  static constexpr int kStatePlanes = 4;  // as the products read them: cos t, sin t, U_x, U_y
+  // as stored per site: FP32 (t, U_x, U_y), FP64 (cos t, sin t, U_x, U_y); U is
+  // copied beside the angle so that a site's state is one record
+  static constexpr int kStateRec = sizeof(T) == 4 ? 3 : 4;
+  static constexpr int kOwnState = 4;     // workspace planes per site (the wider record)
   static constexpr int kRadius = 1;       // stencil radius of J^T J
   enum : uint32_t { ACTIVE = 1, INGRID = 2, FIT = 4 };
 
@@ -41,13 +48,32 @@ struct ArapWarp {
   const T* __restrict__ U;    // [2][n]
   const T* __restrict__ Ct;   // [2][n]
   const uint8_t* __restrict__ mask;
-  T* __restrict__ st;         // [n][4]: cos t, sin t at the linearisation point, U_x, U_y
+  T* __restrict__ st;         // [n][kStateRec]: the angle (or its cos, sin) at the linearisation point, U_x, U_y
   uint8_t* __restrict__ flags;
   T wf, wr;                   // w_fit, w_reg in the bulk type
   double wf_d, wr_d;          // and in double for the cost
 
-  __device__ __forceinline__ T state_at(int k, int site) const { return st[(size_t)site * 4 + k]; }
+  __device__ __forceinline__ T state_at(int k, int site) const {
+    const T* r = st + (size_t)site * kStateRec;
+    if constexpr (kStateRec == 4) {
+      return r[k];
+    } else {
+      if (k >= 2) return r[k - 1];
+      float sn, c;
+      sincos_angle(r[0], &sn, &c);
+      return k == 0 ? c : sn;
+    }
+  }
   __device__ __forceinline__ const T* state_base() const { return st; }
+  // The four planes from a record loaded into their last kStateRec places.
+  __device__ __forceinline__ static void expand_state(T* s) {
+    if constexpr (kStateRec == 3) {
+      float sn, c;
+      sincos_angle(s[1], &sn, &c);
+      s[0] = c;
+      s[1] = sn;
+    }
+  }
 
   // Neighbour k of site (i, j) in the order (1,0), (-1,0), (0,1), (0,-1);
   // its id, or -1 off the grid.
@@ -90,15 +116,20 @@ struct ArapWarp {
     return e;
   }
 
-  // Per-site state for the products: cos/sin of the angle and the flags.
+  // Per-site state for the products: the angle (or its cos/sin), U and the flags.
   __device__ __forceinline__ void linearize(const T* __restrict__ x, int s) const {
-    T sn, c;
-    sincos_t(x[2 * (size_t)n + s], &sn, &c);
-    T* q = st + (size_t)s * 4;
-    q[0] = c;
-    q[1] = sn;
-    q[2] = U[s];
-    q[3] = U[n + s];
+    const T t = x[2 * (size_t)n + s];
+    T* q = st + (size_t)s * kStateRec;
+    if constexpr (kStateRec == 4) {
+      T sn, c;
+      sincos_t(t, &sn, &c);
+      q[0] = c;
+      q[1] = sn;
+    } else {
+      q[0] = t;
+    }
+    q[kStateRec - 2] = U[s];
+    q[kStateRec - 1] = U[n + s];
     const bool fit = Ct[s] >= T(0) && Ct[n + s] >= T(0);
     flags[s] = (uint8_t)(INGRID | (mask[s] == 0 ? ACTIVE : 0) | (fit ? FIT : 0));
   }
@@ -169,13 +200,12 @@ struct ArapWarp {
   __device__ __forceinline__ void eval_j(int s, T* __restrict__ val, int* __restrict__ col) const {
     const int i = s % W, j = s / W;
     const uint32_t fp = flags[s];
-    const T* sp = st + (size_t)s * 4;
-    const T c = sp[0], sn = sp[1], Ux = sp[2], Uy = sp[3];
+    const T c = state_at(0, s), sn = state_at(1, s), Ux = state_at(2, s), Uy = state_at(3, s);
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
       const int q = nbr(i, j, s, k);
       const bool on = (fp & ACTIVE) && q >= 0 && (flags[q] & ACTIVE);
-      const T dx = on ? Ux - st[(size_t)q * 4 + 2] : T(0), dy = on ? Uy - st[(size_t)q * 4 + 3] : T(0);
+      const T dx = on ? Ux - state_at(2, q) : T(0), dy = on ? Uy - state_at(3, q) : T(0);
       const T a[2] = {-sn * dx - c * dy, c * dx - sn * dy};  // R'(t_p)(U_p - U_q)
 #pragma unroll
       for (int ch = 0; ch < 2; ++ch) {

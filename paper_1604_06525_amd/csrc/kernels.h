@@ -778,6 +778,20 @@ template <class E>
 struct FusedPrefetchOf<E, std::void_t<decltype(E::kFusedPrefetch)>> {
   static constexpr int value = E::kFusedPrefetch;
 };
+// The record an energy stores per site may hold fewer values than the state
+// planes its products read (`static constexpr int kStateRec`): the walk loads
+// it into the last kStateRec places of a row's state and the energy's
+// expand_state fills the rest once the row's loads have landed.
+template <class E, class = void>
+struct StateRecOf {
+  static constexpr int value = E::kStatePlanes;
+  static constexpr bool kExpand = false;
+};
+template <class E>
+struct StateRecOf<E, std::void_t<decltype(E::kStateRec)>> {
+  static constexpr int value = E::kStateRec;
+  static constexpr bool kExpand = E::kStateRec != E::kStatePlanes;
+};
 
 // The K steps of a strip walk; step(PH, k, steady) gets the ring slot k % N as
 // a constant.  Plain form: groups of N steps, each step tested against K.
@@ -861,7 +875,9 @@ __device__ __forceinline__ void run(const FusedArgs<E, DAMP, BIG>& a, VG g, int 
   // the first row the strip touches (yb) and covers only its rows ylo..yhi, so
   // that offsets stay small however large the grid is (the other keeps whole
   // vectors: fewer live registers, which the FP32 warp kernel needs).
-  constexpr unsigned VB = C * sizeof(T), SB = (NS > 0 ? NS : 1) * sizeof(T);
+  using SR = StateRecOf<E>;
+  constexpr int NR = SR::value;  // values stored per site
+  constexpr unsigned VB = C * sizeof(T), SB = (NR > 0 ? NR : 1) * sizeof(T);
   const int yb = BIG ? ylo : 0;
   const size_t span = BIG ? (has_strip ? (size_t)(yhi - ylo + 1) * W : 0) : (size_t)n;  // sites
   const size_t rb = BIG && has_strip ? (size_t)yb * W : 0;                               // first site
@@ -871,7 +887,7 @@ __device__ __forceinline__ void run(const FusedArgs<E, DAMP, BIG>& a, VG g, int 
   const Buf<T> Bx = Buf<T>::make(a.b.x + rb * C, xupd ? vbytes : 0);
   const Buf<T> Buout = Buf<T>::make(pick(a.b.u, (iter + 1) & 1) + rb * C, write_out ? vbytes : 0);
   const Buf<T> Bpout = Buf<T>::make(pick(a.b.p, iter & 1) + rb * C, write_out ? vbytes : 0);
-  const Buf<T> Bst = Buf<T>::make(e.state_base() + (NS > 0 ? rb * NS : 0), NS > 0 ? span * SB : 0);
+  const Buf<T> Bst = Buf<T>::make(e.state_base() + (NR > 0 ? rb * NR : 0), NR > 0 ? span * SB : 0);
   const Buf<uint8_t> Bf = Buf<uint8_t>::make(e.flags + rb, span);
   // Byte offsets are a per-lane column part plus a scalar row part (rows
   // counted from yb).  Either part may be kBufOutOfRange; the sum then stays at
@@ -888,8 +904,8 @@ __device__ __forceinline__ void run(const FusedArgs<E, DAMP, BIG>& a, VG g, int 
   auto issue = [&](Row& R, int y) {
     const bool in = y >= ylo && y <= yhi;
     const unsigned rs = (unsigned)((y - yb) * W);
-    if constexpr (NS > 0) {
-      buf_loadv<NS>(Bst, lane_s + (in ? rs * SB : kBufOutOfRange), 0, R.st);
+    if constexpr (NR > 0) {
+      buf_loadv<NR>(Bst, lane_s + (in ? rs * SB : kBufOutOfRange), 0, R.st + (NS - NR));
     } else {
       R.st[0] = T(0);
     }
@@ -975,6 +991,7 @@ __device__ __forceinline__ void run(const FusedArgs<E, DAMP, BIG>& a, VG g, int 
       Row& R3 = ring[(ph + N - 3) % N];  // y - 3 dir
       const int y = ybeg + dir * k;
       issue(ring[(ph + kPrefetch) % N], y + dir * kPrefetch);
+      if constexpr (SR::kExpand) E::expand_state(R0.st);
       // p_i = u_i + beta p_{i-1} on row y
 #pragma unroll
       for (int c = 0; c < C; ++c) {

@@ -1,6 +1,6 @@
 """Host logic under AddressSanitizer and UndefinedBehaviorSanitizer, no GPU.
 
-Two C++ harnesses, built here with g++ (-fsanitize=address,undefined) against
+Three C++ harnesses, built here with g++ (-fsanitize=address,undefined) against
 the library's HIP-free headers and run as child processes:
 
 * serve_sched_harness.cpp drives the batching server's scheduling
@@ -19,6 +19,11 @@ the library's HIP-free headers and run as child processes:
   hub, grid, loop and repeated-edge graphs and for Morton-ordered icospheres
   written here from the workload generator, and checks that an edge naming a
   missing vertex is refused.
+* angle_trig_harness.cpp checks the branch-free FP32 sine and cosine that the
+  FP32 warp energy forms from its stored angles (angle_trig.h) against the C
+  library's double sin and cos on a dense grid of angles, at and beside every
+  quadrant boundary and at tiny angles: within 2^-23 absolute (one FP32 ulp of 1)
+  over [-3000, 3000] radians.
 """
 import os
 import shutil
@@ -74,3 +79,10 @@ def test_graph_lists_against_brute_force(tmp_path):
     assert "with fused rows" in out
     for seed in (2, 3):
         _run([exe, str(seed)])
+
+
+def test_angle_sine_and_cosine(tmp_path):
+    exe = _build("angle_trig_harness.cpp", tmp_path / "trig")
+    for lim in ("1", "100", "3000"):
+        out = _run([exe, lim, "2.0"])
+        assert float(out.split()[1]) <= 2.0
