@@ -241,7 +241,9 @@ def _serve_pool(torch, pkg, dev):
         x0 = torch.from_numpy(np.ascontiguousarray(np.asarray(d["x0"], np.float32).reshape(-1))).to(dev)
         method, K, L = SCHEDULE[kind]
         sp = pkg.default_params(method=method, outer_iters=K, pcg_iters=L)
-        plain = pkg.Problem(energy, arrays, params, precision="mixed", **dims)
+        # plain solves run the shape the server gives the request, so that the
+        # two legs can be compared bit for bit
+        plain = pkg.Problem(energy, arrays, params, precision="mixed", tuning="served", **dims)
         entries.append(dict(spec=spec, energy=energy, arrays=arrays, params=params, dims=dims, x0=x0,
                             sp=sp, plain=plain))
     return entries

@@ -250,7 +250,10 @@ class Problem:
     ``arrays`` are device tensors in the energy's order (include/opt.h); float64
     under precision "fp64", float32 under "mixed", uint8 for masks.  They are
     referenced, not copied, and kept alive by this object.  The workspace is a
-    torch uint8 tensor on the same device.
+    torch uint8 tensor on the same device.  ``tuning``: "auto" takes the launch
+    shape from the committed tuning table (the library's own choice where it has
+    no entry), "served" the shape a Server gives the same request, a dict sets
+    one by hand, None keeps the library's choice.
     """
 
     def __init__(self, energy, arrays, params=(), precision="mixed", width=0, height=0,
@@ -281,9 +284,9 @@ class Problem:
                "opt_problem_create")
         self.handle = h
         self._lib = lib()
-        if tuning == "auto" and not n_vertices and not depth:
+        if tuning in ("auto", "served") and not n_vertices and not depth:
             from . import tune
-            t = tune.best(tune.load(), energy, precision, self.n_sites)
+            t = tune.best(tune.load(), energy, precision, self.n_sites, served=tuning == "served")
             if t["strip_rows"] or t["waves_per_simd"]:
                 self.set_tuning(**t)
         elif isinstance(tuning, dict):

@@ -4,14 +4,24 @@
 
 For each grid energy with a fused kernel (ARAP warp, Poisson, optical flow,
 shape from shading, the Laplacian, l_p smoothing, intrinsic decomposition), each
-precision and each size class (grid sides 128, 256, 512, 1024, 2048), it times
+precision and each size class (grid sides 64, 128, 256, 512, 1024, 2048), it times
 the PCG phase of a short solve on a seeded synthetic problem for every candidate
 launch shape (fixed strip heights, and balanced partitions with 1 to 4 strips
 per SIMD), and keeps the fastest.  The result is a JSON list of entries
 {energy, precision, min_sites, max_sites, strip_rows, waves_per_simd, iter_us,
 candidates}; a class covers the sites from half its own count up to twice it.  ``apply()``
 feeds the entries to a Server (used at admission) and ``best()`` looks one up for
-a single Problem.  Every choice gives the same iterates; only the speed differs.
+a single Problem.  Every choice gives the same iterates up to rounding; only the
+speed differs.
+
+A small grid alone on the chip is fastest in strips of one to three rows (its
+launch is latency-bound and a strip's walk is its rows plus four halo steps).
+A served request shares each batched launch with others, whose length the
+largest request sets, so there such strips only add waves: the server takes the
+fastest candidate of at least SERVED_MIN_ROWS rows from the same entry (``best``
+and ``apply`` with ``served=True``), and a Problem created with
+``tuning="served"`` runs the shape the server would give it, bit for bit the
+same solve.
 """
 import argparse
 import json
@@ -22,9 +32,10 @@ import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 DEFAULT_PATH = os.path.join(HERE, "tuning.json")
-CANDIDATES = tuple(("rows", r) for r in (4, 6, 8, 12, 16, 24, 32)) + \
+CANDIDATES = tuple(("rows", r) for r in (1, 2, 3, 4, 6, 8, 12, 16, 24, 32)) + \
     tuple(("waves", w) for w in (1, 2, 3, 4)) + (("auto", 0),)
-SIDES = (128, 256, 512, 1024, 2048)
+SIDES = (64, 128, 256, 512, 1024, 2048)
+SERVED_MIN_ROWS = 4
 ENERGIES = ("arap_warp", "poisson", "flow", "sfs", "laplacian", "lp_smooth", "intrinsic")
 
 
@@ -113,19 +124,37 @@ def load(path=DEFAULT_PATH):
         return json.load(f)
 
 
-def best(entries, energy, precision, n_sites):
+def choice(entry, served=False):
+    """The entry's launch shape: its fastest candidate, or with served=True the
+    fastest one whose strips have at least SERVED_MIN_ROWS rows."""
+    rows = entry.get("strip_rows", 0)
+    if not served or rows == 0 or rows >= SERVED_MIN_ROWS:
+        return {"strip_rows": rows, "waves_per_simd": entry.get("waves_per_simd", 0)}
+    ok = {}
+    for k, v in entry.get("candidates", {}).items():
+        kind, val = k.split("=")
+        if kind != "rows" or int(val) >= SERVED_MIN_ROWS:
+            ok[(kind, int(val))] = v
+    if not ok:
+        return {"strip_rows": SERVED_MIN_ROWS, "waves_per_simd": 0}
+    return _fields(min(ok, key=ok.get))
+
+
+def best(entries, energy, precision, n_sites, served=False):
     """Tuning fields of the last matching entry, or the automatic choice."""
     hit = {"strip_rows": 0, "waves_per_simd": 0}
     for e in entries:
         if e["energy"] == energy and e["precision"] == precision and e["min_sites"] <= n_sites <= e["max_sites"]:
-            hit = {"strip_rows": e.get("strip_rows", 0), "waves_per_simd": e.get("waves_per_simd", 0)}
+            hit = choice(e, served)
     return hit
 
 
 def apply(server, entries):
+    """Register the entries with a Server, in their served form."""
     for e in entries:
+        c = choice(e, served=True)
         server.add_tuning(e["energy"], e["precision"], e["min_sites"], e["max_sites"],
-                          e.get("strip_rows", 0), e.get("waves_per_simd", 0))
+                          c["strip_rows"], c["waves_per_simd"])
 
 
 def main():
@@ -134,14 +163,20 @@ def main():
     ap.add_argument("--quick", action="store_true", help="mixed precision, ARAP warp only")
     ap.add_argument("--energies", default="", help="comma list: retune these energies only, keeping the "
                     "other energies' entries of --base")
+    ap.add_argument("--sides", default="", help="comma list: retune these grid sides only, keeping the other "
+                    "sides' entries of --base")
     ap.add_argument("--base", default=DEFAULT_PATH)
     a = ap.parse_args()
     if a.quick:
         entries = autotune(energies=("arap_warp",), precisions=("mixed",))
-    elif a.energies:
-        names = tuple(a.energies.split(","))
-        kept = [e for e in load(a.base) if e["energy"] not in names]
-        entries = kept + autotune(energies=names)
+    elif a.energies or a.sides:
+        names = tuple(a.energies.split(",")) if a.energies else ENERGIES
+        sides = tuple(int(v) for v in a.sides.split(",")) if a.sides else SIDES
+        kept = [e for e in load(a.base) if not (e["energy"] in names and e["side"] in sides)]
+        entries = kept + autotune(energies=names, sides=sides)
+        order = {(en, p, s): i for i, (en, p, s) in enumerate(
+            (en, p, s) for en in ENERGIES for p in ("mixed", "fp64") for s in SIDES)}
+        entries.sort(key=lambda e: order.get((e["energy"], e["precision"], e["side"]), len(order)))
     else:
         entries = autotune()
     save(entries, a.out)

@@ -38,7 +38,9 @@ def _request(d, precision, **solve):
 
 
 def _alone(r):
-    prob = pkg.Problem(r["energy"], r["arrays"], r["params"], precision=r["precision"], **r["dims"])
+    # the launch shape the server gives the request (tuning entries, served form)
+    prob = pkg.Problem(r["energy"], r["arrays"], r["params"], precision=r["precision"], tuning="served",
+                       **r["dims"])
     x = r["x0"].clone().reshape(prob.channels, -1)
     rep = prob.solve(x, **r["solve"])
     return x.reshape(-1), rep
