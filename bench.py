@@ -405,6 +405,11 @@ CONFIGS = [
     ("flow_1920x1080_gn10x50_mixed", lambda w: w.optical_flow(1920, 1080, seed=4), "mixed", "gn", 10, 50, (24, 8)),
     ("flow_1920x1080_gn10x50_fp64", lambda w: w.optical_flow(1920, 1080, seed=4), "fp64", "gn", 10, 50, (24, 8)),
     ("poisson_1024x1024_gn10x50_mixed", lambda w: w.poisson_edit(1024, 1024, seed=5), "mixed", "gn", 10, 50, (24, 1)),
+    # a small grid alone on the chip: the tuning table's one-row strips, and
+    # the four-row strips a server gives the same request
+    ("warp_128x128_gn10x50_mixed", lambda w: w.arap_warp(128, 128, seed=8), "mixed", "gn", 10, 50, (24, 13)),
+    ("warp_128x128_gn10x50_mixed_served", lambda w: w.arap_warp(128, 128, seed=8), "mixed", "gn", 10, 50, (24, 13),
+     dict(tuning="served")),
     # large grids: at 8192^2 a vector (805 MB) is past the regular fused
     # instantiation's 256 MB buffer range and its large-grid instantiation runs
     ("warp_4096x4096_gn10x50_mixed", lambda w: w.arap_warp(4096, 4096, seed=6), "mixed", "gn", 10, 50, (24, 13)),
