@@ -524,6 +524,8 @@ class Server:
 
     ``arena_bytes`` of device memory are allocated here as one torch tensor and
     handed to the library: it is the memory budget of the requests held at once.
+    ``tuning="auto"`` registers the committed tuning table in its served form
+    (each entry's fastest launch shape with strips of at least four rows).
     """
 
     def __init__(self, arena_bytes, max_slots=64, device="cuda", stream=None, tuning="auto"):
