@@ -12,7 +12,7 @@ def require_gpu():
         pytest.skip("no GPU")
 
 
-def make_problem(d, precision="fp64"):
+def make_problem(d, precision="fp64", tuning="auto"):
     import paper_1604_06525_amd as pkg
     dt = np.float64 if precision == "fp64" else np.float32
     energy, arrs, params, dims = problem_args(d, dt)
@@ -20,7 +20,7 @@ def make_problem(d, precision="fp64"):
     t_arrs = [torch.from_numpy(a).to(dev) for a in arrs]
     if "edges" in dims:
         dims = dict(dims, edges=torch.from_numpy(dims["edges"]).to(dev))
-    prob = pkg.Problem(energy, t_arrs, params, precision=precision, **dims)
+    prob = pkg.Problem(energy, t_arrs, params, precision=precision, tuning=tuning, **dims)
     return prob
 
 

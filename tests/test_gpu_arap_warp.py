@@ -214,7 +214,8 @@ def test_zero_iterations_and_tiny_grid():
     assert np.allclose(rep["cost_trace"], costs, rtol=1e-12, atol=1e-300)
 
 
-@pytest.mark.parametrize("tuning", [dict(strip_rows=4), dict(strip_rows=7), dict(strip_rows=200),
+@pytest.mark.parametrize("tuning", [dict(strip_rows=1), dict(strip_rows=2), dict(strip_rows=4), dict(strip_rows=7),
+                                    dict(strip_rows=200),
                                     dict(waves_per_simd=1), dict(waves_per_simd=3)])
 def test_launch_shapes_agree(tuning):
     """Every strip partition of the fused kernel gives the oracle's PCG iterates

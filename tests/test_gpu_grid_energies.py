@@ -241,3 +241,26 @@ def test_sfs_fused_launch_shapes(tuning):
         tol = pcg_tol(ref, ref2)
         got = to_np(prob.pcg(14, lam=lam, variant="fused"))
         assert relmax(got, ref) < tol, (tuning, lam, tol)
+
+
+@pytest.mark.parametrize("kind", ["poisson", "flow", "warp"])
+@pytest.mark.parametrize("rows", [1, 2, 3])
+def test_short_strips(kind, rows):
+    """The one- to three-row strips the tuning table gives small grids: FP64
+    PCG iterates match the oracle's (1e-9, as every launch shape), and a mixed
+    precision GN 4 x 20 in those strips reaches the oracle's cost within the
+    mixed-precision bar of 1e-4 (as test_gn_mixed in the library's own shape)."""
+    d, x = MAKERS[kind](130, 70)
+    e = o.make_energy(d)
+    lin = o.Linearization(e, x)
+    ref, _ = o.pcg(lin.apply, lin.jtf(), lin.minv(True), 20)
+    prob = make_problem(d, "fp64", tuning=None)
+    prob.set_tuning(strip_rows=rows)
+    assert prob.get_tuning()["strip_rows"] == rows
+    prob.linearize(to_dev(prob, x))
+    assert relmax(to_np(prob.pcg(20, variant="fused")), ref) < 1e-9
+    _, costs = o.gauss_newton(e, d["x0"], 4, 20)
+    p32 = make_problem(d, "mixed", tuning=None)
+    p32.set_tuning(strip_rows=rows)
+    rep = p32.solve(to_dev(p32, d["x0"]), method="gn", outer_iters=4, pcg_iters=20)
+    assert abs(rep["cost_final"] - costs[-1]) <= 1e-4 * costs[-1]
